@@ -1,0 +1,169 @@
+/*
+ * tridiag -- block-tridiagonal solver for AMD MI355X (gfx950), C ABI.
+ *
+ * Solves P X = F for one fixed block-tridiagonal matrix P and many right-hand
+ * sides, with the matrix factored once and the factor reused for every F.
+ * P is the matrix of eq. (main-eq) in Sec. 1 of A. V. Terekhov, "A fast
+ * parallel algorithm for solving block-tridiagonal systems of linear
+ * equations including the domain decomposition method": N block rows of
+ * M x M blocks, block row j reading
+ *
+ *     -A_j X_{j-1} + C_j X_j - B_j X_{j+1} = F_j ,   j = 1..N,
+ *
+ * (note the minus signs on A and B; A_1 and B_N are not part of P and are
+ * ignored).  The solver is the paper's Algorithm 2 (Sec. 2.2): the rows are
+ * cut into p subdomains whose first rows are the interface rows; per
+ * subdomain the sub-problems of eqs. (sub1)-(sub3) give U, V and W; the
+ * interface unknowns solve the reduced system of eq. (red1) by the dichotomy
+ * of Algorithm 1 (Sec. 2.1) with stored rows of the inverse; eq.
+ * (superposition) then gives every other row.  Everything runs in HIP
+ * kernels on one GPU; all pointers to matrix and vector data are DEVICE
+ * pointers unless stated otherwise.
+ *
+ * Layouts (all float64):
+ *   DENSE block field   : [N][M][M], block j column-major (entry (r,c) at j*M*M + r + c*M)
+ *   DIAG block field    : [N][M], the diagonal of each block
+ *   TRIDIAG block field : [N][3][M], (sub, diag, super): C_j(i,i-1) = [j][0][i],
+ *                         C_j(i,i) = [j][1][i], C_j(i,i+1) = [j][2][i]; [j][0][0] and
+ *                         [j][2][M-1] are ignored
+ *   right-hand sides and solutions: column-major (N*M) x K with leading dimension
+ *                         ld >= N*M; column k holds X_1..X_N of right-hand side k
+ *
+ * Threading: a plan may be used from one host thread at a time.  Calls are
+ * stream-ordered on the HIP stream passed in (NULL = the default stream).
+ */
+#ifndef TRIDIAG_H
+#define TRIDIAG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TD_OK = 0,
+  TD_EINVAL = 1,     /* an argument is out of range; nothing was launched */
+  TD_ENOMEM = 2,     /* the plan or its workspace does not fit in free device memory */
+  TD_ESINGULAR = 3,  /* a pivot block (or a block of the reduced system) is singular */
+  TD_ENOCONV = 4,    /* iterative refinement did not reach the requested residual */
+  TD_ENOADJ = 5,     /* an adjoint solve on a plan factored without the transpose */
+  TD_EHIP = 6,       /* a HIP runtime call failed; tridiag_last_error() has its text */
+  TD_ENOTSUP = 7     /* a valid but unsupported combination (for example M > 512) */
+} td_status;
+
+typedef enum { TD_FMT_DENSE = 0, TD_FMT_DIAG = 1, TD_FMT_TRIDIAG = 2 } td_format;
+
+typedef enum { TD_PREC_F64 = 0, TD_PREC_F32 = 1, TD_PREC_BF16 = 2 } td_precision;
+
+/* Description of the matrix and of the plan to build. */
+typedef struct {
+  int64_t N;            /* block rows, >= 1 */
+  int64_t M;            /* block size, 1 <= M <= 512 */
+  int64_t subdomains;   /* p in [1, N]: number of subdomains of Algorithm 2; 0 = chosen by the library */
+  int32_t fmt_A;        /* TD_FMT_DENSE or TD_FMT_DIAG */
+  int32_t fmt_B;        /* TD_FMT_DENSE or TD_FMT_DIAG */
+  int32_t fmt_C;        /* TD_FMT_DENSE or TD_FMT_TRIDIAG */
+  int32_t sweep_prec;   /* TD_PREC_F64: plain float64 solve; TD_PREC_F32 / TD_PREC_BF16: the
+                           subdomain sweeps and the superposition run on rounded copies of the
+                           factor (float32 accumulation), see tridiag_solve */
+  int32_t adjoint;      /* nonzero: also factor P^T so that tridiag_solve_adjoint can be used */
+  int32_t reserved;     /* must be 0 */
+} td_desc;
+
+/* Iterative refinement (used by tridiag_solve and tridiag_solve_adjoint). */
+typedef struct {
+  int32_t enable;       /* nonzero: refine in float64 until the residual test passes */
+  int32_t max_iter;     /* at most this many correction solves (<= 0: 10) */
+  double tol;           /* stop when max_k ||F_k - P X_k||_2 / ||F_k||_2 <= tol (<= 0: 1e-10) */
+} td_refine;
+
+/* Result report of one solve (host memory). */
+typedef struct {
+  int32_t iterations;          /* correction solves done after the first solve */
+  int32_t nonfinite;           /* nonzero if F or the result held Inf/NaN */
+  double max_col_rel_residual; /* max_k ||F_k - P X_k||_2 / ||F_k||_2 (float64), or -1 if not computed */
+} td_info;
+
+typedef struct td_plan_s* td_plan;
+
+/*
+ * Factor P once (Algorithm 2, preliminary step 1 of Sec. 2.2).
+ *   desc    : host pointer to the description.
+ *   A, B, C : device pointers to the blocks in the formats named by desc.  They are read
+ *             during the call only; the plan keeps its own compact copies.
+ *   stream  : hipStream_t (as void*), or NULL.
+ *   out     : receives the plan (NULL on failure).
+ * The call is synchronous: it returns after the factor is complete and its pivots have been
+ * checked.  Returns TD_ESINGULAR if a diagonal block of the elimination (or of the reduced
+ * system) has a pivot below 1e-14 times its infinity norm; tridiag_last_error() names the
+ * block row.  The plan owns all its device memory until tridiag_destroy.
+ */
+td_status tridiag_factor(const td_desc* desc, const double* A, const double* B, const double* C,
+                         void* stream, td_plan* out);
+
+/*
+ * Solve P X = F for K right-hand sides (Algorithm 2, solution step 2 of Sec. 2.2).
+ *   F, ldf : device, column-major (N*M) x K, ldf >= N*M.  Read only.
+ *   X, ldx : device, column-major (N*M) x K, ldx >= N*M.  Written.  Must not overlap F.
+ *   refine : host, may be NULL (= disabled).  For a plan with sweep_prec F32/BF16 and refine
+ *            disabled, the result carries the rounding error of that precision.
+ *   info   : host, may be NULL.  If non-NULL, or if refinement is on, the call computes the
+ *            float64 residual and synchronises the stream before returning.
+ * Without refinement and with info == NULL the call only enqueues work on the stream.
+ * K == 0 is a no-op.  Returns TD_ENOCONV if refinement stops at max_iter above tol (X then
+ * holds the last iterate).
+ */
+td_status tridiag_solve(td_plan plan, const double* F, int64_t ldf, double* X, int64_t ldx, int64_t K,
+                        const td_refine* refine, td_info* info, void* stream);
+
+/*
+ * Solve P^T Lam = G (same conventions as tridiag_solve).  The transposed matrix is again
+ * block tridiagonal with blocks C'_j = C_j^T, A'_j = B_{j-1}^T, B'_j = A_{j+1}^T.
+ * Returns TD_ENOADJ if the plan was factored with desc.adjoint == 0.
+ */
+td_status tridiag_solve_adjoint(td_plan plan, const double* G, int64_t ldg, double* Lam, int64_t ldl,
+                                int64_t K, const td_refine* refine, td_info* info, void* stream);
+
+/*
+ * Gradient with respect to a shift sigma added to the diagonal of the blocks C_j:
+ *   out[r] = - sum_{k < K} Lam[r + k*ldl] * X[r + k*ldx],   r < n   (n = N*M)
+ * with Lam = P^{-T} dL/dX and X = P^{-1} F.  All device pointers; out has n entries.
+ * The sum over k runs in a fixed order (bitwise reproducible).
+ */
+td_status tridiag_diag_grad(const double* Lam, int64_t ldl, const double* X, int64_t ldx, int64_t n, int64_t K,
+                            double* out, void* stream);
+
+/* Free every device buffer of the plan (synchronises the plan's last stream). */
+td_status tridiag_destroy(td_plan plan);
+
+/* Plan facts (host memory). */
+typedef struct {
+  int64_t N, M, subdomains;
+  int64_t Mp;                 /* block size padded for the kernels (multiple of 16, 32 or 64) */
+  int64_t tree_depth;         /* levels of the dichotomy tree over the p interface rows */
+  int64_t device_bytes;       /* device memory owned by the plan */
+  double factor_ms;           /* wall time of tridiag_factor */
+  int32_t sweep_prec, adjoint;
+} td_plan_info;
+td_status tridiag_plan_info(td_plan plan, td_plan_info* out);
+
+/*
+ * Per-stage timing of the solves (HIP events on the solve's stream).  When enabled, every
+ * following solve records events around each stage; tridiag_stage_times returns, for the
+ * last solve, the milliseconds of: [0] subdomain sweeps, [1] interface right-hand side,
+ * [2] dichotomy partial sums, [3] dichotomy levels, [4] superposition, [5] residual and
+ * update (refinement), [6] whole solve.  It synchronises the stream.
+ */
+td_status tridiag_set_profiling(td_plan plan, int enable);
+td_status tridiag_stage_times(td_plan plan, double* ms, int n);
+
+const char* tridiag_status_string(td_status s);
+/* Text of the last error on the calling host thread ("" if none). */
+const char* tridiag_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRIDIAG_H */

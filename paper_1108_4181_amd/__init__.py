@@ -1,0 +1,253 @@
+"""Python binding of the MI355X block-tridiagonal solver (libtridiag.so).
+
+Argument marshalling only: every step of the factor and of the solve runs in the
+HIP kernels behind the C ABI of include/tridiag.h.  Tensors are torch float64
+tensors on the current HIP device; the current torch stream is passed to the
+library.  The solver is Algorithm 2 of Terekhov's paper (Sec. 2.2) with the
+dichotomy of Algorithm 1 (Sec. 2.1) on the reduced interface system.
+
+Layouts: DIAG fields [N][M], TRIDIAG fields [N][3][M] (sub, diag, super), DENSE
+fields [N][M][M] with each block column-major; right-hand sides are tensors of
+shape (K, N*M) (row k = right-hand side k), i.e. column-major (N*M) x K.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtridiag.so")
+
+FMT = {"dense": 0, "diag": 1, "tridiag": 2}
+PREC = {"f64": 0, "f32": 1, "bf16": 2}
+STATUS = {0: "TD_OK", 1: "TD_EINVAL", 2: "TD_ENOMEM", 3: "TD_ESINGULAR", 4: "TD_ENOCONV", 5: "TD_ENOADJ",
+          6: "TD_EHIP", 7: "TD_ENOTSUP"}
+
+
+class TridiagError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Desc(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int64), ("M", ctypes.c_int64), ("subdomains", ctypes.c_int64),
+                ("fmt_A", ctypes.c_int32), ("fmt_B", ctypes.c_int32), ("fmt_C", ctypes.c_int32),
+                ("sweep_prec", ctypes.c_int32), ("adjoint", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class _Refine(ctypes.Structure):
+    _fields_ = [("enable", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("nonfinite", ctypes.c_int32),
+                ("max_col_rel_residual", ctypes.c_double)]
+
+
+class _PlanInfo(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int64), ("M", ctypes.c_int64), ("subdomains", ctypes.c_int64),
+                ("Mp", ctypes.c_int64), ("tree_depth", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("factor_ms", ctypes.c_double), ("sweep_prec", ctypes.c_int32), ("adjoint", ctypes.c_int32)]
+
+
+# every symbol the header declares
+EXPORTS = ["tridiag_factor", "tridiag_solve", "tridiag_solve_adjoint", "tridiag_diag_grad", "tridiag_destroy",
+           "tridiag_plan_info", "tridiag_set_profiling", "tridiag_stage_times", "tridiag_status_string",
+           "tridiag_last_error"]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libtridiag.so; raise if it is not built (there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built: run __graft_entry__.build() (hipcc, gfx950)")
+    lib = ctypes.CDLL(path)
+    vp, i64, i32, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    lib.tridiag_factor.argtypes = [ctypes.POINTER(_Desc), vp, vp, vp, vp, ctypes.POINTER(vp)]
+    lib.tridiag_factor.restype = i32
+    lib.tridiag_solve.argtypes = [vp, vp, i64, vp, i64, i64, ctypes.POINTER(_Refine), ctypes.POINTER(_Info), vp]
+    lib.tridiag_solve.restype = i32
+    lib.tridiag_solve_adjoint.argtypes = lib.tridiag_solve.argtypes
+    lib.tridiag_solve_adjoint.restype = i32
+    lib.tridiag_diag_grad.argtypes = [vp, i64, vp, i64, i64, i64, vp, vp]
+    lib.tridiag_diag_grad.restype = i32
+    lib.tridiag_destroy.argtypes = [vp]
+    lib.tridiag_destroy.restype = i32
+    lib.tridiag_plan_info.argtypes = [vp, ctypes.POINTER(_PlanInfo)]
+    lib.tridiag_plan_info.restype = i32
+    lib.tridiag_set_profiling.argtypes = [vp, ctypes.c_int]
+    lib.tridiag_set_profiling.restype = i32
+    lib.tridiag_stage_times.argtypes = [vp, ctypes.POINTER(dp), ctypes.c_int]
+    lib.tridiag_stage_times.restype = i32
+    lib.tridiag_status_string.argtypes = [i32]
+    lib.tridiag_status_string.restype = ctypes.c_char_p
+    lib.tridiag_last_error.argtypes = []
+    lib.tridiag_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(code: int):
+    if code != 0:
+        msg = _lib.tridiag_last_error().decode()
+        raise TridiagError(code, msg)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64:
+        raise TypeError(f"{name} must be a float64 tensor on a HIP device")
+    if not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous")
+    return t
+
+
+def _rhs(t: torch.Tensor, n: int, name: str):
+    """(K, n) tensor with row stride >= n -> (pointer, ld, K)."""
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64:
+        raise TypeError(f"{name} must be a float64 tensor on a HIP device")
+    if t.dim() != 2 or t.shape[1] != n or t.stride(1) != 1 or (t.shape[0] > 1 and t.stride(0) < n):
+        raise TypeError(f"{name} must have shape (K, {n}) with unit column stride")
+    ld = t.stride(0) if t.shape[0] > 1 else n
+    return ctypes.c_void_p(t.data_ptr()), max(ld, n), t.shape[0]
+
+
+class Plan:
+    """A factored block-tridiagonal matrix (tridiag_factor) reusable for many right-hand sides."""
+
+    def __init__(self, A, B, C, N, M, fmt_A="diag", fmt_B="diag", fmt_C="tridiag", subdomains=0,
+                 sweep_prec="f64", adjoint=False):
+        self.lib = load_library()
+        self.N, self.M = int(N), int(M)
+        d = _Desc(self.N, self.M, int(subdomains), FMT[fmt_A], FMT[fmt_B], FMT[fmt_C], PREC[sweep_prec],
+                  1 if adjoint else 0, 0)
+        A, B, C = _dev(A, "A"), _dev(B, "B"), _dev(C, "C")
+        h = ctypes.c_void_p()
+        code = self.lib.tridiag_factor(ctypes.byref(d), ctypes.c_void_p(A.data_ptr()),
+                                       ctypes.c_void_p(B.data_ptr()), ctypes.c_void_p(C.data_ptr()), _stream(),
+                                       ctypes.byref(h))
+        _check(code)
+        self.h = h
+        self.device = A.device
+
+    @classmethod
+    def from_system(cls, sys, device="cuda", **kw):
+        """Factor a synth.System (numpy arrays in the C-ABI layouts)."""
+        t = lambda a: torch.as_tensor(a, dtype=torch.float64).to(device).contiguous()
+        return cls(t(sys.A), t(sys.B), t(sys.C), sys.N, sys.M, sys.fmt_A, sys.fmt_B, sys.fmt_C, **kw)
+
+    def _solve(self, fn, F, X, refine, info):
+        n = self.N * self.M
+        fp, ldf, K = _rhs(F, n, "F")
+        if X is None:
+            X = torch.empty((K, n), dtype=torch.float64, device=F.device)
+        xp, ldx, K2 = _rhs(X, n, "X")
+        if K2 != K:
+            raise ValueError("F and X have different numbers of columns")
+        rf = None
+        if refine:
+            if refine is True:
+                refine = {}
+            rf = _Refine(1, int(refine.get("max_iter", 10)), float(refine.get("tol", 1e-10)))
+        inf = _Info() if info else None
+        code = fn(self.h, fp, ldf, xp, ldx, K, ctypes.byref(rf) if rf else None,
+                  ctypes.byref(inf) if inf else None, _stream())
+        if code == 4 and info:  # no convergence: report instead of raising when the caller asked for info
+            return X, {"iterations": inf.iterations, "nonfinite": inf.nonfinite,
+                       "max_col_rel_residual": inf.max_col_rel_residual, "converged": False}
+        _check(code)
+        if info:
+            return X, {"iterations": inf.iterations, "nonfinite": inf.nonfinite,
+                       "max_col_rel_residual": inf.max_col_rel_residual, "converged": True}
+        return X
+
+    def solve(self, F, X=None, refine=None, info=False):
+        """X = P^{-1} F.  F: (K, N*M) float64 on the device.  refine: None, True or dict(tol, max_iter)."""
+        return self._solve(self.lib.tridiag_solve, F, X, refine, info)
+
+    def solve_adjoint(self, G, Lam=None, refine=None, info=False):
+        """Lam = P^{-T} G (needs adjoint=True at factor time)."""
+        return self._solve(self.lib.tridiag_solve_adjoint, G, Lam, refine, info)
+
+    def plan_info(self) -> dict:
+        pi = _PlanInfo()
+        _check(self.lib.tridiag_plan_info(self.h, ctypes.byref(pi)))
+        return {f: getattr(pi, f) for f, _ in _PlanInfo._fields_}
+
+    def set_profiling(self, on: bool = True):
+        _check(self.lib.tridiag_set_profiling(self.h, 1 if on else 0))
+
+    def stage_times(self) -> dict:
+        buf = (ctypes.c_double * 7)()
+        _check(self.lib.tridiag_stage_times(self.h, buf, 7))
+        names = ["sweep", "interface_rhs", "dichotomy_partial", "dichotomy_levels", "superposition",
+                 "refinement", "total"]
+        return dict(zip(names, list(buf)))
+
+    def close(self):
+        h = getattr(self, "h", None)
+        if h:
+            self.lib.tridiag_destroy(h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def diag_grad(Lam: torch.Tensor, X: torch.Tensor) -> torch.Tensor:
+    """out[r] = -sum_k Lam[k, r] X[k, r] (gradient w.r.t. a shift of the diagonal of the C_j)."""
+    lib = load_library()
+    n = Lam.shape[1]
+    lp, ldl, K = _rhs(Lam, n, "Lam")
+    xp, ldx, K2 = _rhs(X, n, "X")
+    if K2 != K:
+        raise ValueError("Lam and X have different numbers of columns")
+    out = torch.empty(n, dtype=torch.float64, device=Lam.device)
+    _check(lib.tridiag_diag_grad(lp, ldl, xp, ldx, n, K, ctypes.c_void_p(out.data_ptr()), _stream()))
+    return out
+
+
+class ShiftedSolve(torch.autograd.Function):
+    """X = P(sigma)^{-1} F for C_j = tridiag(sub_j, base_j + sigma_j, super_j) with fixed A_j, B_j.
+
+    Backward: Lam = P^{-T} dL/dX (the factored transpose), dL/dF = Lam and
+    dL/dsigma = -sum_k Lam o X (the diagonal entries of dL/dP = -Lam X^T).
+    """
+
+    @staticmethod
+    def forward(ctx, F, sigma, base_C, A, B, subdomains, sweep_prec, refine):
+        N, M = sigma.shape
+        C = base_C.clone()
+        C[:, 1, :] += sigma
+        plan = Plan(A, B, C.contiguous(), N, M, "diag", "diag", "tridiag", subdomains=subdomains,
+                    sweep_prec=sweep_prec, adjoint=True)
+        X = plan.solve(F.contiguous(), refine=refine)
+        ctx.plan = plan
+        ctx.refine = refine
+        ctx.save_for_backward(X)
+        ctx.NM = (N, M)
+        return X
+
+    @staticmethod
+    def backward(ctx, gX):
+        (X,) = ctx.saved_tensors
+        Lam = ctx.plan.solve_adjoint(gX.contiguous(), refine=ctx.refine)
+        dsig = diag_grad(Lam, X).view(*ctx.NM)
+        return Lam, dsig, None, None, None, None, None, None
+
+
+def shifted_solve(F, sigma, base_C, A, B, subdomains=0, sweep_prec="f64", refine=None):
+    return ShiftedSolve.apply(F, sigma, base_C, A, B, subdomains, sweep_prec, refine)

@@ -1,0 +1,115 @@
+// Internal declarations shared by the host plan code and the HIP kernels of the
+// block-tridiagonal solver.  Not part of the public C ABI (include/tridiag.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace td {
+
+// ---------------------------------------------------------------------------
+// Block GEMM: every product in this library has the shape
+//   C (Mp x ncols) = alpha * A (Mp x kd) * B (kd x ncols) [+ Cin] [+ sum of partials]
+// with A and B column-major.  One launch runs a list of such problems (all with the
+// same buffers and leading dimensions, different offsets); one work-group computes
+// the full Mp rows of one 4*CT-column tile of one problem.  B may consist of
+// several segments of `segrows` inner rows each, at a stride of `bseg` elements,
+// so that non-adjacent blocks can form one inner dimension.
+// ---------------------------------------------------------------------------
+struct BDesc {
+  int64_t a_off;    // A = args.A + a_off (lda = args.lda)
+  int64_t b_off;    // B segment q = args.B + b_off + q * bseg (ldb = args.ldb)
+  int64_t bseg;
+  int64_t bs_off;   // per-inner-row scale of B: args.bscale + bs_off (if args.bscale)
+  int64_t c_off;    // C = args.C + c_off (if args.C)
+  int64_t cin_off;  // addend = args.Cin + cin_off (if args.Cin)
+  int64_t sp_off;   // partial sums: args.Sp + sp_off + q * args.spstride, q < nsp
+  int64_t x2_off;   // second output (first x2rows rows only): args.X2 + x2_off
+  int32_t kd;       // inner dimension (multiple of 16)
+  int32_t segrows;  // inner rows per B segment (multiple of 16, divides kd)
+  int32_t nsp;      // number of partial sums to add
+  int32_t pad_;
+};
+
+struct BArgs {
+  const BDesc* descs;
+  int32_t nprob;
+  int32_t ncols;      // columns of B and C
+  int32_t Mp;         // rows of A and C
+  int32_t ncoltiles;
+  int32_t total;      // nprob * ncoltiles
+  int32_t x2rows;
+  double alpha;
+  const double* A; int64_t lda;
+  const double* B; int64_t ldb;
+  const double* bscale;
+  double* C; int64_t ldc;
+  const double* Cin; int64_t ldcin;
+  const double* Sp; int64_t ldsp; int64_t spstride;
+  double* X2; int64_t ldx2;
+};
+
+// Subdomain forward + backward sweeps (eq. sub3, float64).
+struct SweepArgs {
+  const int64_t* ks;     // p + 1 interface rows (0-based; ks[p] = N)
+  const double* Dinv;    // [N][Mp][Mp]: D_i^{-1} of interior row i
+  const double* alpha;   // [N][Mp][Mp]: alpha_i = D_i^{-1} B_i
+  const double* adiag;   // [N][Mp]: diagonal of A_i (zero padded)
+  const double* F; int64_t ldf;
+  double* W; int64_t ldw;
+  int32_t N, M, Mp, p, K, ncoltiles, total;
+};
+
+// Batched Gauss-Jordan inversion with partial pivoting.
+struct GJArgs {
+  double* work;          // matrix q (Mp x Mp col-major, destroyed) at work + work_off[q],
+  const int64_t* work_off;  // or at work + q * wstride when work_off is null
+  int64_t wstride;
+  double* out;           // inverse of matrix q at out + out_off[q]
+  const int64_t* out_off;
+  double* alpha;         // optional: alpha = inverse * diag(bdiag + bd_off[q]) at alpha + out_off[q]
+  const double* bdiag;
+  const int64_t* bd_off;
+  const int32_t* tag;    // block label reported on a singular pivot
+  int32_t* bad;          // atomic min of the labels of singular matrices
+  int32_t nmat, Mp;
+};
+
+// Launch wrappers (kernels_f64.hip)
+hipError_t launch_bgemm(const BArgs& a, hipStream_t st);
+hipError_t launch_sweep(const SweepArgs& a, hipStream_t st);
+hipError_t launch_gj(const GJArgs& a, hipStream_t st);
+int bgemm_coltile(int ncols);    // columns per work-group chosen for ncols
+int sweep_coltile(int Mp, int K);
+
+// Factor helpers
+hipError_t launch_build_D(double* Dwork, int64_t wstride, int nmat, const int64_t* rows, const int32_t* first,
+                          const void* C, int fmtC, const double* adiag, const double* alpha, int M, int Mp,
+                          hipStream_t st);
+hipError_t launch_expand_C(double* out, const void* C, int fmtC, int64_t row, int M, int Mp, hipStream_t st);
+hipError_t launch_reduced(double* At, double* Ct, double* Bt, const int64_t* ks, const double* UV,
+                          const void* C, int fmtC, const double* adiag, const double* bdiag, int p, int N,
+                          int M, int Mp, hipStream_t st);
+hipError_t launch_pad_diag(double* dst, const double* src, int N, int M, int Mp, int zero_first,
+                           int zero_last, hipStream_t st);
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
+hipError_t launch_identity(double* p, int Mp, hipStream_t st);
+hipError_t launch_negate_fill_check(int32_t* flag, int32_t v, hipStream_t st);
+
+// Solve helpers
+hipError_t launch_ftilde(double* Ft, int64_t ldft, const double* F, int64_t ldf, const double* W, int64_t ldw,
+                         const int64_t* ks, const double* adiag, const double* bdiag, int p, int M, int Mp,
+                         int K, hipStream_t st);
+hipError_t launch_residual(double* R, int64_t ldr, const double* F, int64_t ldf, const double* X,
+                           int64_t ldx, const void* A, int fmtA, const void* B, int fmtB, const void* C,
+                           int fmtC, int N, int M, int K, double* colpart, int nblk, hipStream_t st);
+hipError_t launch_colnorm_finish(double* out, const double* colpart, int nblk, int K, hipStream_t st);
+hipError_t launch_scale_cols(double* Y, int64_t ldy, const double* X, int64_t ldx, const double* s,
+                             int invert, int64_t n, int K, hipStream_t st);
+hipError_t launch_axpy_cols(double* X, int64_t ldx, const double* D, int64_t ldd, const double* s,
+                            int64_t n, int K, hipStream_t st);
+hipError_t launch_diag_grad(double* out, const double* Lam, int64_t ldl, const double* X, int64_t ldx,
+                            int64_t n, int K, hipStream_t st);
+hipError_t launch_nonfinite(int32_t* flag, const double* X, int64_t ldx, int64_t n, int K, hipStream_t st);
+
+}  // namespace td

@@ -1,0 +1,894 @@
+// Float64 HIP kernels of the block-tridiagonal solver for gfx950 (MI355X).
+//
+// Dense block products run on v_mfma_f64_4x4x4f64 (four 4x4x4 blocks per
+// instruction).  Used as one 16 x 4 output tile: the A operand supplies 16 rows
+// (lane L holds A[L%16][L/16]), the B operand is the same 4 x 4 block in all four
+// blocks (lane L holds B[L/16][L%4]), and lane L receives D[4*((L/4)%4) + L/16][L%4].
+// On gfx950 this instruction sustains the full float64 matrix rate, while the
+// 16x16x4 float64 form issues at well under half of it.
+#include "internal.h"
+
+#include <cfloat>
+#include <climits>
+
+namespace td {
+
+__device__ __forceinline__ double mfma4(double a, double b, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ int out_row(int L) { return 4 * ((L >> 2) & 3) + (L >> 4); }
+__device__ __forceinline__ int out_col(int L) { return L & 3; }
+
+// Work-groups are handed to the 8 XCDs of the chip round-robin by blockIdx.  This
+// maps blockIdx so that logical work items [x*per, (x+1)*per) run on XCD x, in
+// order: consecutive logical items (the column tiles of one block row, which read
+// the same matrix) then share that XCD's L2.  gridDim.x is a multiple of 8.
+__device__ __forceinline__ int xcd_remap(int b, int grid) {
+  const int per = grid >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+static inline int grid_pad8(int total) { return (total + 7) & ~7; }
+
+// rows per wave = 16*RT; waves per work-group = Mp / (16*RT)
+static inline int choose_rt(int Mp) {
+  if (Mp >= 256 && Mp % 64 == 0) return 4;
+  if (Mp >= 64 && Mp % 32 == 0) return 2;
+  return 1;
+}
+
+// ---------------------------------------------------------------------------
+// Block GEMM (see BArgs): one work-group = Mp rows x 4*CT columns of one problem.
+// ---------------------------------------------------------------------------
+template <int RT, int CT>
+__global__ void __launch_bounds__(512) k_bgemm(BArgs args) {
+  constexpr int KC = 16;
+  constexpr int KT = 4 * CT;
+  constexpr int SB = KT + 2;
+  constexpr int NSTG = (KC * KT + 63) / 64;
+  __shared__ double Bs[2][KC * SB];
+
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int L = tid & 63, w = tid >> 6;
+  const int lg = xcd_remap(blockIdx.x, gridDim.x);
+  if (lg >= args.total) return;
+  const int prob = lg / args.ncoltiles;
+  const int ct = lg - prob * args.ncoltiles;
+  const BDesc d = args.descs[prob];
+  const int col0 = ct * KT;
+  const int rb = w * 16 * RT;
+  const double* __restrict__ A = args.A + d.a_off;
+  const int64_t lda = args.lda;
+
+  double acc[RT][CT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int c = 0; c < CT; ++c) acc[t][c] = 0.0;
+
+  const int nch = d.kd / KC;
+  double stg[NSTG];
+  auto gload = [&](int q) {
+    const int k0 = q * KC;
+    const int seg = k0 / d.segrows;
+    const int kin = k0 - seg * d.segrows;
+    const double* Bq = args.B + d.b_off + (int64_t)seg * d.bseg + kin;
+#pragma unroll
+    for (int u = 0; u < NSTG; ++u) {
+      const int e = tid + u * nthr;
+      double v = 0.0;
+      if (e < KC * KT) {
+        const int k = e % KC, c = e / KC;
+        const int col = col0 + c;
+        if (col < args.ncols) {
+          v = Bq[k + (int64_t)col * args.ldb];
+          if (args.bscale) v *= args.bscale[d.bs_off + k0 + k];
+        }
+      }
+      stg[u] = v;
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < NSTG; ++u) {
+      const int e = tid + u * nthr;
+      if (e < KC * KT) {
+        const int k = e % KC, c = e / KC;
+        Bs[buf][k * SB + c] = stg[u];
+      }
+    }
+  };
+
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int q = 0; q < nch; ++q) {
+    const int buf = q & 1;
+    if (q + 1 < nch) gload(q + 1);
+#pragma unroll
+    for (int kk = 0; kk < KC / 4; ++kk) {
+      const int kg = q * KC + 4 * kk + (L >> 4);
+      double a[RT];
+#pragma unroll
+      for (int t = 0; t < RT; ++t) a[t] = A[(rb + 16 * t + (L & 15)) + (int64_t)kg * lda];
+      const double* bp = &Bs[buf][(4 * kk + (L >> 4)) * SB + (L & 3) * CT];
+      double b[CT];
+#pragma unroll
+      for (int c = 0; c < CT; ++c) b[c] = bp[c];
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[t][c] = mfma4(a[t], b[c], acc[t][c]);
+    }
+    if (q + 1 < nch) lstore(buf ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int t = 0; t < RT; ++t) {
+    const int row = rb + 16 * t + out_row(L);
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      const int col = col0 + out_col(L) * CT + c;
+      if (col < args.ncols) {
+        double v = args.alpha * acc[t][c];
+        if (args.Cin) v += args.Cin[d.cin_off + row + (int64_t)col * args.ldcin];
+        for (int s = 0; s < d.nsp; ++s) v += args.Sp[d.sp_off + s * args.spstride + row + (int64_t)col * args.ldsp];
+        if (args.C) args.C[d.c_off + row + (int64_t)col * args.ldc] = v;
+        if (args.X2 && row < args.x2rows) args.X2[d.x2_off + row + (int64_t)col * args.ldx2] = v;
+      }
+    }
+  }
+}
+
+int bgemm_coltile(int ncols) {
+  if (ncols <= 8) return 8;
+  if (ncols <= 16) return 16;
+  return 32;
+}
+
+template <int RT>
+static hipError_t launch_bgemm_rt(const BArgs& a0, hipStream_t st) {
+  BArgs a = a0;
+  const int nthr = a.Mp / (16 * RT) * 64;
+  const int kt = bgemm_coltile(a.ncols);
+  a.ncoltiles = (a.ncols + kt - 1) / kt;
+  a.total = a.nprob * a.ncoltiles;
+  if (a.total == 0) return hipSuccess;
+  dim3 grid(grid_pad8(a.total)), block(nthr);
+  switch (kt) {
+    case 8: hipLaunchKernelGGL((k_bgemm<RT, 2>), grid, block, 0, st, a); break;
+    case 16: hipLaunchKernelGGL((k_bgemm<RT, 4>), grid, block, 0, st, a); break;
+    default: hipLaunchKernelGGL((k_bgemm<RT, 8>), grid, block, 0, st, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_bgemm(const BArgs& a, hipStream_t st) {
+  switch (choose_rt(a.Mp)) {
+    case 4: return launch_bgemm_rt<4>(a, st);
+    case 2: return launch_bgemm_rt<2>(a, st);
+    default: return launch_bgemm_rt<1>(a, st);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Subdomain sweeps, float64.  One work-group owns (subdomain s, 4*CT columns) and
+// walks its interior rows: forward beta_i = D_i^{-1} (F_i + a_i o beta_{i-1})
+// with beta_{k_s} = 0, then backward W_i = alpha_i W_{i+1} + beta_i with
+// W_{k_{s+1}} = 0 (eq. sub3).  The operand of each step (Mp x 4*CT) stays in
+// LDS; the Mp x Mp matrix of the step streams from global memory (L2-shared by
+// the column tiles of the subdomain, which run on one XCD).
+// ---------------------------------------------------------------------------
+template <int RT, int CT>
+__global__ void __launch_bounds__(512) k_sweep_f64(SweepArgs a) {
+  constexpr int KT = 4 * CT;
+  constexpr int SB = KT + 2;
+  extern __shared__ double In[];  // [Mp][SB]
+
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int L = tid & 63, w = tid >> 6;
+  const int lg = xcd_remap(blockIdx.x, gridDim.x);
+  if (lg >= a.total) return;
+  const int s = lg / a.ncoltiles;
+  const int ct = lg - s * a.ncoltiles;
+  const int col0 = ct * KT;
+  const int64_t first = a.ks[s] + 1, last = a.ks[s + 1] - 1;
+  if (first > last) return;
+  const int Mp = a.Mp, M = a.M, K = a.K;
+  const int rb = w * 16 * RT;
+  const int64_t MM = (int64_t)Mp * Mp;
+
+  for (int e = tid; e < Mp * KT; e += nthr) {
+    const int row = e % Mp, c = e / Mp;
+    const int col = col0 + c;
+    In[row * SB + c] = (row < M && col < K) ? a.F[first * M + row + (int64_t)col * a.ldf] : 0.0;
+  }
+  __syncthreads();
+
+  double acc[RT][CT];
+  // ---- forward
+  for (int64_t i = first; i <= last; ++i) {
+    double fn[RT][CT], an[RT];
+    const bool more = i < last;
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int row = rb + 16 * t + out_row(L);
+      an[t] = more ? a.adiag[(i + 1) * Mp + row] : 0.0;
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const int col = col0 + out_col(L) * CT + c;
+        fn[t][c] = (more && row < M && col < K) ? a.F[(i + 1) * M + row + (int64_t)col * a.ldf] : 0.0;
+        acc[t][c] = 0.0;
+      }
+    }
+    const double* __restrict__ D = a.Dinv + i * MM;
+    for (int kk = 0; kk < Mp / 4; ++kk) {
+      const int k = 4 * kk + (L >> 4);
+      double av[RT];
+#pragma unroll
+      for (int t = 0; t < RT; ++t) av[t] = D[(rb + 16 * t + (L & 15)) + (int64_t)k * Mp];
+      const double* bp = &In[k * SB + (L & 3) * CT];
+      double b[CT];
+#pragma unroll
+      for (int c = 0; c < CT; ++c) b[c] = bp[c];
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[t][c] = mfma4(av[t], b[c], acc[t][c]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int row = rb + 16 * t + out_row(L);
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const int lc = out_col(L) * CT + c;
+        const int col = col0 + lc;
+        if (col < K) a.W[i * Mp + row + (int64_t)col * a.ldw] = acc[t][c];
+        In[row * SB + lc] = more ? fn[t][c] + an[t] * acc[t][c] : acc[t][c];
+      }
+    }
+    __syncthreads();
+  }
+  // ---- backward
+  for (int64_t i = last - 1; i >= first; --i) {
+    double bi[RT][CT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int row = rb + 16 * t + out_row(L);
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const int col = col0 + out_col(L) * CT + c;
+        bi[t][c] = (col < K) ? a.W[i * Mp + row + (int64_t)col * a.ldw] : 0.0;
+        acc[t][c] = 0.0;
+      }
+    }
+    const double* __restrict__ Al = a.alpha + i * MM;
+    for (int kk = 0; kk < Mp / 4; ++kk) {
+      const int k = 4 * kk + (L >> 4);
+      double av[RT];
+#pragma unroll
+      for (int t = 0; t < RT; ++t) av[t] = Al[(rb + 16 * t + (L & 15)) + (int64_t)k * Mp];
+      const double* bp = &In[k * SB + (L & 3) * CT];
+      double b[CT];
+#pragma unroll
+      for (int c = 0; c < CT; ++c) b[c] = bp[c];
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[t][c] = mfma4(av[t], b[c], acc[t][c]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int row = rb + 16 * t + out_row(L);
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const int lc = out_col(L) * CT + c;
+        const int col = col0 + lc;
+        const double v = acc[t][c] + bi[t][c];
+        if (col < K) a.W[i * Mp + row + (int64_t)col * a.ldw] = v;
+        In[row * SB + lc] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+int sweep_coltile(int Mp, int K) {
+  (void)Mp;
+  if (K <= 8) return 8;
+  if (K <= 16) return 16;
+  return 32;
+}
+
+template <int RT>
+static hipError_t launch_sweep_rt(const SweepArgs& a0, hipStream_t st) {
+  SweepArgs a = a0;
+  const int kt = sweep_coltile(a.Mp, a.K);
+  a.ncoltiles = (a.K + kt - 1) / kt;
+  a.total = a.p * a.ncoltiles;
+  if (a.total == 0) return hipSuccess;
+  const int nthr = a.Mp / (16 * RT) * 64;
+  const size_t lds = (size_t)a.Mp * (kt + 2) * sizeof(double);
+  dim3 grid(grid_pad8(a.total)), block(nthr);
+  hipError_t e = hipSuccess;
+  switch (kt) {
+    case 8:
+      e = hipFuncSetAttribute((const void*)k_sweep_f64<RT, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e == hipSuccess) hipLaunchKernelGGL((k_sweep_f64<RT, 2>), grid, block, lds, st, a);
+      break;
+    case 16:
+      e = hipFuncSetAttribute((const void*)k_sweep_f64<RT, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e == hipSuccess) hipLaunchKernelGGL((k_sweep_f64<RT, 4>), grid, block, lds, st, a);
+      break;
+    default:
+      e = hipFuncSetAttribute((const void*)k_sweep_f64<RT, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e == hipSuccess) hipLaunchKernelGGL((k_sweep_f64<RT, 8>), grid, block, lds, st, a);
+      break;
+  }
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep(const SweepArgs& a, hipStream_t st) {
+  switch (choose_rt(a.Mp)) {
+    case 4: return launch_sweep_rt<4>(a, st);
+    case 2: return launch_sweep_rt<2>(a, st);
+    default: return launch_sweep_rt<1>(a, st);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batched Gauss-Jordan inversion with partial pivoting (row interchanges chosen
+// by the largest remaining entry of each column; ties go to the lowest row).
+// One work-group per matrix.  Columns are processed in panels of NB: the panel
+// is eliminated in LDS, then its combined transform (identity except in the NB
+// pivot-row columns) updates every other column as one rank-NB product on MFMA.
+// Rows are never physically swapped; the final inverse is read out through the
+// pivot permutation.  A pivot whose magnitude is not above 1e-14 times the
+// infinity norm of the matrix (or is NaN) marks the matrix singular.
+// ---------------------------------------------------------------------------
+template <int RT>
+__global__ void __launch_bounds__(512) k_gj(GJArgs g) {
+  constexpr int NB = 16;
+  constexpr int CT = 4;           // 16 columns per update tile
+  constexpr int KT = 4 * CT;
+  constexpr int SBY = KT + 2;
+  extern __shared__ double sm[];
+  const int Mp = g.Mp;
+  double* Pn = sm;                         // [NB][Mp]
+  double* Ys = Pn + NB * Mp;               // [NB][SBY]
+  double* prow = Ys + NB * SBY;            // [NB]
+  double* redv = prow + NB;                // [32]: per-wave reduction values, [16] = singular flag
+  int* pivrow = (int*)(redv + 32);         // [Mp]
+  int* used = pivrow + Mp;                 // [Mp]
+  int* redi = used + Mp;                   // [16]
+
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int L = tid & 63, w = tid >> 6, nw = nthr >> 6;
+  const int q = blockIdx.x;
+  if (q >= g.nmat) return;
+  double* W = g.work + (g.work_off ? g.work_off[q] : q * g.wstride);
+  const int rb = w * 16 * RT;
+
+  // infinity norm (row sums), one row per thread (nthr >= Mp)
+  double rs = 0.0;
+  if (tid < Mp) {
+    for (int c = 0; c < Mp; ++c) rs += fabs(W[tid + (int64_t)c * Mp]);
+    used[tid] = 0;
+  }
+  for (int off = 32; off > 0; off >>= 1) rs = fmax(rs, __shfl_xor(rs, off));
+  if (L == 0) redv[w] = rs;
+  __syncthreads();
+  double norm = 0.0;
+  for (int v = 0; v < nw; ++v) norm = fmax(norm, redv[v]);
+  const double tol = 1e-14 * norm;
+  __syncthreads();
+  bool singular = false;
+
+  for (int p0 = 0; p0 < Mp; p0 += NB) {
+    for (int e = tid; e < NB * Mp; e += nthr) {
+      const int i = e % Mp, jj = e / Mp;
+      Pn[jj * Mp + i] = W[i + (int64_t)(p0 + jj) * Mp];
+    }
+    __syncthreads();
+    for (int j = 0; j < NB; ++j) {
+      // pivot search over unused rows
+      double bv = -1.0;
+      int bi = INT_MAX;
+      for (int i = tid; i < Mp; i += nthr) {
+        if (!used[i]) {
+          const double v = fabs(Pn[j * Mp + i]);
+          const double vv = (v == v) ? v : DBL_MAX;  // NaN ranks first so that it is reported
+          if (vv > bv || (vv == bv && i < bi)) { bv = vv; bi = i; }
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(bv, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+      }
+      if (L == 0) { redv[w] = bv; redi[w] = bi; }
+      __syncthreads();
+      if (tid == 0) {
+        double b2 = redv[0];
+        int i2 = redi[0];
+        for (int v = 1; v < nw; ++v)
+          if (redv[v] > b2 || (redv[v] == b2 && redi[v] < i2)) { b2 = redv[v]; i2 = redi[v]; }
+        pivrow[p0 + j] = i2;
+        used[i2] = 1;
+        const double pv = Pn[j * Mp + i2];
+        redv[16] = (fabs(pv) > tol) ? 0.0 : 1.0;
+        for (int jj = 0; jj < NB; ++jj) prow[jj] = (jj == j) ? 1.0 / pv : Pn[jj * Mp + i2] / pv;
+      }
+      __syncthreads();
+      if (redv[16] != 0.0) singular = true;
+      const int r = pivrow[p0 + j];
+      if (tid < Mp) {
+        const int i = tid;
+        if (i == r) {
+#pragma unroll
+          for (int jj = 0; jj < NB; ++jj) Pn[jj * Mp + i] = prow[jj];
+        } else {
+          const double f = Pn[j * Mp + i];
+#pragma unroll
+          for (int jj = 0; jj < NB; ++jj) Pn[jj * Mp + i] = (jj == j ? 0.0 : Pn[jj * Mp + i]) - f * prow[jj];
+        }
+      }
+      __syncthreads();
+    }
+    // rank-NB update of all other columns: W[:, c] += (Pn - E_R) * W[R, c]
+    for (int c0 = 0; c0 < Mp; c0 += KT) {
+      if (c0 + KT > p0 && c0 < p0 + NB) continue;  // tile lies inside the panel (NB == KT)
+      for (int e = tid; e < NB * KT; e += nthr) {
+        const int jj = e / KT, c = e % KT;
+        Ys[jj * SBY + c] = W[pivrow[p0 + jj] + (int64_t)(c0 + c) * Mp];
+      }
+      __syncthreads();
+      double acc[RT][CT];
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int row = rb + 16 * t + out_row(L);
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[t][c] = W[row + (int64_t)(c0 + out_col(L) * CT + c) * Mp];
+      }
+#pragma unroll
+      for (int kk = 0; kk < NB / 4; ++kk) {
+        const int k = 4 * kk + (L >> 4);
+        const int pr = pivrow[p0 + k];
+        double av[RT];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          const int row = rb + 16 * t + (L & 15);
+          av[t] = Pn[k * Mp + row] - (row == pr ? 1.0 : 0.0);
+        }
+        const double* bp = &Ys[k * SBY + (L & 3) * CT];
+        double b[CT];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) b[c] = bp[c];
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+          for (int c = 0; c < CT; ++c) acc[t][c] = mfma4(av[t], b[c], acc[t][c]);
+      }
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int row = rb + 16 * t + out_row(L);
+#pragma unroll
+        for (int c = 0; c < CT; ++c) W[row + (int64_t)(c0 + out_col(L) * CT + c) * Mp] = acc[t][c];
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < NB * Mp; e += nthr) {
+      const int i = e % Mp, jj = e / Mp;
+      W[i + (int64_t)(p0 + jj) * Mp] = Pn[jj * Mp + i];
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && singular) atomicMin(g.bad, g.tag[q]);
+  // inverse: Dinv[c][pivrow[c']] = S[pivrow[c]][c']
+  int* invpiv = used;  // reuse
+  for (int c = tid; c < Mp; c += nthr) invpiv[pivrow[c]] = c;
+  __syncthreads();
+  double* out = g.out + g.out_off[q];
+  double* al = g.alpha ? g.alpha + g.out_off[q] : nullptr;
+  const double* bd = g.alpha ? g.bdiag + g.bd_off[q] : nullptr;
+  for (int e = tid; e < Mp * Mp; e += nthr) {
+    const int row = e % Mp, oc = e / Mp;
+    const double v = W[pivrow[row] + (int64_t)invpiv[oc] * Mp];
+    out[row + (int64_t)oc * Mp] = v;
+    if (al) al[row + (int64_t)oc * Mp] = v * bd[oc];
+  }
+}
+
+template <int RT>
+static hipError_t launch_gj_rt(const GJArgs& g, hipStream_t st) {
+  const int nthr = g.Mp / (16 * RT) * 64;
+  const size_t lds = (size_t)(16 * g.Mp + 16 * 18 + 16 + 32) * sizeof(double) + (size_t)(2 * g.Mp + 16) * sizeof(int);
+  hipError_t e = hipFuncSetAttribute((const void*)k_gj<RT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_gj<RT>), dim3(g.nmat), dim3(nthr), lds, st, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_gj(const GJArgs& g, hipStream_t st) {
+  if (g.nmat == 0) return hipSuccess;
+  switch (choose_rt(g.Mp)) {
+    case 4: return launch_gj_rt<4>(g, st);
+    case 2: return launch_gj_rt<2>(g, st);
+    default: return launch_gj_rt<1>(g, st);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Element-wise helpers of the factor
+// ---------------------------------------------------------------------------
+
+// entry (r, c) of block `row` of C in its storage format, padded to Mp with the identity
+__device__ __forceinline__ double c_entry(const void* C, int fmt, int64_t row, int r, int c, int M) {
+  if (r >= M || c >= M) return (r == c) ? 1.0 : 0.0;
+  if (fmt == 2) {  // TRIDIAG [N][3][M]
+    const double* t = (const double*)C + row * 3 * M;
+    if (c == r) return t[M + r];
+    if (c == r - 1) return t[r];
+    if (c == r + 1) return t[2 * M + r];
+    return 0.0;
+  }
+  return ((const double*)C)[row * (int64_t)M * M + r + (int64_t)c * M];  // DENSE
+}
+
+// D_q = C_row - a_row o alpha_{row-1} (the second term only where first[q] == 0)
+__global__ void k_build_D(double* Dwork, int64_t wstride, int nmat, const int64_t* rows, const int32_t* first,
+                          const void* C, int fmtC, const double* adiag, const double* alpha, int M, int Mp) {
+  const int q = blockIdx.y;
+  if (q >= nmat) return;
+  const int64_t MM = (int64_t)Mp * Mp;
+  const int64_t row = rows[q];
+  const bool f = first[q] != 0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < MM; e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e % Mp), c = (int)(e / Mp);
+    double v = c_entry(C, fmtC, row, r, c, M);
+    if (!f) v -= adiag[row * Mp + r] * alpha[(row - 1) * MM + e];
+    Dwork[q * wstride + e] = v;
+  }
+}
+
+hipError_t launch_build_D(double* Dwork, int64_t wstride, int nmat, const int64_t* rows, const int32_t* first,
+                          const void* C, int fmtC, const double* adiag, const double* alpha, int M, int Mp,
+                          hipStream_t st) {
+  if (nmat == 0) return hipSuccess;
+  const int64_t MM = (int64_t)Mp * Mp;
+  int bx = (int)((MM + 255) / 256);
+  if (bx > 1024) bx = 1024;
+  hipLaunchKernelGGL(k_build_D, dim3(bx, nmat), dim3(256), 0, st, Dwork, wstride, nmat, rows, first, C, fmtC, adiag,
+                     alpha, M, Mp);
+  return hipGetLastError();
+}
+
+__global__ void k_expand_C(double* out, const void* C, int fmt, int64_t row, int M, int Mp) {
+  const int64_t MM = (int64_t)Mp * Mp;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < MM; e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = c_entry(C, fmt, row, (int)(e % Mp), (int)(e / Mp), M);
+}
+
+hipError_t launch_expand_C(double* out, const void* C, int fmtC, int64_t row, int M, int Mp, hipStream_t st) {
+  const int64_t MM = (int64_t)Mp * Mp;
+  int bx = (int)((MM + 255) / 256);
+  if (bx > 1024) bx = 1024;
+  hipLaunchKernelGGL(k_expand_C, dim3(bx), dim3(256), 0, st, out, C, fmtC, row, M, Mp);
+  return hipGetLastError();
+}
+
+// Blocks of the reduced system, eq. (red1), for diagonal A and B:
+//   At_s = diag(a_k) U_{k-1},  Ct_s = C_k - diag(a_k) V_{k-1} - diag(b_k) U_{k+1},  Bt_s = diag(b_k) V_{k+1}
+// with k = k_s.  U_{k-1}, V_{k-1} are the coefficients of X_{k_{s-1}}, X_{k_s} in row k-1 (the last
+// interior row of subdomain s-1); if that subdomain has no interior row, row k-1 is itself the
+// interface row k_{s-1} (U = I, V = 0).  Likewise U_{k+1}, V_{k+1} come from the first interior row of
+// subdomain s, or are (U = 0, V = I) when row k+1 is the next interface row.
+// UV points at U_0: U_i = UV + 2*i*Mp*Mp, V_i = U_i + Mp*Mp.
+__global__ void k_reduced(double* At, double* Ct, double* Bt, const int64_t* ks, const double* UV, const void* C,
+                          int fmtC, const double* adiag, const double* bdiag, int p, int N, int M, int Mp) {
+  const int s = blockIdx.y;
+  const int64_t MM = (int64_t)Mp * Mp;
+  const int64_t k = ks[s];
+  const bool left_int = (s > 0) && (k - 1 > ks[s - 1]);       // row k-1 is an interior row of s-1
+  const bool right_int = (k + 1 < ks[s + 1]);                 // row k+1 is an interior row of s
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < MM; e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e % Mp), c = (int)(e / Mp);
+    const double ak = adiag[k * Mp + r], bk = bdiag[k * Mp + r];
+    double at = 0.0, ct = c_entry(C, fmtC, k, r, c, M), bt = 0.0;
+    if (s > 0) {
+      if (left_int) {
+        const double* U = UV + (k - 1) * 2 * MM;
+        at = ak * U[e];
+        ct -= ak * U[MM + e];
+      } else {
+        at = (r == c) ? ak : 0.0;
+      }
+    }
+    if (k + 1 < N) {
+      if (right_int) {
+        const double* U = UV + (k + 1) * 2 * MM;
+        ct -= bk * U[e];
+        bt = bk * U[MM + e];
+      } else {
+        bt = (r == c) ? bk : 0.0;
+      }
+    }
+    At[s * MM + e] = at;
+    Ct[s * MM + e] = ct;
+    Bt[s * MM + e] = bt;
+  }
+}
+
+hipError_t launch_reduced(double* At, double* Ct, double* Bt, const int64_t* ks, const double* UV, const void* C,
+                          int fmtC, const double* adiag, const double* bdiag, int p, int N, int M, int Mp,
+                          hipStream_t st) {
+  const int64_t MM = (int64_t)Mp * Mp;
+  int bx = (int)((MM + 255) / 256);
+  if (bx > 256) bx = 256;
+  hipLaunchKernelGGL(k_reduced, dim3(bx, p), dim3(256), 0, st, At, Ct, Bt, ks, UV, C, fmtC, adiag, bdiag, p, N, M, Mp);
+  return hipGetLastError();
+}
+
+// dst[N][Mp] = src[N][M] zero padded; optionally zero the first / last block row
+__global__ void k_pad_diag(double* dst, const double* src, int N, int M, int Mp, int zero_first, int zero_last) {
+  const int64_t n = (int64_t)N * Mp;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = e / Mp;
+    const int r = (int)(e % Mp);
+    double v = (r < M) ? src[j * M + r] : 0.0;
+    if ((zero_first && j == 0) || (zero_last && j == N - 1)) v = 0.0;
+    dst[e] = v;
+  }
+}
+
+hipError_t launch_pad_diag(double* dst, const double* src, int N, int M, int Mp, int zero_first, int zero_last,
+                           hipStream_t st) {
+  const int64_t n = (int64_t)N * Mp;
+  int bx = (int)((n + 255) / 256);
+  if (bx > 4096) bx = 4096;
+  hipLaunchKernelGGL(k_pad_diag, dim3(bx), dim3(256), 0, st, dst, src, N, M, Mp, zero_first, zero_last);
+  return hipGetLastError();
+}
+
+__global__ void k_fill(double* p, int64_t n, double v) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) p[e] = v;
+}
+
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int bx = (int)((n + 255) / 256);
+  if (bx > 8192) bx = 8192;
+  hipLaunchKernelGGL(k_fill, dim3(bx), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+__global__ void k_identity(double* p, int Mp) {
+  const int64_t MM = (int64_t)Mp * Mp;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < MM; e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = ((e % Mp) == (e / Mp)) ? 1.0 : 0.0;
+}
+
+hipError_t launch_identity(double* p, int Mp, hipStream_t st) {
+  const int64_t MM = (int64_t)Mp * Mp;
+  int bx = (int)((MM + 255) / 256);
+  if (bx > 1024) bx = 1024;
+  hipLaunchKernelGGL(k_identity, dim3(bx), dim3(256), 0, st, p, Mp);
+  return hipGetLastError();
+}
+
+__global__ void k_set_flag(int32_t* flag, int32_t v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) flag[0] = v;
+}
+
+hipError_t launch_negate_fill_check(int32_t* flag, int32_t v, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(64), 0, st, flag, v);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Solve helpers
+// ---------------------------------------------------------------------------
+
+// Right-hand side of the reduced system, eq. (red1), diagonal A and B:
+//   Ft_s = F_k + diag(a_k) W_{k-1} + diag(b_k) W_{k+1},  k = k_s,
+// where W of a row that is itself an interface row is zero.
+__global__ void k_ftilde(double* Ft, int64_t ldft, const double* F, int64_t ldf, const double* W, int64_t ldw,
+                         const int64_t* ks, const double* adiag, const double* bdiag, int p, int M, int Mp, int K) {
+  const int64_t n = (int64_t)p * Mp * K;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e % Mp);
+    const int64_t sc = e / Mp;
+    const int s = (int)(sc % p);
+    const int64_t col = sc / p;
+    const int64_t k = ks[s];
+    double v = (r < M) ? F[k * M + r + col * ldf] : 0.0;
+    if (s > 0 && k - 1 > ks[s - 1]) v += adiag[k * Mp + r] * W[(k - 1) * Mp + r + col * ldw];
+    if (k + 1 < ks[s + 1]) v += bdiag[k * Mp + r] * W[(k + 1) * Mp + r + col * ldw];
+    Ft[(int64_t)s * Mp + r + col * ldft] = v;
+  }
+}
+
+hipError_t launch_ftilde(double* Ft, int64_t ldft, const double* F, int64_t ldf, const double* W, int64_t ldw,
+                         const int64_t* ks, const double* adiag, const double* bdiag, int p, int M, int Mp, int K,
+                         hipStream_t st) {
+  const int64_t n = (int64_t)p * Mp * K;
+  if (n == 0) return hipSuccess;
+  int bx = (int)((n + 255) / 256);
+  if (bx > 8192) bx = 8192;
+  hipLaunchKernelGGL(k_ftilde, dim3(bx), dim3(256), 0, st, Ft, ldft, F, ldf, W, ldw, ks, adiag, bdiag, p, M, Mp, K);
+  return hipGetLastError();
+}
+
+// R = F - P X for compact formats (A, B diagonal or dense; C tridiagonal or dense), plus per-block
+// partial sums of squares of R and of F per column: colpart[(col * nblk + blk) * 2 + {0,1}].
+// One work-group per (block row j, column); entries r < M.
+__global__ void k_residual(double* R, int64_t ldr, const double* F, int64_t ldf, const double* X, int64_t ldx,
+                           const double* A, int fmtA, const double* B, int fmtB, const double* C, int fmtC, int N,
+                           int M, int K, double* colpart, int nblk) {
+  __shared__ double red[2][16];
+  const int j = blockIdx.x;
+  const int col = blockIdx.y;
+  const int tid = threadIdx.x;
+  const double* x = X + (int64_t)col * ldx;
+  const double* f = F + (int64_t)col * ldf;
+  const int64_t MM = (int64_t)M * M;
+  double sr = 0.0, sf = 0.0;
+  for (int r = tid; r < M; r += blockDim.x) {
+    const int64_t g = (int64_t)j * M + r;
+    double y;
+    if (fmtC == 2) {
+      const double* t = C + (int64_t)j * 3 * M;
+      y = t[M + r] * x[g];
+      if (r > 0) y += t[r] * x[g - 1];
+      if (r < M - 1) y += t[2 * M + r] * x[g + 1];
+    } else {
+      const double* Cj = C + j * MM;
+      y = 0.0;
+      for (int c = 0; c < M; ++c) y += Cj[r + (int64_t)c * M] * x[(int64_t)j * M + c];
+    }
+    if (j > 0) {
+      if (fmtA == 1) y -= A[(int64_t)j * M + r] * x[g - M];
+      else {
+        const double* Aj = A + j * MM;
+        for (int c = 0; c < M; ++c) y -= Aj[r + (int64_t)c * M] * x[(int64_t)(j - 1) * M + c];
+      }
+    }
+    if (j < N - 1) {
+      if (fmtB == 1) y -= B[(int64_t)j * M + r] * x[g + M];
+      else {
+        const double* Bj = B + j * MM;
+        for (int c = 0; c < M; ++c) y -= Bj[r + (int64_t)c * M] * x[(int64_t)(j + 1) * M + c];
+      }
+    }
+    const double rv = f[g] - y;
+    if (R) R[g + (int64_t)col * ldr] = rv;
+    sr += rv * rv;
+    sf += f[g] * f[g];
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    sr += __shfl_xor(sr, off);
+    sf += __shfl_xor(sf, off);
+  }
+  if ((tid & 63) == 0) { red[0][tid >> 6] = sr; red[1][tid >> 6] = sf; }
+  __syncthreads();
+  if (tid == 0) {
+    double a = 0.0, b = 0.0;
+    for (int v = 0; v < (int)(blockDim.x >> 6); ++v) { a += red[0][v]; b += red[1][v]; }
+    colpart[((int64_t)col * nblk + j) * 2 + 0] = a;
+    colpart[((int64_t)col * nblk + j) * 2 + 1] = b;
+  }
+}
+
+hipError_t launch_residual(double* R, int64_t ldr, const double* F, int64_t ldf, const double* X, int64_t ldx,
+                           const void* A, int fmtA, const void* B, int fmtB, const void* C, int fmtC, int N, int M,
+                           int K, double* colpart, int nblk, hipStream_t st) {
+  if (K == 0) return hipSuccess;
+  int nthr = M >= 256 ? 256 : ((M + 63) / 64) * 64;
+  hipLaunchKernelGGL(k_residual, dim3(N, K), dim3(nthr), 0, st, R, ldr, F, ldf, X, ldx, (const double*)A, fmtA,
+                     (const double*)B, fmtB, (const double*)C, fmtC, N, M, K, colpart, nblk);
+  return hipGetLastError();
+}
+
+// out[col] = sqrt(sum_blk colpart[..][0]) / sqrt(sum_blk colpart[..][1]) as (rnorm, fnorm) pairs:
+// out[2*col] = ||R_col||, out[2*col+1] = ||F_col||  (fixed summation order)
+__global__ void k_colnorm_finish(double* out, const double* colpart, int nblk, int K) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= K) return;
+  double a = 0.0, b = 0.0;
+  for (int j = 0; j < nblk; ++j) {
+    a += colpart[((int64_t)col * nblk + j) * 2 + 0];
+    b += colpart[((int64_t)col * nblk + j) * 2 + 1];
+  }
+  out[2 * col] = sqrt(a);
+  out[2 * col + 1] = sqrt(b);
+}
+
+hipError_t launch_colnorm_finish(double* out, const double* colpart, int nblk, int K, hipStream_t st) {
+  if (K == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_colnorm_finish, dim3((K + 127) / 128), dim3(128), 0, st, out, colpart, nblk, K);
+  return hipGetLastError();
+}
+
+// Y[:, col] = X[:, col] * (invert ? 1/s[2col] : s[2col])   (s holds (norm, other) pairs; norm 0 -> 0)
+__global__ void k_scale_cols(double* Y, int64_t ldy, const double* X, int64_t ldx, const double* s, int invert,
+                             int64_t n, int K) {
+  const int64_t tot = n * K;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t col = e / n, r = e % n;
+    const double nv = s[2 * col];
+    const double f = invert ? (nv > 0.0 ? 1.0 / nv : 0.0) : nv;
+    Y[r + col * ldy] = X[r + col * ldx] * f;
+  }
+}
+
+hipError_t launch_scale_cols(double* Y, int64_t ldy, const double* X, int64_t ldx, const double* s, int invert,
+                             int64_t n, int K, hipStream_t st) {
+  const int64_t tot = n * K;
+  if (tot == 0) return hipSuccess;
+  int bx = (int)((tot + 255) / 256);
+  if (bx > 16384) bx = 16384;
+  hipLaunchKernelGGL(k_scale_cols, dim3(bx), dim3(256), 0, st, Y, ldy, X, ldx, s, invert, n, K);
+  return hipGetLastError();
+}
+
+// X[:, col] += s[2col] * D[:, col]
+__global__ void k_axpy_cols(double* X, int64_t ldx, const double* D, int64_t ldd, const double* s, int64_t n, int K) {
+  const int64_t tot = n * K;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t col = e / n, r = e % n;
+    X[r + col * ldx] += s[2 * col] * D[r + col * ldd];
+  }
+}
+
+hipError_t launch_axpy_cols(double* X, int64_t ldx, const double* D, int64_t ldd, const double* s, int64_t n, int K,
+                            hipStream_t st) {
+  const int64_t tot = n * K;
+  if (tot == 0) return hipSuccess;
+  int bx = (int)((tot + 255) / 256);
+  if (bx > 16384) bx = 16384;
+  hipLaunchKernelGGL(k_axpy_cols, dim3(bx), dim3(256), 0, st, X, ldx, D, ldd, s, n, K);
+  return hipGetLastError();
+}
+
+// out[r] = -sum_k Lam[r,k] X[r,k], summed in column order
+__global__ void k_diag_grad(double* out, const double* Lam, int64_t ldl, const double* X, int64_t ldx, int64_t n,
+                            int K) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int k = 0; k < K; ++k) s += Lam[r + (int64_t)k * ldl] * X[r + (int64_t)k * ldx];
+    out[r] = -s;
+  }
+}
+
+hipError_t launch_diag_grad(double* out, const double* Lam, int64_t ldl, const double* X, int64_t ldx, int64_t n,
+                            int K, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  int bx = (int)((n + 255) / 256);
+  if (bx > 8192) bx = 8192;
+  hipLaunchKernelGGL(k_diag_grad, dim3(bx), dim3(256), 0, st, out, Lam, ldl, X, ldx, n, K);
+  return hipGetLastError();
+}
+
+__global__ void k_nonfinite(int32_t* flag, const double* X, int64_t ldx, int64_t n, int K) {
+  const int64_t tot = n * K;
+  int bad = 0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    const double v = X[(e % n) + (e / n) * ldx];
+    if (!(v - v == 0.0)) bad = 1;
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+hipError_t launch_nonfinite(int32_t* flag, const double* X, int64_t ldx, int64_t n, int K, hipStream_t st) {
+  const int64_t tot = n * K;
+  if (tot == 0) return hipSuccess;
+  int bx = (int)((tot + 255) / 256);
+  if (bx > 4096) bx = 4096;
+  hipLaunchKernelGGL(k_nonfinite, dim3(bx), dim3(256), 0, st, flag, X, ldx, n, K);
+  return hipGetLastError();
+}
+
+}  // namespace td

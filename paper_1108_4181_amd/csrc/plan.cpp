@@ -1,0 +1,1019 @@
+// Host side of the block-tridiagonal solver: argument checks, the subdomain
+// partition, the dichotomy tree, device memory, and the order of the kernel
+// launches of the factor (Algorithm 2, step 1, Sec. 2.2) and of the solve
+// (Algorithm 2, step 2).  Implements the C ABI of include/tridiag.h.
+#include "internal.h"
+#include "tridiag.h"
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace td;
+
+namespace {
+
+thread_local std::string g_err;
+
+td_status fail(td_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+struct HipFail {
+  hipError_t e;
+  std::string where;
+};
+
+#define HIPCHK(x)                                                            \
+  do {                                                                       \
+    hipError_t e_ = (x);                                                     \
+    if (e_ != hipSuccess) throw HipFail{e_, std::string(#x) + " @" + std::to_string(__LINE__)}; \
+  } while (0)
+
+struct Node {
+  int l, r, m, level;
+  int64_t g_off;        // offset of G (Mp x len*Mp) in the G buffer
+  int chunk0, nchunk;   // partial-sum chunks of this node
+};
+
+struct StageEvents {
+  hipEvent_t ev[8] = {};
+  bool made = false;
+};
+
+}  // namespace
+
+struct td_plan_s {
+  int64_t N = 0, M = 0, Mp = 0, p = 0;
+  int fmtA = 1, fmtB = 1, fmtC = 2, prec = 0, adjoint = 0;
+  std::vector<int64_t> ks;  // p + 1
+  int64_t* d_ks = nullptr;
+  // compact float64 copies of the input (user layout) for residuals
+  double* cA = nullptr; double* cB = nullptr; double* cC = nullptr;
+  double* adiag = nullptr; double* bdiag = nullptr;  // [N][Mp], a_0 = 0, b_{N-1} = 0
+  // factor
+  double* Dinv = nullptr;     // [N][Mp][Mp]
+  double* alpha = nullptr;    // [N][Mp][Mp]
+  double* UVa = nullptr;      // [Ident | Zero | (U_i, V_i) for i < N]
+  double* red = nullptr;      // [At | Ct | Bt], each [p][Mp][Mp]
+  double* G = nullptr;        // dichotomy rows of the inverse
+  double* H = nullptr;        // [nodes][H^L | H^R]
+  std::vector<Node> nodes;
+  int depth = 0;
+  int nchunks = 0;
+  // solve descriptors (device)
+  BDesc* d_sup = nullptr; int n_sup = 0;
+  BDesc* d_part = nullptr; int n_part = 0;
+  BDesc* d_corr = nullptr; std::vector<int> corr_begin, corr_count;
+  // workspace
+  int64_t kcap = 0;
+  double* Wbuf = nullptr; double* Ft = nullptr; double* Xi = nullptr; double* Sp = nullptr;
+  int64_t rcap = 0;
+  double* Rbuf = nullptr; double* Dbuf = nullptr; double* colpart = nullptr; double* norms = nullptr;
+  int32_t* d_flag = nullptr;
+  td_plan_s* adj = nullptr;
+  bool prof = false;
+  StageEvents se;
+  double stage_ms[7] = {0};
+  bool stage_valid = false;
+  double factor_ms = 0.0;
+  int64_t bytes = 0;
+  std::vector<void*> allocs;
+  hipStream_t last_stream = nullptr;
+
+  double* alloc(int64_t n_doubles) {
+    void* p = nullptr;
+    if (n_doubles <= 0) n_doubles = 1;
+    HIPCHK(hipMalloc(&p, (size_t)n_doubles * sizeof(double)));
+    allocs.push_back(p);
+    bytes += n_doubles * (int64_t)sizeof(double);
+    return (double*)p;
+  }
+  template <class T>
+  T* upload(const std::vector<T>& v) {
+    void* p = nullptr;
+    size_t nb = std::max<size_t>(1, v.size()) * sizeof(T);
+    HIPCHK(hipMalloc(&p, nb));
+    allocs.push_back(p);
+    bytes += (int64_t)nb;
+    if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return (T*)p;
+  }
+  void release(void* p) {
+    if (!p) return;
+    auto it = std::find(allocs.begin(), allocs.end(), p);
+    if (it != allocs.end()) allocs.erase(it);
+    (void)hipFree(p);
+  }
+  ~td_plan_s() {
+    for (void* p : allocs) (void)hipFree(p);
+    if (se.made)
+      for (auto& e : se.ev) (void)hipEventDestroy(e);
+    delete adj;
+  }
+};
+
+namespace {
+
+// Block size padded for the kernels' wave tiling: at most 8 waves of 16, 32 or 64 rows each.
+int64_t pad_block(int64_t m) {
+  if (m <= 128) return (m + 15) / 16 * 16;
+  if (m <= 256) return (m + 31) / 32 * 32;
+  return (m + 63) / 64 * 64;
+}
+
+std::vector<int64_t> partition(int64_t N, int64_t p) {
+  // interface rows: the first N mod p subdomains get ceil(N/p) rows
+  std::vector<int64_t> ks(p + 1);
+  const int64_t base = N / p, extra = N % p;
+  int64_t k = 0;
+  for (int64_t s = 0; s < p; ++s) {
+    ks[s] = k;
+    k += base + (s < extra ? 1 : 0);
+  }
+  ks[p] = N;
+  return ks;
+}
+
+// dichotomy tree over rows [l, r] of the reduced system: split row m = floor((l+r)/2)
+void build_tree(std::vector<Node>& nodes, int l, int r, int level, int& depth) {
+  const int m = (l + r) / 2;
+  nodes.push_back(Node{l, r, m, level, 0, 0, 0});
+  depth = std::max(depth, level + 1);
+  if (m > l) build_tree(nodes, l, m - 1, level + 1, depth);
+  if (m < r) build_tree(nodes, m + 1, r, level + 1, depth);
+}
+
+BArgs bargs_base(int Mp) {
+  BArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.Mp = Mp;
+  a.alpha = 1.0;
+  return a;
+}
+
+BDesc desc0() {
+  BDesc d;
+  std::memset(&d, 0, sizeof(d));
+  return d;
+}
+
+// Uploads a batch of descriptors, launches, and frees the upload after the stream is done with it.
+struct DescPool {
+  std::vector<void*> bufs;
+  BDesc* put(const std::vector<BDesc>& v) {
+    void* p = nullptr;
+    HIPCHK(hipMalloc(&p, std::max<size_t>(1, v.size()) * sizeof(BDesc)));
+    bufs.push_back(p);
+    if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(BDesc), hipMemcpyHostToDevice));
+    return (BDesc*)p;
+  }
+  template <class T>
+  T* put_vec(const std::vector<T>& v) {
+    void* p = nullptr;
+    HIPCHK(hipMalloc(&p, std::max<size_t>(1, v.size()) * sizeof(T)));
+    bufs.push_back(p);
+    if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return (T*)p;
+  }
+  ~DescPool() {
+    for (void* p : bufs) (void)hipFree(p);
+  }
+};
+
+void run_bgemm(BArgs a, const std::vector<BDesc>& d, DescPool& pool, hipStream_t st) {
+  if (d.empty()) return;
+  a.descs = pool.put(d);
+  a.nprob = (int32_t)d.size();
+  HIPCHK(launch_bgemm(a, st));
+}
+
+int64_t choose_p(int64_t N) {
+  int64_t p = N / 32;
+  return std::max<int64_t>(1, std::min<int64_t>(p, N));
+}
+
+// ------------------------------------------------------------------------------------------
+// Factor: Algorithm 2, step 1 (sub-problems (sub1), (sub2); reduced matrix (red1); rows of the
+// inverse of the reduced matrix for Algorithm 1).
+// ------------------------------------------------------------------------------------------
+void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C, hipStream_t st) {
+  const int64_t N = P->N, M = P->M, Mp = P->Mp, p = P->p;
+  const int64_t MM = Mp * Mp;
+  const auto& ks = P->ks;
+  DescPool pool;
+
+  // compact copies of the input
+  const int64_t nA = (P->fmtA == TD_FMT_DIAG) ? N * M : N * M * M;
+  const int64_t nB = (P->fmtB == TD_FMT_DIAG) ? N * M : N * M * M;
+  const int64_t nC = (P->fmtC == TD_FMT_TRIDIAG) ? N * 3 * M : N * M * M;
+  P->cA = P->alloc(nA);
+  P->cB = P->alloc(nB);
+  P->cC = P->alloc(nC);
+  HIPCHK(hipMemcpyAsync(P->cA, A, nA * 8, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(P->cB, B, nB * 8, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(P->cC, C, nC * 8, hipMemcpyDeviceToDevice, st));
+  P->adiag = P->alloc(N * Mp);
+  P->bdiag = P->alloc(N * Mp);
+  HIPCHK(launch_pad_diag(P->adiag, P->cA, (int)N, (int)M, (int)Mp, 1, 0, st));
+  HIPCHK(launch_pad_diag(P->bdiag, P->cB, (int)N, (int)M, (int)Mp, 0, 1, st));
+  P->d_ks = P->upload(ks);
+  P->d_flag = (int32_t*)P->alloc(2);
+
+  P->Dinv = P->alloc(N * MM);
+  P->alpha = P->alloc(N * MM);
+  P->UVa = P->alloc((2 + 2 * N) * MM);
+  double* Ident = P->UVa;
+  HIPCHK(launch_identity(Ident, (int)Mp, st));
+  HIPCHK(launch_fill(P->UVa + MM, MM, 0.0, st));
+  // Gamma arena: [Ident | Gamma_i for i < N]
+  double* Ga = P->alloc((1 + N) * MM);
+  HIPCHK(launch_identity(Ga, (int)Mp, st));
+  double* Dwork = P->alloc(p * MM);
+
+  int32_t* bad = P->d_flag;
+  HIPCHK(launch_negate_fill_check(bad, INT_MAX, st));
+
+  std::vector<int64_t> nint(p);
+  int64_t maxn = 0;
+  for (int64_t s = 0; s < p; ++s) {
+    nint[s] = ks[s + 1] - ks[s] - 1;
+    maxn = std::max(maxn, nint[s]);
+  }
+
+  // ---- forward elimination inside every subdomain: D_i, D_i^{-1}, alpha_i, Gamma_i
+  for (int64_t t = 0; t < maxn; ++t) {
+    std::vector<int64_t> rows, outoff, bdoff;
+    std::vector<int32_t> first, tag;
+    std::vector<BDesc> gam;
+    for (int64_t s = 0; s < p; ++s) {
+      if (nint[s] <= t) continue;
+      const int64_t i = ks[s] + 1 + t;
+      rows.push_back(i);
+      first.push_back(t == 0 ? 1 : 0);
+      outoff.push_back(i * MM);
+      bdoff.push_back(i * Mp);
+      tag.push_back((int32_t)i);
+      BDesc d = desc0();
+      d.a_off = i * MM;                              // D_i^{-1}
+      d.b_off = (t == 0) ? 0 : (1 + (i - 1)) * MM;   // Gamma_{i-1} (identity at the interface)
+      d.bs_off = i * Mp;                             // rows scaled by a_i
+      d.c_off = (1 + i) * MM;                        // Gamma_i
+      d.kd = (int32_t)Mp;
+      d.segrows = (int32_t)Mp;
+      gam.push_back(d);
+    }
+    const int nm = (int)rows.size();
+    int64_t* d_rows = pool.put_vec(rows);
+    int32_t* d_first = pool.put_vec(first);
+    HIPCHK(launch_build_D(Dwork, MM, nm, d_rows, d_first, P->cC, P->fmtC, P->adiag, P->alpha, (int)M, (int)Mp, st));
+    GJArgs g;
+    g.work = Dwork; g.work_off = nullptr; g.wstride = MM;
+    g.out = P->Dinv; g.out_off = pool.put_vec(outoff);
+    g.alpha = P->alpha; g.bdiag = P->bdiag; g.bd_off = pool.put_vec(bdoff);
+    g.tag = pool.put_vec(tag); g.bad = bad;
+    g.nmat = nm; g.Mp = (int32_t)Mp;
+    HIPCHK(launch_gj(g, st));
+    BArgs a = bargs_base((int)Mp);
+    a.A = P->Dinv; a.lda = Mp;
+    a.B = Ga; a.ldb = Mp;
+    a.bscale = P->adiag;
+    a.C = Ga; a.ldc = Mp;
+    a.ncols = (int32_t)Mp;
+    run_bgemm(a, gam, pool, st);
+  }
+
+  // ---- backward: U_i = alpha_i U_{i+1} + Gamma_i, V_i = alpha_i V_{i+1}; U_{k_{s+1}} = 0, V_{k_{s+1}} = I
+  for (int64_t t = maxn - 1; t >= 0; --t) {
+    std::vector<BDesc> du, dv;
+    for (int64_t s = 0; s < p; ++s) {
+      if (nint[s] <= t) continue;
+      const int64_t i = ks[s] + 1 + t;
+      const bool lastrow = (t == nint[s] - 1);
+      BDesc d = desc0();
+      d.a_off = i * MM;
+      d.kd = (int32_t)Mp;
+      d.segrows = (int32_t)Mp;
+      BDesc u = d, v = d;
+      u.b_off = lastrow ? MM : (2 + 2 * (i + 1)) * MM;        // Zero or U_{i+1}
+      u.cin_off = (1 + i) * MM;                                 // Gamma_i
+      u.c_off = (2 + 2 * i) * MM;
+      v.b_off = lastrow ? 0 : (2 + 2 * (i + 1) + 1) * MM;      // Ident or V_{i+1}
+      v.c_off = (2 + 2 * i + 1) * MM;
+      du.push_back(u);
+      dv.push_back(v);
+    }
+    BArgs a = bargs_base((int)Mp);
+    a.A = P->alpha; a.lda = Mp;
+    a.B = P->UVa; a.ldb = Mp;
+    a.C = P->UVa; a.ldc = Mp;
+    a.ncols = (int32_t)Mp;
+    BArgs au = a;
+    au.Cin = Ga; au.ldcin = Mp;
+    run_bgemm(au, du, pool, st);
+    run_bgemm(a, dv, pool, st);
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  P->release(Ga);
+  P->release(Dwork);
+
+  // ---- reduced system, eq. (red1)
+  P->red = P->alloc(3 * p * MM);
+  double* At = P->red;
+  double* Ct = P->red + p * MM;
+  double* Bt = P->red + 2 * p * MM;
+  HIPCHK(launch_reduced(At, Ct, Bt, P->d_ks, P->UVa + 2 * MM, P->cC, P->fmtC, P->adiag, P->bdiag, (int)p, (int)N, (int)M,
+                        (int)Mp, st));
+
+  // ---- dichotomy tree (Algorithm 1 applied to the reduced system)
+  P->nodes.clear();
+  P->depth = 0;
+  build_tree(P->nodes, 0, (int)p - 1, 0, P->depth);
+  auto& nodes = P->nodes;
+  const int nn = (int)nodes.size();
+  int64_t goff = 0;
+  const int CB = 4;  // blocks per partial-sum chunk
+  int nch = 0;
+  for (auto& n : nodes) {
+    n.g_off = goff;
+    goff += (int64_t)(n.r - n.l + 1) * MM;
+    n.chunk0 = nch;
+    n.nchunk = (n.r - n.l + 1 + CB - 1) / CB;
+    nch += n.nchunk;
+  }
+  P->nchunks = nch;
+  P->G = P->alloc(goff);
+  P->H = P->alloc((int64_t)nn * 2 * MM);
+  HIPCHK(launch_fill(P->H, (int64_t)nn * 2 * MM, 0.0, st));
+  // arena: [Zero | DWL | DWR | AL | AR | TL | TR] per node
+  double* Da = P->alloc((1 + 6 * (int64_t)nn) * MM);
+  HIPCHK(launch_fill(Da, MM, 0.0, st));
+  auto DWL = [&](int n) { return (1 + 0 * (int64_t)nn + n) * MM; };
+  auto DWR = [&](int n) { return (1 + 1 * (int64_t)nn + n) * MM; };
+  auto AL = [&](int n) { return (1 + 2 * (int64_t)nn + n) * MM; };
+  auto AR = [&](int n) { return (1 + 3 * (int64_t)nn + n) * MM; };
+  auto TL = [&](int n) { return (1 + 4 * (int64_t)nn + n) * MM; };
+  auto TR = [&](int n) { return (1 + 5 * (int64_t)nn + n) * MM; };
+  auto gslot = [&](int n, int j) { return nodes[n].g_off + (int64_t)(j - nodes[n].l) * MM; };
+  const int64_t oA = 0, oC = p * MM, oB = 2 * p * MM;  // offsets of At, Ct, Bt in red
+
+  int maxchain = 0;
+  for (auto& n : nodes) maxchain = std::max(maxchain, std::max(n.m - n.l, n.r - n.m));
+
+  // left chains D^L_j = Ct_j - At_j alphaL_{j-1}, alphaL_j = (D^L_j)^{-1} Bt_j  (j = l..m-1)
+  // right chains D^R_j = Ct_j - Bt_j alphaR_{j+1}, alphaR_j = (D^R_j)^{-1} At_j (j = r..m+1)
+  for (int t = 0; t < maxchain; ++t) {
+    std::vector<BDesc> dd, da;
+    std::vector<int64_t> outoff;
+    std::vector<int32_t> tag;
+    std::vector<int64_t> woff;
+    for (int n = 0; n < nn; ++n) {
+      const Node& nd = nodes[n];
+      if (nd.m - nd.l > t) {
+        const int j = nd.l + t;
+        BDesc d = desc0();
+        d.kd = (int32_t)Mp; d.segrows = (int32_t)Mp;
+        d.a_off = oA + j * MM;
+        d.b_off = (t == 0) ? 0 : AL(n);
+        d.cin_off = oC + j * MM;
+        d.c_off = DWL(n);
+        dd.push_back(d);
+        BDesc e = desc0();
+        e.kd = (int32_t)Mp; e.segrows = (int32_t)Mp;
+        e.a_off = gslot(n, j);
+        e.b_off = oB + j * MM;
+        e.c_off = AL(n);
+        da.push_back(e);
+        woff.push_back(DWL(n));
+        outoff.push_back(gslot(n, j));
+        tag.push_back((int32_t)(N + j));
+      }
+      if (nd.r - nd.m > t) {
+        const int j = nd.r - t;
+        BDesc d = desc0();
+        d.kd = (int32_t)Mp; d.segrows = (int32_t)Mp;
+        d.a_off = oB + j * MM;
+        d.b_off = (t == 0) ? 0 : AR(n);
+        d.cin_off = oC + j * MM;
+        d.c_off = DWR(n);
+        dd.push_back(d);
+        BDesc e = desc0();
+        e.kd = (int32_t)Mp; e.segrows = (int32_t)Mp;
+        e.a_off = gslot(n, j);
+        e.b_off = oA + j * MM;
+        e.c_off = AR(n);
+        da.push_back(e);
+        woff.push_back(DWR(n));
+        outoff.push_back(gslot(n, j));
+        tag.push_back((int32_t)(N + j));
+      }
+    }
+    BArgs a = bargs_base((int)Mp);
+    a.A = P->red; a.lda = Mp;
+    a.B = Da; a.ldb = Mp;
+    a.Cin = P->red; a.ldcin = Mp;
+    a.C = Da; a.ldc = Mp;
+    a.alpha = -1.0;
+    a.ncols = (int32_t)Mp;
+    run_bgemm(a, dd, pool, st);
+    // invert the chain matrices in place in the arena (one launch for all nodes)
+    const int nm = (int)woff.size();
+    if (nm > 0) {
+      GJArgs g;
+      g.work = Da; g.work_off = pool.put_vec(woff); g.wstride = 0;
+      g.out = P->G; g.out_off = pool.put_vec(outoff);
+      g.alpha = nullptr; g.bdiag = nullptr; g.bd_off = nullptr;
+      g.tag = pool.put_vec(tag); g.bad = bad;
+      g.nmat = nm; g.Mp = (int32_t)Mp;
+      HIPCHK(launch_gj(g, st));
+    }
+    BArgs b = bargs_base((int)Mp);
+    b.A = P->G; b.lda = Mp;
+    b.B = P->red; b.ldb = Mp;
+    b.C = Da; b.ldc = Mp;
+    b.ncols = (int32_t)Mp;
+    run_bgemm(b, da, pool, st);
+  }
+  // S_m = Ct_m - At_m alphaL_{m-1} - Bt_m alphaR_{m+1};  G_m = S_m^{-1}
+  {
+    std::vector<BDesc> d1, d2;
+    std::vector<int64_t> outoff;
+    std::vector<int32_t> tag;
+    for (int n = 0; n < nn; ++n) {
+      const Node& nd = nodes[n];
+      BDesc d = desc0();
+      d.kd = (int32_t)Mp; d.segrows = (int32_t)Mp;
+      d.a_off = oA + nd.m * MM;
+      d.b_off = (nd.m > nd.l) ? AL(n) : 0;
+      d.cin_off = oC + nd.m * MM;
+      d.c_off = DWL(n);
+      d1.push_back(d);
+      BDesc e = desc0();
+      e.kd = (int32_t)Mp; e.segrows = (int32_t)Mp;
+      e.a_off = oB + nd.m * MM;
+      e.b_off = (nd.r > nd.m) ? AR(n) : 0;
+      e.cin_off = DWL(n);
+      e.c_off = DWL(n);
+      d2.push_back(e);
+      outoff.push_back(gslot(n, nd.m));
+      tag.push_back((int32_t)(N + nd.m));
+    }
+    BArgs a = bargs_base((int)Mp);
+    a.A = P->red; a.lda = Mp;
+    a.B = Da; a.ldb = Mp;
+    a.Cin = P->red; a.ldcin = Mp;
+    a.C = Da; a.ldc = Mp;
+    a.alpha = -1.0;
+    a.ncols = (int32_t)Mp;
+    run_bgemm(a, d1, pool, st);
+    BArgs a2 = a;
+    a2.Cin = Da;
+    run_bgemm(a2, d2, pool, st);
+    std::vector<int64_t> woff;
+    for (int n = 0; n < nn; ++n) woff.push_back(DWL(n));
+    GJArgs g;
+    g.work = Da; g.work_off = pool.put_vec(woff); g.wstride = 0;
+    g.out = P->G; g.out_off = pool.put_vec(outoff);
+    g.alpha = nullptr; g.bdiag = nullptr; g.bd_off = nullptr;
+    g.tag = pool.put_vec(tag); g.bad = bad;
+    g.nmat = nn; g.Mp = (int32_t)Mp;
+    HIPCHK(launch_gj(g, st));
+  }
+  // G_j = G_{j+1} At_{j+1} (D^L_j)^{-1} for j < m;  G_j = G_{j-1} Bt_{j-1} (D^R_j)^{-1} for j > m
+  for (int t = 0; t < maxchain; ++t) {
+    std::vector<BDesc> d1, d2;
+    for (int n = 0; n < nn; ++n) {
+      const Node& nd = nodes[n];
+      if (nd.m - nd.l > t) {
+        const int j = nd.m - 1 - t;
+        BDesc d = desc0();
+        d.kd = (int32_t)Mp; d.segrows = (int32_t)Mp;
+        d.a_off = gslot(n, j + 1);
+        d.b_off = oA + (j + 1) * MM;
+        d.c_off = TL(n);
+        d1.push_back(d);
+        BDesc e = desc0();
+        e.kd = (int32_t)Mp; e.segrows = (int32_t)Mp;
+        e.a_off = TL(n);
+        e.b_off = gslot(n, j);
+        e.c_off = gslot(n, j);
+        d2.push_back(e);
+      }
+      if (nd.r - nd.m > t) {
+        const int j = nd.m + 1 + t;
+        BDesc d = desc0();
+        d.kd = (int32_t)Mp; d.segrows = (int32_t)Mp;
+        d.a_off = gslot(n, j - 1);
+        d.b_off = oB + (j - 1) * MM;
+        d.c_off = TR(n);
+        d1.push_back(d);
+        BDesc e = desc0();
+        e.kd = (int32_t)Mp; e.segrows = (int32_t)Mp;
+        e.a_off = TR(n);
+        e.b_off = gslot(n, j);
+        e.c_off = gslot(n, j);
+        d2.push_back(e);
+      }
+    }
+    BArgs a = bargs_base((int)Mp);
+    a.A = P->G; a.lda = Mp;
+    a.B = P->red; a.ldb = Mp;
+    a.C = Da; a.ldc = Mp;
+    a.ncols = (int32_t)Mp;
+    run_bgemm(a, d1, pool, st);
+    BArgs b = bargs_base((int)Mp);
+    b.A = Da; b.lda = Mp;
+    b.B = P->G; b.ldb = Mp;
+    b.C = P->G; b.ldc = Mp;
+    b.ncols = (int32_t)Mp;
+    run_bgemm(b, d2, pool, st);
+  }
+  // H^L = G_l At_l (l > 0), H^R = G_r Bt_r (r < p-1)
+  {
+    std::vector<BDesc> dh;
+    for (int n = 0; n < nn; ++n) {
+      const Node& nd = nodes[n];
+      if (nd.l > 0) {
+        BDesc d = desc0();
+        d.kd = (int32_t)Mp; d.segrows = (int32_t)Mp;
+        d.a_off = gslot(n, nd.l);
+        d.b_off = oA + nd.l * MM;
+        d.c_off = (int64_t)n * 2 * MM;
+        dh.push_back(d);
+      }
+      if (nd.r < p - 1) {
+        BDesc d = desc0();
+        d.kd = (int32_t)Mp; d.segrows = (int32_t)Mp;
+        d.a_off = gslot(n, nd.r);
+        d.b_off = oB + nd.r * MM;
+        d.c_off = (int64_t)n * 2 * MM + MM;
+        dh.push_back(d);
+      }
+    }
+    BArgs a = bargs_base((int)Mp);
+    a.A = P->G; a.lda = Mp;
+    a.B = P->red; a.ldb = Mp;
+    a.C = P->H; a.ldc = Mp;
+    a.ncols = (int32_t)Mp;
+    run_bgemm(a, dh, pool, st);
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  P->release(Da);
+
+  // ---- descriptors of the solve
+  {
+    std::vector<BDesc> sup;
+    for (int64_t s = 0; s < p; ++s)
+      for (int64_t i = ks[s] + 1; i < ks[s + 1]; ++i) {
+        BDesc d = desc0();
+        d.a_off = (2 + 2 * i) * MM;             // [U_i | V_i], Mp x 2Mp
+        d.kd = (int32_t)(2 * Mp);
+        d.segrows = (int32_t)(2 * Mp);
+        d.b_off = (s + 1) * Mp;                  // [X_{k_s}; X_{k_{s+1}}] in the padded interface buffer
+        d.cin_off = i * Mp;                      // W_i
+        d.x2_off = i * M;                        // X_i
+        sup.push_back(d);
+      }
+    P->n_sup = (int)sup.size();
+    P->d_sup = P->upload(sup);
+    std::vector<BDesc> part;
+    for (int n = 0; n < nn; ++n) {
+      const Node& nd = nodes[n];
+      for (int c = 0; c < nd.nchunk; ++c) {
+        const int jb = nd.l + c * CB, je = std::min(nd.r + 1, jb + CB);
+        BDesc d = desc0();
+        d.a_off = nd.g_off + (int64_t)(jb - nd.l) * MM;
+        d.kd = (int32_t)((je - jb) * Mp);
+        d.segrows = d.kd;
+        d.b_off = jb * Mp;
+        d.c_off = (int64_t)(nd.chunk0 + c) * Mp;
+        part.push_back(d);
+      }
+    }
+    P->n_part = (int)part.size();
+    P->d_part = P->upload(part);
+    std::vector<BDesc> corr;
+    P->corr_begin.assign(P->depth, 0);
+    P->corr_count.assign(P->depth, 0);
+    for (int lv = 0; lv < P->depth; ++lv) {
+      P->corr_begin[lv] = (int)corr.size();
+      for (int n = 0; n < nn; ++n) {
+        const Node& nd = nodes[n];
+        if (nd.level != lv) continue;
+        BDesc d = desc0();
+        d.a_off = (int64_t)n * 2 * MM;            // [H^L | H^R]
+        d.kd = (int32_t)(2 * Mp);
+        d.segrows = (int32_t)Mp;
+        d.b_off = (int64_t)nd.l * Mp;            // X_{l-1} (padded index l)
+        d.bseg = (int64_t)(nd.r + 2 - nd.l) * Mp; // X_{r+1} (padded index r+2)
+        d.sp_off = (int64_t)nd.chunk0 * Mp;
+        d.nsp = nd.nchunk;
+        d.c_off = (int64_t)(nd.m + 1) * Mp;
+        d.x2_off = ks[nd.m] * M;
+        corr.push_back(d);
+      }
+      P->corr_count[lv] = (int)corr.size() - P->corr_begin[lv];
+    }
+    P->d_corr = P->upload(corr);
+  }
+  // pivot check
+  int32_t badv = INT_MAX;
+  HIPCHK(hipMemcpy(&badv, bad, sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (badv != INT_MAX) {
+    char buf[160];
+    if (badv < N)
+      std::snprintf(buf, sizeof buf, "singular pivot block at block row %d (0-based) of the subdomain elimination", badv);
+    else
+      std::snprintf(buf, sizeof buf, "singular block at row %d (0-based) of the reduced interface system", (int)(badv - N));
+    throw std::string(buf);
+  }
+}
+
+void ensure_workspace(td_plan_s* P, int64_t K, hipStream_t st) {
+  if (K <= P->kcap) return;
+  const int64_t N = P->N, Mp = P->Mp, p = P->p;
+  P->release(P->Wbuf); P->release(P->Ft); P->release(P->Xi); P->release(P->Sp);
+  P->Wbuf = P->Ft = P->Xi = P->Sp = nullptr;
+  P->Wbuf = P->alloc(N * Mp * K);
+  P->Ft = P->alloc(p * Mp * K);
+  P->Xi = P->alloc((p + 2) * Mp * K);
+  P->Sp = P->alloc((int64_t)P->nchunks * Mp * K);
+  HIPCHK(launch_fill(P->Xi, (p + 2) * Mp * K, 0.0, st));
+  P->kcap = K;
+}
+
+void ensure_refine_ws(td_plan_s* P, int64_t K) {
+  if (K <= P->rcap) return;
+  const int64_t n = P->N * P->M;
+  P->release(P->Rbuf); P->release(P->Dbuf); P->release(P->colpart); P->release(P->norms);
+  P->Rbuf = P->alloc(n * K);
+  P->Dbuf = P->alloc(n * K);
+  P->colpart = P->alloc(P->N * K * 2);
+  P->norms = P->alloc(2 * K);
+  P->rcap = K;
+}
+
+void stage_mark(td_plan_s* P, int idx, hipStream_t st) {
+  if (!P->prof) return;
+  HIPCHK(hipEventRecord(P->se.ev[idx], st));
+}
+
+// One pass of Algorithm 2, step 2 (float64): eq. (sub3) sweeps, eq. (red1) right-hand side,
+// Algorithm 1 on the reduced system, eq. (superposition).
+void solve_pass(td_plan_s* P, const double* F, int64_t ldf, double* X, int64_t ldx, int64_t K, hipStream_t st) {
+  const int64_t N = P->N, M = P->M, Mp = P->Mp, p = P->p;
+  const int64_t ldw = N * Mp, ldft = p * Mp, ldxi = (p + 2) * Mp, ldsp = (int64_t)P->nchunks * Mp;
+  stage_mark(P, 0, st);
+  SweepArgs sa;
+  sa.ks = P->d_ks; sa.Dinv = P->Dinv; sa.alpha = P->alpha; sa.adiag = P->adiag;
+  sa.F = F; sa.ldf = ldf; sa.W = P->Wbuf; sa.ldw = ldw;
+  sa.N = (int32_t)N; sa.M = (int32_t)M; sa.Mp = (int32_t)Mp; sa.p = (int32_t)p; sa.K = (int32_t)K;
+  sa.ncoltiles = 0; sa.total = 0;
+  HIPCHK(launch_sweep(sa, st));
+  stage_mark(P, 1, st);
+  HIPCHK(launch_ftilde(P->Ft, ldft, F, ldf, P->Wbuf, ldw, P->d_ks, P->adiag, P->bdiag, (int)p, (int)M, (int)Mp,
+                       (int)K, st));
+  stage_mark(P, 2, st);
+  {
+    BArgs a = bargs_base((int)Mp);
+    a.descs = P->d_part; a.nprob = P->n_part;
+    a.A = P->G; a.lda = Mp;
+    a.B = P->Ft; a.ldb = ldft;
+    a.C = P->Sp; a.ldc = ldsp;
+    a.ncols = (int32_t)K;
+    HIPCHK(launch_bgemm(a, st));
+  }
+  stage_mark(P, 3, st);
+  for (int lv = 0; lv < P->depth; ++lv) {
+    BArgs a = bargs_base((int)Mp);
+    a.descs = P->d_corr + P->corr_begin[lv];
+    a.nprob = P->corr_count[lv];
+    a.A = P->H; a.lda = Mp;
+    a.B = P->Xi; a.ldb = ldxi;
+    a.Sp = P->Sp; a.ldsp = ldsp; a.spstride = Mp;
+    a.C = P->Xi; a.ldc = ldxi;
+    a.X2 = X; a.ldx2 = ldx; a.x2rows = (int32_t)M;
+    a.ncols = (int32_t)K;
+    HIPCHK(launch_bgemm(a, st));
+  }
+  stage_mark(P, 4, st);
+  {
+    BArgs a = bargs_base((int)Mp);
+    a.descs = P->d_sup; a.nprob = P->n_sup;
+    a.A = P->UVa; a.lda = Mp;
+    a.B = P->Xi; a.ldb = ldxi;
+    a.Cin = P->Wbuf; a.ldcin = ldw;
+    a.X2 = X; a.ldx2 = ldx; a.x2rows = (int32_t)M;
+    a.ncols = (int32_t)K;
+    HIPCHK(launch_bgemm(a, st));
+  }
+  stage_mark(P, 5, st);
+}
+
+// max over columns of ||F - P X|| / ||F||; R (if non-null) receives F - P X.  Synchronises.
+double residual(td_plan_s* P, const double* F, int64_t ldf, const double* X, int64_t ldx, int64_t K, double* R,
+                int64_t ldr, std::vector<double>& nrm, hipStream_t st) {
+  ensure_refine_ws(P, K);
+  HIPCHK(launch_residual(R, ldr, F, ldf, X, ldx, P->cA, P->fmtA, P->cB, P->fmtB, P->cC, P->fmtC, (int)P->N,
+                         (int)P->M, (int)K, P->colpart, (int)P->N, st));
+  HIPCHK(launch_colnorm_finish(P->norms, P->colpart, (int)P->N, (int)K, st));
+  nrm.resize(2 * K);
+  HIPCHK(hipMemcpyAsync(nrm.data(), P->norms, 2 * K * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  double worst = 0.0;
+  for (int64_t k = 0; k < K; ++k) {
+    const double r = nrm[2 * k], f = nrm[2 * k + 1];
+    const double rel = (f > 0.0) ? r / f : (r > 0.0 ? INFINITY : 0.0);
+    if (!(rel <= worst)) worst = rel;  // NaN propagates
+  }
+  return worst;
+}
+
+td_status solve_impl(td_plan_s* P, const double* F, int64_t ldf, double* X, int64_t ldx, int64_t K,
+                     const td_refine* rf, td_info* info, hipStream_t st) {
+  const int64_t n = P->N * P->M;
+  if (!F || !X) return fail(TD_EINVAL, "null F or X");
+  if (K < 0 || ldf < n || ldx < n) return fail(TD_EINVAL, "K < 0 or leading dimension below N*M");
+  if (K > INT_MAX / 2) return fail(TD_EINVAL, "K too large");
+  // overlap check of the column ranges
+  const char* f0 = (const char*)F;
+  const char* f1 = (const char*)(F + (K ? (K - 1) * ldf + n : 0));
+  const char* x0 = (const char*)X;
+  const char* x1 = (const char*)(X + (K ? (K - 1) * ldx + n : 0));
+  if (K > 0 && f0 < x1 && x0 < f1) return fail(TD_EINVAL, "X overlaps F");
+  if (info) { info->iterations = 0; info->nonfinite = 0; info->max_col_rel_residual = -1.0; }
+  if (K == 0) return TD_OK;
+  P->last_stream = st;
+  if (P->prof && !P->se.made) {
+    for (auto& e : P->se.ev) HIPCHK(hipEventCreate(&e));
+    P->se.made = true;
+  }
+  ensure_workspace(P, K, st);
+  if (P->prof) HIPCHK(hipEventRecord(P->se.ev[6], st));
+  solve_pass(P, F, ldf, X, ldx, K, st);
+  const bool refine = rf && rf->enable;
+  td_status status = TD_OK;
+  if (refine || info) {
+    const double tol = (rf && rf->tol > 0.0) ? rf->tol : 1e-10;
+    const int maxit = (rf && rf->max_iter > 0) ? rf->max_iter : 10;
+    std::vector<double> nrm;
+    ensure_refine_ws(P, K);
+    double res = residual(P, F, ldf, X, ldx, K, refine ? P->Rbuf : nullptr, n, nrm, st);
+    int it = 0;
+    while (refine && !(res <= tol)) {
+      if (it >= maxit || !std::isfinite(res)) { status = TD_ENOCONV; break; }
+      // X += ||r|| * S(r / ||r||), column by column
+      HIPCHK(launch_scale_cols(P->Rbuf, n, P->Rbuf, n, P->norms, 1, n, (int)K, st));
+      solve_pass(P, P->Rbuf, n, P->Dbuf, n, K, st);
+      HIPCHK(launch_axpy_cols(X, ldx, P->Dbuf, n, P->norms, n, (int)K, st));
+      ++it;
+      res = residual(P, F, ldf, X, ldx, K, P->Rbuf, n, nrm, st);
+    }
+    if (info) {
+      info->iterations = it;
+      info->max_col_rel_residual = res;
+      HIPCHK(launch_negate_fill_check(P->d_flag + 1, 0, st));
+      HIPCHK(launch_nonfinite(P->d_flag + 1, X, ldx, n, (int)K, st));
+      int32_t nf = 0;
+      HIPCHK(hipMemcpyAsync(&nf, P->d_flag + 1, 4, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      info->nonfinite = nf;
+    }
+  }
+  if (P->prof) {
+    HIPCHK(hipEventRecord(P->se.ev[7], st));
+    HIPCHK(hipEventSynchronize(P->se.ev[7]));
+    float ms = 0.f;
+    for (int s = 0; s < 5; ++s) {
+      HIPCHK(hipEventElapsedTime(&ms, P->se.ev[s], P->se.ev[s + 1]));
+      P->stage_ms[s] = ms;
+    }
+    P->stage_ms[5] = 0.0;
+    HIPCHK(hipEventElapsedTime(&ms, P->se.ev[6], P->se.ev[7]));
+    P->stage_ms[6] = ms;
+    P->stage_valid = true;
+  }
+  if (status == TD_ENOCONV) return fail(status, "refinement did not reach the requested residual");
+  return TD_OK;
+}
+
+td_status check_desc(const td_desc* d) {
+  if (!d) return fail(TD_EINVAL, "null descriptor");
+  if (d->N < 1 || d->M < 1) return fail(TD_EINVAL, "N and M must be >= 1");
+  if (d->subdomains < 0 || d->subdomains > d->N) return fail(TD_EINVAL, "subdomains must be in [0, N]");
+  if (!(d->fmt_A == TD_FMT_DENSE || d->fmt_A == TD_FMT_DIAG)) return fail(TD_EINVAL, "fmt_A must be DENSE or DIAG");
+  if (!(d->fmt_B == TD_FMT_DENSE || d->fmt_B == TD_FMT_DIAG)) return fail(TD_EINVAL, "fmt_B must be DENSE or DIAG");
+  if (!(d->fmt_C == TD_FMT_DENSE || d->fmt_C == TD_FMT_TRIDIAG)) return fail(TD_EINVAL, "fmt_C must be DENSE or TRIDIAG");
+  if (d->sweep_prec < TD_PREC_F64 || d->sweep_prec > TD_PREC_BF16) return fail(TD_EINVAL, "bad sweep_prec");
+  if (d->reserved != 0) return fail(TD_EINVAL, "reserved must be 0");
+  if (d->M > 512) return fail(TD_ENOTSUP, "M > 512 is not supported");
+  if (d->N > (int64_t)1 << 30) return fail(TD_ENOTSUP, "N too large");
+  if (d->fmt_A == TD_FMT_DENSE || d->fmt_B == TD_FMT_DENSE)
+    return fail(TD_ENOTSUP, "dense A/B blocks are not supported by this build");
+  return TD_OK;
+}
+
+// device bytes the factor needs at its peak (checked against free memory before allocating)
+int64_t factor_bytes(int64_t N, int64_t M, int64_t p, int fA, int fB, int fC) {
+  const int64_t Mp = pad_block(M), MM = Mp * Mp;
+  int64_t depth = 0;
+  for (int64_t q = p; q > 0; q >>= 1) ++depth;
+  int64_t b = 0;
+  b += (fA == TD_FMT_DIAG ? N * M : N * M * M) + (fB == TD_FMT_DIAG ? N * M : N * M * M);
+  b += (fC == TD_FMT_TRIDIAG ? 3 * N * M : N * M * M) + 2 * N * Mp;
+  b += N * MM * 2 + (2 + 2 * N) * MM;     // Dinv, alpha, UV
+  b += (1 + N) * MM + p * MM;              // Gamma arena, Dwork (temporary)
+  b += 3 * p * MM + p * (depth + 1) * MM + 2 * p * MM + (1 + 6 * p) * MM + p * MM;  // reduced, G, H, arenas
+  return b * 8;
+}
+
+// blocks of P^T (compact formats): C'_j = C_j^T, A'_j = B_{j-1}^T, B'_j = A_{j+1}^T
+void transpose_inputs(const td_plan_s* P, std::vector<double>& A2, std::vector<double>& B2, std::vector<double>& C2) {
+  const int64_t N = P->N, M = P->M;
+  std::vector<double> a(N * M), b(N * M);
+  HIPCHK(hipMemcpy(a.data(), P->cA, N * M * 8, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(b.data(), P->cB, N * M * 8, hipMemcpyDeviceToHost));
+  A2.assign(N * M, 0.0);
+  B2.assign(N * M, 0.0);
+  for (int64_t j = 1; j < N; ++j)
+    for (int64_t r = 0; r < M; ++r) A2[j * M + r] = b[(j - 1) * M + r];
+  for (int64_t j = 0; j + 1 < N; ++j)
+    for (int64_t r = 0; r < M; ++r) B2[j * M + r] = a[(j + 1) * M + r];
+  if (P->fmtC == TD_FMT_TRIDIAG) {
+    std::vector<double> c(N * 3 * M);
+    HIPCHK(hipMemcpy(c.data(), P->cC, N * 3 * M * 8, hipMemcpyDeviceToHost));
+    C2.assign(N * 3 * M, 0.0);
+    for (int64_t j = 0; j < N; ++j) {
+      const double* t = &c[j * 3 * M];
+      double* u = &C2[j * 3 * M];
+      for (int64_t r = 0; r < M; ++r) {
+        u[M + r] = t[M + r];
+        if (r > 0) u[r] = t[2 * M + r - 1];        // (C^T)(r, r-1) = C(r-1, r)
+        if (r + 1 < M) u[2 * M + r] = t[r + 1];    // (C^T)(r, r+1) = C(r+1, r)
+      }
+    }
+  } else {
+    std::vector<double> c(N * M * M);
+    HIPCHK(hipMemcpy(c.data(), P->cC, N * M * M * 8, hipMemcpyDeviceToHost));
+    C2.assign(N * M * M, 0.0);
+    for (int64_t j = 0; j < N; ++j)
+      for (int64_t r = 0; r < M; ++r)
+        for (int64_t q = 0; q < M; ++q) C2[j * M * M + q + r * M] = c[j * M * M + r + q * M];
+  }
+}
+
+td_status factor_top(const td_desc* d, const double* A, const double* B, const double* C, hipStream_t st,
+                     td_plan* out, bool allow_adjoint) {
+  td_status s = check_desc(d);
+  if (s != TD_OK) return s;
+  if (!A || !B || !C) return fail(TD_EINVAL, "null A, B or C");
+  const auto t0 = std::chrono::steady_clock::now();
+  td_plan_s* P = new td_plan_s();
+  P->N = d->N; P->M = d->M; P->Mp = pad_block(d->M);
+  P->p = d->subdomains ? d->subdomains : choose_p(d->N);
+  P->fmtA = d->fmt_A; P->fmtB = d->fmt_B; P->fmtC = d->fmt_C;
+  P->prec = d->sweep_prec; P->adjoint = d->adjoint;
+  P->ks = partition(P->N, P->p);
+  try {
+    size_t freeb = 0, totb = 0;
+    HIPCHK(hipMemGetInfo(&freeb, &totb));
+    const int64_t need = factor_bytes(P->N, P->M, P->p, P->fmtA, P->fmtB, P->fmtC);
+    if ((double)need > 0.95 * (double)freeb) {
+      delete P;
+      return fail(TD_ENOMEM, "factor needs " + std::to_string(need) + " bytes, " + std::to_string(freeb) + " free");
+    }
+    factor_impl(P, A, B, C, st);
+    if (d->adjoint && allow_adjoint) {
+      std::vector<double> A2, B2, C2;
+      transpose_inputs(P, A2, B2, C2);
+      double *dA = nullptr, *dB = nullptr, *dC = nullptr;
+      HIPCHK(hipMalloc((void**)&dA, A2.size() * 8));
+      HIPCHK(hipMalloc((void**)&dB, B2.size() * 8));
+      HIPCHK(hipMalloc((void**)&dC, C2.size() * 8));
+      HIPCHK(hipMemcpy(dA, A2.data(), A2.size() * 8, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(dB, B2.data(), B2.size() * 8, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(dC, C2.data(), C2.size() * 8, hipMemcpyHostToDevice));
+      td_desc d2 = *d;
+      d2.subdomains = P->p;
+      d2.adjoint = 0;
+      td_plan adj = nullptr;
+      td_status s2 = factor_top(&d2, dA, dB, dC, st, &adj, false);
+      (void)hipFree(dA); (void)hipFree(dB); (void)hipFree(dC);
+      if (s2 != TD_OK) {
+        delete P;
+        return s2;
+      }
+      P->adj = adj;
+    }
+  } catch (const HipFail& e) {
+    delete P;
+    const td_status code = (e.e == hipErrorOutOfMemory) ? TD_ENOMEM : TD_EHIP;
+    return fail(code, std::string("HIP error ") + hipGetErrorString(e.e) + " in " + e.where);
+  } catch (const std::string& msg) {
+    delete P;
+    return fail(TD_ESINGULAR, msg);
+  }
+  P->factor_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  P->last_stream = st;
+  *out = P;
+  return TD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+td_status tridiag_factor(const td_desc* desc, const double* A, const double* B, const double* C, void* stream,
+                         td_plan* out) {
+  if (!out) return fail(TD_EINVAL, "null out");
+  *out = nullptr;
+  g_err.clear();
+  return factor_top(desc, A, B, C, (hipStream_t)stream, out, true);
+}
+
+td_status tridiag_solve(td_plan plan, const double* F, int64_t ldf, double* X, int64_t ldx, int64_t K,
+                        const td_refine* refine, td_info* info, void* stream) {
+  if (!plan) return fail(TD_EINVAL, "null plan");
+  g_err.clear();
+  try {
+    return solve_impl(plan, F, ldf, X, ldx, K, refine, info, (hipStream_t)stream);
+  } catch (const HipFail& e) {
+    const td_status code = (e.e == hipErrorOutOfMemory) ? TD_ENOMEM : TD_EHIP;
+    return fail(code, std::string("HIP error ") + hipGetErrorString(e.e) + " in " + e.where);
+  }
+}
+
+td_status tridiag_solve_adjoint(td_plan plan, const double* G, int64_t ldg, double* Lam, int64_t ldl, int64_t K,
+                                const td_refine* refine, td_info* info, void* stream) {
+  if (!plan) return fail(TD_EINVAL, "null plan");
+  if (!plan->adj) return fail(TD_ENOADJ, "plan was factored without the transpose (desc.adjoint == 0)");
+  return tridiag_solve(plan->adj, G, ldg, Lam, ldl, K, refine, info, stream);
+}
+
+td_status tridiag_diag_grad(const double* Lam, int64_t ldl, const double* X, int64_t ldx, int64_t n, int64_t K,
+                            double* out, void* stream) {
+  g_err.clear();
+  if (!Lam || !X || !out) return fail(TD_EINVAL, "null pointer");
+  if (n < 0 || K < 0 || ldl < n || ldx < n) return fail(TD_EINVAL, "bad sizes");
+  if (K > INT_MAX) return fail(TD_EINVAL, "K too large");
+  hipError_t e = launch_diag_grad(out, Lam, ldl, X, ldx, n, (int)K, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(TD_EHIP, hipGetErrorString(e));
+  return TD_OK;
+}
+
+td_status tridiag_destroy(td_plan plan) {
+  if (!plan) return TD_OK;
+  if (plan->last_stream) (void)hipStreamSynchronize(plan->last_stream);
+  else (void)hipDeviceSynchronize();
+  delete plan;
+  return TD_OK;
+}
+
+td_status tridiag_plan_info(td_plan plan, td_plan_info* out) {
+  if (!plan || !out) return fail(TD_EINVAL, "null argument");
+  out->N = plan->N; out->M = plan->M; out->subdomains = plan->p; out->Mp = plan->Mp;
+  out->tree_depth = plan->depth;
+  out->device_bytes = plan->bytes + (plan->adj ? plan->adj->bytes : 0);
+  out->factor_ms = plan->factor_ms;
+  out->sweep_prec = plan->prec;
+  out->adjoint = plan->adj != nullptr;
+  return TD_OK;
+}
+
+td_status tridiag_set_profiling(td_plan plan, int enable) {
+  if (!plan) return fail(TD_EINVAL, "null plan");
+  plan->prof = enable != 0;
+  if (plan->adj) plan->adj->prof = enable != 0;
+  return TD_OK;
+}
+
+td_status tridiag_stage_times(td_plan plan, double* ms, int n) {
+  if (!plan || !ms || n < 0) return fail(TD_EINVAL, "bad argument");
+  if (!plan->stage_valid) return fail(TD_EINVAL, "no profiled solve yet");
+  for (int i = 0; i < n && i < 7; ++i) ms[i] = plan->stage_ms[i];
+  return TD_OK;
+}
+
+const char* tridiag_status_string(td_status s) {
+  switch (s) {
+    case TD_OK: return "TD_OK";
+    case TD_EINVAL: return "TD_EINVAL: invalid argument";
+    case TD_ENOMEM: return "TD_ENOMEM: not enough device memory";
+    case TD_ESINGULAR: return "TD_ESINGULAR: singular pivot block";
+    case TD_ENOCONV: return "TD_ENOCONV: refinement did not converge";
+    case TD_ENOADJ: return "TD_ENOADJ: plan has no transposed factor";
+    case TD_EHIP: return "TD_EHIP: HIP runtime error";
+    case TD_ENOTSUP: return "TD_ENOTSUP: unsupported combination";
+  }
+  return "unknown status";
+}
+
+const char* tridiag_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

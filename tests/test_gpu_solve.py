@@ -1,0 +1,121 @@
+"""Parity of the HIP float64 path (through the C ABI) with the CPU oracle.
+
+Tolerance: relative Frobenius error <= 1e-12 against the oracle for every float64
+solve (the method is direct; both sides only differ in rounding order).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from dense_ref import rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def td():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1108_4181_amd as m
+
+    m.load_library()
+    return m
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _solve(td, sys, F, p, **kw):
+    plan = td.Plan.from_system(sys, subdomains=p, **kw)
+    X = plan.solve(_dev(F)).cpu().numpy()
+    return plan, X
+
+
+def test_tiny_workload(td):
+    w = synth.WORKLOADS["tiny_n64_m16_k8"]
+    sys = synth.workload_system("tiny_n64_m16_k8")
+    F = synth.rhs_columns(w["seed"], sys.N, sys.M, range(w["K"]))
+    _, X = _solve(td, sys, F, w["p"])
+    assert rel_err(X, oracle.solve(sys, F)) < TOL
+
+
+@pytest.mark.parametrize("N,M,K,p", [
+    (37, 16, 5, 6),      # uneven partition
+    (40, 16, 3, 1),      # one subdomain: the reduced system is C~_0 only
+    (24, 16, 2, 24),     # p = N: every row an interface row (Algorithm 1 on P itself)
+    (50, 32, 33, 7),     # ragged column tail (33 = 32 + 1)
+    (64, 20, 9, 5),      # M not a multiple of 16 (padded block)
+    (96, 64, 40, 8),     # several row tiles per wave group
+])
+def test_varcoef_shapes(td, N, M, K, p):
+    sys = synth.varcoef_system(N, M, seed=100 + N)
+    F = synth.rhs_columns(100 + N, N, M, range(K))
+    _, X = _solve(td, sys, F, p)
+    assert rel_err(X, oracle.solve(sys, F)) < TOL
+
+
+def test_block_150(td):
+    """M = 150 (one of the paper's block sizes): padded to 160."""
+    sys = synth.varcoef_system(48, 150, seed=7)
+    F = synth.rhs_columns(7, 48, 150, range(10))
+    _, X = _solve(td, sys, F, 6)
+    assert rel_err(X, oracle.solve(sys, F)) < TOL
+
+
+def test_m256_moderate(td):
+    sys = synth.varcoef_system(128, 256, seed=8)
+    F = synth.rhs_columns(8, 128, 256, range(40))
+    _, X = _solve(td, sys, F, 8)
+    assert rel_err(X, oracle.solve(sys, F)) < TOL
+
+
+def test_residual_info_and_determinism(td):
+    sys = synth.varcoef_system(64, 32, seed=9)
+    F = synth.rhs_columns(9, 64, 32, range(12))
+    plan = td.Plan.from_system(sys, subdomains=4)
+    Fd = _dev(F)
+    X1, info = plan.solve(Fd, info=True)
+    X2 = plan.solve(Fd)
+    assert torch.equal(X1, X2)
+    assert info["max_col_rel_residual"] < 1e-13 and info["nonfinite"] == 0
+
+
+def test_singular_reported(td):
+    """A zero block C_i on the first interior row of a subdomain makes the first pivot block of that
+    subdomain's sub-problems (eqs. sub1-sub3) zero: the factor must stop with TD_ESINGULAR."""
+    sys = synth.varcoef_system(16, 16, seed=10)
+    C = sys.C.copy()
+    C[9] = 0.0                     # p = 2: interface rows 0 and 8, row 9 opens subdomain 1
+    bad = synth.System(16, 16, sys.A, sys.B, C)
+    with pytest.raises(td.TridiagError) as e:
+        td.Plan.from_system(bad, subdomains=2)
+    assert e.value.code == 3 and "block row 9" in str(e.value)
+
+
+def test_nan_input_reported(td):
+    sys = synth.varcoef_system(16, 16, seed=13)
+    C = sys.C.copy()
+    C[3, 1, 4] = np.nan
+    with pytest.raises(td.TridiagError) as e:
+        td.Plan.from_system(synth.System(16, 16, sys.A, sys.B, C), subdomains=2)
+    assert e.value.code == 3
+
+
+def test_adjoint_nonsymmetric(td):
+    sys = synth.varcoef_system(40, 16, seed=11)
+    G = synth.rhs_columns(11, 40, 16, range(6))
+    plan = td.Plan.from_system(sys, subdomains=5, adjoint=True)
+    Lam = plan.solve_adjoint(_dev(G)).cpu().numpy()
+    assert rel_err(Lam, oracle.solve_adjoint(sys, G)) < TOL
+
+
+def test_zero_columns(td):
+    sys = synth.varcoef_system(16, 16, seed=12)
+    plan = td.Plan.from_system(sys, subdomains=2)
+    X = plan.solve(torch.empty((0, 256), dtype=torch.float64, device="cuda"))
+    assert X.shape == (0, 256)
