@@ -149,11 +149,14 @@ typedef struct {
 td_status tridiag_plan_info(td_plan plan, td_plan_info* out);
 
 /*
- * Per-stage timing of the solves (HIP events on the solve's stream).  When enabled, every
- * following solve records events around each stage; tridiag_stage_times returns, for the
- * last solve, the milliseconds of: [0] subdomain sweeps, [1] interface right-hand side,
- * [2] dichotomy partial sums, [3] dichotomy levels, [4] superposition, [5] residual and
- * update (refinement), [6] whole solve.  It synchronises the stream.
+ * Per-stage timing of the solves (HIP events recorded on each solve's own stream, no extra
+ * synchronisation).  While enabled, every solve (up to 4096 between read-outs) records events
+ * around its stages.  tridiag_stage_times waits for the last recorded solve and writes the
+ * average milliseconds per solve over the solves recorded since the previous read-out of:
+ * [0] subdomain sweeps, [1] interface right-hand side, [2] dichotomy partial sums,
+ * [3] dichotomy levels, [4] superposition, [5] residual tests and refinement, [6] whole
+ * solve, and, if n >= 8, [7] the number of solves averaged; then it starts a new count.
+ * With refinement the stage times [0]-[4] are those of the last correction pass.
  */
 td_status tridiag_set_profiling(td_plan plan, int enable);
 td_status tridiag_stage_times(td_plan plan, double* ms, int n);

@@ -188,10 +188,11 @@ class Plan:
         _check(self.lib.tridiag_set_profiling(self.h, 1 if on else 0))
 
     def stage_times(self) -> dict:
-        buf = (ctypes.c_double * 7)()
-        _check(self.lib.tridiag_stage_times(self.h, buf, 7))
+        """Average ms per solve of each stage over the solves profiled since the last call."""
+        buf = (ctypes.c_double * 8)()
+        _check(self.lib.tridiag_stage_times(self.h, buf, 8))
         names = ["sweep", "interface_rhs", "dichotomy_partial", "dichotomy_levels", "superposition",
-                 "refinement", "total"]
+                 "refinement", "total", "count"]
         return dict(zip(names, list(buf)))
 
     def close(self):

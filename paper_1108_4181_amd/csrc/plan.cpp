@@ -42,9 +42,9 @@ struct Node {
   int chunk0, nchunk;   // partial-sum chunks of this node
 };
 
+// events of one profiled solve: [0..5] stage boundaries, [6] start, [7] end
 struct StageEvents {
   hipEvent_t ev[8] = {};
-  bool made = false;
 };
 
 }  // namespace
@@ -79,9 +79,9 @@ struct td_plan_s {
   int32_t* d_flag = nullptr;
   td_plan_s* adj = nullptr;
   bool prof = false;
-  StageEvents se;
-  double stage_ms[7] = {0};
-  bool stage_valid = false;
+  std::vector<StageEvents> evsets;  // one set per profiled solve since the last read-out
+  int prof_n = 0;
+  StageEvents* se = nullptr;        // set of the solve in progress
   double factor_ms = 0.0;
   int64_t bytes = 0;
   std::vector<void*> allocs;
@@ -113,8 +113,8 @@ struct td_plan_s {
   }
   ~td_plan_s() {
     for (void* p : allocs) (void)hipFree(p);
-    if (se.made)
-      for (auto& e : se.ev) (void)hipEventDestroy(e);
+    for (auto& s : evsets)
+      for (auto& e : s.ev) (void)hipEventDestroy(e);
     delete adj;
   }
 };
@@ -660,8 +660,8 @@ void ensure_refine_ws(td_plan_s* P, int64_t K) {
 }
 
 void stage_mark(td_plan_s* P, int idx, hipStream_t st) {
-  if (!P->prof) return;
-  HIPCHK(hipEventRecord(P->se.ev[idx], st));
+  if (!P->prof || !P->se) return;
+  HIPCHK(hipEventRecord(P->se->ev[idx], st));
 }
 
 // One pass of Algorithm 2, step 2 (float64): eq. (sub3) sweeps, eq. (red1) right-hand side,
@@ -750,12 +750,17 @@ td_status solve_impl(td_plan_s* P, const double* F, int64_t ldf, double* X, int6
   if (info) { info->iterations = 0; info->nonfinite = 0; info->max_col_rel_residual = -1.0; }
   if (K == 0) return TD_OK;
   P->last_stream = st;
-  if (P->prof && !P->se.made) {
-    for (auto& e : P->se.ev) HIPCHK(hipEventCreate(&e));
-    P->se.made = true;
+  P->se = nullptr;
+  if (P->prof && P->prof_n < 4096) {
+    if ((int)P->evsets.size() <= P->prof_n) {
+      StageEvents s;
+      for (auto& e : s.ev) HIPCHK(hipEventCreate(&e));
+      P->evsets.push_back(s);
+    }
+    P->se = &P->evsets[P->prof_n++];
   }
   ensure_workspace(P, K, st);
-  if (P->prof) HIPCHK(hipEventRecord(P->se.ev[6], st));
+  if (P->se) HIPCHK(hipEventRecord(P->se->ev[6], st));
   solve_pass(P, F, ldf, X, ldx, K, st);
   const bool refine = rf && rf->enable;
   td_status status = TD_OK;
@@ -786,19 +791,8 @@ td_status solve_impl(td_plan_s* P, const double* F, int64_t ldf, double* X, int6
       info->nonfinite = nf;
     }
   }
-  if (P->prof) {
-    HIPCHK(hipEventRecord(P->se.ev[7], st));
-    HIPCHK(hipEventSynchronize(P->se.ev[7]));
-    float ms = 0.f;
-    for (int s = 0; s < 5; ++s) {
-      HIPCHK(hipEventElapsedTime(&ms, P->se.ev[s], P->se.ev[s + 1]));
-      P->stage_ms[s] = ms;
-    }
-    P->stage_ms[5] = 0.0;
-    HIPCHK(hipEventElapsedTime(&ms, P->se.ev[6], P->se.ev[7]));
-    P->stage_ms[6] = ms;
-    P->stage_valid = true;
-  }
+  if (P->se) HIPCHK(hipEventRecord(P->se->ev[7], st));
+  P->se = nullptr;
   if (status == TD_ENOCONV) return fail(status, "refinement did not reach the requested residual");
   return TD_OK;
 }
@@ -995,8 +989,29 @@ td_status tridiag_set_profiling(td_plan plan, int enable) {
 
 td_status tridiag_stage_times(td_plan plan, double* ms, int n) {
   if (!plan || !ms || n < 0) return fail(TD_EINVAL, "bad argument");
-  if (!plan->stage_valid) return fail(TD_EINVAL, "no profiled solve yet");
-  for (int i = 0; i < n && i < 7; ++i) ms[i] = plan->stage_ms[i];
+  if (plan->prof_n == 0) return fail(TD_EINVAL, "no profiled solve since the last read-out");
+  double acc[8] = {0};
+  try {
+    HIPCHK(hipEventSynchronize(plan->evsets[plan->prof_n - 1].ev[7]));
+    for (int q = 0; q < plan->prof_n; ++q) {
+      const StageEvents& s = plan->evsets[q];
+      float t = 0.f;
+      for (int i = 0; i < 5; ++i) {
+        HIPCHK(hipEventElapsedTime(&t, s.ev[i], s.ev[i + 1]));
+        acc[i] += t;
+      }
+      HIPCHK(hipEventElapsedTime(&t, s.ev[5], s.ev[7]));
+      acc[5] += t;
+      HIPCHK(hipEventElapsedTime(&t, s.ev[6], s.ev[7]));
+      acc[6] += t;
+    }
+  } catch (const HipFail& e) {
+    return fail(TD_EHIP, std::string("HIP error ") + hipGetErrorString(e.e) + " in " + e.where);
+  }
+  const double cnt = plan->prof_n;
+  for (int i = 0; i < n && i < 7; ++i) ms[i] = acc[i] / cnt;
+  if (n >= 8) ms[7] = cnt;
+  plan->prof_n = 0;
   return TD_OK;
 }
 
