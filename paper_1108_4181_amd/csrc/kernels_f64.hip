@@ -98,28 +98,44 @@ __global__ void __launch_bounds__(512) k_bgemm(BArgs args) {
     }
   };
 
-  gload(0);
-  lstore(0);
-  __syncthreads();
-  for (int q = 0; q < nch; ++q) {
-    const int buf = q & 1;
-    if (q + 1 < nch) gload(q + 1);
+  // A streams through two register buffers (halves of a 16-deep chunk), each loaded one
+  // half-chunk ahead of its use; B chunks go through double-buffered LDS.
+  const int64_t lane_off = rb + (L & 15) + (int64_t)(L >> 4) * lda;
+  double a0[2][RT], a1[2][RT];
+  auto loadA = [&](double (&dst)[2][RT], int kbase) {   // k-steps kbase/4 and kbase/4 + 1
+    const double* __restrict__ pa = A + lane_off + (int64_t)kbase * lda;
 #pragma unroll
-    for (int kk = 0; kk < KC / 4; ++kk) {
-      const int kg = q * KC + 4 * kk + (L >> 4);
-      double a[RT];
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
-      for (int t = 0; t < RT; ++t) a[t] = A[(rb + 16 * t + (L & 15)) + (int64_t)kg * lda];
-      const double* bp = &Bs[buf][(4 * kk + (L >> 4)) * SB + (L & 3) * CT];
+      for (int t = 0; t < RT; ++t) dst[u][t] = pa[16 * t + (int64_t)(4 * u) * lda];
+  };
+  auto compute = [&](const double (&av)[2][RT], int buf, int half) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const double* bp = &Bs[buf][(8 * half + 4 * u + (L >> 4)) * SB + (L & 3) * CT];
       double b[CT];
 #pragma unroll
       for (int c = 0; c < CT; ++c) b[c] = bp[c];
 #pragma unroll
       for (int t = 0; t < RT; ++t)
 #pragma unroll
-        for (int c = 0; c < CT; ++c) acc[t][c] = mfma4(a[t], b[c], acc[t][c]);
+        for (int c = 0; c < CT; ++c) acc[t][c] = mfma4(av[u][t], b[c], acc[t][c]);
     }
-    if (q + 1 < nch) lstore(buf ^ 1);
+  };
+
+  gload(0);
+  loadA(a0, 0);
+  lstore(0);
+  __syncthreads();
+  for (int q = 0; q < nch; ++q) {
+    const int buf = q & 1;
+    const bool more = q + 1 < nch;
+    if (more) gload(q + 1);
+    loadA(a1, q * KC + 8);
+    compute(a0, buf, 0);
+    loadA(a0, more ? (q + 1) * KC : 0);
+    compute(a1, buf, 1);
+    if (more) lstore(buf ^ 1);
     __syncthreads();
   }
 
@@ -197,19 +213,68 @@ __global__ void __launch_bounds__(512) k_sweep_f64(SweepArgs a) {
   const int Mp = a.Mp, M = a.M, K = a.K;
   const int rb = w * 16 * RT;
   const int64_t MM = (int64_t)Mp * Mp;
+  constexpr int KU = 2;      // MFMA k-steps (of 4) per register chunk of the streamed matrix
+  const int nkc = Mp / (4 * KU);   // even: Mp is a multiple of 16
+
+  // The step matrix streams through two register buffers, each loaded one chunk ahead of
+  // its use; after the last chunk of a step comes the first chunk of the next step's
+  // matrix.  Step order: forward rows first..last (D^{-1}), then backward rows
+  // last-1..first (alpha).
+  const int64_t nsteps = 2 * (last - first) + 1;
+  auto step_matrix = [&](int64_t q) -> const double* {
+    return (q <= last - first) ? a.Dinv + (first + q) * MM : a.alpha + (last - 1 - (q - (last - first + 1))) * MM;
+  };
+  const int64_t lane_off = rb + (L & 15) + (int64_t)(L >> 4) * Mp;
+  double a0[KU][RT], a1[KU][RT];
+  auto loadA = [&](double (&dst)[KU][RT], const double* __restrict__ Ab, int q) {
+    const double* __restrict__ pa = Ab + lane_off + (int64_t)(4 * KU * q) * Mp;
+#pragma unroll
+    for (int u = 0; u < KU; ++u)
+#pragma unroll
+      for (int t = 0; t < RT; ++t) dst[u][t] = pa[16 * t + (int64_t)(4 * u) * Mp];
+  };
+  double acc[RT][CT];
+  auto compute = [&](const double (&av)[KU][RT], int q) {
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      const double* bp = &In[(4 * KU * q + 4 * u + (L >> 4)) * SB + (L & 3) * CT];
+      double b[CT];
+#pragma unroll
+      for (int c = 0; c < CT; ++c) b[c] = bp[c];
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[t][c] = mfma4(av[u][t], b[c], acc[t][c]);
+    }
+  };
 
   for (int e = tid; e < Mp * KT; e += nthr) {
     const int row = e % Mp, c = e / Mp;
     const int col = col0 + c;
     In[row * SB + c] = (row < M && col < K) ? a.F[first * M + row + (int64_t)col * a.ldf] : 0.0;
   }
+  loadA(a0, step_matrix(0), 0);
   __syncthreads();
 
-  double acc[RT][CT];
-  // ---- forward
-  for (int64_t i = first; i <= last; ++i) {
-    double fn[RT][CT], an[RT];
-    const bool more = i < last;
+  for (int64_t q = 0; q < nsteps; ++q) {
+    const bool fwd = q <= last - first;
+    const int64_t i = fwd ? first + q : last - 1 - (q - (last - first + 1));
+    const double* __restrict__ Ai = step_matrix(q);
+    const double* __restrict__ Anx = (q + 1 < nsteps) ? step_matrix(q + 1) : Ai;
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int c = 0; c < CT; ++c) acc[t][c] = 0.0;
+    for (int kc = 0; kc < nkc - 2; kc += 2) {
+      loadA(a1, Ai, kc + 1);
+      compute(a0, kc);
+      loadA(a0, Ai, kc + 2);
+      compute(a1, kc + 1);
+    }
+    // operands of the epilogue, fetched before the last two chunks: F_{i+1} and a_{i+1}
+    // (forward) or beta_i (backward)
+    double ex[RT][CT], an[RT];
+    const bool more = fwd && i < last;
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
       const int row = rb + 16 * t + out_row(L);
@@ -217,25 +282,19 @@ __global__ void __launch_bounds__(512) k_sweep_f64(SweepArgs a) {
 #pragma unroll
       for (int c = 0; c < CT; ++c) {
         const int col = col0 + out_col(L) * CT + c;
-        fn[t][c] = (more && row < M && col < K) ? a.F[(i + 1) * M + row + (int64_t)col * a.ldf] : 0.0;
-        acc[t][c] = 0.0;
+        double v = 0.0;
+        if (fwd) {
+          if (more && row < M && col < K) v = a.F[(i + 1) * M + row + (int64_t)col * a.ldf];
+        } else if (col < K) {
+          v = a.W[i * Mp + row + (int64_t)col * a.ldw];
+        }
+        ex[t][c] = v;
       }
     }
-    const double* __restrict__ D = a.Dinv + i * MM;
-    for (int kk = 0; kk < Mp / 4; ++kk) {
-      const int k = 4 * kk + (L >> 4);
-      double av[RT];
-#pragma unroll
-      for (int t = 0; t < RT; ++t) av[t] = D[(rb + 16 * t + (L & 15)) + (int64_t)k * Mp];
-      const double* bp = &In[k * SB + (L & 3) * CT];
-      double b[CT];
-#pragma unroll
-      for (int c = 0; c < CT; ++c) b[c] = bp[c];
-#pragma unroll
-      for (int t = 0; t < RT; ++t)
-#pragma unroll
-        for (int c = 0; c < CT; ++c) acc[t][c] = mfma4(av[t], b[c], acc[t][c]);
-    }
+    loadA(a1, Ai, nkc - 1);
+    compute(a0, nkc - 2);
+    loadA(a0, Anx, 0);
+    compute(a1, nkc - 1);
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
@@ -244,51 +303,11 @@ __global__ void __launch_bounds__(512) k_sweep_f64(SweepArgs a) {
       for (int c = 0; c < CT; ++c) {
         const int lc = out_col(L) * CT + c;
         const int col = col0 + lc;
-        if (col < K) a.W[i * Mp + row + (int64_t)col * a.ldw] = acc[t][c];
-        In[row * SB + lc] = more ? fn[t][c] + an[t] * acc[t][c] : acc[t][c];
-      }
-    }
-    __syncthreads();
-  }
-  // ---- backward
-  for (int64_t i = last - 1; i >= first; --i) {
-    double bi[RT][CT];
-#pragma unroll
-    for (int t = 0; t < RT; ++t) {
-      const int row = rb + 16 * t + out_row(L);
-#pragma unroll
-      for (int c = 0; c < CT; ++c) {
-        const int col = col0 + out_col(L) * CT + c;
-        bi[t][c] = (col < K) ? a.W[i * Mp + row + (int64_t)col * a.ldw] : 0.0;
-        acc[t][c] = 0.0;
-      }
-    }
-    const double* __restrict__ Al = a.alpha + i * MM;
-    for (int kk = 0; kk < Mp / 4; ++kk) {
-      const int k = 4 * kk + (L >> 4);
-      double av[RT];
-#pragma unroll
-      for (int t = 0; t < RT; ++t) av[t] = Al[(rb + 16 * t + (L & 15)) + (int64_t)k * Mp];
-      const double* bp = &In[k * SB + (L & 3) * CT];
-      double b[CT];
-#pragma unroll
-      for (int c = 0; c < CT; ++c) b[c] = bp[c];
-#pragma unroll
-      for (int t = 0; t < RT; ++t)
-#pragma unroll
-        for (int c = 0; c < CT; ++c) acc[t][c] = mfma4(av[t], b[c], acc[t][c]);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < RT; ++t) {
-      const int row = rb + 16 * t + out_row(L);
-#pragma unroll
-      for (int c = 0; c < CT; ++c) {
-        const int lc = out_col(L) * CT + c;
-        const int col = col0 + lc;
-        const double v = acc[t][c] + bi[t][c];
+        // forward: beta_i; next operand F_{i+1} + a_{i+1} o beta_i (or beta_last = W_last)
+        // backward: W_i = alpha_i W_{i+1} + beta_i
+        const double v = fwd ? acc[t][c] : acc[t][c] + ex[t][c];
         if (col < K) a.W[i * Mp + row + (int64_t)col * a.ldw] = v;
-        In[row * SB + lc] = v;
+        In[row * SB + lc] = more ? ex[t][c] + an[t] * v : v;
       }
     }
     __syncthreads();

@@ -738,17 +738,17 @@ double residual(td_plan_s* P, const double* F, int64_t ldf, const double* X, int
 td_status solve_impl(td_plan_s* P, const double* F, int64_t ldf, double* X, int64_t ldx, int64_t K,
                      const td_refine* rf, td_info* info, hipStream_t st) {
   const int64_t n = P->N * P->M;
-  if (!F || !X) return fail(TD_EINVAL, "null F or X");
   if (K < 0 || ldf < n || ldx < n) return fail(TD_EINVAL, "K < 0 or leading dimension below N*M");
   if (K > INT_MAX / 2) return fail(TD_EINVAL, "K too large");
-  // overlap check of the column ranges
-  const char* f0 = (const char*)F;
-  const char* f1 = (const char*)(F + (K ? (K - 1) * ldf + n : 0));
-  const char* x0 = (const char*)X;
-  const char* x1 = (const char*)(X + (K ? (K - 1) * ldx + n : 0));
-  if (K > 0 && f0 < x1 && x0 < f1) return fail(TD_EINVAL, "X overlaps F");
   if (info) { info->iterations = 0; info->nonfinite = 0; info->max_col_rel_residual = -1.0; }
   if (K == 0) return TD_OK;
+  if (!F || !X) return fail(TD_EINVAL, "null F or X");
+  // overlap check of the column ranges
+  const char* f0 = (const char*)F;
+  const char* f1 = (const char*)(F + (K - 1) * ldf + n);
+  const char* x0 = (const char*)X;
+  const char* x1 = (const char*)(X + (K - 1) * ldx + n);
+  if (f0 < x1 && x0 < f1) return fail(TD_EINVAL, "X overlaps F");
   P->last_stream = st;
   P->se = nullptr;
   if (P->prof && P->prof_n < 4096) {
