@@ -60,6 +60,17 @@ struct SweepArgs {
   int32_t N, M, Mp, p, K, ncoltiles, total;
 };
 
+// Superposition, eq. (superposition): X_i = W_i + U_i X_{k_s} + V_i X_{k_{s+1}} for the interior rows.
+struct SupArgs {
+  const int64_t* ks;     // p + 1 interface rows
+  const double* UV;      // U_i = UV + 2*i*Mp*Mp (Mp x 2Mp col-major, V_i in the second half)
+  const double* Xi;      // interface values, ((p+2)*Mp) x K: block s+1 holds X_{k_s}, blocks 0 and p+1 are 0
+  int64_t ldxi;
+  const double* W; int64_t ldw;
+  double* X; int64_t ldx;
+  int32_t N, M, Mp, p, K, ncoltiles, total;
+};
+
 // Batched Gauss-Jordan inversion with partial pivoting.
 struct GJArgs {
   double* work;          // matrix q (Mp x Mp col-major, destroyed) at work + work_off[q],
@@ -78,6 +89,7 @@ struct GJArgs {
 // Launch wrappers (kernels_f64.hip)
 hipError_t launch_bgemm(const BArgs& a, hipStream_t st);
 hipError_t launch_sweep(const SweepArgs& a, hipStream_t st);
+hipError_t launch_superpose(const SupArgs& a, hipStream_t st);
 hipError_t launch_gj(const GJArgs& a, hipStream_t st);
 int bgemm_coltile(int ncols);    // columns per work-group chosen for ncols
 int sweep_coltile(int Mp, int K);

@@ -359,6 +359,144 @@ hipError_t launch_sweep(const SweepArgs& a, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
+// Superposition, eq. (superposition): X_i = W_i + [U_i V_i] [X_{k_s}; X_{k_{s+1}}].
+// One work-group owns (subdomain s, 4*CT columns): the 2Mp x 4*CT interface panel
+// stays in LDS for all interior rows of s, and the Mp x 2Mp matrices [U_i V_i]
+// stream through registers one chunk ahead of the MFMAs, across row boundaries,
+// so the work-group runs its rows back to back without barriers.
+// ---------------------------------------------------------------------------
+template <int RT, int CT>
+__global__ void __launch_bounds__(512) k_superpose_f64(SupArgs a) {
+  constexpr int KT = 4 * CT;
+  constexpr int SB = KT + 2;
+  extern __shared__ double Xs[];  // [2 Mp][SB]
+
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int L = tid & 63, w = tid >> 6;
+  const int lg = xcd_remap(blockIdx.x, gridDim.x);
+  if (lg >= a.total) return;
+  const int s = lg / a.ncoltiles;
+  const int ct = lg - s * a.ncoltiles;
+  const int col0 = ct * KT;
+  const int64_t first = a.ks[s] + 1, last = a.ks[s + 1] - 1;
+  if (first > last) return;
+  const int Mp = a.Mp, M = a.M, K = a.K;
+  const int rb = w * 16 * RT;
+  const int64_t MM = (int64_t)Mp * Mp;
+  const int kd = 2 * Mp;
+  const int nkc = kd / 8;  // chunks of 2 MFMA k-steps; even
+
+  for (int e = tid; e < kd * KT; e += nthr) {
+    const int k = e % kd, c = e / kd;
+    const int col = col0 + c;
+    Xs[k * SB + c] = (col < K) ? a.Xi[(int64_t)(s + 1) * Mp + k + (int64_t)col * a.ldxi] : 0.0;
+  }
+
+  const int64_t lane_off = rb + (L & 15) + (int64_t)(L >> 4) * Mp;
+  double a0[2][RT], a1[2][RT];
+  auto loadA = [&](double (&dst)[2][RT], const double* __restrict__ Ab, int q) {
+    const double* __restrict__ pa = Ab + lane_off + (int64_t)(8 * q) * Mp;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int t = 0; t < RT; ++t) dst[u][t] = pa[16 * t + (int64_t)(4 * u) * Mp];
+  };
+  double acc[RT][CT];
+  auto compute = [&](const double (&av)[2][RT], int q) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const double* bp = &Xs[(8 * q + 4 * u + (L >> 4)) * SB + (L & 3) * CT];
+      double b[CT];
+#pragma unroll
+      for (int c = 0; c < CT; ++c) b[c] = bp[c];
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[t][c] = mfma4(av[u][t], b[c], acc[t][c]);
+    }
+  };
+
+  loadA(a0, a.UV + 2 * first * MM, 0);
+  __syncthreads();
+  for (int64_t i = first; i <= last; ++i) {
+    const double* __restrict__ Ai = a.UV + 2 * i * MM;
+    const double* __restrict__ Anx = (i < last) ? Ai + 2 * MM : Ai;
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int c = 0; c < CT; ++c) acc[t][c] = 0.0;
+    for (int kc = 0; kc < nkc - 2; kc += 2) {
+      loadA(a1, Ai, kc + 1);
+      compute(a0, kc);
+      loadA(a0, Ai, kc + 2);
+      compute(a1, kc + 1);
+    }
+    double ex[RT][CT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int row = rb + 16 * t + out_row(L);
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const int col = col0 + out_col(L) * CT + c;
+        ex[t][c] = (col < K) ? a.W[i * Mp + row + (int64_t)col * a.ldw] : 0.0;
+      }
+    }
+    loadA(a1, Ai, nkc - 1);
+    compute(a0, nkc - 2);
+    loadA(a0, Anx, 0);
+    compute(a1, nkc - 1);
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int row = rb + 16 * t + out_row(L);
+      if (row < M) {
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+          const int col = col0 + out_col(L) * CT + c;
+          if (col < K) a.X[i * M + row + (int64_t)col * a.ldx] = acc[t][c] + ex[t][c];
+        }
+      }
+    }
+  }
+}
+
+template <int RT, int CT>
+static hipError_t launch_superpose_cfg(const SupArgs& a0, hipStream_t st) {
+  SupArgs a = a0;
+  constexpr int kt = 4 * CT;
+  a.ncoltiles = (a.K + kt - 1) / kt;
+  a.total = a.p * a.ncoltiles;
+  if (a.total == 0) return hipSuccess;
+  const int nthr = a.Mp / (16 * RT) * 64;
+  const size_t lds = (size_t)2 * a.Mp * (kt + 2) * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void*)k_superpose_f64<RT, CT>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_superpose_f64<RT, CT>), dim3(grid_pad8(a.total)), dim3(nthr), lds, st, a);
+  return hipGetLastError();
+}
+
+template <int RT>
+static hipError_t launch_superpose_rt(const SupArgs& a, hipStream_t st) {
+  // the LDS panel is 2 Mp x (4 CT + 2) doubles and must fit in 160 KB
+  const int64_t bytes8 = (int64_t)2 * a.Mp * 34 * 8;
+  if (a.K <= 8) return launch_superpose_cfg<RT, 2>(a, st);
+  if (a.K <= 16 || bytes8 > 160 * 1024 || RT == 4) return launch_superpose_cfg<RT, 4>(a, st);
+  return launch_superpose_cfg<RT, (RT == 4 ? 4 : 8)>(a, st);
+}
+
+hipError_t launch_superpose(const SupArgs& a, hipStream_t st) {
+  // twice the waves of the other kernels where that keeps at most 8 waves per work-group
+  int rt = choose_rt(a.Mp);
+  const int nw = a.Mp / (16 * rt);
+  if (rt >= 2 && 2 * nw <= 8) rt /= 2;
+  switch (rt) {
+    case 4: return launch_superpose_rt<4>(a, st);
+    case 2: return launch_superpose_rt<2>(a, st);
+    default: return launch_superpose_rt<1>(a, st);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Batched Gauss-Jordan inversion with partial pivoting (row interchanges chosen
 // by the largest remaining entry of each column; ties go to the lowest row).
 // One work-group per matrix.  Columns are processed in panels of NB: the panel

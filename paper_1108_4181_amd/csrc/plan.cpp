@@ -68,7 +68,6 @@ struct td_plan_s {
   int depth = 0;
   int nchunks = 0;
   // solve descriptors (device)
-  BDesc* d_sup = nullptr; int n_sup = 0;
   BDesc* d_part = nullptr; int n_part = 0;
   BDesc* d_corr = nullptr; std::vector<int> corr_begin, corr_count;
   // workspace
@@ -568,20 +567,6 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
 
   // ---- descriptors of the solve
   {
-    std::vector<BDesc> sup;
-    for (int64_t s = 0; s < p; ++s)
-      for (int64_t i = ks[s] + 1; i < ks[s + 1]; ++i) {
-        BDesc d = desc0();
-        d.a_off = (2 + 2 * i) * MM;             // [U_i | V_i], Mp x 2Mp
-        d.kd = (int32_t)(2 * Mp);
-        d.segrows = (int32_t)(2 * Mp);
-        d.b_off = (s + 1) * Mp;                  // [X_{k_s}; X_{k_{s+1}}] in the padded interface buffer
-        d.cin_off = i * Mp;                      // W_i
-        d.x2_off = i * M;                        // X_i
-        sup.push_back(d);
-      }
-    P->n_sup = (int)sup.size();
-    P->d_sup = P->upload(sup);
     std::vector<BDesc> part;
     for (int n = 0; n < nn; ++n) {
       const Node& nd = nodes[n];
@@ -704,14 +689,14 @@ void solve_pass(td_plan_s* P, const double* F, int64_t ldf, double* X, int64_t l
   }
   stage_mark(P, 4, st);
   {
-    BArgs a = bargs_base((int)Mp);
-    a.descs = P->d_sup; a.nprob = P->n_sup;
-    a.A = P->UVa; a.lda = Mp;
-    a.B = P->Xi; a.ldb = ldxi;
-    a.Cin = P->Wbuf; a.ldcin = ldw;
-    a.X2 = X; a.ldx2 = ldx; a.x2rows = (int32_t)M;
-    a.ncols = (int32_t)K;
-    HIPCHK(launch_bgemm(a, st));
+    SupArgs u;
+    u.ks = P->d_ks; u.UV = P->UVa + 2 * Mp * Mp;
+    u.Xi = P->Xi; u.ldxi = ldxi;
+    u.W = P->Wbuf; u.ldw = ldw;
+    u.X = X; u.ldx = ldx;
+    u.N = (int32_t)N; u.M = (int32_t)M; u.Mp = (int32_t)Mp; u.p = (int32_t)p; u.K = (int32_t)K;
+    u.ncoltiles = 0; u.total = 0;
+    HIPCHK(launch_superpose(u, st));
   }
   stage_mark(P, 5, st);
 }
