@@ -122,6 +122,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=0, help="block rows of the oracle sample (0 = all)")
     ap.add_argument("--cpu-cols", type=int, default=128, help="right-hand sides of the oracle sample")
+    ap.add_argument("--mixed", default="f32,bf16",
+                    help="low-precision sweep types to time with float64 refinement ('' = none)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="bytes of a plain device-to-device copy run before the timed region (counter calibration)")
     args = ap.parse_args()
@@ -212,6 +214,36 @@ def main():
         "max_col_rel_residual": info["max_col_rel_residual"],
         "plan_device_bytes": pinfo["device_bytes"],
     }
+    # mixed precision + float64 refinement to the same residual bar, same workload
+    mixed = {}
+    for prec in [m for m in args.mixed.split(",") if m]:
+        del plan
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mplan = td.Plan.from_system(sysw, device=dev, subdomains=p, sweep_prec=prec)
+        torch.cuda.synchronize()
+        mfac = (time.perf_counter() - t0) * 1e3
+        ref = {"tol": 1e-10, "max_iter": 20}
+        _, minfo = mplan.solve(F, X, refine=ref, info=True)
+        for _ in range(args.warmup):
+            mplan.solve(F, X, refine=ref)
+        mplan.set_profiling(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            mplan.solve(F, X, refine=ref)
+        torch.cuda.synchronize()
+        mel = time.perf_counter() - t0
+        mst = mplan.stage_times()
+        mms = mel * 1e3 / args.steps
+        mixed[prec] = {"value": K / (mms / 1e3), "unit": "RHS/s", "ms_per_step": mms,
+                       "speedup_vs_f64": ms_per_step / mms, "iterations": minfo["iterations"],
+                       "max_col_rel_residual": minfo["max_col_rel_residual"], "factor_ms": mfac,
+                       "first_pass_stages_ms": {k: v for k, v in mst.items() if k != "count"}}
+        mplan.close()
+        del mplan
+        plan = None
+    out["mixed_refined"] = mixed
     if not args.no_cpu_baseline:
         import oracle
 

@@ -39,6 +39,8 @@ struct BArgs {
   int32_t ncoltiles;
   int32_t total;      // nprob * ncoltiles
   int32_t x2rows;
+  int32_t x2accum;    // nonzero: X2 += result instead of X2 = result
+  int32_t pad_;
   double alpha;
   const double* A; int64_t lda;
   const double* B; int64_t ldb;
@@ -68,7 +70,28 @@ struct SupArgs {
   int64_t ldxi;
   const double* W; int64_t ldw;
   double* X; int64_t ldx;
+  int32_t N, M, Mp, p, K, ncoltiles, total, accumulate;  // accumulate: X += result
+};
+
+// Low-precision sweeps (PREC 1 = float32, 2 = bfloat16): matrices row-major in that type,
+// beta / W in float32 (the workspace), right-hand side in float64.
+struct LpSweepArgs {
+  const int64_t* ks;
+  const void* Dinv;      // [N][Mp][Mp] row-major
+  const void* alpha;     // [N][Mp][Mp] row-major
+  const double* adiag;
+  const double* F; int64_t ldf;
+  float* W; int64_t ldw;
   int32_t N, M, Mp, p, K, ncoltiles, total;
+};
+
+struct LpSupArgs {
+  const int64_t* ks;
+  const void* UV;        // U_0 base, [U_i V_i] row-major Mp x 2Mp at UV + i * 2 Mp^2
+  const double* Xi; int64_t ldxi;
+  const float* W; int64_t ldw;
+  double* X; int64_t ldx;
+  int32_t N, M, Mp, p, K, ncoltiles, total, accumulate;
 };
 
 // Batched Gauss-Jordan inversion with partial pivoting.
@@ -123,5 +146,18 @@ hipError_t launch_axpy_cols(double* X, int64_t ldx, const double* D, int64_t ldd
 hipError_t launch_diag_grad(double* out, const double* Lam, int64_t ldl, const double* X, int64_t ldx,
                             int64_t n, int K, hipStream_t st);
 hipError_t launch_nonfinite(int32_t* flag, const double* X, int64_t ldx, int64_t n, int K, hipStream_t st);
+
+// Low-precision path (kernels_lp.hip)
+hipError_t launch_cast_rowmajor(int prec, void* dst, int64_t dstride, const double* src, int64_t sstride,
+                                const int64_t* list, int nmat, int rows, int cols, hipStream_t st);
+hipError_t launch_sweep_lp(int prec, const LpSweepArgs& a, hipStream_t st);
+hipError_t launch_superpose_lp(int prec, const LpSupArgs& a, hipStream_t st);
+hipError_t launch_ftilde_f32(double* Ft, int64_t ldft, const double* F, int64_t ldf, const float* W, int64_t ldw,
+                             const int64_t* ks, const double* adiag, const double* bdiag, int p, int M, int Mp, int K,
+                             hipStream_t st);
+int residual_chunks(int64_t n);
+hipError_t launch_residual_stencil(double* R, int64_t ldr, const double* F, int64_t ldf, const double* X, int64_t ldx,
+                                   const double* A, const double* B, const double* C, int N, int M, int K,
+                                   double* colpart, hipStream_t st);
 
 }  // namespace td

@@ -150,7 +150,10 @@ __global__ void __launch_bounds__(512) k_bgemm(BArgs args) {
         if (args.Cin) v += args.Cin[d.cin_off + row + (int64_t)col * args.ldcin];
         for (int s = 0; s < d.nsp; ++s) v += args.Sp[d.sp_off + s * args.spstride + row + (int64_t)col * args.ldsp];
         if (args.C) args.C[d.c_off + row + (int64_t)col * args.ldc] = v;
-        if (args.X2 && row < args.x2rows) args.X2[d.x2_off + row + (int64_t)col * args.ldx2] = v;
+        if (args.X2 && row < args.x2rows) {
+          double* xp = args.X2 + d.x2_off + row + (int64_t)col * args.ldx2;
+          *xp = args.x2accum ? *xp + v : v;
+        }
       }
     }
   }
@@ -452,7 +455,11 @@ __global__ void __launch_bounds__(512) k_superpose_f64(SupArgs a) {
 #pragma unroll
         for (int c = 0; c < CT; ++c) {
           const int col = col0 + out_col(L) * CT + c;
-          if (col < K) a.X[i * M + row + (int64_t)col * a.ldx] = acc[t][c] + ex[t][c];
+          if (col < K) {
+            double* xp = a.X + i * M + row + (int64_t)col * a.ldx;
+            const double d = acc[t][c] + ex[t][c];
+            *xp = a.accumulate ? *xp + d : d;
+          }
         }
       }
     }

@@ -73,8 +73,12 @@ struct td_plan_s {
   // workspace
   int64_t kcap = 0;
   double* Wbuf = nullptr; double* Ft = nullptr; double* Xi = nullptr; double* Sp = nullptr;
+  float* W32 = nullptr;       // float32 beta / W of the low-precision sweeps
   int64_t rcap = 0;
-  double* Rbuf = nullptr; double* Dbuf = nullptr; double* colpart = nullptr; double* norms = nullptr;
+  double* Rbuf = nullptr; double* colpart = nullptr; double* norms = nullptr;
+  // low-precision copies of the factor (sweep_prec F32 / BF16), row-major
+  void* Dlp = nullptr; void* Alp = nullptr; void* UVlp = nullptr;
+  bool first_pass = false;
   int32_t* d_flag = nullptr;
   td_plan_s* adj = nullptr;
   bool prof = false;
@@ -121,10 +125,13 @@ struct td_plan_s {
 namespace {
 
 // Block size padded for the kernels' wave tiling: at most 8 waves of 16, 32 or 64 rows each.
-int64_t pad_block(int64_t m) {
-  if (m <= 128) return (m + 15) / 16 * 16;
-  if (m <= 256) return (m + 31) / 32 * 32;
-  return (m + 63) / 64 * 64;
+int64_t pad_block(int64_t m, int prec) {
+  int64_t mp;
+  if (m <= 128) mp = (m + 15) / 16 * 16;
+  else if (m <= 256) mp = (m + 31) / 32 * 32;
+  else mp = (m + 63) / 64 * 64;
+  if (prec == TD_PREC_BF16 && mp % 32 != 0) mp += 16;  // bfloat16 k-groups are 32 deep
+  return mp;
 }
 
 std::vector<int64_t> partition(int64_t N, int64_t p) {
@@ -623,9 +630,13 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
 void ensure_workspace(td_plan_s* P, int64_t K, hipStream_t st) {
   if (K <= P->kcap) return;
   const int64_t N = P->N, Mp = P->Mp, p = P->p;
-  P->release(P->Wbuf); P->release(P->Ft); P->release(P->Xi); P->release(P->Sp);
+  P->release(P->Wbuf); P->release(P->W32); P->release(P->Ft); P->release(P->Xi); P->release(P->Sp);
   P->Wbuf = P->Ft = P->Xi = P->Sp = nullptr;
-  P->Wbuf = P->alloc(N * Mp * K);
+  P->W32 = nullptr;
+  if (P->prec == TD_PREC_F64)
+    P->Wbuf = P->alloc(N * Mp * K);
+  else
+    P->W32 = (float*)P->alloc((N * Mp * K + 1) / 2);
   P->Ft = P->alloc(p * Mp * K);
   P->Xi = P->alloc((p + 2) * Mp * K);
   P->Sp = P->alloc((int64_t)P->nchunks * Mp * K);
@@ -633,37 +644,60 @@ void ensure_workspace(td_plan_s* P, int64_t K, hipStream_t st) {
   P->kcap = K;
 }
 
+bool stencil_formats(const td_plan_s* P) {
+  return P->fmtA == TD_FMT_DIAG && P->fmtB == TD_FMT_DIAG && P->fmtC == TD_FMT_TRIDIAG;
+}
+
+int residual_parts(const td_plan_s* P) {
+  return stencil_formats(P) ? residual_chunks(P->N * P->M) : (int)P->N;
+}
+
 void ensure_refine_ws(td_plan_s* P, int64_t K) {
   if (K <= P->rcap) return;
   const int64_t n = P->N * P->M;
-  P->release(P->Rbuf); P->release(P->Dbuf); P->release(P->colpart); P->release(P->norms);
+  P->release(P->Rbuf); P->release(P->colpart); P->release(P->norms);
   P->Rbuf = P->alloc(n * K);
-  P->Dbuf = P->alloc(n * K);
-  P->colpart = P->alloc(P->N * K * 2);
+  P->colpart = P->alloc((int64_t)residual_parts(P) * K * 2);
   P->norms = P->alloc(2 * K);
   P->rcap = K;
 }
 
+// stage boundaries are recorded for the first pass of a solve only
 void stage_mark(td_plan_s* P, int idx, hipStream_t st) {
-  if (!P->prof || !P->se) return;
+  if (!P->prof || !P->se || !P->first_pass) return;
   HIPCHK(hipEventRecord(P->se->ev[idx], st));
 }
 
-// One pass of Algorithm 2, step 2 (float64): eq. (sub3) sweeps, eq. (red1) right-hand side,
-// Algorithm 1 on the reduced system, eq. (superposition).
-void solve_pass(td_plan_s* P, const double* F, int64_t ldf, double* X, int64_t ldx, int64_t K, hipStream_t st) {
+// One pass of Algorithm 2, step 2: eq. (sub3) sweeps, eq. (red1) right-hand side, Algorithm 1 on
+// the reduced system, eq. (superposition).  The sweeps and the superposition run in the plan's
+// precision (float64, or float32 / bfloat16 with float32 accumulation); the reduced system always
+// in float64.  With `accumulate` the result is added to X (a refinement correction).
+void solve_pass(td_plan_s* P, const double* F, int64_t ldf, double* X, int64_t ldx, int64_t K, bool accumulate,
+                hipStream_t st) {
   const int64_t N = P->N, M = P->M, Mp = P->Mp, p = P->p;
   const int64_t ldw = N * Mp, ldft = p * Mp, ldxi = (p + 2) * Mp, ldsp = (int64_t)P->nchunks * Mp;
   stage_mark(P, 0, st);
-  SweepArgs sa;
-  sa.ks = P->d_ks; sa.Dinv = P->Dinv; sa.alpha = P->alpha; sa.adiag = P->adiag;
-  sa.F = F; sa.ldf = ldf; sa.W = P->Wbuf; sa.ldw = ldw;
-  sa.N = (int32_t)N; sa.M = (int32_t)M; sa.Mp = (int32_t)Mp; sa.p = (int32_t)p; sa.K = (int32_t)K;
-  sa.ncoltiles = 0; sa.total = 0;
-  HIPCHK(launch_sweep(sa, st));
-  stage_mark(P, 1, st);
-  HIPCHK(launch_ftilde(P->Ft, ldft, F, ldf, P->Wbuf, ldw, P->d_ks, P->adiag, P->bdiag, (int)p, (int)M, (int)Mp,
-                       (int)K, st));
+  if (P->prec == TD_PREC_F64) {
+    SweepArgs sa;
+    sa.ks = P->d_ks; sa.Dinv = P->Dinv; sa.alpha = P->alpha; sa.adiag = P->adiag;
+    sa.F = F; sa.ldf = ldf; sa.W = P->Wbuf; sa.ldw = ldw;
+    sa.N = (int32_t)N; sa.M = (int32_t)M; sa.Mp = (int32_t)Mp; sa.p = (int32_t)p; sa.K = (int32_t)K;
+    sa.ncoltiles = 0; sa.total = 0;
+    HIPCHK(launch_sweep(sa, st));
+    stage_mark(P, 1, st);
+    HIPCHK(launch_ftilde(P->Ft, ldft, F, ldf, P->Wbuf, ldw, P->d_ks, P->adiag, P->bdiag, (int)p, (int)M, (int)Mp,
+                         (int)K, st));
+  } else {
+    LpSweepArgs sa;
+    sa.ks = P->d_ks; sa.Dinv = P->Dlp; sa.alpha = P->Alp; sa.adiag = P->adiag;
+    sa.F = F; sa.ldf = ldf; sa.W = P->W32; sa.ldw = ldw;
+    sa.N = (int32_t)N; sa.M = (int32_t)M; sa.Mp = (int32_t)Mp; sa.p = (int32_t)p; sa.K = (int32_t)K;
+    sa.ncoltiles = 0; sa.total = 0;
+    HIPCHK(launch_sweep_lp(P->prec, sa, st));
+    stage_mark(P, 1, st);
+    HIPCHK(launch_ftilde_f32(P->Ft, ldft, F, ldf, P->W32, ldw, P->d_ks, P->adiag, P->bdiag, (int)p, (int)M,
+                             (int)Mp, (int)K, st));
+  }
   stage_mark(P, 2, st);
   {
     BArgs a = bargs_base((int)Mp);
@@ -683,31 +717,46 @@ void solve_pass(td_plan_s* P, const double* F, int64_t ldf, double* X, int64_t l
     a.B = P->Xi; a.ldb = ldxi;
     a.Sp = P->Sp; a.ldsp = ldsp; a.spstride = Mp;
     a.C = P->Xi; a.ldc = ldxi;
-    a.X2 = X; a.ldx2 = ldx; a.x2rows = (int32_t)M;
+    a.X2 = X; a.ldx2 = ldx; a.x2rows = (int32_t)M; a.x2accum = accumulate ? 1 : 0;
     a.ncols = (int32_t)K;
     HIPCHK(launch_bgemm(a, st));
   }
   stage_mark(P, 4, st);
-  {
+  if (P->prec == TD_PREC_F64) {
     SupArgs u;
     u.ks = P->d_ks; u.UV = P->UVa + 2 * Mp * Mp;
     u.Xi = P->Xi; u.ldxi = ldxi;
     u.W = P->Wbuf; u.ldw = ldw;
     u.X = X; u.ldx = ldx;
     u.N = (int32_t)N; u.M = (int32_t)M; u.Mp = (int32_t)Mp; u.p = (int32_t)p; u.K = (int32_t)K;
-    u.ncoltiles = 0; u.total = 0;
+    u.ncoltiles = 0; u.total = 0; u.accumulate = accumulate ? 1 : 0;
     HIPCHK(launch_superpose(u, st));
+  } else {
+    LpSupArgs u;
+    u.ks = P->d_ks; u.UV = P->UVlp;
+    u.Xi = P->Xi; u.ldxi = ldxi;
+    u.W = P->W32; u.ldw = ldw;
+    u.X = X; u.ldx = ldx;
+    u.N = (int32_t)N; u.M = (int32_t)M; u.Mp = (int32_t)Mp; u.p = (int32_t)p; u.K = (int32_t)K;
+    u.ncoltiles = 0; u.total = 0; u.accumulate = accumulate ? 1 : 0;
+    HIPCHK(launch_superpose_lp(P->prec, u, st));
   }
   stage_mark(P, 5, st);
+  P->first_pass = false;
 }
 
 // max over columns of ||F - P X|| / ||F||; R (if non-null) receives F - P X.  Synchronises.
 double residual(td_plan_s* P, const double* F, int64_t ldf, const double* X, int64_t ldx, int64_t K, double* R,
                 int64_t ldr, std::vector<double>& nrm, hipStream_t st) {
   ensure_refine_ws(P, K);
-  HIPCHK(launch_residual(R, ldr, F, ldf, X, ldx, P->cA, P->fmtA, P->cB, P->fmtB, P->cC, P->fmtC, (int)P->N,
-                         (int)P->M, (int)K, P->colpart, (int)P->N, st));
-  HIPCHK(launch_colnorm_finish(P->norms, P->colpart, (int)P->N, (int)K, st));
+  const int nparts = residual_parts(P);
+  if (stencil_formats(P))
+    HIPCHK(launch_residual_stencil(R, ldr, F, ldf, X, ldx, P->cA, P->cB, P->cC, (int)P->N, (int)P->M, (int)K,
+                                   P->colpart, st));
+  else
+    HIPCHK(launch_residual(R, ldr, F, ldf, X, ldx, P->cA, P->fmtA, P->cB, P->fmtB, P->cC, P->fmtC, (int)P->N,
+                           (int)P->M, (int)K, P->colpart, nparts, st));
+  HIPCHK(launch_colnorm_finish(P->norms, P->colpart, nparts, (int)K, st));
   nrm.resize(2 * K);
   HIPCHK(hipMemcpyAsync(nrm.data(), P->norms, 2 * K * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -746,7 +795,8 @@ td_status solve_impl(td_plan_s* P, const double* F, int64_t ldf, double* X, int6
   }
   ensure_workspace(P, K, st);
   if (P->se) HIPCHK(hipEventRecord(P->se->ev[6], st));
-  solve_pass(P, F, ldf, X, ldx, K, st);
+  P->first_pass = true;
+  solve_pass(P, F, ldf, X, ldx, K, false, st);
   const bool refine = rf && rf->enable;
   td_status status = TD_OK;
   if (refine || info) {
@@ -758,10 +808,10 @@ td_status solve_impl(td_plan_s* P, const double* F, int64_t ldf, double* X, int6
     int it = 0;
     while (refine && !(res <= tol)) {
       if (it >= maxit || !std::isfinite(res)) { status = TD_ENOCONV; break; }
-      // X += ||r|| * S(r / ||r||), column by column
-      HIPCHK(launch_scale_cols(P->Rbuf, n, P->Rbuf, n, P->norms, 1, n, (int)K, st));
-      solve_pass(P, P->Rbuf, n, P->Dbuf, n, K, st);
-      HIPCHK(launch_axpy_cols(X, ldx, P->Dbuf, n, P->norms, n, (int)K, st));
+      // X += S(F - P X): the correction pass adds its result to X.  The residual is not
+      // rescaled: for the relative residuals reached here its entries stay far above the
+      // smallest normal float32 / bfloat16 number (about 1e-38).
+      solve_pass(P, P->Rbuf, n, X, ldx, K, true, st);
       ++it;
       res = residual(P, F, ldf, X, ldx, K, P->Rbuf, n, nrm, st);
     }
@@ -799,8 +849,8 @@ td_status check_desc(const td_desc* d) {
 }
 
 // device bytes the factor needs at its peak (checked against free memory before allocating)
-int64_t factor_bytes(int64_t N, int64_t M, int64_t p, int fA, int fB, int fC) {
-  const int64_t Mp = pad_block(M), MM = Mp * Mp;
+int64_t factor_bytes(int64_t N, int64_t M, int64_t p, int fA, int fB, int fC, int prec) {
+  const int64_t Mp = pad_block(M, prec), MM = Mp * Mp;
   int64_t depth = 0;
   for (int64_t q = p; q > 0; q >>= 1) ++depth;
   int64_t b = 0;
@@ -809,6 +859,7 @@ int64_t factor_bytes(int64_t N, int64_t M, int64_t p, int fA, int fB, int fC) {
   b += N * MM * 2 + (2 + 2 * N) * MM;     // Dinv, alpha, UV
   b += (1 + N) * MM + p * MM;              // Gamma arena, Dwork (temporary)
   b += 3 * p * MM + p * (depth + 1) * MM + 2 * p * MM + (1 + 6 * p) * MM + p * MM;  // reduced, G, H, arenas
+  if (prec != TD_PREC_F64) b += (4 * N * MM * (prec == TD_PREC_F32 ? 4 : 2) + 7) / 8;  // rounded copies
   return b * 8;
 }
 
@@ -847,6 +898,32 @@ void transpose_inputs(const td_plan_s* P, std::vector<double>& A2, std::vector<d
   }
 }
 
+// Rounded copies of D^{-1}, alpha and [U V] for the low-precision sweeps and superposition
+// (row-major, k contiguous); the float64 originals are then released.
+void make_lowprec(td_plan_s* P, hipStream_t st) {
+  const int64_t N = P->N, Mp = P->Mp, MM = Mp * Mp;
+  const int64_t esz = (P->prec == TD_PREC_F32) ? 4 : 2;
+  std::vector<int64_t> rows;
+  for (int64_t s = 0; s < P->p; ++s)
+    for (int64_t i = P->ks[s] + 1; i < P->ks[s + 1]; ++i) rows.push_back(i);
+  if (rows.empty()) rows.push_back(0);
+  DescPool pool;
+  int64_t* d_rows = pool.put_vec(rows);
+  const int nm = (int)rows.size();
+  P->Dlp = P->alloc((N * MM * esz + 7) / 8);
+  P->Alp = P->alloc((N * MM * esz + 7) / 8);
+  P->UVlp = P->alloc((N * 2 * MM * esz + 7) / 8);
+  HIPCHK(launch_cast_rowmajor(P->prec, P->Dlp, MM, P->Dinv, MM, d_rows, nm, (int)Mp, (int)Mp, st));
+  HIPCHK(launch_cast_rowmajor(P->prec, P->Alp, MM, P->alpha, MM, d_rows, nm, (int)Mp, (int)Mp, st));
+  HIPCHK(launch_cast_rowmajor(P->prec, P->UVlp, 2 * MM, P->UVa + 2 * MM, 2 * MM, d_rows, nm, (int)Mp, (int)(2 * Mp),
+                              st));
+  HIPCHK(hipStreamSynchronize(st));
+  P->release(P->Dinv);
+  P->release(P->alpha);
+  P->release(P->UVa);
+  P->Dinv = P->alpha = P->UVa = nullptr;
+}
+
 td_status factor_top(const td_desc* d, const double* A, const double* B, const double* C, hipStream_t st,
                      td_plan* out, bool allow_adjoint) {
   td_status s = check_desc(d);
@@ -854,7 +931,7 @@ td_status factor_top(const td_desc* d, const double* A, const double* B, const d
   if (!A || !B || !C) return fail(TD_EINVAL, "null A, B or C");
   const auto t0 = std::chrono::steady_clock::now();
   td_plan_s* P = new td_plan_s();
-  P->N = d->N; P->M = d->M; P->Mp = pad_block(d->M);
+  P->N = d->N; P->M = d->M; P->Mp = pad_block(d->M, d->sweep_prec);
   P->p = d->subdomains ? d->subdomains : choose_p(d->N);
   P->fmtA = d->fmt_A; P->fmtB = d->fmt_B; P->fmtC = d->fmt_C;
   P->prec = d->sweep_prec; P->adjoint = d->adjoint;
@@ -862,12 +939,13 @@ td_status factor_top(const td_desc* d, const double* A, const double* B, const d
   try {
     size_t freeb = 0, totb = 0;
     HIPCHK(hipMemGetInfo(&freeb, &totb));
-    const int64_t need = factor_bytes(P->N, P->M, P->p, P->fmtA, P->fmtB, P->fmtC);
+    const int64_t need = factor_bytes(P->N, P->M, P->p, P->fmtA, P->fmtB, P->fmtC, P->prec);
     if ((double)need > 0.95 * (double)freeb) {
       delete P;
       return fail(TD_ENOMEM, "factor needs " + std::to_string(need) + " bytes, " + std::to_string(freeb) + " free");
     }
     factor_impl(P, A, B, C, st);
+    if (P->prec != TD_PREC_F64) make_lowprec(P, st);
     if (d->adjoint && allow_adjoint) {
       std::vector<double> A2, B2, C2;
       transpose_inputs(P, A2, B2, C2);
