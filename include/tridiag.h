@@ -161,6 +161,27 @@ td_status tridiag_plan_info(td_plan plan, td_plan_info* out);
 td_status tridiag_set_profiling(td_plan plan, int enable);
 td_status tridiag_stage_times(td_plan plan, double* ms, int n);
 
+/*
+ * Batched solve of many independent systems (not in the paper): one persistent launch over
+ * a work list of all systems' stages, captured once in a HIP graph and replayed by
+ * tridiag_batch_solve.  Each pass solves every system (pass 0 with F, later passes with the
+ * float64 residual, adding the correction to X); a system that has reached `tol` skips the
+ * remaining passes.  The plans must have sweep_prec TD_PREC_F32, diagonal A and B,
+ * tridiagonal C and padded block sizes 64, 128 or 256; they must outlive the batch, and the
+ * F / X buffers given here are the ones every replay reads and writes (device pointers, one
+ * per system, column-major N_q*M_q x K_q).  Calls that share a plan's workspace must not
+ * overlap.  tridiag_batch_info synchronises and reports, per system, the passes used after the
+ * first (iterations) and the final max column relative residual; it returns TD_ENOCONV if
+ * a system did not reach `tol`, TD_EHIP if a dependency wait inside the launch timed out.
+ */
+typedef struct td_batch_s* td_batch;
+td_status tridiag_batch_create(int n, const td_plan* plans, const double* const* F, const int64_t* ldf,
+                               double* const* X, const int64_t* ldx, const int64_t* K, int passes, double tol,
+                               void* stream, td_batch* out);
+td_status tridiag_batch_solve(td_batch batch, void* stream);
+td_status tridiag_batch_info(td_batch batch, td_info* infos);
+td_status tridiag_batch_destroy(td_batch batch);
+
 const char* tridiag_status_string(td_status s);
 /* Text of the last error on the calling host thread ("" if none). */
 const char* tridiag_last_error(void);

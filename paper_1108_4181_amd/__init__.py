@@ -56,7 +56,8 @@ class _PlanInfo(ctypes.Structure):
 # every symbol the header declares
 EXPORTS = ["tridiag_factor", "tridiag_solve", "tridiag_solve_adjoint", "tridiag_diag_grad", "tridiag_destroy",
            "tridiag_plan_info", "tridiag_set_profiling", "tridiag_stage_times", "tridiag_status_string",
-           "tridiag_last_error"]
+           "tridiag_last_error", "tridiag_batch_create", "tridiag_batch_solve", "tridiag_batch_info",
+           "tridiag_batch_destroy"]
 
 _lib = None
 
@@ -90,6 +91,17 @@ def load_library(path: str = LIB_PATH):
     lib.tridiag_status_string.restype = ctypes.c_char_p
     lib.tridiag_last_error.argtypes = []
     lib.tridiag_last_error.restype = ctypes.c_char_p
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    pi64 = ctypes.POINTER(ctypes.c_int64)
+    lib.tridiag_batch_create.argtypes = [ctypes.c_int, pp, pp, pi64, pp, pi64, pi64, ctypes.c_int, dp, vp,
+                                         ctypes.POINTER(vp)]
+    lib.tridiag_batch_create.restype = i32
+    lib.tridiag_batch_solve.argtypes = [vp, vp]
+    lib.tridiag_batch_solve.restype = i32
+    lib.tridiag_batch_info.argtypes = [vp, ctypes.POINTER(_Info)]
+    lib.tridiag_batch_info.restype = i32
+    lib.tridiag_batch_destroy.argtypes = [vp]
+    lib.tridiag_batch_destroy.restype = i32
     _lib = lib
     return lib
 
@@ -252,3 +264,60 @@ class ShiftedSolve(torch.autograd.Function):
 
 def shifted_solve(F, sigma, base_C, A, B, subdomains=0, sweep_prec="f64", refine=None):
     return ShiftedSolve.apply(F, sigma, base_C, A, B, subdomains, sweep_prec, refine)
+
+
+class Batch:
+    """Many independent systems solved by one persistent launch replayed from a HIP graph.
+
+    plans: Plan objects factored with sweep_prec="f32"; Fs, Xs: per-system (K_q, N_q*M_q) float64
+    device tensors (the graph reads and writes exactly these buffers on every solve()).
+    passes: solve passes (1 + correction passes); tol: residual bar for the per-system early exit.
+    """
+
+    def __init__(self, plans, Fs, Xs, passes=3, tol=1e-10):
+        self.lib = load_library()
+        n = len(plans)
+        if not (n == len(Fs) == len(Xs)) or n == 0:
+            raise ValueError("plans, Fs and Xs must have the same non-zero length")
+        self._keep = (list(plans), list(Fs), list(Xs))
+        P = (ctypes.c_void_p * n)(*[p.h.value for p in plans])
+        fptr, ldf, K, xptr, ldx = [], [], [], [], []
+        for p, F, X in zip(plans, Fs, Xs):
+            n_ = p.N * p.M
+            a, lf, k = _rhs(F, n_, "F")
+            b, lx, k2 = _rhs(X, n_, "X")
+            if k != k2:
+                raise ValueError("F and X column counts differ")
+            fptr.append(a.value); ldf.append(lf); K.append(k); xptr.append(b.value); ldx.append(lx)
+        self.n = n
+        h = ctypes.c_void_p()
+        code = self.lib.tridiag_batch_create(
+            n, P, (ctypes.c_void_p * n)(*fptr), (ctypes.c_int64 * n)(*ldf), (ctypes.c_void_p * n)(*xptr),
+            (ctypes.c_int64 * n)(*ldx), (ctypes.c_int64 * n)(*K), int(passes), float(tol), _stream(),
+            ctypes.byref(h))
+        _check(code)
+        self.h = h
+
+    def solve(self):
+        _check(self.lib.tridiag_batch_solve(self.h, _stream()))
+
+    def info(self):
+        """Per-system dicts; converged is False for a system that missed tol within the passes."""
+        infos = (_Info * self.n)()
+        code = self.lib.tridiag_batch_info(self.h, infos)
+        if code not in (0, 4):
+            _check(code)
+        return [{"iterations": i.iterations, "max_col_rel_residual": i.max_col_rel_residual,
+                 "nonfinite": i.nonfinite} for i in infos], code == 0
+
+    def close(self):
+        h = getattr(self, "h", None)
+        if h:
+            self.lib.tridiag_batch_destroy(h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

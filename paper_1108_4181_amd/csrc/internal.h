@@ -147,6 +147,54 @@ hipError_t launch_diag_grad(double* out, const double* Lam, int64_t ldl, const d
                             int64_t n, int K, hipStream_t st);
 hipError_t launch_nonfinite(int32_t* flag, const double* X, int64_t ldx, int64_t n, int K, hipStream_t st);
 
+// ---------------------------------------------------------------------------
+// Batched solve of many independent systems in one persistent launch
+// (kernels_batched.hip).  Work items are dequeued in a topological order from one
+// global counter; an item waits (bounded spin) until the counter of the stage it
+// depends on reaches the expected value, runs, and then increments its own counter.
+// ---------------------------------------------------------------------------
+constexpr int BATCH_MAXDEPTH = 16;
+enum { BI_SWEEP = 0, BI_FTILDE = 1, BI_PART = 2, BI_LEVEL = 3, BI_SUP = 4, BI_RES = 5, BI_RFIN = 6 };
+
+struct BatchItem {
+  int32_t type, sys, pass, lvl;
+  int32_t i0, i1;          // sweep/sup: subdomain, column tile; part/level: problem, column tile;
+                           // ftilde: element chunk; res: row chunk, first column
+  int32_t dep;             // counter index this item waits for (-1: none)
+  int32_t need;            // value that counter must reach
+  int32_t mine;            // counter index this item increments
+  int32_t pad_;
+};
+
+struct BatchSys {
+  LpSweepArgs sweep;       // input F; the correction passes read R instead
+  LpSupArgs sup;
+  BArgs part;
+  BArgs lev[BATCH_MAXDEPTH];
+  double* Ft; int64_t ldft;
+  const double* adiag; const double* bdiag;
+  const double* F; int64_t ldf;
+  double* X; int64_t ldx;
+  double* R; int64_t ldr;
+  const double* cA; const double* cB; const double* cC;
+  double* colpart;         // [K][nchunk][2]
+  double* resid;           // [passes]: max column relative residual after each pass
+  int32_t N, M, Mp, p, K, rt, nchunk, rescols;
+  int32_t conv_pass;       // unused on the device (host bookkeeping)
+  int32_t pad_;
+  double tol;
+};
+
+struct BatchCtl {
+  int32_t head;            // next item to dequeue
+  int32_t error;           // nonzero: a dependency wait timed out
+  int32_t pad_[2];
+};
+
+hipError_t launch_batched(const BatchItem* items, int nitems, const BatchSys* sys, int32_t* counters, int ncounters,
+                          int32_t* conv, int nsys, BatchCtl* ctl, int grid, int64_t spin_limit, hipStream_t st);
+int batched_lds_bytes();
+
 // Low-precision path (kernels_lp.hip)
 hipError_t launch_cast_rowmajor(int prec, void* dst, int64_t dstride, const double* src, int64_t sstride,
                                 const int64_t* list, int nmat, int rows, int cols, hipStream_t st);

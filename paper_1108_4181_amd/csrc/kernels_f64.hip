@@ -7,156 +7,23 @@
 // On gfx950 this instruction sustains the full float64 matrix rate, while the
 // 16x16x4 float64 form issues at well under half of it.
 #include "internal.h"
+#include "tile_bodies.h"
 
 #include <cfloat>
 #include <climits>
 
 namespace td {
 
-__device__ __forceinline__ double mfma4(double a, double b, double c) {
-  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ int out_row(int L) { return 4 * ((L >> 2) & 3) + (L >> 4); }
-__device__ __forceinline__ int out_col(int L) { return L & 3; }
-
-// Work-groups are handed to the 8 XCDs of the chip round-robin by blockIdx.  This
-// maps blockIdx so that logical work items [x*per, (x+1)*per) run on XCD x, in
-// order: consecutive logical items (the column tiles of one block row, which read
-// the same matrix) then share that XCD's L2.  gridDim.x is a multiple of 8.
-__device__ __forceinline__ int xcd_remap(int b, int grid) {
-  const int per = grid >> 3;
-  return (b & 7) * per + (b >> 3);
-}
-static inline int grid_pad8(int total) { return (total + 7) & ~7; }
-
-// rows per wave = 16*RT; waves per work-group = Mp / (16*RT)
-static inline int choose_rt(int Mp) {
-  if (Mp >= 256 && Mp % 64 == 0) return 4;
-  if (Mp >= 64 && Mp % 32 == 0) return 2;
-  return 1;
-}
-
 // ---------------------------------------------------------------------------
 // Block GEMM (see BArgs): one work-group = Mp rows x 4*CT columns of one problem.
 // ---------------------------------------------------------------------------
 template <int RT, int CT>
 __global__ void __launch_bounds__(512) k_bgemm(BArgs args) {
-  constexpr int KC = 16;
-  constexpr int KT = 4 * CT;
-  constexpr int SB = KT + 2;
-  constexpr int NSTG = (KC * KT + 63) / 64;
-  __shared__ double Bs[2][KC * SB];
-
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int L = tid & 63, w = tid >> 6;
+  __shared__ double Bs[2 * 16 * (4 * CT + 2)];
   const int lg = xcd_remap(blockIdx.x, gridDim.x);
   if (lg >= args.total) return;
   const int prob = lg / args.ncoltiles;
-  const int ct = lg - prob * args.ncoltiles;
-  const BDesc d = args.descs[prob];
-  const int col0 = ct * KT;
-  const int rb = w * 16 * RT;
-  const double* __restrict__ A = args.A + d.a_off;
-  const int64_t lda = args.lda;
-
-  double acc[RT][CT];
-#pragma unroll
-  for (int t = 0; t < RT; ++t)
-#pragma unroll
-    for (int c = 0; c < CT; ++c) acc[t][c] = 0.0;
-
-  const int nch = d.kd / KC;
-  double stg[NSTG];
-  auto gload = [&](int q) {
-    const int k0 = q * KC;
-    const int seg = k0 / d.segrows;
-    const int kin = k0 - seg * d.segrows;
-    const double* Bq = args.B + d.b_off + (int64_t)seg * d.bseg + kin;
-#pragma unroll
-    for (int u = 0; u < NSTG; ++u) {
-      const int e = tid + u * nthr;
-      double v = 0.0;
-      if (e < KC * KT) {
-        const int k = e % KC, c = e / KC;
-        const int col = col0 + c;
-        if (col < args.ncols) {
-          v = Bq[k + (int64_t)col * args.ldb];
-          if (args.bscale) v *= args.bscale[d.bs_off + k0 + k];
-        }
-      }
-      stg[u] = v;
-    }
-  };
-  auto lstore = [&](int buf) {
-#pragma unroll
-    for (int u = 0; u < NSTG; ++u) {
-      const int e = tid + u * nthr;
-      if (e < KC * KT) {
-        const int k = e % KC, c = e / KC;
-        Bs[buf][k * SB + c] = stg[u];
-      }
-    }
-  };
-
-  // A streams through two register buffers (halves of a 16-deep chunk), each loaded one
-  // half-chunk ahead of its use; B chunks go through double-buffered LDS.
-  const int64_t lane_off = rb + (L & 15) + (int64_t)(L >> 4) * lda;
-  double a0[2][RT], a1[2][RT];
-  auto loadA = [&](double (&dst)[2][RT], int kbase) {   // k-steps kbase/4 and kbase/4 + 1
-    const double* __restrict__ pa = A + lane_off + (int64_t)kbase * lda;
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int t = 0; t < RT; ++t) dst[u][t] = pa[16 * t + (int64_t)(4 * u) * lda];
-  };
-  auto compute = [&](const double (&av)[2][RT], int buf, int half) {
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const double* bp = &Bs[buf][(8 * half + 4 * u + (L >> 4)) * SB + (L & 3) * CT];
-      double b[CT];
-#pragma unroll
-      for (int c = 0; c < CT; ++c) b[c] = bp[c];
-#pragma unroll
-      for (int t = 0; t < RT; ++t)
-#pragma unroll
-        for (int c = 0; c < CT; ++c) acc[t][c] = mfma4(av[u][t], b[c], acc[t][c]);
-    }
-  };
-
-  gload(0);
-  loadA(a0, 0);
-  lstore(0);
-  __syncthreads();
-  for (int q = 0; q < nch; ++q) {
-    const int buf = q & 1;
-    const bool more = q + 1 < nch;
-    if (more) gload(q + 1);
-    loadA(a1, q * KC + 8);
-    compute(a0, buf, 0);
-    loadA(a0, more ? (q + 1) * KC : 0);
-    compute(a1, buf, 1);
-    if (more) lstore(buf ^ 1);
-    __syncthreads();
-  }
-
-#pragma unroll
-  for (int t = 0; t < RT; ++t) {
-    const int row = rb + 16 * t + out_row(L);
-#pragma unroll
-    for (int c = 0; c < CT; ++c) {
-      const int col = col0 + out_col(L) * CT + c;
-      if (col < args.ncols) {
-        double v = args.alpha * acc[t][c];
-        if (args.Cin) v += args.Cin[d.cin_off + row + (int64_t)col * args.ldcin];
-        for (int s = 0; s < d.nsp; ++s) v += args.Sp[d.sp_off + s * args.spstride + row + (int64_t)col * args.ldsp];
-        if (args.C) args.C[d.c_off + row + (int64_t)col * args.ldc] = v;
-        if (args.X2 && row < args.x2rows) {
-          double* xp = args.X2 + d.x2_off + row + (int64_t)col * args.ldx2;
-          *xp = args.x2accum ? *xp + v : v;
-        }
-      }
-    }
-  }
+  bgemm_tile<RT, CT>(args, prob, lg - prob * args.ncoltiles, Bs);
 }
 
 int bgemm_coltile(int ncols) {

@@ -13,50 +13,11 @@
 // Matrices are stored row-major (k contiguous) and the LDS operand column-major
 // (k contiguous per column) so that every operand read is one 16-byte access.
 #include "internal.h"
+#include "tile_bodies.h"
 
 #include <cstdint>
 
 namespace td {
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
-// round-to-nearest-even float -> bfloat16 bits; NaN stays a quiet NaN
-__device__ __forceinline__ uint16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x0040u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-
-template <int PREC> struct LP;
-template <> struct LP<1> {   // float32
-  using T = float;
-  static constexpr int KG = 16;                    // k per group
-  __device__ static T from_f(float v) { return v; }
-  __device__ static void mma(f32x4& acc, const uint4& a, const uint4& b) {
-    const f32x4 av = __builtin_bit_cast(f32x4, a);
-    const f32x4 bv = __builtin_bit_cast(f32x4, b);
-#pragma unroll
-    for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], bv[u], acc, 0, 0, 0);
-  }
-};
-template <> struct LP<2> {   // bfloat16
-  using T = uint16_t;
-  static constexpr int KG = 32;
-  __device__ static T from_f(float v) { return f2bf(v); }
-  __device__ static void mma(f32x4& acc, const uint4& a, const uint4& b) {
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
-                                                   acc, 0, 0, 0);
-  }
-};
-
-__device__ __forceinline__ int lp_xcd_remap(int b, int grid) {
-  const int per = grid >> 3;
-  return (b & 7) * per + (b >> 3);
-}
-static inline int lp_pad8(int t) { return (t + 7) & ~7; }
 
 // ---------------------------------------------------------------------------
 // Casts of the float64 factor: dst (row-major, k contiguous) = RNE(src col-major).
@@ -98,133 +59,11 @@ hipError_t launch_cast_rowmajor(int prec, void* dst, int64_t dstride, const doub
 // ---------------------------------------------------------------------------
 template <int PREC, int RT, int CT>
 __global__ void __launch_bounds__(512) k_sweep_lp(LpSweepArgs a) {
-  using Tr = LP<PREC>;
-  using T = typename Tr::T;
-  constexpr int KG = Tr::KG;
-  constexpr int KT = 16 * CT;
   extern __shared__ uint4 lds_raw[];
-  T* In = reinterpret_cast<T*>(lds_raw);     // [KT][SK]
-  const int Mp = a.Mp, M = a.M, K = a.K;
-  const int SK = Mp + 16 / (int)sizeof(T);   // column stride (elements), padded by 16 bytes
-
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int L = tid & 63, w = tid >> 6;
   const int lg = lp_xcd_remap(blockIdx.x, gridDim.x);
   if (lg >= a.total) return;
   const int s = lg / a.ncoltiles;
-  const int ct = lg - s * a.ncoltiles;
-  const int col0 = ct * KT;
-  const int64_t first = a.ks[s] + 1, last = a.ks[s + 1] - 1;
-  if (first > last) return;
-  const int rb = w * 16 * RT;
-  const int64_t MM = (int64_t)Mp * Mp;
-  const int ng = Mp / KG;   // k-groups per step
-
-  const int64_t nsteps = 2 * (last - first) + 1;
-  auto step_matrix = [&](int64_t q) -> const T* {
-    return (q <= last - first) ? (const T*)a.Dinv + (first + q) * MM
-                               : (const T*)a.alpha + (last - 1 - (q - (last - first + 1))) * MM;
-  };
-  // lane's 16-byte slice of row (rb + 16t + L%16), k-group g
-  const int64_t lane_off = (int64_t)(rb + (L & 15)) * Mp + (KG / 4) * (L >> 4);
-  uint4 a0[RT], a1[RT];
-  auto loadA = [&](uint4 (&dst)[RT], const T* __restrict__ Ab, int g) {
-#pragma unroll
-    for (int t = 0; t < RT; ++t)
-      dst[t] = *reinterpret_cast<const uint4*>(Ab + lane_off + (int64_t)16 * t * Mp + KG * g);
-  };
-  f32x4 acc[RT][CT];
-  auto compute = [&](const uint4 (&av)[RT], int g) {
-    uint4 b[CT];
-#pragma unroll
-    for (int c = 0; c < CT; ++c)
-      b[c] = *reinterpret_cast<const uint4*>(In + (16 * c + (L & 15)) * SK + KG * g + (KG / 4) * (L >> 4));
-#pragma unroll
-    for (int t = 0; t < RT; ++t)
-#pragma unroll
-      for (int c = 0; c < CT; ++c) Tr::mma(acc[t][c], av[t], b[c]);
-  };
-
-  for (int e = tid; e < Mp * KT; e += nthr) {
-    const int row = e % Mp, c = e / Mp;
-    const int col = col0 + c;
-    const double v = (row < M && col < K) ? a.F[first * M + row + (int64_t)col * a.ldf] : 0.0;
-    In[c * SK + row] = Tr::from_f((float)v);
-  }
-  loadA(a0, step_matrix(0), 0);
-  __syncthreads();
-
-  for (int64_t q = 0; q < nsteps; ++q) {
-    const bool fwd = q <= last - first;
-    const int64_t i = fwd ? first + q : last - 1 - (q - (last - first + 1));
-    const T* __restrict__ Ai = step_matrix(q);
-    const T* __restrict__ Anx = (q + 1 < nsteps) ? step_matrix(q + 1) : Ai;
-#pragma unroll
-    for (int t = 0; t < RT; ++t)
-#pragma unroll
-      for (int c = 0; c < CT; ++c) acc[t][c] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    int g = 0;
-    for (; g + 2 < ng; g += 2) {
-      loadA(a1, Ai, g + 1);
-      compute(a0, g);
-      loadA(a0, Ai, g + 2);
-      compute(a1, g + 1);
-    }
-    // epilogue operands: rows 4(L/16)..+3 of column L%16 of each tile
-    const bool more = fwd && i < last;
-    float ex[RT][CT][4];
-    float an[RT][4];
-#pragma unroll
-    for (int t = 0; t < RT; ++t) {
-      const int row0 = rb + 16 * t + 4 * (L >> 4);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) an[t][v] = more ? (float)a.adiag[(i + 1) * Mp + row0 + v] : 0.f;
-#pragma unroll
-      for (int c = 0; c < CT; ++c) {
-        const int col = col0 + 16 * c + (L & 15);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = row0 + v;
-          float x = 0.f;
-          if (fwd) {
-            if (more && row < M && col < K) x = (float)a.F[(i + 1) * M + row + (int64_t)col * a.ldf];
-          } else if (col < K) {
-            x = a.W[i * Mp + row + (int64_t)col * a.ldw];
-          }
-          ex[t][c][v] = x;
-        }
-      }
-    }
-    if (ng - g == 2) {
-      loadA(a1, Ai, g + 1);
-      compute(a0, g);
-      loadA(a0, Anx, 0);
-      compute(a1, g + 1);
-    } else {
-      compute(a0, g);
-      loadA(a0, Anx, 0);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < RT; ++t) {
-      const int row0 = rb + 16 * t + 4 * (L >> 4);
-#pragma unroll
-      for (int c = 0; c < CT; ++c) {
-        const int lc = 16 * c + (L & 15);
-        const int col = col0 + lc;
-        f32x4 vv;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) vv[v] = fwd ? acc[t][c][v] : acc[t][c][v] + ex[t][c][v];
-        if (col < K) *reinterpret_cast<f32x4*>(a.W + i * Mp + row0 + (int64_t)col * a.ldw) = vv;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const float nxt = more ? ex[t][c][v] + an[t][v] * vv[v] : vv[v];
-          In[lc * SK + row0 + v] = Tr::from_f(nxt);
-        }
-      }
-    }
-    __syncthreads();
-  }
+  sweep_lp_tile<PREC, RT, CT>(a, s, lg - s * a.ncoltiles, lds_raw);
 }
 
 // ---------------------------------------------------------------------------
@@ -234,113 +73,11 @@ __global__ void __launch_bounds__(512) k_sweep_lp(LpSweepArgs a) {
 // ---------------------------------------------------------------------------
 template <int PREC, int RT, int CT>
 __global__ void __launch_bounds__(512) k_superpose_lp(LpSupArgs a) {
-  using Tr = LP<PREC>;
-  using T = typename Tr::T;
-  constexpr int KG = Tr::KG;
-  constexpr int KT = 16 * CT;
   extern __shared__ uint4 lds_raw[];
-  T* Xs = reinterpret_cast<T*>(lds_raw);   // [KT][SK]
-  const int Mp = a.Mp, M = a.M, K = a.K;
-  const int kd = 2 * Mp;
-  const int SK = kd + 16 / (int)sizeof(T);
-
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int L = tid & 63, w = tid >> 6;
   const int lg = lp_xcd_remap(blockIdx.x, gridDim.x);
   if (lg >= a.total) return;
   const int s = lg / a.ncoltiles;
-  const int ct = lg - s * a.ncoltiles;
-  const int col0 = ct * KT;
-  const int64_t first = a.ks[s] + 1, last = a.ks[s + 1] - 1;
-  if (first > last) return;
-  const int rb = w * 16 * RT;
-  const int64_t MM2 = (int64_t)Mp * kd;
-  const int ng = kd / KG;
-
-  for (int e = tid; e < kd * KT; e += nthr) {
-    const int k = e % kd, c = e / kd;
-    const int col = col0 + c;
-    const double v = (col < K) ? a.Xi[(int64_t)(s + 1) * Mp + k + (int64_t)col * a.ldxi] : 0.0;
-    Xs[c * SK + k] = Tr::from_f((float)v);
-  }
-
-  const int64_t lane_off = (int64_t)(rb + (L & 15)) * kd + (KG / 4) * (L >> 4);
-  uint4 a0[RT], a1[RT];
-  auto loadA = [&](uint4 (&dst)[RT], const T* __restrict__ Ab, int g) {
-#pragma unroll
-    for (int t = 0; t < RT; ++t)
-      dst[t] = *reinterpret_cast<const uint4*>(Ab + lane_off + (int64_t)16 * t * kd + KG * g);
-  };
-  f32x4 acc[RT][CT];
-  auto compute = [&](const uint4 (&av)[RT], int g) {
-    uint4 b[CT];
-#pragma unroll
-    for (int c = 0; c < CT; ++c)
-      b[c] = *reinterpret_cast<const uint4*>(Xs + (16 * c + (L & 15)) * SK + KG * g + (KG / 4) * (L >> 4));
-#pragma unroll
-    for (int t = 0; t < RT; ++t)
-#pragma unroll
-      for (int c = 0; c < CT; ++c) Tr::mma(acc[t][c], av[t], b[c]);
-  };
-
-  const T* UVb = (const T*)a.UV;
-  loadA(a0, UVb + first * MM2, 0);
-  __syncthreads();
-  for (int64_t i = first; i <= last; ++i) {
-    const T* __restrict__ Ai = UVb + i * MM2;
-    const T* __restrict__ Anx = (i < last) ? Ai + MM2 : Ai;
-#pragma unroll
-    for (int t = 0; t < RT; ++t)
-#pragma unroll
-      for (int c = 0; c < CT; ++c) acc[t][c] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    int g = 0;
-    for (; g + 2 < ng; g += 2) {
-      loadA(a1, Ai, g + 1);
-      compute(a0, g);
-      loadA(a0, Ai, g + 2);
-      compute(a1, g + 1);
-    }
-    float wv[RT][CT][4];
-#pragma unroll
-    for (int t = 0; t < RT; ++t) {
-      const int row0 = rb + 16 * t + 4 * (L >> 4);
-#pragma unroll
-      for (int c = 0; c < CT; ++c) {
-        const int col = col0 + 16 * c + (L & 15);
-        f32x4 x = (f32x4){0.f, 0.f, 0.f, 0.f};
-        if (col < K) x = *reinterpret_cast<const f32x4*>(a.W + i * Mp + row0 + (int64_t)col * a.ldw);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) wv[t][c][v] = x[v];
-      }
-    }
-    if (ng - g == 2) {
-      loadA(a1, Ai, g + 1);
-      compute(a0, g);
-      loadA(a0, Anx, 0);
-      compute(a1, g + 1);
-    } else {
-      compute(a0, g);
-      loadA(a0, Anx, 0);
-    }
-#pragma unroll
-    for (int t = 0; t < RT; ++t) {
-      const int row0 = rb + 16 * t + 4 * (L >> 4);
-#pragma unroll
-      for (int c = 0; c < CT; ++c) {
-        const int col = col0 + 16 * c + (L & 15);
-        if (col >= K) continue;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = row0 + v;
-          if (row < M) {
-            double* xp = a.X + i * M + row + (int64_t)col * a.ldx;
-            const double d = (double)acc[t][c][v] + (double)wv[t][c][v];
-            *xp = a.accumulate ? *xp + d : d;
-          }
-        }
-      }
-    }
-  }
+  superpose_lp_tile<PREC, RT, CT>(a, s, lg - s * a.ncoltiles, lds_raw);
 }
 
 static inline int lp_choose_rt(int Mp) {
@@ -466,43 +203,7 @@ __global__ void __launch_bounds__(256) k_residual_stencil(double* R, int64_t ldr
                                                           const double* B, const double* C, int N, int M, int K,
                                                           int chunk, double* colpart, int nchunk) {
   __shared__ double red[2][4];
-  const int q = blockIdx.x, col = blockIdx.y;
-  const int64_t n = (int64_t)N * M;
-  const int64_t g0 = (int64_t)q * chunk;
-  const int64_t g1 = g0 + chunk < n ? g0 + chunk : n;
-  const double* x = X + (int64_t)col * ldx;
-  const double* f = F + (int64_t)col * ldf;
-  double sr = 0.0, sf = 0.0;
-  for (int64_t g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
-    const int64_t j = g / M;
-    const int r = (int)(g - j * M);
-    const double* t = C + j * 3 * M;
-    double y = t[M + r] * x[g];
-    if (r > 0) y += t[r] * x[g - 1];
-    if (r < M - 1) y += t[2 * M + r] * x[g + 1];
-    if (j > 0) y -= A[g] * x[g - M];
-    if (j < N - 1) y -= B[g] * x[g + M];
-    const double fv = f[g];
-    const double rv = fv - y;
-    if (R) R[g + (int64_t)col * ldr] = rv;
-    sr += rv * rv;
-    sf += fv * fv;
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    sr += __shfl_xor(sr, off);
-    sf += __shfl_xor(sf, off);
-  }
-  if ((threadIdx.x & 63) == 0) {
-    red[0][threadIdx.x >> 6] = sr;
-    red[1][threadIdx.x >> 6] = sf;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double a = 0.0, b = 0.0;
-    for (int v = 0; v < 4; ++v) { a += red[0][v]; b += red[1][v]; }
-    colpart[((int64_t)col * nchunk + q) * 2 + 0] = a;
-    colpart[((int64_t)col * nchunk + q) * 2 + 1] = b;
-  }
+  residual_stencil_tile(R, ldr, F, ldf, X, ldx, A, B, C, N, M, chunk, colpart, nchunk, blockIdx.x, blockIdx.y, red);
 }
 
 int residual_chunks(int64_t n) { return (int)((n + 8191) / 8192); }

@@ -984,6 +984,230 @@ td_status factor_top(const td_desc* d, const double* A, const double* B, const d
 
 }  // namespace
 
+// ------------------------------------------------------------------------------------------
+// Batched solve of many independent systems: one persistent launch (k_batched) over a work
+// list, captured once in a HIP graph and replayed.  Float32 sweeps and superposition, float64
+// reduced systems, residuals and a fixed number of correction passes with per-system early exit.
+// ------------------------------------------------------------------------------------------
+struct td_batch_s {
+  int n = 0;
+  std::vector<td_plan> plans;
+  std::vector<void*> allocs;
+  BatchItem* d_items = nullptr; int nitems = 0;
+  BatchSys* d_sys = nullptr;
+  int32_t* d_counters = nullptr; int ncounters = 0;
+  int32_t* d_conv = nullptr;
+  BatchCtl* d_ctl = nullptr;
+  double* d_resid = nullptr;
+  int passes = 0;
+  int grid = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t last = nullptr;
+  ~td_batch_s() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (void* p : allocs) (void)hipFree(p);
+  }
+  template <class T>
+  T* dalloc(size_t count) {
+    void* p = nullptr;
+    HIPCHK(hipMalloc(&p, std::max<size_t>(1, count) * sizeof(T)));
+    allocs.push_back(p);
+    return (T*)p;
+  }
+  template <class T>
+  T* upload(const std::vector<T>& v) {
+    T* p = dalloc<T>(v.size());
+    if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return p;
+  }
+};
+
+namespace {
+
+td_status batch_create_impl(int n, const td_plan* plans, const double* const* F, const int64_t* ldf,
+                            double* const* X, const int64_t* ldx, const int64_t* K, int passes, double tol,
+                            hipStream_t st, td_batch_s* B) {
+  if (n <= 0 || !plans || !F || !ldf || !X || !ldx || !K) return fail(TD_EINVAL, "bad batch arguments");
+  if (passes < 1 || passes > 16) return fail(TD_EINVAL, "passes must be in [1, 16]");
+  for (int q = 0; q < n; ++q) {
+    td_plan_s* P = plans[q];
+    if (!P) return fail(TD_EINVAL, "null plan in batch");
+    if (P->prec != TD_PREC_F32) return fail(TD_ENOTSUP, "batched plans must have sweep_prec TD_PREC_F32");
+    if (!stencil_formats(P)) return fail(TD_ENOTSUP, "batched plans need diagonal A, B and tridiagonal C");
+    if (!(P->Mp == 64 || P->Mp == 128 || P->Mp == 256)) return fail(TD_ENOTSUP, "batched plans need Mp in {64,128,256}");
+    if (P->depth > BATCH_MAXDEPTH) return fail(TD_ENOTSUP, "dichotomy tree too deep for the batched kernel");
+    if (K[q] < 1 || ldf[q] < P->N * P->M || ldx[q] < P->N * P->M || !F[q] || !X[q])
+      return fail(TD_EINVAL, "bad K, leading dimension or pointer in batch");
+    if (K[q] > INT_MAX / 2) return fail(TD_EINVAL, "K too large");
+  }
+  B->n = n;
+  B->passes = passes;
+  B->plans.assign(plans, plans + n);
+  std::vector<BatchSys> sys(n);
+  std::vector<int> cbase(n), nst(n);
+  int nctr = 0;
+  for (int q = 0; q < n; ++q) {
+    td_plan_s* P = plans[q];
+    const int64_t Kq = K[q];
+    ensure_workspace(P, Kq, st);
+    const int64_t N = P->N, M = P->M, Mp = P->Mp, p = P->p;
+    const int64_t ldw = N * Mp, ldft = p * Mp, ldxi = (p + 2) * Mp, ldsp = (int64_t)P->nchunks * Mp;
+    BatchSys& S = sys[q];
+    std::memset(&S, 0, sizeof(S));
+    S.sweep.ks = P->d_ks; S.sweep.Dinv = P->Dlp; S.sweep.alpha = P->Alp; S.sweep.adiag = P->adiag;
+    S.sweep.F = F[q]; S.sweep.ldf = ldf[q]; S.sweep.W = P->W32; S.sweep.ldw = ldw;
+    S.sweep.N = (int32_t)N; S.sweep.M = (int32_t)M; S.sweep.Mp = (int32_t)Mp; S.sweep.p = (int32_t)p;
+    S.sweep.K = (int32_t)Kq;
+    S.sup.ks = P->d_ks; S.sup.UV = P->UVlp; S.sup.Xi = P->Xi; S.sup.ldxi = ldxi;
+    S.sup.W = P->W32; S.sup.ldw = ldw; S.sup.X = X[q]; S.sup.ldx = ldx[q];
+    S.sup.N = (int32_t)N; S.sup.M = (int32_t)M; S.sup.Mp = (int32_t)Mp; S.sup.p = (int32_t)p; S.sup.K = (int32_t)Kq;
+    BArgs a = bargs_base((int)Mp);
+    a.descs = P->d_part; a.nprob = P->n_part;
+    a.A = P->G; a.lda = Mp; a.B = P->Ft; a.ldb = ldft; a.C = P->Sp; a.ldc = ldsp; a.ncols = (int32_t)Kq;
+    S.part = a;
+    for (int lv = 0; lv < P->depth; ++lv) {
+      BArgs b = bargs_base((int)Mp);
+      b.descs = P->d_corr + P->corr_begin[lv]; b.nprob = P->corr_count[lv];
+      b.A = P->H; b.lda = Mp; b.B = P->Xi; b.ldb = ldxi;
+      b.Sp = P->Sp; b.ldsp = ldsp; b.spstride = Mp;
+      b.C = P->Xi; b.ldc = ldxi;
+      b.X2 = X[q]; b.ldx2 = ldx[q]; b.x2rows = (int32_t)M;
+      b.ncols = (int32_t)Kq;
+      S.lev[lv] = b;
+    }
+    S.Ft = P->Ft; S.ldft = ldft; S.adiag = P->adiag; S.bdiag = P->bdiag;
+    S.F = F[q]; S.ldf = ldf[q]; S.X = X[q]; S.ldx = ldx[q];
+    S.R = B->dalloc<double>((size_t)(N * M * Kq)); S.ldr = N * M;
+    S.cA = P->cA; S.cB = P->cB; S.cC = P->cC;
+    S.nchunk = residual_chunks(N * M);
+    S.colpart = B->dalloc<double>((size_t)(S.nchunk * Kq * 2));
+    S.resid = nullptr;  // set below
+    S.N = (int32_t)N; S.M = (int32_t)M; S.Mp = (int32_t)Mp; S.p = (int32_t)p; S.K = (int32_t)Kq;
+    S.rt = (int32_t)(Mp / 64);
+    S.rescols = 8;
+    S.tol = tol;
+    nst[q] = 6 + P->depth;
+    cbase[q] = nctr;
+    nctr += passes * nst[q];
+  }
+  B->d_resid = B->dalloc<double>((size_t)n * passes);
+  for (int q = 0; q < n; ++q) sys[q].resid = B->d_resid + (int64_t)q * passes;
+
+  // ---- work list in topological order: (pass, stage) outer, systems inner
+  std::vector<BatchItem> items;
+  auto ctr = [&](int q, int r, int stage) { return cbase[q] + r * nst[q] + stage; };
+  std::vector<int> order(n);
+  for (int q = 0; q < n; ++q) order[q] = q;
+  // longest sweeps first (they are the longest single items)
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    const td_plan_s *a = plans[x], *b = plans[y];
+    const double wa = (double)(a->N / a->p) * a->Mp * a->Mp, wb = (double)(b->N / b->p) * b->Mp * b->Mp;
+    return wa > wb;
+  });
+  std::vector<int> cnt_sweep(n), cnt_ft(n), cnt_part(n), cnt_sup(n), cnt_res(n);
+  std::vector<std::vector<int>> cnt_lev(n);
+  for (int q = 0; q < n; ++q) {
+    td_plan_s* P = plans[q];
+    const int nct = (int)((K[q] + 31) / 32);
+    cnt_sweep[q] = (int)P->p * nct;
+    cnt_ft[q] = (int)((P->p * P->Mp * K[q] + 16383) / 16384);
+    cnt_part[q] = P->n_part * nct;
+    cnt_lev[q].resize(P->depth);
+    for (int lv = 0; lv < P->depth; ++lv) cnt_lev[q][lv] = P->corr_count[lv] * nct;
+    cnt_sup[q] = (int)P->p * nct;
+    cnt_res[q] = sys[q].nchunk * (int)((K[q] + 7) / 8);
+  }
+  int maxdepth = 0;
+  for (int q = 0; q < n; ++q) maxdepth = std::max(maxdepth, plans[q]->depth);
+  auto add = [&](int type, int q, int r, int lvl, int i0, int i1, int dep, int need, int mine) {
+    BatchItem it;
+    it.type = type; it.sys = q; it.pass = r; it.lvl = lvl; it.i0 = i0; it.i1 = i1;
+    it.dep = dep; it.need = need; it.mine = mine; it.pad_ = 0;
+    items.push_back(it);
+  };
+  for (int r = 0; r < passes; ++r) {
+    for (int q : order) {   // sweeps
+      td_plan_s* P = plans[q];
+      const int nct = (int)((K[q] + 31) / 32);
+      const int dep = r == 0 ? -1 : ctr(q, r - 1, 5 + P->depth);
+      for (int s = 0; s < P->p; ++s)
+        for (int c = 0; c < nct; ++c) add(BI_SWEEP, q, r, 0, s, c, dep, r == 0 ? 0 : 1, ctr(q, r, 0));
+    }
+    for (int q : order)
+      for (int c = 0; c < cnt_ft[q]; ++c) add(BI_FTILDE, q, r, 0, c, 0, ctr(q, r, 0), cnt_sweep[q], ctr(q, r, 1));
+    for (int q : order) {
+      td_plan_s* P = plans[q];
+      const int nct = (int)((K[q] + 31) / 32);
+      for (int pr = 0; pr < P->n_part; ++pr)
+        for (int c = 0; c < nct; ++c) add(BI_PART, q, r, 0, pr, c, ctr(q, r, 1), cnt_ft[q], ctr(q, r, 2));
+    }
+    for (int lv = 0; lv < maxdepth; ++lv)
+      for (int q : order) {
+        td_plan_s* P = plans[q];
+        if (lv >= P->depth) continue;
+        const int nct = (int)((K[q] + 31) / 32);
+        const int dep = lv == 0 ? ctr(q, r, 2) : ctr(q, r, 3 + lv - 1);
+        const int need = lv == 0 ? cnt_part[q] : cnt_lev[q][lv - 1];
+        for (int pr = 0; pr < P->corr_count[lv]; ++pr)
+          for (int c = 0; c < nct; ++c) add(BI_LEVEL, q, r, lv, pr, c, dep, need, ctr(q, r, 3 + lv));
+      }
+    for (int q : order) {
+      td_plan_s* P = plans[q];
+      const int nct = (int)((K[q] + 31) / 32);
+      for (int s = 0; s < P->p; ++s)
+        for (int c = 0; c < nct; ++c)
+          add(BI_SUP, q, r, 0, s, c, ctr(q, r, 3 + P->depth - 1), cnt_lev[q][P->depth - 1], ctr(q, r, 3 + P->depth));
+    }
+    for (int q : order) {
+      td_plan_s* P = plans[q];
+      for (int ch = 0; ch < sys[q].nchunk; ++ch)
+        for (int c0 = 0; c0 < K[q]; c0 += 8)
+          add(BI_RES, q, r, 0, ch, c0, ctr(q, r, 3 + P->depth), cnt_sup[q], ctr(q, r, 4 + P->depth));
+    }
+    for (int q : order) {
+      td_plan_s* P = plans[q];
+      add(BI_RFIN, q, r, 0, 0, 0, ctr(q, r, 4 + P->depth), cnt_res[q], ctr(q, r, 5 + P->depth));
+    }
+  }
+  B->nitems = (int)items.size();
+  B->d_items = B->upload(items);
+  B->d_sys = B->upload(sys);
+  B->ncounters = nctr;
+  B->d_counters = B->dalloc<int32_t>((size_t)nctr);
+  B->d_conv = B->dalloc<int32_t>((size_t)n);
+  B->d_ctl = B->dalloc<BatchCtl>(1);
+  int dev = 0, cus = 0, occ = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  B->grid = cus;
+  (void)occ;
+  // capture the reset + persistent launch once, on a private stream (the caller's stream may be
+  // the legacy default stream, which cannot be captured); replays go to the caller's stream
+  HIPCHK(hipStreamSynchronize(st));
+  hipStream_t cs = nullptr;
+  HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipError_t be = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  hipError_t le = hipSuccess, ce = hipSuccess;
+  hipGraph_t g = nullptr;
+  if (be == hipSuccess) {
+    le = launch_batched(B->d_items, B->nitems, B->d_sys, B->d_counters, B->ncounters, B->d_conv, n, B->d_ctl, B->grid,
+                        (int64_t)1 << 26, cs);
+    ce = hipStreamEndCapture(cs, &g);
+  }
+  (void)hipStreamDestroy(cs);
+  HIPCHK(be);
+  HIPCHK(le);
+  HIPCHK(ce);
+  B->graph = g;
+  HIPCHK(hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0));
+  B->last = st;
+  return TD_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 td_status tridiag_factor(const td_desc* desc, const double* A, const double* B, const double* C, void* stream,
@@ -1093,5 +1317,65 @@ const char* tridiag_status_string(td_status s) {
 }
 
 const char* tridiag_last_error(void) { return g_err.c_str(); }
+
+td_status tridiag_batch_create(int n, const td_plan* plans, const double* const* F, const int64_t* ldf,
+                               double* const* X, const int64_t* ldx, const int64_t* K, int passes, double tol,
+                               void* stream, td_batch* out) {
+  if (!out) return fail(TD_EINVAL, "null out");
+  *out = nullptr;
+  g_err.clear();
+  td_batch_s* B = new td_batch_s();
+  td_status s;
+  try {
+    s = batch_create_impl(n, plans, F, ldf, X, ldx, K, passes, tol > 0.0 ? tol : 1e-10, (hipStream_t)stream, B);
+  } catch (const HipFail& e) {
+    s = fail(e.e == hipErrorOutOfMemory ? TD_ENOMEM : TD_EHIP,
+             std::string("HIP error ") + hipGetErrorString(e.e) + " in " + e.where);
+  }
+  if (s != TD_OK) {
+    delete B;
+    return s;
+  }
+  *out = B;
+  return TD_OK;
+}
+
+td_status tridiag_batch_solve(td_batch b, void* stream) {
+  if (!b) return fail(TD_EINVAL, "null batch");
+  hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(TD_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+  b->last = (hipStream_t)stream;
+  return TD_OK;
+}
+
+td_status tridiag_batch_info(td_batch b, td_info* infos) {
+  if (!b || !infos) return fail(TD_EINVAL, "null argument");
+  BatchCtl ctl;
+  std::vector<int32_t> conv(b->n);
+  std::vector<double> res((size_t)b->n * b->passes);
+  hipError_t e = hipStreamSynchronize(b->last);
+  if (e == hipSuccess) e = hipMemcpy(&ctl, b->d_ctl, sizeof(ctl), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(conv.data(), b->d_conv, b->n * sizeof(int32_t), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(res.data(), b->d_resid, res.size() * sizeof(double), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(TD_EHIP, hipGetErrorString(e));
+  if (ctl.error) return fail(TD_EHIP, "a dependency wait of the batched kernel timed out");
+  bool allconv = true;
+  for (int q = 0; q < b->n; ++q) {
+    const int last = conv[q] < b->passes ? conv[q] : b->passes - 1;
+    infos[q].iterations = last;
+    infos[q].nonfinite = std::isfinite(res[(size_t)q * b->passes + last]) ? 0 : 1;
+    infos[q].max_col_rel_residual = res[(size_t)q * b->passes + last];
+    if (conv[q] >= b->passes) allconv = false;
+  }
+  if (!allconv) return fail(TD_ENOCONV, "some systems did not reach the residual tolerance within the passes");
+  return TD_OK;
+}
+
+td_status tridiag_batch_destroy(td_batch b) {
+  if (!b) return TD_OK;
+  if (b->last) (void)hipStreamSynchronize(b->last);
+  delete b;
+  return TD_OK;
+}
 
 }  // extern "C"

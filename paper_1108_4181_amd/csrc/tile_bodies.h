@@ -1,0 +1,401 @@
+// Work-group tile bodies of the solver's main kernels, shared by the one-stage kernels
+// (kernels_f64.hip, kernels_lp.hip) and the persistent batched kernel (kernels_batched.hip).
+#pragma once
+
+#include "device_common.h"
+#include "internal.h"
+
+namespace td {
+
+template <int RT, int CT>
+__device__ __forceinline__ void bgemm_tile(const BArgs& args, int prob, int ct, double* lds) {
+  constexpr int KC = 16;
+  constexpr int KT = 4 * CT;
+  constexpr int SB = KT + 2;
+  constexpr int NSTG = (KC * KT + 63) / 64;
+  double* Bs0 = lds;              // [2][KC * SB]
+
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int L = tid & 63, w = tid >> 6;
+  const BDesc d = args.descs[prob];
+  const int col0 = ct * KT;
+  const int rb = w * 16 * RT;
+  const double* __restrict__ A = args.A + d.a_off;
+  const int64_t lda = args.lda;
+
+  double acc[RT][CT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int c = 0; c < CT; ++c) acc[t][c] = 0.0;
+
+  const int nch = d.kd / KC;
+  double stg[NSTG];
+  auto gload = [&](int q) {
+    const int k0 = q * KC;
+    const int seg = k0 / d.segrows;
+    const int kin = k0 - seg * d.segrows;
+    const double* Bq = args.B + d.b_off + (int64_t)seg * d.bseg + kin;
+#pragma unroll
+    for (int u = 0; u < NSTG; ++u) {
+      const int e = tid + u * nthr;
+      double v = 0.0;
+      if (e < KC * KT) {
+        const int k = e % KC, c = e / KC;
+        const int col = col0 + c;
+        if (col < args.ncols) {
+          v = Bq[k + (int64_t)col * args.ldb];
+          if (args.bscale) v *= args.bscale[d.bs_off + k0 + k];
+        }
+      }
+      stg[u] = v;
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < NSTG; ++u) {
+      const int e = tid + u * nthr;
+      if (e < KC * KT) {
+        const int k = e % KC, c = e / KC;
+        Bs0[buf * KC * SB + k * SB + c] = stg[u];
+      }
+    }
+  };
+
+  // A streams through two register buffers (halves of a 16-deep chunk), each loaded one
+  // half-chunk ahead of its use; B chunks go through double-buffered LDS.
+  const int64_t lane_off = rb + (L & 15) + (int64_t)(L >> 4) * lda;
+  double a0[2][RT], a1[2][RT];
+  auto loadA = [&](double (&dst)[2][RT], int kbase) {   // k-steps kbase/4 and kbase/4 + 1
+    const double* __restrict__ pa = A + lane_off + (int64_t)kbase * lda;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int t = 0; t < RT; ++t) dst[u][t] = pa[16 * t + (int64_t)(4 * u) * lda];
+  };
+  auto compute = [&](const double (&av)[2][RT], int buf, int half) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const double* bp = &Bs0[buf * KC * SB + (8 * half + 4 * u + (L >> 4)) * SB + (L & 3) * CT];
+      double b[CT];
+#pragma unroll
+      for (int c = 0; c < CT; ++c) b[c] = bp[c];
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[t][c] = mfma4(av[u][t], b[c], acc[t][c]);
+    }
+  };
+
+  gload(0);
+  loadA(a0, 0);
+  lstore(0);
+  __syncthreads();
+  for (int q = 0; q < nch; ++q) {
+    const int buf = q & 1;
+    const bool more = q + 1 < nch;
+    if (more) gload(q + 1);
+    loadA(a1, q * KC + 8);
+    compute(a0, buf, 0);
+    loadA(a0, more ? (q + 1) * KC : 0);
+    compute(a1, buf, 1);
+    if (more) lstore(buf ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int t = 0; t < RT; ++t) {
+    const int row = rb + 16 * t + out_row(L);
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      const int col = col0 + out_col(L) * CT + c;
+      if (col < args.ncols) {
+        double v = args.alpha * acc[t][c];
+        if (args.Cin) v += args.Cin[d.cin_off + row + (int64_t)col * args.ldcin];
+        for (int s = 0; s < d.nsp; ++s) v += args.Sp[d.sp_off + s * args.spstride + row + (int64_t)col * args.ldsp];
+        if (args.C) args.C[d.c_off + row + (int64_t)col * args.ldc] = v;
+        if (args.X2 && row < args.x2rows) {
+          double* xp = args.X2 + d.x2_off + row + (int64_t)col * args.ldx2;
+          *xp = args.x2accum ? *xp + v : v;
+        }
+      }
+    }
+  }
+}
+
+template <int PREC, int RT, int CT>
+__device__ __forceinline__ void sweep_lp_tile(const LpSweepArgs& a, int s, int ct, uint4* lds_raw) {
+  using Tr = LP<PREC>;
+  using T = typename Tr::T;
+  constexpr int KG = Tr::KG;
+  constexpr int KT = 16 * CT;
+  T* In = reinterpret_cast<T*>(lds_raw);     // [KT][SK]
+  const int Mp = a.Mp, M = a.M, K = a.K;
+  const int SK = Mp + 16 / (int)sizeof(T);   // column stride (elements), padded by 16 bytes
+
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int L = tid & 63, w = tid >> 6;
+  const int col0 = ct * KT;
+  const int64_t first = a.ks[s] + 1, last = a.ks[s + 1] - 1;
+  if (first > last) return;
+  const int rb = w * 16 * RT;
+  const int64_t MM = (int64_t)Mp * Mp;
+  const int ng = Mp / KG;   // k-groups per step
+
+  const int64_t nsteps = 2 * (last - first) + 1;
+  auto step_matrix = [&](int64_t q) -> const T* {
+    return (q <= last - first) ? (const T*)a.Dinv + (first + q) * MM
+                               : (const T*)a.alpha + (last - 1 - (q - (last - first + 1))) * MM;
+  };
+  // lane's 16-byte slice of row (rb + 16t + L%16), k-group g
+  const int64_t lane_off = (int64_t)(rb + (L & 15)) * Mp + (KG / 4) * (L >> 4);
+  uint4 a0[RT], a1[RT];
+  auto loadA = [&](uint4 (&dst)[RT], const T* __restrict__ Ab, int g) {
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+      dst[t] = *reinterpret_cast<const uint4*>(Ab + lane_off + (int64_t)16 * t * Mp + KG * g);
+  };
+  f32x4 acc[RT][CT];
+  auto compute = [&](const uint4 (&av)[RT], int g) {
+    uint4 b[CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c)
+      b[c] = *reinterpret_cast<const uint4*>(In + (16 * c + (L & 15)) * SK + KG * g + (KG / 4) * (L >> 4));
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int c = 0; c < CT; ++c) Tr::mma(acc[t][c], av[t], b[c]);
+  };
+
+  for (int e = tid; e < Mp * KT; e += nthr) {
+    const int row = e % Mp, c = e / Mp;
+    const int col = col0 + c;
+    const double v = (row < M && col < K) ? a.F[first * M + row + (int64_t)col * a.ldf] : 0.0;
+    In[c * SK + row] = Tr::from_f((float)v);
+  }
+  loadA(a0, step_matrix(0), 0);
+  __syncthreads();
+
+  for (int64_t q = 0; q < nsteps; ++q) {
+    const bool fwd = q <= last - first;
+    const int64_t i = fwd ? first + q : last - 1 - (q - (last - first + 1));
+    const T* __restrict__ Ai = step_matrix(q);
+    const T* __restrict__ Anx = (q + 1 < nsteps) ? step_matrix(q + 1) : Ai;
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int c = 0; c < CT; ++c) acc[t][c] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    int g = 0;
+    for (; g + 2 < ng; g += 2) {
+      loadA(a1, Ai, g + 1);
+      compute(a0, g);
+      loadA(a0, Ai, g + 2);
+      compute(a1, g + 1);
+    }
+    // epilogue operands: rows 4(L/16)..+3 of column L%16 of each tile
+    const bool more = fwd && i < last;
+    float ex[RT][CT][4];
+    float an[RT][4];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int row0 = rb + 16 * t + 4 * (L >> 4);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) an[t][v] = more ? (float)a.adiag[(i + 1) * Mp + row0 + v] : 0.f;
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const int col = col0 + 16 * c + (L & 15);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = row0 + v;
+          float x = 0.f;
+          if (fwd) {
+            if (more && row < M && col < K) x = (float)a.F[(i + 1) * M + row + (int64_t)col * a.ldf];
+          } else if (col < K) {
+            x = a.W[i * Mp + row + (int64_t)col * a.ldw];
+          }
+          ex[t][c][v] = x;
+        }
+      }
+    }
+    if (ng - g == 2) {
+      loadA(a1, Ai, g + 1);
+      compute(a0, g);
+      loadA(a0, Anx, 0);
+      compute(a1, g + 1);
+    } else {
+      compute(a0, g);
+      loadA(a0, Anx, 0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int row0 = rb + 16 * t + 4 * (L >> 4);
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const int lc = 16 * c + (L & 15);
+        const int col = col0 + lc;
+        f32x4 vv;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) vv[v] = fwd ? acc[t][c][v] : acc[t][c][v] + ex[t][c][v];
+        if (col < K) *reinterpret_cast<f32x4*>(a.W + i * Mp + row0 + (int64_t)col * a.ldw) = vv;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float nxt = more ? ex[t][c][v] + an[t][v] * vv[v] : vv[v];
+          In[lc * SK + row0 + v] = Tr::from_f(nxt);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int PREC, int RT, int CT>
+__device__ __forceinline__ void superpose_lp_tile(const LpSupArgs& a, int s, int ct, uint4* lds_raw) {
+  using Tr = LP<PREC>;
+  using T = typename Tr::T;
+  constexpr int KG = Tr::KG;
+  constexpr int KT = 16 * CT;
+  T* Xs = reinterpret_cast<T*>(lds_raw);   // [KT][SK]
+  const int Mp = a.Mp, M = a.M, K = a.K;
+  const int kd = 2 * Mp;
+  const int SK = kd + 16 / (int)sizeof(T);
+
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int L = tid & 63, w = tid >> 6;
+  const int col0 = ct * KT;
+  const int64_t first = a.ks[s] + 1, last = a.ks[s + 1] - 1;
+  if (first > last) return;
+  const int rb = w * 16 * RT;
+  const int64_t MM2 = (int64_t)Mp * kd;
+  const int ng = kd / KG;
+
+  for (int e = tid; e < kd * KT; e += nthr) {
+    const int k = e % kd, c = e / kd;
+    const int col = col0 + c;
+    const double v = (col < K) ? a.Xi[(int64_t)(s + 1) * Mp + k + (int64_t)col * a.ldxi] : 0.0;
+    Xs[c * SK + k] = Tr::from_f((float)v);
+  }
+
+  const int64_t lane_off = (int64_t)(rb + (L & 15)) * kd + (KG / 4) * (L >> 4);
+  uint4 a0[RT], a1[RT];
+  auto loadA = [&](uint4 (&dst)[RT], const T* __restrict__ Ab, int g) {
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+      dst[t] = *reinterpret_cast<const uint4*>(Ab + lane_off + (int64_t)16 * t * kd + KG * g);
+  };
+  f32x4 acc[RT][CT];
+  auto compute = [&](const uint4 (&av)[RT], int g) {
+    uint4 b[CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c)
+      b[c] = *reinterpret_cast<const uint4*>(Xs + (16 * c + (L & 15)) * SK + KG * g + (KG / 4) * (L >> 4));
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int c = 0; c < CT; ++c) Tr::mma(acc[t][c], av[t], b[c]);
+  };
+
+  const T* UVb = (const T*)a.UV;
+  loadA(a0, UVb + first * MM2, 0);
+  __syncthreads();
+  for (int64_t i = first; i <= last; ++i) {
+    const T* __restrict__ Ai = UVb + i * MM2;
+    const T* __restrict__ Anx = (i < last) ? Ai + MM2 : Ai;
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int c = 0; c < CT; ++c) acc[t][c] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    int g = 0;
+    for (; g + 2 < ng; g += 2) {
+      loadA(a1, Ai, g + 1);
+      compute(a0, g);
+      loadA(a0, Ai, g + 2);
+      compute(a1, g + 1);
+    }
+    float wv[RT][CT][4];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int row0 = rb + 16 * t + 4 * (L >> 4);
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const int col = col0 + 16 * c + (L & 15);
+        f32x4 x = (f32x4){0.f, 0.f, 0.f, 0.f};
+        if (col < K) x = *reinterpret_cast<const f32x4*>(a.W + i * Mp + row0 + (int64_t)col * a.ldw);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) wv[t][c][v] = x[v];
+      }
+    }
+    if (ng - g == 2) {
+      loadA(a1, Ai, g + 1);
+      compute(a0, g);
+      loadA(a0, Anx, 0);
+      compute(a1, g + 1);
+    } else {
+      compute(a0, g);
+      loadA(a0, Anx, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int row0 = rb + 16 * t + 4 * (L >> 4);
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const int col = col0 + 16 * c + (L & 15);
+        if (col >= K) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = row0 + v;
+          if (row < M) {
+            double* xp = a.X + i * M + row + (int64_t)col * a.ldx;
+            const double d = (double)acc[t][c][v] + (double)wv[t][c][v];
+            *xp = a.accumulate ? *xp + d : d;
+          }
+        }
+      }
+    }
+  }
+}
+
+// one work-group of 256 threads: rows [q*chunk, (q+1)*chunk) of column col; red holds 8 doubles
+__device__ __forceinline__ void residual_stencil_tile(double* R, int64_t ldr, const double* F, int64_t ldf,
+                                                      const double* X, int64_t ldx, const double* A, const double* B,
+                                                      const double* C, int N, int M, int chunk, double* colpart,
+                                                      int nchunk, int q, int col, double (*red)[4]) {
+  const int64_t n = (int64_t)N * M;
+  const int64_t g0 = (int64_t)q * chunk;
+  const int64_t g1 = g0 + chunk < n ? g0 + chunk : n;
+  const double* x = X + (int64_t)col * ldx;
+  const double* f = F + (int64_t)col * ldf;
+  double sr = 0.0, sf = 0.0;
+  for (int64_t g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
+    const int64_t j = g / M;
+    const int r = (int)(g - j * M);
+    const double* t = C + j * 3 * M;
+    double y = t[M + r] * x[g];
+    if (r > 0) y += t[r] * x[g - 1];
+    if (r < M - 1) y += t[2 * M + r] * x[g + 1];
+    if (j > 0) y -= A[g] * x[g - M];
+    if (j < N - 1) y -= B[g] * x[g + M];
+    const double fv = f[g];
+    const double rv = fv - y;
+    if (R) R[g + (int64_t)col * ldr] = rv;
+    sr += rv * rv;
+    sf += fv * fv;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    sr += __shfl_xor(sr, off);
+    sf += __shfl_xor(sf, off);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = sr;
+    red[1][threadIdx.x >> 6] = sf;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int v = 0; v < 4; ++v) { a += red[0][v]; b += red[1][v]; }
+    colpart[((int64_t)col * nchunk + q) * 2 + 0] = a;
+    colpart[((int64_t)col * nchunk + q) * 2 + 1] = b;
+  }
+}
+
+}  // namespace td

@@ -1,0 +1,73 @@
+"""Batched solve of uneven systems (one persistent launch replayed from a HIP graph) against the
+CPU oracle: float32 sweeps, float64 reduced systems and refinement to a max column relative
+residual of 1e-10; error vs the float64 oracle <= 1e-9.  Replays of the graph give bitwise the
+same result as the first run."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from dense_ref import rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SHAPES = [  # N, M, K, p
+    (40, 64, 5, 4), (97, 64, 33, 6), (128, 128, 64, 8), (200, 64, 17, 10), (64, 256, 40, 4), (150, 128, 3, 15),
+]
+
+
+@pytest.fixture(scope="module")
+def td():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1108_4181_amd as m
+
+    m.load_library()
+    return m
+
+
+def _build(td):
+    plans, Fs, Xs, systems, Fh = [], [], [], [], []
+    for q, (N, M, K, p) in enumerate(SHAPES):
+        sys = synth.laplace_system(N, M, 4.5) if q % 2 == 0 else synth.varcoef_system(N, M, seed=300 + q)
+        F = synth.rhs_columns(300 + q, N, M, range(K))
+        plans.append(td.Plan.from_system(sys, subdomains=p, sweep_prec="f32"))
+        Fs.append(torch.as_tensor(F, device="cuda"))
+        Xs.append(torch.zeros((K, N * M), dtype=torch.float64, device="cuda"))
+        systems.append(sys)
+        Fh.append(F)
+    return plans, Fs, Xs, systems, Fh
+
+
+def test_batched_matches_oracle_and_replays(td):
+    plans, Fs, Xs, systems, Fh = _build(td)
+    batch = td.Batch(plans, Fs, Xs, passes=4, tol=1e-10)
+    batch.solve()
+    infos, ok = batch.info()
+    assert ok, infos
+    first = [x.clone() for x in Xs]
+    for q, (sys, F) in enumerate(zip(systems, Fh)):
+        X = Xs[q].cpu().numpy()
+        R = F - oracle.apply(sys, X)
+        res = float(np.max(np.linalg.norm(R, axis=1) / np.linalg.norm(F, axis=1)))
+        assert res <= 1e-10 and infos[q]["max_col_rel_residual"] <= 1e-10, (q, res, infos[q])
+        assert rel_err(X, oracle.solve(sys, F)) <= 1e-9
+    for _ in range(2):
+        for x in Xs:
+            x.zero_()
+        batch.solve()
+        _, ok = batch.info()
+        assert ok
+        for a, b in zip(first, Xs):
+            assert torch.equal(a, b)
+    batch.close()
+
+
+def test_batched_rejects_float64_plans(td):
+    sys = synth.laplace_system(32, 64, 4.5)
+    plan = td.Plan.from_system(sys, subdomains=2)
+    F = torch.zeros((2, 32 * 64), dtype=torch.float64, device="cuda")
+    with pytest.raises(td.TridiagError) as e:
+        td.Batch([plan], [F], [torch.zeros_like(F)])
+    assert e.value.code == 7
