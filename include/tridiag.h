@@ -162,6 +162,16 @@ td_status tridiag_set_profiling(td_plan plan, int enable);
 td_status tridiag_stage_times(td_plan plan, double* ms, int n);
 
 /*
+ * Autotuner: times the solve of a probe system (probe_N block rows of M x M blocks,
+ * C = tridiag(-1, 4.5, -1), A = B = I, K hashed right-hand sides) for each candidate subdomain
+ * length L (p = probe_N / L) in the given precision and returns the fastest L in *best_L and
+ * the per-candidate milliseconds per solve in ms_per_solve (ncand entries, may be NULL).
+ * Allocates and frees its own device memory; synchronises the stream.
+ */
+td_status tridiag_autotune(int64_t M, int64_t K, int32_t sweep_prec, int64_t probe_N, const int64_t* candidates,
+                           int ncand, void* stream, int64_t* best_L, double* ms_per_solve);
+
+/*
  * Batched solve of many independent systems (not in the paper): one persistent launch over
  * a work list of all systems' stages, captured once in a HIP graph and replayed by
  * tridiag_batch_solve.  Each pass solves every system (pass 0 with F, later passes with the

@@ -57,7 +57,7 @@ class _PlanInfo(ctypes.Structure):
 EXPORTS = ["tridiag_factor", "tridiag_solve", "tridiag_solve_adjoint", "tridiag_diag_grad", "tridiag_destroy",
            "tridiag_plan_info", "tridiag_set_profiling", "tridiag_stage_times", "tridiag_status_string",
            "tridiag_last_error", "tridiag_batch_create", "tridiag_batch_solve", "tridiag_batch_info",
-           "tridiag_batch_destroy"]
+           "tridiag_batch_destroy", "tridiag_autotune"]
 
 _lib = None
 
@@ -102,6 +102,8 @@ def load_library(path: str = LIB_PATH):
     lib.tridiag_batch_info.restype = i32
     lib.tridiag_batch_destroy.argtypes = [vp]
     lib.tridiag_batch_destroy.restype = i32
+    lib.tridiag_autotune.argtypes = [i64, i64, i32, i64, pi64, ctypes.c_int, vp, pi64, ctypes.POINTER(dp)]
+    lib.tridiag_autotune.restype = i32
     _lib = lib
     return lib
 
@@ -321,3 +323,56 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def choose_subdomains(N: int, M: int, K: int, sweep_prec: str = "f64") -> int:
+    """Subdomain count for an N x M system with K right-hand sides: N / L with the subdomain length
+    L chosen by the autotuner's cached result for (M, K bucket, precision) when present, else 32."""
+    L = autotuned_length(M, K, sweep_prec)
+    return max(1, min(N, N // L))
+
+
+def _cache_path():
+    return os.environ.get("TD_AUTOTUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "tridiag_autotune.json"))
+
+
+def _kbucket(K):
+    b = 16
+    while b < K:
+        b *= 2
+    return b
+
+
+def autotuned_length(M, K, sweep_prec="f64", default=32):
+    import json
+    try:
+        with open(_cache_path()) as f:
+            cache = json.load(f)
+    except (OSError, ValueError):
+        return default
+    return int(cache.get(f"gfx950|M{M}|K{_kbucket(K)}|{sweep_prec}", {}).get("L", default))
+
+
+def autotune(M, K, sweep_prec="f64", probe_N=1024, candidates=(8, 16, 32, 64, 128), store=True):
+    """Time the candidate subdomain lengths on a probe system (C++ search in the library) and
+    record the fastest in the JSON cache keyed by (arch, M, K bucket, precision)."""
+    import json
+    lib = load_library()
+    cand = [c for c in candidates if c <= probe_N]
+    best = ctypes.c_int64()
+    ms = (ctypes.c_double * len(cand))()
+    _check(lib.tridiag_autotune(int(M), int(_kbucket(K)), PREC[sweep_prec], int(probe_N),
+                                (ctypes.c_int64 * len(cand))(*cand), len(cand), _stream(), ctypes.byref(best), ms))
+    result = {"L": int(best.value), "ms_per_solve": dict(zip(map(str, cand), list(ms))), "probe_N": probe_N}
+    if store:
+        path = _cache_path()
+        try:
+            with open(path) as f:
+                cache = json.load(f)
+        except (OSError, ValueError):
+            cache = {}
+        cache[f"gfx950|M{M}|K{_kbucket(K)}|{sweep_prec}"] = result
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        with open(path, "w") as f:
+            json.dump(cache, f, indent=1)
+    return result

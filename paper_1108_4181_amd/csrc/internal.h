@@ -146,6 +146,7 @@ hipError_t launch_axpy_cols(double* X, int64_t ldx, const double* D, int64_t ldd
 hipError_t launch_diag_grad(double* out, const double* Lam, int64_t ldl, const double* X, int64_t ldx,
                             int64_t n, int K, hipStream_t st);
 hipError_t launch_nonfinite(int32_t* flag, const double* X, int64_t ldx, int64_t n, int K, hipStream_t st);
+hipError_t launch_probe_inputs(double* A, double* B, double* C, double* F, int N, int M, int64_t K, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Batched solve of many independent systems in one persistent launch

@@ -922,4 +922,35 @@ hipError_t launch_nonfinite(int32_t* flag, const double* X, int64_t ldx, int64_t
   return hipGetLastError();
 }
 
+// Probe inputs of the autotuner: tridiag(-1, d, -1) blocks and hashed uniform[-1,1) right-hand sides.
+__global__ void k_fill_tridiag(double* C, int N, int M, double d) {
+  const int64_t n = (int64_t)N * 3 * M;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int part = (int)((e / M) % 3);
+    const int r = (int)(e % M);
+    double v = (part == 1) ? d : -1.0;
+    if ((part == 0 && r == 0) || (part == 2 && r == M - 1)) v = 0.0;
+    C[e] = v;
+  }
+}
+
+__global__ void k_fill_hash(double* F, int64_t n, uint64_t seed) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t z = seed + (uint64_t)(e + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    F[e] = 2.0 * ((double)(z >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
+  }
+}
+
+hipError_t launch_probe_inputs(double* A, double* B, double* C, double* F, int N, int M, int64_t K, hipStream_t st) {
+  hipError_t e = launch_fill(A, (int64_t)N * M, 1.0, st);
+  if (e == hipSuccess) e = launch_fill(B, (int64_t)N * M, 1.0, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fill_tridiag, dim3(256), dim3(256), 0, st, C, N, M, 4.5);
+  hipLaunchKernelGGL(k_fill_hash, dim3(1024), dim3(256), 0, st, F, (int64_t)N * M * K, (uint64_t)12345);
+  return hipGetLastError();
+}
+
 }  // namespace td

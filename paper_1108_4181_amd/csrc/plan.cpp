@@ -1318,6 +1318,60 @@ const char* tridiag_status_string(td_status s) {
 
 const char* tridiag_last_error(void) { return g_err.c_str(); }
 
+td_status tridiag_autotune(int64_t M, int64_t K, int32_t sweep_prec, int64_t probe_N, const int64_t* candidates,
+                           int ncand, void* stream, int64_t* best_L, double* ms_per_solve) {
+  g_err.clear();
+  if (M < 1 || M > 512 || K < 1 || probe_N < 2 || !candidates || ncand < 1 || !best_L)
+    return fail(TD_EINVAL, "bad autotune arguments");
+  hipStream_t st = (hipStream_t)stream;
+  double *A = nullptr, *B = nullptr, *C = nullptr, *F = nullptr, *X = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  td_status result = TD_OK;
+  try {
+    HIPCHK(hipMalloc((void**)&A, probe_N * M * 8));
+    HIPCHK(hipMalloc((void**)&B, probe_N * M * 8));
+    HIPCHK(hipMalloc((void**)&C, probe_N * 3 * M * 8));
+    HIPCHK(hipMalloc((void**)&F, probe_N * M * K * 8));
+    HIPCHK(hipMalloc((void**)&X, probe_N * M * K * 8));
+    HIPCHK(launch_probe_inputs(A, B, C, F, (int)probe_N, (int)M, K, st));
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    double best = INFINITY;
+    *best_L = candidates[0];
+    for (int c = 0; c < ncand; ++c) {
+      const int64_t L = std::max<int64_t>(1, candidates[c]);
+      td_desc d;
+      std::memset(&d, 0, sizeof d);
+      d.N = probe_N; d.M = M; d.subdomains = std::max<int64_t>(1, probe_N / L);
+      d.fmt_A = TD_FMT_DIAG; d.fmt_B = TD_FMT_DIAG; d.fmt_C = TD_FMT_TRIDIAG; d.sweep_prec = sweep_prec;
+      td_plan P = nullptr;
+      td_status s = factor_top(&d, A, B, C, st, &P, false);
+      if (s != TD_OK) { result = s; break; }
+      s = solve_impl(P, F, probe_N * M, X, probe_N * M, K, nullptr, nullptr, st);
+      if (s == TD_OK) {
+        HIPCHK(hipEventRecord(e0, st));
+        for (int r = 0; r < 3 && s == TD_OK; ++r) s = solve_impl(P, F, probe_N * M, X, probe_N * M, K, nullptr, nullptr, st);
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+      }
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      delete P;
+      if (s != TD_OK) { result = s; break; }
+      if (ms_per_solve) ms_per_solve[c] = ms / 3.0;
+      if (ms / 3.0 < best) { best = ms / 3.0; *best_L = L; }
+    }
+  } catch (const HipFail& e) {
+    result = fail(e.e == hipErrorOutOfMemory ? TD_ENOMEM : TD_EHIP,
+                  std::string("HIP error ") + hipGetErrorString(e.e) + " in " + e.where);
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(A); (void)hipFree(B); (void)hipFree(C); (void)hipFree(F); (void)hipFree(X);
+  return result;
+}
+
 td_status tridiag_batch_create(int n, const td_plan* plans, const double* const* F, const int64_t* ldf,
                                double* const* X, const int64_t* ldx, const int64_t* K, int passes, double tol,
                                void* stream, td_batch* out) {
