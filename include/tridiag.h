@@ -176,13 +176,15 @@ td_status tridiag_autotune(int64_t M, int64_t K, int32_t sweep_prec, int64_t pro
  * a work list of all systems' stages, captured once in a HIP graph and replayed by
  * tridiag_batch_solve.  Each pass solves every system (pass 0 with F, later passes with the
  * float64 residual, adding the correction to X); a system that has reached `tol` skips the
- * remaining passes.  The plans must have sweep_prec TD_PREC_F32, diagonal A and B,
+ * remaining passes.  The plans must have sweep_prec TD_PREC_F64 or TD_PREC_F32, diagonal A and B,
  * tridiagonal C and padded block sizes 64, 128 or 256; they must outlive the batch, and the
  * F / X buffers given here are the ones every replay reads and writes (device pointers, one
  * per system, column-major N_q*M_q x K_q).  Calls that share a plan's workspace must not
  * overlap.  tridiag_batch_info synchronises and reports, per system, the passes used after the
  * first (iterations) and the final max column relative residual; it returns TD_ENOCONV if
  * a system did not reach `tol`, TD_EHIP if a dependency wait inside the launch timed out.
+ * Plans may mix TD_PREC_F64 (float64 sweeps) and TD_PREC_F32.  tol == 0 means 1e-10; tol < 0
+ * runs a single pass without residual test (infos then report -1).
  */
 typedef struct td_batch_s* td_batch;
 td_status tridiag_batch_create(int n, const td_plan* plans, const double* const* F, const int64_t* ldf,

@@ -168,8 +168,10 @@ struct BatchItem {
 };
 
 struct BatchSys {
-  LpSweepArgs sweep;       // input F; the correction passes read R instead
+  LpSweepArgs sweep;       // float32 plans: input F; the correction passes read R instead
   LpSupArgs sup;
+  SweepArgs sweep64;       // float64 plans
+  SupArgs sup64;
   BArgs part;
   BArgs lev[BATCH_MAXDEPTH];
   double* Ft; int64_t ldft;
@@ -181,7 +183,7 @@ struct BatchSys {
   double* colpart;         // [K][nchunk][2]
   double* resid;           // [passes]: max column relative residual after each pass
   int32_t N, M, Mp, p, K, rt, nchunk, rescols;
-  int32_t conv_pass;       // unused on the device (host bookkeeping)
+  int32_t prec;            // TD_PREC_F64 (0) or TD_PREC_F32 (1)
   int32_t pad_;
   double tol;
 };

@@ -37,9 +37,15 @@ __device__ void run_item(const BatchItem& it, const BatchSys& S, uint4* lds, dou
   const int tid = threadIdx.x;
   switch (it.type) {
     case BI_SWEEP: {
-      LpSweepArgs a = S.sweep;
-      if (it.pass > 0) { a.F = S.R; a.ldf = S.ldr; }
-      sweep_lp_tile<1, RT, 2>(a, it.i0, it.i1, lds);
+      if (S.prec == 0) {
+        SweepArgs a = S.sweep64;
+        if (it.pass > 0) { a.F = S.R; a.ldf = S.ldr; }
+        sweep_f64_tile<RT, 4>(a, it.i0, it.i1, reinterpret_cast<double*>(lds));
+      } else {
+        LpSweepArgs a = S.sweep;
+        if (it.pass > 0) { a.F = S.R; a.ldf = S.ldr; }
+        sweep_lp_tile<1, RT, 2>(a, it.i0, it.i1, lds);
+      }
       break;
     }
     case BI_FTILDE: {
@@ -49,7 +55,8 @@ __device__ void run_item(const BatchItem& it, const BatchSys& S, uint4* lds, dou
       const int64_t e0 = (int64_t)it.i0 * FT_CHUNK;
       const int64_t e1 = e0 + FT_CHUNK < n ? e0 + FT_CHUNK : n;
       const int64_t* ks = S.sweep.ks;
-      const float* W = S.sweep.W;
+      const float* W32 = S.sweep.W;
+      const double* W64 = S.sweep64.W;
       const int64_t ldw = S.sweep.ldw;
       for (int64_t e = e0 + tid; e < e1; e += BATCH_THREADS) {
         const int r = (int)(e % S.Mp);
@@ -58,25 +65,37 @@ __device__ void run_item(const BatchItem& it, const BatchSys& S, uint4* lds, dou
         const int64_t col = sc / S.p;
         const int64_t k = ks[s];
         double v = (r < S.M) ? F[k * S.M + r + col * ldf] : 0.0;
-        if (s > 0 && k - 1 > ks[s - 1]) v += S.adiag[k * S.Mp + r] * (double)W[(k - 1) * S.Mp + r + col * ldw];
-        if (k + 1 < ks[s + 1]) v += S.bdiag[k * S.Mp + r] * (double)W[(k + 1) * S.Mp + r + col * ldw];
+        if (s > 0 && k - 1 > ks[s - 1]) {
+          const int64_t o = (k - 1) * S.Mp + r + col * ldw;
+          v += S.adiag[k * S.Mp + r] * (S.prec == 0 ? W64[o] : (double)W32[o]);
+        }
+        if (k + 1 < ks[s + 1]) {
+          const int64_t o = (k + 1) * S.Mp + r + col * ldw;
+          v += S.bdiag[k * S.Mp + r] * (S.prec == 0 ? W64[o] : (double)W32[o]);
+        }
         S.Ft[(int64_t)s * S.Mp + r + col * S.ldft] = v;
       }
       break;
     }
     case BI_PART:
-      bgemm_tile<RT, 8>(S.part, it.i0, it.i1, reinterpret_cast<double*>(lds));
+      bgemm_tile<RT, 4>(S.part, it.i0, it.i1, reinterpret_cast<double*>(lds));
       break;
     case BI_LEVEL: {
       BArgs b = S.lev[it.lvl];
       b.x2accum = it.pass > 0 ? 1 : 0;
-      bgemm_tile<RT, 8>(b, it.i0, it.i1, reinterpret_cast<double*>(lds));
+      bgemm_tile<RT, 4>(b, it.i0, it.i1, reinterpret_cast<double*>(lds));
       break;
     }
     case BI_SUP: {
-      LpSupArgs u = S.sup;
-      u.accumulate = it.pass > 0 ? 1 : 0;
-      superpose_lp_tile<1, RT, 2>(u, it.i0, it.i1, lds);
+      if (S.prec == 0) {
+        SupArgs u = S.sup64;
+        u.accumulate = it.pass > 0 ? 1 : 0;
+        superpose_f64_tile<RT, 4>(u, it.i0, it.i1, reinterpret_cast<double*>(lds));
+      } else {
+        LpSupArgs u = S.sup;
+        u.accumulate = it.pass > 0 ? 1 : 0;
+        superpose_lp_tile<1, RT, 2>(u, it.i0, it.i1, lds);
+      }
       break;
     }
     case BI_RES: {
@@ -115,7 +134,7 @@ __device__ void run_item(const BatchItem& it, const BatchSys& S, uint4* lds, dou
   }
 }
 
-__global__ void __launch_bounds__(BATCH_THREADS) k_batched(const BatchItem* __restrict__ items, int nitems,
+__global__ void __launch_bounds__(BATCH_THREADS, 2) k_batched(const BatchItem* __restrict__ items, int nitems,
                                                            const BatchSys* __restrict__ sys, int32_t* counters,
                                                            int32_t* conv, BatchCtl* ctl, int64_t spin_limit) {
   extern __shared__ uint4 lds[];
@@ -127,9 +146,10 @@ __global__ void __launch_bounds__(BATCH_THREADS) k_batched(const BatchItem* __re
     const int idx = sh_idx;
     if (idx >= nitems) break;
     const BatchItem it = items[idx];
+    // thread 0's agent-scope acquire (in the wait) invalidates this CU's L1 and the XCD's L2 for
+    // every wave of the work-group; the barrier orders the other waves after it
     if (threadIdx.x == 0) sh_ok = (it.dep < 0) ? 1 : (wait_counter(counters + it.dep, it.need, &ctl->error, spin_limit) ? 1 : 0);
     __syncthreads();
-    __threadfence();   // acquire the producers' results in every wave
     const BatchSys& S = sys[it.sys];
     const bool skip = it.pass > 0 && __hip_atomic_load(conv + it.sys, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < it.pass;
     if (!skip) {
@@ -139,7 +159,9 @@ __global__ void __launch_bounds__(BATCH_THREADS) k_batched(const BatchItem* __re
         default: run_item<1>(it, S, lds, red, conv); break;
       }
     }
-    __threadfence();   // release this item's results before it is counted
+    // every wave's stores complete (workgroup release), then one agent-scope release (L2 write-back)
+    // and the count
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
     if (threadIdx.x == 0) __hip_atomic_fetch_add(counters + it.mine, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     (void)sh_ok;
@@ -152,8 +174,9 @@ __global__ void k_batch_reset(int32_t* counters, int ncounters, int32_t* conv, i
   if (blockIdx.x == 0 && threadIdx.x == 0) { ctl->head = 0; ctl->error = 0; }
 }
 
-// LDS of the largest tile body: float32 superposition with 32 columns of 2*256 rows
-int batched_lds_bytes() { return 32 * (2 * 256 * 4 + 16); }
+// LDS of the largest tile body: float64 superposition with 16 columns of 2*256 rows
+// (float64 sweep: 256 x 18 doubles; float32 superposition: 32 x (2*256 + 4) floats)
+int batched_lds_bytes() { return 2 * 256 * 18 * 8; }
 
 hipError_t launch_batched(const BatchItem* items, int nitems, const BatchSys* sys, int32_t* counters, int ncounters,
                           int32_t* conv, int nsys, BatchCtl* ctl, int grid, int64_t spin_limit, hipStream_t st) {

@@ -67,121 +67,11 @@ hipError_t launch_bgemm(const BArgs& a, hipStream_t st) {
 // ---------------------------------------------------------------------------
 template <int RT, int CT>
 __global__ void __launch_bounds__(512) k_sweep_f64(SweepArgs a) {
-  constexpr int KT = 4 * CT;
-  constexpr int SB = KT + 2;
-  extern __shared__ double In[];  // [Mp][SB]
-
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int L = tid & 63, w = tid >> 6;
+  extern __shared__ double In[];  // [Mp][4 CT + 2]
   const int lg = xcd_remap(blockIdx.x, gridDim.x);
   if (lg >= a.total) return;
   const int s = lg / a.ncoltiles;
-  const int ct = lg - s * a.ncoltiles;
-  const int col0 = ct * KT;
-  const int64_t first = a.ks[s] + 1, last = a.ks[s + 1] - 1;
-  if (first > last) return;
-  const int Mp = a.Mp, M = a.M, K = a.K;
-  const int rb = w * 16 * RT;
-  const int64_t MM = (int64_t)Mp * Mp;
-  constexpr int KU = 2;      // MFMA k-steps (of 4) per register chunk of the streamed matrix
-  const int nkc = Mp / (4 * KU);   // even: Mp is a multiple of 16
-
-  // The step matrix streams through two register buffers, each loaded one chunk ahead of
-  // its use; after the last chunk of a step comes the first chunk of the next step's
-  // matrix.  Step order: forward rows first..last (D^{-1}), then backward rows
-  // last-1..first (alpha).
-  const int64_t nsteps = 2 * (last - first) + 1;
-  auto step_matrix = [&](int64_t q) -> const double* {
-    return (q <= last - first) ? a.Dinv + (first + q) * MM : a.alpha + (last - 1 - (q - (last - first + 1))) * MM;
-  };
-  const int64_t lane_off = rb + (L & 15) + (int64_t)(L >> 4) * Mp;
-  double a0[KU][RT], a1[KU][RT];
-  auto loadA = [&](double (&dst)[KU][RT], const double* __restrict__ Ab, int q) {
-    const double* __restrict__ pa = Ab + lane_off + (int64_t)(4 * KU * q) * Mp;
-#pragma unroll
-    for (int u = 0; u < KU; ++u)
-#pragma unroll
-      for (int t = 0; t < RT; ++t) dst[u][t] = pa[16 * t + (int64_t)(4 * u) * Mp];
-  };
-  double acc[RT][CT];
-  auto compute = [&](const double (&av)[KU][RT], int q) {
-#pragma unroll
-    for (int u = 0; u < KU; ++u) {
-      const double* bp = &In[(4 * KU * q + 4 * u + (L >> 4)) * SB + (L & 3) * CT];
-      double b[CT];
-#pragma unroll
-      for (int c = 0; c < CT; ++c) b[c] = bp[c];
-#pragma unroll
-      for (int t = 0; t < RT; ++t)
-#pragma unroll
-        for (int c = 0; c < CT; ++c) acc[t][c] = mfma4(av[u][t], b[c], acc[t][c]);
-    }
-  };
-
-  for (int e = tid; e < Mp * KT; e += nthr) {
-    const int row = e % Mp, c = e / Mp;
-    const int col = col0 + c;
-    In[row * SB + c] = (row < M && col < K) ? a.F[first * M + row + (int64_t)col * a.ldf] : 0.0;
-  }
-  loadA(a0, step_matrix(0), 0);
-  __syncthreads();
-
-  for (int64_t q = 0; q < nsteps; ++q) {
-    const bool fwd = q <= last - first;
-    const int64_t i = fwd ? first + q : last - 1 - (q - (last - first + 1));
-    const double* __restrict__ Ai = step_matrix(q);
-    const double* __restrict__ Anx = (q + 1 < nsteps) ? step_matrix(q + 1) : Ai;
-#pragma unroll
-    for (int t = 0; t < RT; ++t)
-#pragma unroll
-      for (int c = 0; c < CT; ++c) acc[t][c] = 0.0;
-    for (int kc = 0; kc < nkc - 2; kc += 2) {
-      loadA(a1, Ai, kc + 1);
-      compute(a0, kc);
-      loadA(a0, Ai, kc + 2);
-      compute(a1, kc + 1);
-    }
-    // operands of the epilogue, fetched before the last two chunks: F_{i+1} and a_{i+1}
-    // (forward) or beta_i (backward)
-    double ex[RT][CT], an[RT];
-    const bool more = fwd && i < last;
-#pragma unroll
-    for (int t = 0; t < RT; ++t) {
-      const int row = rb + 16 * t + out_row(L);
-      an[t] = more ? a.adiag[(i + 1) * Mp + row] : 0.0;
-#pragma unroll
-      for (int c = 0; c < CT; ++c) {
-        const int col = col0 + out_col(L) * CT + c;
-        double v = 0.0;
-        if (fwd) {
-          if (more && row < M && col < K) v = a.F[(i + 1) * M + row + (int64_t)col * a.ldf];
-        } else if (col < K) {
-          v = a.W[i * Mp + row + (int64_t)col * a.ldw];
-        }
-        ex[t][c] = v;
-      }
-    }
-    loadA(a1, Ai, nkc - 1);
-    compute(a0, nkc - 2);
-    loadA(a0, Anx, 0);
-    compute(a1, nkc - 1);
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < RT; ++t) {
-      const int row = rb + 16 * t + out_row(L);
-#pragma unroll
-      for (int c = 0; c < CT; ++c) {
-        const int lc = out_col(L) * CT + c;
-        const int col = col0 + lc;
-        // forward: beta_i; next operand F_{i+1} + a_{i+1} o beta_i (or beta_last = W_last)
-        // backward: W_i = alpha_i W_{i+1} + beta_i
-        const double v = fwd ? acc[t][c] : acc[t][c] + ex[t][c];
-        if (col < K) a.W[i * Mp + row + (int64_t)col * a.ldw] = v;
-        In[row * SB + lc] = more ? ex[t][c] + an[t] * v : v;
-      }
-    }
-    __syncthreads();
-  }
+  sweep_f64_tile<RT, CT>(a, s, lg - s * a.ncoltiles, In);
 }
 
 int sweep_coltile(int Mp, int K) {
@@ -237,100 +127,11 @@ hipError_t launch_sweep(const SweepArgs& a, hipStream_t st) {
 // ---------------------------------------------------------------------------
 template <int RT, int CT>
 __global__ void __launch_bounds__(512) k_superpose_f64(SupArgs a) {
-  constexpr int KT = 4 * CT;
-  constexpr int SB = KT + 2;
-  extern __shared__ double Xs[];  // [2 Mp][SB]
-
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int L = tid & 63, w = tid >> 6;
+  extern __shared__ double Xs[];  // [2 Mp][4 CT + 2]
   const int lg = xcd_remap(blockIdx.x, gridDim.x);
   if (lg >= a.total) return;
   const int s = lg / a.ncoltiles;
-  const int ct = lg - s * a.ncoltiles;
-  const int col0 = ct * KT;
-  const int64_t first = a.ks[s] + 1, last = a.ks[s + 1] - 1;
-  if (first > last) return;
-  const int Mp = a.Mp, M = a.M, K = a.K;
-  const int rb = w * 16 * RT;
-  const int64_t MM = (int64_t)Mp * Mp;
-  const int kd = 2 * Mp;
-  const int nkc = kd / 8;  // chunks of 2 MFMA k-steps; even
-
-  for (int e = tid; e < kd * KT; e += nthr) {
-    const int k = e % kd, c = e / kd;
-    const int col = col0 + c;
-    Xs[k * SB + c] = (col < K) ? a.Xi[(int64_t)(s + 1) * Mp + k + (int64_t)col * a.ldxi] : 0.0;
-  }
-
-  const int64_t lane_off = rb + (L & 15) + (int64_t)(L >> 4) * Mp;
-  double a0[2][RT], a1[2][RT];
-  auto loadA = [&](double (&dst)[2][RT], const double* __restrict__ Ab, int q) {
-    const double* __restrict__ pa = Ab + lane_off + (int64_t)(8 * q) * Mp;
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int t = 0; t < RT; ++t) dst[u][t] = pa[16 * t + (int64_t)(4 * u) * Mp];
-  };
-  double acc[RT][CT];
-  auto compute = [&](const double (&av)[2][RT], int q) {
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const double* bp = &Xs[(8 * q + 4 * u + (L >> 4)) * SB + (L & 3) * CT];
-      double b[CT];
-#pragma unroll
-      for (int c = 0; c < CT; ++c) b[c] = bp[c];
-#pragma unroll
-      for (int t = 0; t < RT; ++t)
-#pragma unroll
-        for (int c = 0; c < CT; ++c) acc[t][c] = mfma4(av[u][t], b[c], acc[t][c]);
-    }
-  };
-
-  loadA(a0, a.UV + 2 * first * MM, 0);
-  __syncthreads();
-  for (int64_t i = first; i <= last; ++i) {
-    const double* __restrict__ Ai = a.UV + 2 * i * MM;
-    const double* __restrict__ Anx = (i < last) ? Ai + 2 * MM : Ai;
-#pragma unroll
-    for (int t = 0; t < RT; ++t)
-#pragma unroll
-      for (int c = 0; c < CT; ++c) acc[t][c] = 0.0;
-    for (int kc = 0; kc < nkc - 2; kc += 2) {
-      loadA(a1, Ai, kc + 1);
-      compute(a0, kc);
-      loadA(a0, Ai, kc + 2);
-      compute(a1, kc + 1);
-    }
-    double ex[RT][CT];
-#pragma unroll
-    for (int t = 0; t < RT; ++t) {
-      const int row = rb + 16 * t + out_row(L);
-#pragma unroll
-      for (int c = 0; c < CT; ++c) {
-        const int col = col0 + out_col(L) * CT + c;
-        ex[t][c] = (col < K) ? a.W[i * Mp + row + (int64_t)col * a.ldw] : 0.0;
-      }
-    }
-    loadA(a1, Ai, nkc - 1);
-    compute(a0, nkc - 2);
-    loadA(a0, Anx, 0);
-    compute(a1, nkc - 1);
-#pragma unroll
-    for (int t = 0; t < RT; ++t) {
-      const int row = rb + 16 * t + out_row(L);
-      if (row < M) {
-#pragma unroll
-        for (int c = 0; c < CT; ++c) {
-          const int col = col0 + out_col(L) * CT + c;
-          if (col < K) {
-            double* xp = a.X + i * M + row + (int64_t)col * a.ldx;
-            const double d = acc[t][c] + ex[t][c];
-            *xp = a.accumulate ? *xp + d : d;
-          }
-        }
-      }
-    }
-  }
+  superpose_f64_tile<RT, CT>(a, s, lg - s * a.ncoltiles, Xs);
 }
 
 template <int RT, int CT>

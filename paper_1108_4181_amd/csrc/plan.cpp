@@ -1000,6 +1000,7 @@ struct td_batch_s {
   BatchCtl* d_ctl = nullptr;
   double* d_resid = nullptr;
   int passes = 0;
+  bool check = true;
   int grid = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1031,10 +1032,12 @@ td_status batch_create_impl(int n, const td_plan* plans, const double* const* F,
                             hipStream_t st, td_batch_s* B) {
   if (n <= 0 || !plans || !F || !ldf || !X || !ldx || !K) return fail(TD_EINVAL, "bad batch arguments");
   if (passes < 1 || passes > 16) return fail(TD_EINVAL, "passes must be in [1, 16]");
+  const bool check = tol >= 0.0;   // tol < 0: one pass, no residual test
+  if (!check) passes = 1;
   for (int q = 0; q < n; ++q) {
     td_plan_s* P = plans[q];
     if (!P) return fail(TD_EINVAL, "null plan in batch");
-    if (P->prec != TD_PREC_F32) return fail(TD_ENOTSUP, "batched plans must have sweep_prec TD_PREC_F32");
+    if (P->prec == TD_PREC_BF16) return fail(TD_ENOTSUP, "batched plans must have sweep_prec F64 or F32");
     if (!stencil_formats(P)) return fail(TD_ENOTSUP, "batched plans need diagonal A, B and tridiagonal C");
     if (!(P->Mp == 64 || P->Mp == 128 || P->Mp == 256)) return fail(TD_ENOTSUP, "batched plans need Mp in {64,128,256}");
     if (P->depth > BATCH_MAXDEPTH) return fail(TD_ENOTSUP, "dichotomy tree too deep for the batched kernel");
@@ -1044,6 +1047,7 @@ td_status batch_create_impl(int n, const td_plan* plans, const double* const* F,
   }
   B->n = n;
   B->passes = passes;
+  B->check = check;
   B->plans.assign(plans, plans + n);
   std::vector<BatchSys> sys(n);
   std::vector<int> cbase(n), nst(n);
@@ -1063,6 +1067,15 @@ td_status batch_create_impl(int n, const td_plan* plans, const double* const* F,
     S.sup.ks = P->d_ks; S.sup.UV = P->UVlp; S.sup.Xi = P->Xi; S.sup.ldxi = ldxi;
     S.sup.W = P->W32; S.sup.ldw = ldw; S.sup.X = X[q]; S.sup.ldx = ldx[q];
     S.sup.N = (int32_t)N; S.sup.M = (int32_t)M; S.sup.Mp = (int32_t)Mp; S.sup.p = (int32_t)p; S.sup.K = (int32_t)Kq;
+    S.sweep64.ks = P->d_ks; S.sweep64.Dinv = P->Dinv; S.sweep64.alpha = P->alpha; S.sweep64.adiag = P->adiag;
+    S.sweep64.F = F[q]; S.sweep64.ldf = ldf[q]; S.sweep64.W = P->Wbuf; S.sweep64.ldw = ldw;
+    S.sweep64.N = (int32_t)N; S.sweep64.M = (int32_t)M; S.sweep64.Mp = (int32_t)Mp; S.sweep64.p = (int32_t)p;
+    S.sweep64.K = (int32_t)Kq;
+    S.sup64.ks = P->d_ks; S.sup64.UV = P->UVa ? P->UVa + 2 * Mp * Mp : nullptr; S.sup64.Xi = P->Xi;
+    S.sup64.ldxi = ldxi; S.sup64.W = P->Wbuf; S.sup64.ldw = ldw; S.sup64.X = X[q]; S.sup64.ldx = ldx[q];
+    S.sup64.N = (int32_t)N; S.sup64.M = (int32_t)M; S.sup64.Mp = (int32_t)Mp; S.sup64.p = (int32_t)p;
+    S.sup64.K = (int32_t)Kq;
+    S.prec = P->prec;
     BArgs a = bargs_base((int)Mp);
     a.descs = P->d_part; a.nprob = P->n_part;
     a.A = P->G; a.lda = Mp; a.B = P->Ft; a.ldb = ldft; a.C = P->Sp; a.ldc = ldsp; a.ncols = (int32_t)Kq;
@@ -1079,10 +1092,11 @@ td_status batch_create_impl(int n, const td_plan* plans, const double* const* F,
     }
     S.Ft = P->Ft; S.ldft = ldft; S.adiag = P->adiag; S.bdiag = P->bdiag;
     S.F = F[q]; S.ldf = ldf[q]; S.X = X[q]; S.ldx = ldx[q];
-    S.R = B->dalloc<double>((size_t)(N * M * Kq)); S.ldr = N * M;
+    S.R = check ? B->dalloc<double>((size_t)(N * M * Kq)) : nullptr;
+    S.ldr = N * M;
     S.cA = P->cA; S.cB = P->cB; S.cC = P->cC;
     S.nchunk = residual_chunks(N * M);
-    S.colpart = B->dalloc<double>((size_t)(S.nchunk * Kq * 2));
+    S.colpart = check ? B->dalloc<double>((size_t)(S.nchunk * Kq * 2)) : nullptr;
     S.resid = nullptr;  // set below
     S.N = (int32_t)N; S.M = (int32_t)M; S.Mp = (int32_t)Mp; S.p = (int32_t)p; S.K = (int32_t)Kq;
     S.rt = (int32_t)(Mp / 64);
@@ -1106,17 +1120,22 @@ td_status batch_create_impl(int n, const td_plan* plans, const double* const* F,
     const double wa = (double)(a->N / a->p) * a->Mp * a->Mp, wb = (double)(b->N / b->p) * b->Mp * b->Mp;
     return wa > wb;
   });
+  // column tiles per item type: float64 sweeps, superpositions and all dichotomy products use 16
+  // columns, float32 sweeps and superpositions 32
+  std::vector<int> nct_sw(n), nct_bg(n), nct_sup(n);
   std::vector<int> cnt_sweep(n), cnt_ft(n), cnt_part(n), cnt_sup(n), cnt_res(n);
   std::vector<std::vector<int>> cnt_lev(n);
   for (int q = 0; q < n; ++q) {
     td_plan_s* P = plans[q];
-    const int nct = (int)((K[q] + 31) / 32);
-    cnt_sweep[q] = (int)P->p * nct;
+    const int w = (P->prec == TD_PREC_F64) ? 16 : 32;
+    nct_sw[q] = nct_sup[q] = (int)((K[q] + w - 1) / w);
+    nct_bg[q] = (int)((K[q] + 15) / 16);
+    cnt_sweep[q] = (int)P->p * nct_sw[q];
     cnt_ft[q] = (int)((P->p * P->Mp * K[q] + 16383) / 16384);
-    cnt_part[q] = P->n_part * nct;
+    cnt_part[q] = P->n_part * nct_bg[q];
     cnt_lev[q].resize(P->depth);
-    for (int lv = 0; lv < P->depth; ++lv) cnt_lev[q][lv] = P->corr_count[lv] * nct;
-    cnt_sup[q] = (int)P->p * nct;
+    for (int lv = 0; lv < P->depth; ++lv) cnt_lev[q][lv] = P->corr_count[lv] * nct_bg[q];
+    cnt_sup[q] = (int)P->p * nct_sup[q];
     cnt_res[q] = sys[q].nchunk * (int)((K[q] + 7) / 8);
   }
   int maxdepth = 0;
@@ -1130,7 +1149,7 @@ td_status batch_create_impl(int n, const td_plan* plans, const double* const* F,
   for (int r = 0; r < passes; ++r) {
     for (int q : order) {   // sweeps
       td_plan_s* P = plans[q];
-      const int nct = (int)((K[q] + 31) / 32);
+      const int nct = nct_sw[q];
       const int dep = r == 0 ? -1 : ctr(q, r - 1, 5 + P->depth);
       for (int s = 0; s < P->p; ++s)
         for (int c = 0; c < nct; ++c) add(BI_SWEEP, q, r, 0, s, c, dep, r == 0 ? 0 : 1, ctr(q, r, 0));
@@ -1139,7 +1158,7 @@ td_status batch_create_impl(int n, const td_plan* plans, const double* const* F,
       for (int c = 0; c < cnt_ft[q]; ++c) add(BI_FTILDE, q, r, 0, c, 0, ctr(q, r, 0), cnt_sweep[q], ctr(q, r, 1));
     for (int q : order) {
       td_plan_s* P = plans[q];
-      const int nct = (int)((K[q] + 31) / 32);
+      const int nct = nct_bg[q];
       for (int pr = 0; pr < P->n_part; ++pr)
         for (int c = 0; c < nct; ++c) add(BI_PART, q, r, 0, pr, c, ctr(q, r, 1), cnt_ft[q], ctr(q, r, 2));
     }
@@ -1147,7 +1166,7 @@ td_status batch_create_impl(int n, const td_plan* plans, const double* const* F,
       for (int q : order) {
         td_plan_s* P = plans[q];
         if (lv >= P->depth) continue;
-        const int nct = (int)((K[q] + 31) / 32);
+        const int nct = nct_bg[q];
         const int dep = lv == 0 ? ctr(q, r, 2) : ctr(q, r, 3 + lv - 1);
         const int need = lv == 0 ? cnt_part[q] : cnt_lev[q][lv - 1];
         for (int pr = 0; pr < P->corr_count[lv]; ++pr)
@@ -1155,11 +1174,12 @@ td_status batch_create_impl(int n, const td_plan* plans, const double* const* F,
       }
     for (int q : order) {
       td_plan_s* P = plans[q];
-      const int nct = (int)((K[q] + 31) / 32);
+      const int nct = cnt_sup[q] / (int)P->p;
       for (int s = 0; s < P->p; ++s)
         for (int c = 0; c < nct; ++c)
           add(BI_SUP, q, r, 0, s, c, ctr(q, r, 3 + P->depth - 1), cnt_lev[q][P->depth - 1], ctr(q, r, 3 + P->depth));
     }
+    if (!check) continue;
     for (int q : order) {
       td_plan_s* P = plans[q];
       for (int ch = 0; ch < sys[q].nchunk; ++ch)
@@ -1381,7 +1401,7 @@ td_status tridiag_batch_create(int n, const td_plan* plans, const double* const*
   td_batch_s* B = new td_batch_s();
   td_status s;
   try {
-    s = batch_create_impl(n, plans, F, ldf, X, ldx, K, passes, tol > 0.0 ? tol : 1e-10, (hipStream_t)stream, B);
+    s = batch_create_impl(n, plans, F, ldf, X, ldx, K, passes, tol == 0.0 ? 1e-10 : tol, (hipStream_t)stream, B);
   } catch (const HipFail& e) {
     s = fail(e.e == hipErrorOutOfMemory ? TD_ENOMEM : TD_EHIP,
              std::string("HIP error ") + hipGetErrorString(e.e) + " in " + e.where);
@@ -1414,6 +1434,14 @@ td_status tridiag_batch_info(td_batch b, td_info* infos) {
   if (e != hipSuccess) return fail(TD_EHIP, hipGetErrorString(e));
   if (ctl.error) return fail(TD_EHIP, "a dependency wait of the batched kernel timed out");
   bool allconv = true;
+  if (!b->check) {
+    for (int q = 0; q < b->n; ++q) {
+      infos[q].iterations = 0;
+      infos[q].nonfinite = 0;
+      infos[q].max_col_rel_residual = -1.0;
+    }
+    return TD_OK;
+  }
   for (int q = 0; q < b->n; ++q) {
     const int last = conv[q] < b->passes ? conv[q] : b->passes - 1;
     infos[q].iterations = last;

@@ -64,9 +64,50 @@ def test_batched_matches_oracle_and_replays(td):
     batch.close()
 
 
-def test_batched_rejects_float64_plans(td):
+def test_batched_float64_and_mixed_plans(td):
+    """float64 plans in the persistent launch: one pass reaches float64 accuracy; float64 and
+    float32 plans can share one batch."""
+    plans, Fs, Xs, systems, Fh = [], [], [], [], []
+    for q, (N, M, K, p) in enumerate(SHAPES):
+        sys = synth.varcoef_system(N, M, seed=400 + q)
+        F = synth.rhs_columns(400 + q, N, M, range(K))
+        plans.append(td.Plan.from_system(sys, subdomains=p, sweep_prec="f64" if q % 2 == 0 else "f32"))
+        Fs.append(torch.as_tensor(F, device="cuda"))
+        Xs.append(torch.zeros((K, N * M), dtype=torch.float64, device="cuda"))
+        systems.append(sys)
+        Fh.append(F)
+    batch = td.Batch(plans, Fs, Xs, passes=3, tol=1e-10)
+    batch.solve()
+    infos, ok = batch.info()
+    assert ok, infos
+    for q, (sys, F) in enumerate(zip(systems, Fh)):
+        X = Xs[q].cpu().numpy()
+        ref = oracle.solve(sys, F)
+        if q % 2 == 0:
+            assert infos[q]["iterations"] == 0 and rel_err(X, ref) <= 1e-12
+        else:
+            assert rel_err(X, ref) <= 1e-9
+    batch.close()
+
+
+def test_batched_single_pass_without_check(td):
+    N, M, K, p = 128, 128, 24, 8
+    sys = synth.varcoef_system(N, M, seed=500)
+    F = synth.rhs_columns(500, N, M, range(K))
+    plan = td.Plan.from_system(sys, subdomains=p)
+    Fd = torch.as_tensor(F, device="cuda")
+    X = torch.zeros_like(Fd)
+    batch = td.Batch([plan], [Fd], [X], passes=3, tol=-1.0)
+    batch.solve()
+    infos, ok = batch.info()
+    assert ok and infos[0]["max_col_rel_residual"] == -1.0
+    assert rel_err(X.cpu().numpy(), oracle.solve(sys, F)) <= 1e-12
+    batch.close()
+
+
+def test_batched_rejects_bf16_plans(td):
     sys = synth.laplace_system(32, 64, 4.5)
-    plan = td.Plan.from_system(sys, subdomains=2)
+    plan = td.Plan.from_system(sys, subdomains=2, sweep_prec="bf16")
     F = torch.zeros((2, 32 * 64), dtype=torch.float64, device="cuda")
     with pytest.raises(td.TridiagError) as e:
         td.Batch([plan], [F], [torch.zeros_like(F)])
