@@ -9,7 +9,7 @@ namespace td {
 
 // ---------------------------------------------------------------------------
 // Block GEMM: every product in this library has the shape
-//   C (Mp x ncols) = alpha * A (Mp x kd) * B (kd x ncols) [+ Cin] [+ sum of partials]
+//   C (Mp x ncols) = alpha * (A (Mp x kd) * B (kd x ncols) [+ sum of partials]) [+ Cin]
 // with A and B column-major.  One launch runs a list of such problems (all with the
 // same buffers and leading dimensions, different offsets); one work-group computes
 // the full Mp rows of one 4*CT-column tile of one problem.  B may consist of
@@ -111,6 +111,27 @@ struct GJArgs {
 
 // Launch wrappers (kernels_f64.hip)
 hipError_t launch_bgemm(const BArgs& a, hipStream_t st);
+
+// Levels of Algorithm 1 with few nodes split the inner dimension [X_{l-1}; X_{r+1}] of
+// X_m = S_m + H^L X_{l-1} + H^R X_{r+1} into slabs, each a separate block-GEMM problem writing
+// a partial product; the combine step adds the slab partials and the partial sums of S_m,
+// then writes X_m to the interface array and to the solution.
+struct CombDesc {
+  int64_t p_off;    // slab q of this node: P + p_off + q * Mp (ld = ldp)
+  int64_t sp_off;   // partial sums of S_m: Sp + sp_off + q * spstride (ld = ldsp), q < nsp
+  int64_t c_off;    // X_m in the interface array: C + c_off (ld = ldc)
+  int64_t x2_off;   // X_m in the solution: X2 + x2_off (first x2rows rows; ld = ldx2)
+  int32_t nslab, nsp;
+};
+struct CombArgs {
+  const CombDesc* descs;
+  int32_t nnode, Mp, ncols, x2rows, x2accum, pad_;
+  const double* P; int64_t ldp;
+  const double* Sp; int64_t ldsp; int64_t spstride;
+  double* C; int64_t ldc;
+  double* X2; int64_t ldx2;
+};
+hipError_t launch_level_combine(const CombArgs& a, hipStream_t st);
 hipError_t launch_sweep(const SweepArgs& a, hipStream_t st);
 hipError_t launch_superpose(const SupArgs& a, hipStream_t st);
 hipError_t launch_gj(const GJArgs& a, hipStream_t st);

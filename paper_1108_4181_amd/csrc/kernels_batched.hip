@@ -90,7 +90,7 @@ __device__ void run_item(const BatchItem& it, const BatchSys& S, uint4* lds, dou
       if (S.prec == 0) {
         SupArgs u = S.sup64;
         u.accumulate = it.pass > 0 ? 1 : 0;
-        superpose_f64_tile<RT, 4>(u, it.i0, it.i1, reinterpret_cast<double*>(lds));
+        superpose_f64_tile<RT, 4, 2, false>(u, it.i0, it.i1, reinterpret_cast<double*>(lds));
       } else {
         LpSupArgs u = S.sup;
         u.accumulate = it.pass > 0 ? 1 : 0;

@@ -26,6 +26,35 @@ __global__ void __launch_bounds__(512) k_bgemm(BArgs args) {
   bgemm_tile<RT, CT>(args, prob, lg - prob * args.ncoltiles, Bs);
 }
 
+// ---------------------------------------------------------------------------
+// Combine step of a split dichotomy level (see CombDesc): one thread per element of X_m.
+// ---------------------------------------------------------------------------
+__global__ void k_level_combine(CombArgs a) {
+  const CombDesc d = a.descs[blockIdx.y];
+  const int64_t n = (int64_t)a.Mp * a.ncols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const int row = (int)(e % a.Mp);
+    const int64_t col = e / a.Mp;
+    double v = 0.0;
+    for (int q = 0; q < d.nslab; ++q) v += a.P[d.p_off + (int64_t)q * a.Mp + row + col * a.ldp];
+    for (int q = 0; q < d.nsp; ++q) v += a.Sp[d.sp_off + q * a.spstride + row + col * a.ldsp];
+    a.C[d.c_off + row + col * a.ldc] = v;
+    if (row < a.x2rows) {
+      double* xp = a.X2 + d.x2_off + row + col * a.ldx2;
+      *xp = a.x2accum ? *xp + v : v;
+    }
+  }
+}
+
+hipError_t launch_level_combine(const CombArgs& a, hipStream_t st) {
+  if (a.nnode <= 0 || a.ncols <= 0) return hipSuccess;
+  const int64_t n = (int64_t)a.Mp * a.ncols;
+  int bx = (int)((n + 255) / 256);
+  if (bx > 4096) bx = 4096;
+  hipLaunchKernelGGL(k_level_combine, dim3(bx, a.nnode), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
 int bgemm_coltile(int ncols) {
   if (ncols <= 8) return 8;
   if (ncols <= 16) return 16;
@@ -131,7 +160,7 @@ __global__ void __launch_bounds__(512) k_superpose_f64(SupArgs a) {
   const int lg = xcd_remap(blockIdx.x, gridDim.x);
   if (lg >= a.total) return;
   const int s = lg / a.ncoltiles;
-  superpose_f64_tile<RT, CT>(a, s, lg - s * a.ncoltiles, Xs);
+  superpose_f64_tile<RT, CT, 4>(a, s, lg - s * a.ncoltiles, Xs);
 }
 
 template <int RT, int CT>

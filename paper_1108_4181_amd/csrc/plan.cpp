@@ -70,9 +70,14 @@ struct td_plan_s {
   // solve descriptors (device)
   BDesc* d_part = nullptr; int n_part = 0;
   BDesc* d_corr = nullptr; std::vector<int> corr_begin, corr_count;
+  // levels with few nodes: slab products (d_split) + combine (d_comb); lev_nslab[lv] == 1 = unsplit
+  std::vector<int> lev_nslab, split_begin, split_count, comb_begin;
+  BDesc* d_split = nullptr; CombDesc* d_comb = nullptr;
+  int pslots = 0;             // slab partials of the largest split level
   // workspace
   int64_t kcap = 0;
   double* Wbuf = nullptr; double* Ft = nullptr; double* Xi = nullptr; double* Sp = nullptr;
+  double* Pbuf = nullptr;     // [pslots][Mp] x K slab partials of a split level
   float* W32 = nullptr;       // float32 beta / W of the low-precision sweeps
   int64_t rcap = 0;
   double* Rbuf = nullptr; double* colpart = nullptr; double* norms = nullptr;
@@ -613,6 +618,59 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
       P->corr_count[lv] = (int)corr.size() - P->corr_begin[lv];
     }
     P->d_corr = P->upload(corr);
+
+    // A level with few nodes nl has too few column tiles to fill the device, and each
+    // work-group walks the whole inner dimension 2 Mp with one chunk of prefetch; split it into
+    // nslab slabs (each within one of the two segments X_{l-1}, X_{r+1}; at most 8), aiming at
+    // nl * nslab >= 16 problems (levels with more nodes already fill the device).
+    std::vector<BDesc> split;
+    std::vector<CombDesc> comb;
+    P->lev_nslab.assign(P->depth, 1);
+    P->split_begin.assign(P->depth, 0);
+    P->split_count.assign(P->depth, 0);
+    P->comb_begin.assign(P->depth, 0);
+    P->pslots = 0;
+    for (int lv = 0; lv < P->depth; ++lv) {
+      const int nl = P->corr_count[lv];
+      // a slab must be a whole number of 16-deep GEMM chunks and lie within one segment
+      auto slab_ok = [&](int n) {
+        const int64_t w = 2 * Mp / n;
+        return (2 * Mp) % n == 0 && w % 16 == 0 && Mp % w == 0;
+      };
+      int ns = 1;
+      while (nl * ns < 16 && ns < 8 && slab_ok(2 * ns)) ns *= 2;
+      P->lev_nslab[lv] = ns;
+      P->split_begin[lv] = (int)split.size();
+      P->comb_begin[lv] = (int)comb.size();
+      if (ns == 1) continue;
+      const int64_t kslab = 2 * Mp / ns;   // a multiple of 16 that divides Mp
+      for (int j = 0; j < nl; ++j) {
+        const BDesc& c = corr[P->corr_begin[lv] + j];
+        for (int q = 0; q < ns; ++q) {
+          const int64_t k0 = q * kslab, seg = k0 / Mp, kin = k0 - seg * Mp;
+          BDesc d = desc0();
+          d.a_off = c.a_off + k0 * Mp;                // columns k0.. of [H^L | H^R]
+          d.kd = (int32_t)kslab;
+          d.segrows = (int32_t)kslab;
+          d.b_off = c.b_off + seg * c.bseg + kin;
+          d.c_off = (int64_t)(j * ns + q) * Mp;
+          split.push_back(d);
+        }
+        CombDesc cd;
+        std::memset(&cd, 0, sizeof(cd));
+        cd.p_off = (int64_t)j * ns * Mp;
+        cd.nslab = ns;
+        cd.sp_off = c.sp_off;
+        cd.nsp = c.nsp;
+        cd.c_off = c.c_off;
+        cd.x2_off = c.x2_off;
+        comb.push_back(cd);
+      }
+      P->split_count[lv] = (int)split.size() - P->split_begin[lv];
+      P->pslots = std::max(P->pslots, nl * ns);
+    }
+    P->d_split = P->upload(split);
+    P->d_comb = P->upload(comb);
   }
   // pivot check
   int32_t badv = INT_MAX;
@@ -631,7 +689,8 @@ void ensure_workspace(td_plan_s* P, int64_t K, hipStream_t st) {
   if (K <= P->kcap) return;
   const int64_t N = P->N, Mp = P->Mp, p = P->p;
   P->release(P->Wbuf); P->release(P->W32); P->release(P->Ft); P->release(P->Xi); P->release(P->Sp);
-  P->Wbuf = P->Ft = P->Xi = P->Sp = nullptr;
+  P->release(P->Pbuf);
+  P->Wbuf = P->Ft = P->Xi = P->Sp = P->Pbuf = nullptr;
   P->W32 = nullptr;
   if (P->prec == TD_PREC_F64)
     P->Wbuf = P->alloc(N * Mp * K);
@@ -640,6 +699,7 @@ void ensure_workspace(td_plan_s* P, int64_t K, hipStream_t st) {
   P->Ft = P->alloc(p * Mp * K);
   P->Xi = P->alloc((p + 2) * Mp * K);
   P->Sp = P->alloc((int64_t)P->nchunks * Mp * K);
+  if (P->pslots > 0) P->Pbuf = P->alloc((int64_t)P->pslots * Mp * K);
   HIPCHK(launch_fill(P->Xi, (p + 2) * Mp * K, 0.0, st));
   P->kcap = K;
 }
@@ -710,6 +770,29 @@ void solve_pass(td_plan_s* P, const double* F, int64_t ldf, double* X, int64_t l
   }
   stage_mark(P, 3, st);
   for (int lv = 0; lv < P->depth; ++lv) {
+    if (P->lev_nslab[lv] > 1) {
+      const int64_t ldp = (int64_t)P->pslots * Mp;
+      BArgs a = bargs_base((int)Mp);
+      a.descs = P->d_split + P->split_begin[lv];
+      a.nprob = P->split_count[lv];
+      a.A = P->H; a.lda = Mp;
+      a.B = P->Xi; a.ldb = ldxi;
+      a.C = P->Pbuf; a.ldc = ldp;
+      a.ncols = (int32_t)K;
+      HIPCHK(launch_bgemm(a, st));
+      CombArgs c;
+      std::memset(&c, 0, sizeof(c));
+      c.descs = P->d_comb + P->comb_begin[lv];
+      c.nnode = P->corr_count[lv];
+      c.Mp = (int32_t)Mp; c.ncols = (int32_t)K;
+      c.x2rows = (int32_t)M; c.x2accum = accumulate ? 1 : 0;
+      c.P = P->Pbuf; c.ldp = ldp;
+      c.Sp = P->Sp; c.ldsp = ldsp; c.spstride = Mp;
+      c.C = P->Xi; c.ldc = ldxi;
+      c.X2 = X; c.ldx2 = ldx;
+      HIPCHK(launch_level_combine(c, st));
+      continue;
+    }
     BArgs a = bargs_base((int)Mp);
     a.descs = P->d_corr + P->corr_begin[lv];
     a.nprob = P->corr_count[lv];

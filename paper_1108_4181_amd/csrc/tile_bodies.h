@@ -103,6 +103,22 @@ __device__ __forceinline__ void bgemm_tile(const BArgs& args, int prob, int ct, 
     __syncthreads();
   }
 
+  // partial sums: the CT loads of one row group of one partial are independent, so they are in
+  // flight together
+  for (int s = 0; s < d.nsp; ++s) {
+    const double* __restrict__ sp = args.Sp + d.sp_off + s * args.spstride;
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      double pv[CT];
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const int col = col0 + out_col(L) * CT + c;
+        pv[c] = (col < args.ncols) ? sp[rb + 16 * t + out_row(L) + (int64_t)col * args.ldsp] : 0.0;
+      }
+#pragma unroll
+      for (int c = 0; c < CT; ++c) acc[t][c] += pv[c];
+    }
+  }
 #pragma unroll
   for (int t = 0; t < RT; ++t) {
     const int row = rb + 16 * t + out_row(L);
@@ -112,7 +128,6 @@ __device__ __forceinline__ void bgemm_tile(const BArgs& args, int prob, int ct, 
       if (col < args.ncols) {
         double v = args.alpha * acc[t][c];
         if (args.Cin) v += args.Cin[d.cin_off + row + (int64_t)col * args.ldcin];
-        for (int s = 0; s < d.nsp; ++s) v += args.Sp[d.sp_off + s * args.spstride + row + (int64_t)col * args.ldsp];
         if (args.C) args.C[d.c_off + row + (int64_t)col * args.ldc] = v;
         if (args.X2 && row < args.x2rows) {
           double* xp = args.X2 + d.x2_off + row + (int64_t)col * args.ldx2;
@@ -398,7 +413,7 @@ __device__ __forceinline__ void residual_stencil_tile(double* R, int64_t ldr, co
   }
 }
 
-template <int RT, int CT>
+template <int RT, int CT, int KU = 2>
 __device__ __forceinline__ void sweep_f64_tile(const SweepArgs& a, int s, int ct, double* In) {
   constexpr int KT = 4 * CT;
   constexpr int SB = KT + 2;
@@ -411,8 +426,9 @@ __device__ __forceinline__ void sweep_f64_tile(const SweepArgs& a, int s, int ct
   const int Mp = a.Mp, M = a.M, K = a.K;
   const int rb = w * 16 * RT;
   const int64_t MM = (int64_t)Mp * Mp;
-  constexpr int KU = 2;      // MFMA k-steps (of 4) per register chunk of the streamed matrix
-  const int nkc = Mp / (4 * KU);   // even: Mp is a multiple of 16
+  // KU = MFMA k-steps (of 4) per register chunk of the streamed matrix; nkc must be even
+  // (Mp a multiple of 16 for KU = 2, of 32 for KU = 4)
+  const int nkc = Mp / (4 * KU);
 
   // The step matrix streams through two register buffers, each loaded one chunk ahead of
   // its use; after the last chunk of a step comes the first chunk of the next step's
@@ -512,7 +528,12 @@ __device__ __forceinline__ void sweep_f64_tile(const SweepArgs& a, int s, int ct
   }
 }
 
-template <int RT, int CT>
+// The Mp x 2Mp matrix [U_i V_i] streams through two register buffers of KU MFMA k-steps each,
+// loaded one buffer ahead; the interface operand of the next k-step is read from LDS before
+// the MFMAs of the current one, and scheduling fences keep that order (otherwise the LDS
+// latency is exposed at every k-step).  KU must be even and 2 Mp / (4 KU) even.  With
+// FENCED = false the compiler schedules freely (fewer live registers, for register-bound callers).
+template <int RT, int CT, int KU = 2, bool FENCED = true>
 __device__ __forceinline__ void superpose_f64_tile(const SupArgs& a, int s, int ct, double* Xs) {
   constexpr int KT = 4 * CT;
   constexpr int SB = KT + 2;
@@ -526,7 +547,7 @@ __device__ __forceinline__ void superpose_f64_tile(const SupArgs& a, int s, int 
   const int rb = w * 16 * RT;
   const int64_t MM = (int64_t)Mp * Mp;
   const int kd = 2 * Mp;
-  const int nkc = kd / 8;  // chunks of 2 MFMA k-steps; even
+  const int nkc = kd / (4 * KU);
 
   for (int e = tid; e < kd * KT; e += nthr) {
     const int k = e % kd, c = e / kd;
@@ -535,26 +556,48 @@ __device__ __forceinline__ void superpose_f64_tile(const SupArgs& a, int s, int 
   }
 
   const int64_t lane_off = rb + (L & 15) + (int64_t)(L >> 4) * Mp;
-  double a0[2][RT], a1[2][RT];
-  auto loadA = [&](double (&dst)[2][RT], const double* __restrict__ Ab, int q) {
-    const double* __restrict__ pa = Ab + lane_off + (int64_t)(8 * q) * Mp;
+  double a0[KU][RT], a1[KU][RT];
+  auto loadA = [&](double (&dst)[KU][RT], const double* __restrict__ Ab, int q) {
+    const double* __restrict__ pa = Ab + lane_off + (int64_t)(4 * KU * q) * Mp;
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
+    for (int u = 0; u < KU; ++u)
 #pragma unroll
       for (int t = 0; t < RT; ++t) dst[u][t] = pa[16 * t + (int64_t)(4 * u) * Mp];
   };
+  const double* Bl = &Xs[(L >> 4) * SB + (L & 3) * CT];
+  double b0[CT], b1[CT];
+  auto ldB = [&](double (&b)[CT], int ks) {
+    const double* bp = Bl + 4 * ks * SB;
+#pragma unroll
+    for (int c = 0; c < CT; ++c) b[c] = bp[c];
+  };
   double acc[RT][CT];
-  auto compute = [&](const double (&av)[2][RT], int q) {
+  auto mm = [&](const double (&av)[RT], const double (&b)[CT]) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const double* bp = &Xs[(8 * q + 4 * u + (L >> 4)) * SB + (L & 3) * CT];
-      double b[CT];
+    for (int t = 0; t < RT; ++t)
 #pragma unroll
-      for (int c = 0; c < CT; ++c) b[c] = bp[c];
+      for (int c = 0; c < CT; ++c) acc[t][c] = mfma4(av[t], b[c], acc[t][c]);
+  };
+  // k-steps KU*q .. KU*q + KU - 1; on entry b0 holds the operand of the first of them
+  auto compute = [&](const double (&av)[KU][RT], int q, bool last_chunk) {
 #pragma unroll
-      for (int t = 0; t < RT; ++t)
-#pragma unroll
-        for (int c = 0; c < CT; ++c) acc[t][c] = mfma4(av[u][t], b[c], acc[t][c]);
+    for (int u = 0; u < KU; u += 2) {
+      const int ks = KU * q + u;
+      if (FENCED) {
+        ldB(b1, ks + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        mm(av[u], b0);
+        __builtin_amdgcn_sched_barrier(0);
+        if (!(last_chunk && u + 2 >= KU)) ldB(b0, ks + 2);
+        __builtin_amdgcn_sched_barrier(0);
+        mm(av[u + 1], b1);
+        __builtin_amdgcn_sched_barrier(0);
+      } else {
+        ldB(b0, ks);
+        mm(av[u], b0);
+        ldB(b0, ks + 1);
+        mm(av[u + 1], b0);
+      }
     }
   };
 
@@ -567,11 +610,12 @@ __device__ __forceinline__ void superpose_f64_tile(const SupArgs& a, int s, int 
     for (int t = 0; t < RT; ++t)
 #pragma unroll
       for (int c = 0; c < CT; ++c) acc[t][c] = 0.0;
+    if (FENCED) ldB(b0, 0);
     for (int kc = 0; kc < nkc - 2; kc += 2) {
       loadA(a1, Ai, kc + 1);
-      compute(a0, kc);
+      compute(a0, kc, false);
       loadA(a0, Ai, kc + 2);
-      compute(a1, kc + 1);
+      compute(a1, kc + 1, false);
     }
     double ex[RT][CT];
 #pragma unroll
@@ -584,9 +628,9 @@ __device__ __forceinline__ void superpose_f64_tile(const SupArgs& a, int s, int 
       }
     }
     loadA(a1, Ai, nkc - 1);
-    compute(a0, nkc - 2);
+    compute(a0, nkc - 2, false);
     loadA(a0, Anx, 0);
-    compute(a1, nkc - 1);
+    compute(a1, nkc - 1, true);
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
       const int row = rb + 16 * t + out_row(L);
