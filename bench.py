@@ -26,25 +26,32 @@ PEAK_F32_MFMA = 157.3
 PEAK_HBM = 8000.0      # GB/s
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (FETCH_SIZE scaled by 2.0,
-# the factor a 1 GiB device copy shows), valid only for the kernel source they were taken on
+# the factor a 1 GiB device copy shows), valid only for the kernel sources they were taken on
 # (profiles/sweep_superposition_varcoef_n2048_m256_k512.md).
 MEASURED_TRAFFIC = {
-    # kernel: (workload, sha256 prefix of kernels_f64.hip, read bytes, write bytes)
-    "sweep": ("varcoef_n2048_m256_k512", "88ad639ee0c9fd19", 8.29996e9, 4.09364e9),
-    "superposition": ("varcoef_n2048_m256_k512", "88ad639ee0c9fd19", 4.38423e9, 2.08037e9),
+    # kernel: (workload, source hash (kernel_source_hash), read bytes, write bytes)
+    "sweep": ("varcoef_n2048_m256_k512", "27ef6073d9b34cfd", 8.54126e9, 4.09364e9),
+    "superposition": ("varcoef_n2048_m256_k512", "27ef6073d9b34cfd", 4.42142e9, 2.08037e9),
 }
+KERNEL_SOURCES = ["kernels_f64.hip", "tile_bodies.h", "device_common.h", "internal.h"]
+
+
+def kernel_source_hash():
+    """sha256 prefix over the sources that define the float64 sweep and superposition kernels."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1108_4181_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel, workload):
-    import hashlib
-
     rec = MEASURED_TRAFFIC.get(kernel)
-    if rec is None or rec[0] != workload:
+    if rec is None or rec[0] != workload or not rec[1]:
         return None
-    path = os.path.join(ROOT, "paper_1108_4181_amd", "csrc", "kernels_f64.hip")
-    with open(path, "rb") as f:
-        h = hashlib.sha256(f.read()).hexdigest()[:16]
-    return rec[2] + rec[3] if h == rec[1] else None
+    return rec[2] + rec[3] if kernel_source_hash() == rec[1] else None
 
 
 def partition(N, p):
@@ -126,22 +133,25 @@ def bench_batched(args):
     # autotune the subdomain length for every (M, K bucket) of the batch (timed search in the library)
     t0 = time.perf_counter()
     tuned = {}
+    prec = "f32"   # float64 plans of all 64 systems with their workspaces exceed one GPU's HBM
+    passes = args.batch_passes
     for M, Kb in sorted({(m, td._kbucket(k)) for _, m, k, _ in shapes}):
-        tuned[f"M{M}|K{Kb}"] = td.autotune(M, Kb, "f32", probe_N=1024, candidates=(16, 32, 64))["L"]
+        tuned[f"M{M}|K{Kb}"] = td.autotune(M, Kb, prec, probe_N=1024, candidates=(16, 32, 64))["L"]
     tune_s = time.perf_counter() - t0
     plans, Fs, Xs, systems = [], [], [], []
     t0 = time.perf_counter()
     for N, M, K, seed in shapes:
         sysq = synth.laplace_system(N, M, 4.5)
-        p = td.choose_subdomains(N, M, K, "f32")
-        plans.append(td.Plan.from_system(sysq, device=dev, subdomains=p, sweep_prec="f32"))
+        p = td.choose_subdomains(N, M, K, prec)
+        plans.append(td.Plan.from_system(sysq, device=dev, subdomains=p, sweep_prec=prec))
         Fs.append(synth.rhs_torch(seed, N, M, K, dev))
         Xs.append(torch.zeros_like(Fs[-1]))
         systems.append((N, M, K, p))
     torch.cuda.synchronize()
     factor_s = time.perf_counter() - t0
     t0 = time.perf_counter()
-    batch = td.Batch(plans, Fs, Xs, passes=args.batch_passes, tol=1e-10)
+    plan_bytes = sum(pl.plan_info()["device_bytes"] for pl in plans)
+    batch = td.Batch(plans, Fs, Xs, passes=passes, tol=1e-10)
     build_s = time.perf_counter() - t0
     batch.solve()
     infos, ok = batch.info()
@@ -180,7 +190,8 @@ def bench_batched(args):
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "batched_64_uneven", "systems": len(systems), "total_rhs": totK,
-                   "passes": args.batch_passes, "subdomains": "autotuned"},
+                   "sweep_prec": prec, "passes": passes, "subdomains": "autotuned"},
+        "plan_device_bytes": plan_bytes,
         "per_system_f64_ms": base_ms, "per_system_f64_rhs_per_s": totK / (base_ms / 1e3),
         "speedup_vs_per_system_f64": base_ms / ms, "all_converged": ok, "max_col_rel_residual": worst,
         "max_passes_used": 1 + max(i["iterations"] for i in infos), "algorithmic_tflops": flops / (ms * 1e-3) / 1e12,

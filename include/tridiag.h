@@ -172,9 +172,14 @@ td_status tridiag_autotune(int64_t M, int64_t K, int32_t sweep_prec, int64_t pro
                            int ncand, void* stream, int64_t* best_L, double* ms_per_solve);
 
 /*
- * Batched solve of many independent systems (not in the paper): one persistent launch over
- * a work list of all systems' stages, captured once in a HIP graph and replayed by
- * tridiag_batch_solve.  Each pass solves every system (pass 0 with F, later passes with the
+ * Batched solve of many independent systems (not in the paper): a work list of all systems'
+ * stages (sweep tiles, interface right-hand sides, dichotomy partial sums and levels,
+ * superposition tiles, residual chunks), captured once in a HIP graph and replayed by
+ * tridiag_batch_solve.  By default the graph holds one launch per stage, each running the
+ * independent items of all systems for that stage; with the environment variable
+ * TD_BATCH_MODE=persistent at creation it holds one persistent launch in which every item
+ * waits (bounded) on counters of the items it depends on.  Both give bitwise the same result.
+ * Each pass solves every system (pass 0 with F, later passes with the
  * float64 residual, adding the correction to X); a system that has reached `tol` skips the
  * remaining passes.  The plans must have sweep_prec TD_PREC_F64 or TD_PREC_F32, diagonal A and B,
  * tridiagonal C and padded block sizes 64, 128 or 256; they must outlive the batch, and the
@@ -182,7 +187,8 @@ td_status tridiag_autotune(int64_t M, int64_t K, int32_t sweep_prec, int64_t pro
  * per system, column-major N_q*M_q x K_q).  Calls that share a plan's workspace must not
  * overlap.  tridiag_batch_info synchronises and reports, per system, the passes used after the
  * first (iterations) and the final max column relative residual; it returns TD_ENOCONV if
- * a system did not reach `tol`, TD_EHIP if a dependency wait inside the launch timed out.
+ * a system did not reach `tol`, TD_EHIP if a dependency wait inside the persistent launch timed
+ * out.
  * Plans may mix TD_PREC_F64 (float64 sweeps) and TD_PREC_F32.  tol == 0 means 1e-10; tol < 0
  * runs a single pass without residual test (infos then report -1).
  */

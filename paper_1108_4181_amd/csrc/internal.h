@@ -217,7 +217,10 @@ struct BatchCtl {
 
 hipError_t launch_batched(const BatchItem* items, int nitems, const BatchSys* sys, int32_t* counters, int ncounters,
                           int32_t* conv, int nsys, BatchCtl* ctl, int grid, int64_t spin_limit, hipStream_t st);
+hipError_t launch_batched_stages(const BatchItem* items, const int* stage_begin, int nstages, const BatchSys* sys,
+                                 int32_t* heads, int32_t* conv, int nsys, BatchCtl* ctl, int max_grid, hipStream_t st);
 int batched_lds_bytes();
+int batched_blocks_per_cu();
 
 // Low-precision path (kernels_lp.hip)
 hipError_t launch_cast_rowmajor(int prec, void* dst, int64_t dstride, const double* src, int64_t sstride,

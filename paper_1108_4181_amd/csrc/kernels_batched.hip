@@ -1,9 +1,11 @@
-// Persistent batched solve: many independent block-tridiagonal systems of uneven N, M, K in one
-// launch.  Each work-group repeatedly takes the next work item from a global counter; items are
-// queued in a topological order (every dependency of an item sits earlier in the queue), so a
-// work-group that waits only waits for items already held by running work-groups and the launch
-// always drains.  Every wait is bounded: on time-out the item records an error and runs anyway,
-// and all other waits then end at once.
+// Batched solve: many independent block-tridiagonal systems of uneven N, M, K.  The host builds
+// one work list of all systems' items in stage order; it runs either as one launch per stage
+// (k_batched_stage: the items of a stage are independent, kernel boundaries order the stages)
+// or as one persistent launch (k_batched): each work-group repeatedly takes the next work item
+// from a global counter; items are queued in a topological order (every dependency of an item
+// sits earlier in the queue), so a work-group that waits only waits for items already held by
+// running work-groups and the launch always drains.  Every wait is bounded: on time-out the item
+// records an error and runs anyway, and all other waits then end at once.
 //
 // Per system and per pass (pass 0 solves with F; later passes solve with the residual and add
 // the correction to X):
@@ -168,6 +170,55 @@ __global__ void __launch_bounds__(BATCH_THREADS, 2) k_batched(const BatchItem* _
   }
 }
 
+__global__ void k_batch_reset(int32_t* counters, int ncounters, int32_t* conv, int nsys, BatchCtl* ctl);
+
+// Stage-synchronous form: one launch per stage (all systems' items of that stage, which are
+// mutually independent); kernel boundaries order the stages, so items neither wait nor count.
+__global__ void __launch_bounds__(BATCH_THREADS, 2) k_batched_stage(const BatchItem* __restrict__ items, int begin,
+                                                                 int end, const BatchSys* __restrict__ sys,
+                                                                 int32_t* conv, int32_t* head) {
+  extern __shared__ uint4 lds[];
+  __shared__ double red[2][4];
+  __shared__ int sh_idx;
+  for (;;) {
+    if (threadIdx.x == 0) sh_idx = begin + atomicAdd(head, 1);
+    __syncthreads();
+    const int idx = sh_idx;
+    if (idx >= end) break;
+    const BatchItem it = items[idx];
+    const BatchSys& S = sys[it.sys];
+    const bool skip = it.pass > 0 && conv[it.sys] < it.pass;
+    if (!skip) {
+      switch (S.rt) {
+        case 4: run_item<4>(it, S, lds, red, conv); break;
+        case 2: run_item<2>(it, S, lds, red, conv); break;
+        default: run_item<1>(it, S, lds, red, conv); break;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_batched_stages(const BatchItem* items, const int* stage_begin, int nstages, const BatchSys* sys,
+                                 int32_t* heads, int32_t* conv, int nsys, BatchCtl* ctl, int max_grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_reset, dim3(64), dim3(256), 0, st, heads, nstages, conv, nsys, ctl);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int lds = batched_lds_bytes();
+  e = hipFuncSetAttribute((const void*)k_batched_stage, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e != hipSuccess) return e;
+  for (int s = 0; s < nstages; ++s) {
+    const int n = stage_begin[s + 1] - stage_begin[s];
+    if (n <= 0) continue;
+    const int grid = n < max_grid ? n : max_grid;
+    hipLaunchKernelGGL(k_batched_stage, dim3(grid), dim3(BATCH_THREADS), lds, st, items, stage_begin[s],
+                       stage_begin[s + 1], sys, conv, heads + s);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 __global__ void k_batch_reset(int32_t* counters, int ncounters, int32_t* conv, int nsys, BatchCtl* ctl) {
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ncounters; e += gridDim.x * blockDim.x) counters[e] = 0;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nsys; e += gridDim.x * blockDim.x) conv[e] = 1 << 30;
@@ -177,6 +228,17 @@ __global__ void k_batch_reset(int32_t* counters, int ncounters, int32_t* conv, i
 // LDS of the largest tile body: float64 superposition with 16 columns of 2*256 rows
 // (float64 sweep: 256 x 18 doubles; float32 superposition: 32 x (2*256 + 4) floats)
 int batched_lds_bytes() { return 2 * 256 * 18 * 8; }
+
+// resident work-groups of the persistent kernel per compute unit (registers and LDS permitting)
+int batched_blocks_per_cu() {
+  int occ = 0;
+  if (hipFuncSetAttribute((const void*)k_batched, hipFuncAttributeMaxDynamicSharedMemorySize, batched_lds_bytes()) !=
+          hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_batched, BATCH_THREADS, batched_lds_bytes()) !=
+          hipSuccess)
+    return 1;
+  return occ < 1 ? 1 : occ;
+}
 
 hipError_t launch_batched(const BatchItem* items, int nitems, const BatchSys* sys, int32_t* counters, int ncounters,
                           int32_t* conv, int nsys, BatchCtl* ctl, int grid, int64_t spin_limit, hipStream_t st) {

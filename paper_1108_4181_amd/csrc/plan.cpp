@@ -10,6 +10,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -1080,6 +1081,7 @@ struct td_batch_s {
   BatchSys* d_sys = nullptr;
   int32_t* d_counters = nullptr; int ncounters = 0;
   int32_t* d_conv = nullptr;
+  int32_t* d_heads = nullptr;   // stage-synchronous form: one dequeue counter per stage
   BatchCtl* d_ctl = nullptr;
   double* d_resid = nullptr;
   int passes = 0;
@@ -1229,7 +1231,10 @@ td_status batch_create_impl(int n, const td_plan* plans, const double* const* F,
     it.dep = dep; it.need = need; it.mine = mine; it.pad_ = 0;
     items.push_back(it);
   };
+  std::vector<int> stage_begin;
+  auto stage = [&]() { stage_begin.push_back((int)items.size()); };
   for (int r = 0; r < passes; ++r) {
+    stage();
     for (int q : order) {   // sweeps
       td_plan_s* P = plans[q];
       const int nct = nct_sw[q];
@@ -1237,15 +1242,18 @@ td_status batch_create_impl(int n, const td_plan* plans, const double* const* F,
       for (int s = 0; s < P->p; ++s)
         for (int c = 0; c < nct; ++c) add(BI_SWEEP, q, r, 0, s, c, dep, r == 0 ? 0 : 1, ctr(q, r, 0));
     }
+    stage();
     for (int q : order)
       for (int c = 0; c < cnt_ft[q]; ++c) add(BI_FTILDE, q, r, 0, c, 0, ctr(q, r, 0), cnt_sweep[q], ctr(q, r, 1));
+    stage();
     for (int q : order) {
       td_plan_s* P = plans[q];
       const int nct = nct_bg[q];
       for (int pr = 0; pr < P->n_part; ++pr)
         for (int c = 0; c < nct; ++c) add(BI_PART, q, r, 0, pr, c, ctr(q, r, 1), cnt_ft[q], ctr(q, r, 2));
     }
-    for (int lv = 0; lv < maxdepth; ++lv)
+    for (int lv = 0; lv < maxdepth; ++lv) {
+      stage();
       for (int q : order) {
         td_plan_s* P = plans[q];
         if (lv >= P->depth) continue;
@@ -1255,6 +1263,8 @@ td_status batch_create_impl(int n, const td_plan* plans, const double* const* F,
         for (int pr = 0; pr < P->corr_count[lv]; ++pr)
           for (int c = 0; c < nct; ++c) add(BI_LEVEL, q, r, lv, pr, c, dep, need, ctr(q, r, 3 + lv));
       }
+    }
+    stage();
     for (int q : order) {
       td_plan_s* P = plans[q];
       const int nct = cnt_sup[q] / (int)P->p;
@@ -1263,17 +1273,20 @@ td_status batch_create_impl(int n, const td_plan* plans, const double* const* F,
           add(BI_SUP, q, r, 0, s, c, ctr(q, r, 3 + P->depth - 1), cnt_lev[q][P->depth - 1], ctr(q, r, 3 + P->depth));
     }
     if (!check) continue;
+    stage();
     for (int q : order) {
       td_plan_s* P = plans[q];
       for (int ch = 0; ch < sys[q].nchunk; ++ch)
         for (int c0 = 0; c0 < K[q]; c0 += 8)
           add(BI_RES, q, r, 0, ch, c0, ctr(q, r, 3 + P->depth), cnt_sup[q], ctr(q, r, 4 + P->depth));
     }
+    stage();
     for (int q : order) {
       td_plan_s* P = plans[q];
       add(BI_RFIN, q, r, 0, 0, 0, ctr(q, r, 4 + P->depth), cnt_res[q], ctr(q, r, 5 + P->depth));
     }
   }
+  stage();
   B->nitems = (int)items.size();
   B->d_items = B->upload(items);
   B->d_sys = B->upload(sys);
@@ -1284,10 +1297,11 @@ td_status batch_create_impl(int n, const td_plan* plans, const double* const* F,
   int dev = 0, cus = 0, occ = 0;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  B->grid = cus;
-  (void)occ;
+  occ = batched_blocks_per_cu();
+  B->grid = cus * occ;
   // capture the reset + persistent launch once, on a private stream (the caller's stream may be
   // the legacy default stream, which cannot be captured); replays go to the caller's stream
+  B->d_heads = B->dalloc<int32_t>(stage_begin.size());
   HIPCHK(hipStreamSynchronize(st));
   hipStream_t cs = nullptr;
   HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
@@ -1295,8 +1309,17 @@ td_status batch_create_impl(int n, const td_plan* plans, const double* const* F,
   hipError_t le = hipSuccess, ce = hipSuccess;
   hipGraph_t g = nullptr;
   if (be == hipSuccess) {
-    le = launch_batched(B->d_items, B->nitems, B->d_sys, B->d_counters, B->ncounters, B->d_conv, n, B->d_ctl, B->grid,
-                        (int64_t)1 << 26, cs);
+    // default: one launch per stage (measured faster: no per-item cache maintenance); with
+    // TD_BATCH_MODE=persistent, one persistent launch with counted dependencies
+    const char* mode = std::getenv("TD_BATCH_MODE");
+    if (mode && std::strcmp(mode, "persistent") == 0) {
+      le = launch_batched(B->d_items, B->nitems, B->d_sys, B->d_counters, B->ncounters, B->d_conv, n, B->d_ctl,
+                          B->grid, (int64_t)1 << 26, cs);
+    } else {
+      const int nst = (int)stage_begin.size() - 1;
+      le = launch_batched_stages(B->d_items, stage_begin.data(), nst, B->d_sys, B->d_heads, B->d_conv, n, B->d_ctl,
+                                 B->grid, cs);
+    }
     ce = hipStreamEndCapture(cs, &g);
   }
   (void)hipStreamDestroy(cs);

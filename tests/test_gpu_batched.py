@@ -1,7 +1,10 @@
-"""Batched solve of uneven systems (one persistent launch replayed from a HIP graph) against the
-CPU oracle: float32 sweeps, float64 reduced systems and refinement to a max column relative
-residual of 1e-10; error vs the float64 oracle <= 1e-9.  Replays of the graph give bitwise the
-same result as the first run."""
+"""Batched solve of uneven systems (a HIP graph of one launch per stage, or one persistent launch
+with counted dependencies) against the CPU oracle: float32 sweeps, float64 reduced systems and
+refinement to a max column relative residual of 1e-10; error vs the float64 oracle <= 1e-9.
+Replays of the graph give bitwise the same result as the first run.  Every test runs in both
+launch forms."""
+import os
+
 import numpy as np
 import pytest
 
@@ -15,6 +18,17 @@ pytestmark = pytest.mark.gpu
 SHAPES = [  # N, M, K, p
     (40, 64, 5, 4), (97, 64, 33, 6), (128, 128, 64, 8), (200, 64, 17, 10), (64, 256, 40, 4), (150, 128, 3, 15),
 ]
+
+
+@pytest.fixture(autouse=True, params=["staged", "persistent"])
+def batch_mode(request):
+    old = os.environ.get("TD_BATCH_MODE")
+    os.environ["TD_BATCH_MODE"] = request.param
+    yield request.param
+    if old is None:
+        del os.environ["TD_BATCH_MODE"]
+    else:
+        os.environ["TD_BATCH_MODE"] = old
 
 
 @pytest.fixture(scope="module")
