@@ -61,7 +61,8 @@ typedef struct {
   int64_t N;            /* block rows, >= 1 */
   int64_t M;            /* block size, 1 <= M <= 512 */
   int64_t subdomains;   /* p in [1, N]: number of subdomains of Algorithm 2; 0 = chosen by the library */
-  int32_t fmt_A;        /* TD_FMT_DENSE or TD_FMT_DIAG */
+  int32_t fmt_A;        /* TD_FMT_DENSE or TD_FMT_DIAG (DENSE A or B: sweep_prec must be F64,
+                           else TD_ENOTSUP; every coupling then becomes a block product) */
   int32_t fmt_B;        /* TD_FMT_DENSE or TD_FMT_DIAG */
   int32_t fmt_C;        /* TD_FMT_DENSE or TD_FMT_TRIDIAG */
   int32_t sweep_prec;   /* TD_PREC_F64: plain float64 solve; TD_PREC_F32 / TD_PREC_BF16: the

@@ -40,7 +40,7 @@ struct BArgs {
   int32_t total;      // nprob * ncoltiles
   int32_t x2rows;
   int32_t x2accum;    // nonzero: X2 += result instead of X2 = result
-  int32_t pad_;
+  int32_t brows;      // > 0: rows of each B segment at or beyond brows read as zero
   double alpha;
   const double* A; int64_t lda;
   const double* B; int64_t ldb;
@@ -57,6 +57,9 @@ struct SweepArgs {
   const double* Dinv;    // [N][Mp][Mp]: D_i^{-1} of interior row i
   const double* alpha;   // [N][Mp][Mp]: alpha_i = D_i^{-1} B_i
   const double* adiag;   // [N][Mp]: diagonal of A_i (zero padded)
+  // dense A: E_i = D_i^{-1} A_i ([N][Mp][Mp]); the forward sweep is then the recurrence
+  // beta_i = E_i beta_{i-1} + G_i with G_i = D_i^{-1} F_i already in W (adiag unused)
+  const double* E;
   const double* F; int64_t ldf;
   double* W; int64_t ldw;
   int32_t N, M, Mp, p, K, ncoltiles, total;
@@ -149,6 +152,10 @@ hipError_t launch_reduced(double* At, double* Ct, double* Bt, const int64_t* ks,
 hipError_t launch_pad_diag(double* dst, const double* src, int N, int M, int Mp, int zero_first,
                            int zero_last, hipStream_t st);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
+// [A_j | B_j] as one zero-padded Mp x 2Mp column-major matrix per block row (DIAG blocks on the
+// diagonal); A_0 and B_{N-1} are stored as zero
+hipError_t launch_expand_AB(double* ABd, const double* A, int fmtA, const double* B, int fmtB, int N, int M, int Mp,
+                            hipStream_t st);
 hipError_t launch_identity(double* p, int Mp, hipStream_t st);
 hipError_t launch_negate_fill_check(int32_t* flag, int32_t v, hipStream_t st);
 

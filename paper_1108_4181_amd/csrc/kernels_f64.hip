@@ -526,6 +526,36 @@ hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st) {
   return hipGetLastError();
 }
 
+__global__ void k_expand_AB(double* ABd, const double* A, int fmtA, const double* B, int fmtB, int N, int M, int Mp) {
+  const int64_t MM = (int64_t)Mp * Mp;
+  for (int64_t j = blockIdx.y; j < N; j += gridDim.y)
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < 2 * MM; e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e % Mp), cc = (int)(e / Mp);
+    const bool isA = cc < Mp;
+    const int c = isA ? cc : cc - Mp;
+    double v = 0.0;
+    if (r < M && c < M && (isA ? j > 0 : j + 1 < N)) {
+      const double* X = isA ? A : B;
+      const int fmt = isA ? fmtA : fmtB;
+      if (fmt == 1)
+        v = (r == c) ? X[j * M + r] : 0.0;                      // DIAG [N][M]
+      else
+        v = X[j * (int64_t)M * M + r + (int64_t)c * M];         // DENSE, column-major block
+    }
+    ABd[j * 2 * MM + e] = v;
+  }
+}
+
+hipError_t launch_expand_AB(double* ABd, const double* A, int fmtA, const double* B, int fmtB, int N, int M, int Mp,
+                            hipStream_t st) {
+  if (N <= 0) return hipSuccess;
+  const int64_t MM = (int64_t)Mp * Mp;
+  int bx = (int)((2 * MM + 255) / 256);
+  if (bx > 1024) bx = 1024;
+  hipLaunchKernelGGL(k_expand_AB, dim3(bx, N < 65535 ? N : 65535), dim3(256), 0, st, ABd, A, fmtA, B, fmtB, N, M, Mp);
+  return hipGetLastError();
+}
+
 __global__ void k_identity(double* p, int Mp) {
   const int64_t MM = (int64_t)Mp * Mp;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < MM; e += (int64_t)gridDim.x * blockDim.x)

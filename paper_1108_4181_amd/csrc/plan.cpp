@@ -57,7 +57,13 @@ struct td_plan_s {
   int64_t* d_ks = nullptr;
   // compact float64 copies of the input (user layout) for residuals
   double* cA = nullptr; double* cB = nullptr; double* cC = nullptr;
-  double* adiag = nullptr; double* bdiag = nullptr;  // [N][Mp], a_0 = 0, b_{N-1} = 0
+  double* adiag = nullptr; double* bdiag = nullptr;  // [N][Mp], a_0 = 0, b_{N-1} = 0 (zero when dense)
+  // dense A or B (float64 plans): every coupling term is a block product
+  bool dense = false;
+  double* ABd = nullptr;      // [N][A_j | B_j], Mp x 2Mp each, zero padded
+  double* E = nullptr;        // [N][Mp][Mp]: E_i = D_i^{-1} A_i
+  BDesc* d_gf = nullptr; int n_gf = 0;     // G_i = D_i^{-1} F_i for every interior row
+  BDesc* d_ftd = nullptr; int n_ftd = 0;   // interface right-hand side coupling products
   // factor
   double* Dinv = nullptr;     // [N][Mp][Mp]
   double* alpha = nullptr;    // [N][Mp][Mp]
@@ -233,8 +239,18 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
   HIPCHK(hipMemcpyAsync(P->cC, C, nC * 8, hipMemcpyDeviceToDevice, st));
   P->adiag = P->alloc(N * Mp);
   P->bdiag = P->alloc(N * Mp);
-  HIPCHK(launch_pad_diag(P->adiag, P->cA, (int)N, (int)M, (int)Mp, 1, 0, st));
-  HIPCHK(launch_pad_diag(P->bdiag, P->cB, (int)N, (int)M, (int)Mp, 0, 1, st));
+  P->dense = (P->fmtA == TD_FMT_DENSE || P->fmtB == TD_FMT_DENSE);
+  if (P->dense) {
+    // the diagonal-coupling kernels then see zero couplings; the block products below add them
+    HIPCHK(launch_fill(P->adiag, N * Mp, 0.0, st));
+    HIPCHK(launch_fill(P->bdiag, N * Mp, 0.0, st));
+    P->ABd = P->alloc(N * 2 * MM);
+    HIPCHK(launch_expand_AB(P->ABd, P->cA, P->fmtA, P->cB, P->fmtB, (int)N, (int)M, (int)Mp, st));
+    P->E = P->alloc(N * MM);
+  } else {
+    HIPCHK(launch_pad_diag(P->adiag, P->cA, (int)N, (int)M, (int)Mp, 1, 0, st));
+    HIPCHK(launch_pad_diag(P->bdiag, P->cB, (int)N, (int)M, (int)Mp, 0, 1, st));
+  }
   P->d_ks = P->upload(ks);
   P->d_flag = (int32_t*)P->alloc(2);
 
@@ -285,20 +301,72 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
     int64_t* d_rows = pool.put_vec(rows);
     int32_t* d_first = pool.put_vec(first);
     HIPCHK(launch_build_D(Dwork, MM, nm, d_rows, d_first, P->cC, P->fmtC, P->adiag, P->alpha, (int)M, (int)Mp, st));
+    if (P->dense && t > 0) {   // D_i -= A_i alpha_{i-1}
+      std::vector<BDesc> da;
+      for (int q = 0; q < nm; ++q) {
+        const int64_t i = rows[q];
+        BDesc d = desc0();
+        d.a_off = i * 2 * MM;
+        d.b_off = (i - 1) * MM;
+        d.c_off = d.cin_off = q * MM;
+        d.kd = d.segrows = (int32_t)Mp;
+        da.push_back(d);
+      }
+      BArgs a = bargs_base((int)Mp);
+      a.alpha = -1.0;
+      a.A = P->ABd; a.lda = Mp;
+      a.B = P->alpha; a.ldb = Mp;
+      a.C = Dwork; a.ldc = Mp;
+      a.Cin = Dwork; a.ldcin = Mp;
+      a.ncols = (int32_t)Mp;
+      run_bgemm(a, da, pool, st);
+    }
     GJArgs g;
     g.work = Dwork; g.work_off = nullptr; g.wstride = MM;
     g.out = P->Dinv; g.out_off = pool.put_vec(outoff);
-    g.alpha = P->alpha; g.bdiag = P->bdiag; g.bd_off = pool.put_vec(bdoff);
+    g.alpha = P->dense ? nullptr : P->alpha; g.bdiag = P->bdiag; g.bd_off = pool.put_vec(bdoff);
     g.tag = pool.put_vec(tag); g.bad = bad;
     g.nmat = nm; g.Mp = (int32_t)Mp;
     HIPCHK(launch_gj(g, st));
-    BArgs a = bargs_base((int)Mp);
-    a.A = P->Dinv; a.lda = Mp;
-    a.B = Ga; a.ldb = Mp;
-    a.bscale = P->adiag;
-    a.C = Ga; a.ldc = Mp;
-    a.ncols = (int32_t)Mp;
-    run_bgemm(a, gam, pool, st);
+    if (P->dense) {   // alpha_i = D_i^{-1} B_i, E_i = D_i^{-1} A_i, Gamma_i = E_i Gamma_{i-1}
+      std::vector<BDesc> dal, de;
+      for (int q = 0; q < nm; ++q) {
+        const int64_t i = rows[q];
+        BDesc d = desc0();
+        d.a_off = i * MM;
+        d.kd = d.segrows = (int32_t)Mp;
+        d.c_off = i * MM;
+        BDesc x = d;
+        d.b_off = i * 2 * MM + MM;
+        x.b_off = i * 2 * MM;
+        dal.push_back(d);
+        de.push_back(x);
+      }
+      BArgs a = bargs_base((int)Mp);
+      a.A = P->Dinv; a.lda = Mp;
+      a.B = P->ABd; a.ldb = Mp;
+      a.ncols = (int32_t)Mp;
+      a.ldc = Mp;
+      BArgs aa = a, ae = a;
+      aa.C = P->alpha;
+      ae.C = P->E;
+      run_bgemm(aa, dal, pool, st);
+      run_bgemm(ae, de, pool, st);
+      BArgs ag = bargs_base((int)Mp);
+      ag.A = P->E; ag.lda = Mp;
+      ag.B = Ga; ag.ldb = Mp;
+      ag.C = Ga; ag.ldc = Mp;
+      ag.ncols = (int32_t)Mp;
+      run_bgemm(ag, gam, pool, st);
+    } else {
+      BArgs a = bargs_base((int)Mp);
+      a.A = P->Dinv; a.lda = Mp;
+      a.B = Ga; a.ldb = Mp;
+      a.bscale = P->adiag;
+      a.C = Ga; a.ldc = Mp;
+      a.ncols = (int32_t)Mp;
+      run_bgemm(a, gam, pool, st);
+    }
   }
 
   // ---- backward: U_i = alpha_i U_{i+1} + Gamma_i, V_i = alpha_i V_{i+1}; U_{k_{s+1}} = 0, V_{k_{s+1}} = I
@@ -342,6 +410,54 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
   double* Bt = P->red + 2 * p * MM;
   HIPCHK(launch_reduced(At, Ct, Bt, P->d_ks, P->UVa + 2 * MM, P->cC, P->fmtC, P->adiag, P->bdiag, (int)p, (int)N, (int)M,
                         (int)Mp, st));
+  if (P->dense) {
+    // with zero diagonal couplings k_reduced left At = 0, Ct = C_k, Bt = 0; add the products of
+    // eq. (red1): At = A_k U_{k-1}, Ct -= A_k V_{k-1} + B_k U_{k+1}, Bt = B_k V_{k+1}, where a
+    // neighbour that is itself an interface row contributes U = I, V = 0 (left) or U = 0,
+    // V = I (right); UVa holds [I | 0 | U_0 V_0 | U_1 V_1 | ...]
+    std::vector<BDesc> dA, dCl, dCr, dB;
+    for (int64_t s = 0; s < p; ++s) {
+      const int64_t kk = ks[s];
+      const bool left_int = s > 0 && kk - 1 > ks[s - 1];
+      const bool right_int = kk + 1 < ks[s + 1];
+      BDesc d = desc0();
+      d.kd = d.segrows = (int32_t)Mp;
+      d.c_off = d.cin_off = s * MM;
+      if (s > 0) {
+        BDesc x = d;
+        x.a_off = kk * 2 * MM;
+        x.b_off = left_int ? (2 + 2 * (kk - 1)) * MM : 0;
+        dA.push_back(x);
+        if (left_int) {
+          x.b_off = (2 + 2 * (kk - 1) + 1) * MM;
+          dCl.push_back(x);
+        }
+      }
+      if (kk + 1 < N) {
+        BDesc x = d;
+        x.a_off = kk * 2 * MM + MM;
+        if (right_int) {
+          x.b_off = (2 + 2 * (kk + 1)) * MM;
+          dCr.push_back(x);
+        }
+        x.b_off = right_int ? (2 + 2 * (kk + 1) + 1) * MM : 0;
+        dB.push_back(x);
+      }
+    }
+    BArgs a = bargs_base((int)Mp);
+    a.A = P->ABd; a.lda = Mp;
+    a.B = P->UVa; a.ldb = Mp;
+    a.ldc = Mp; a.ldcin = Mp;
+    a.ncols = (int32_t)Mp;
+    BArgs aA = a, aC = a, aB = a;
+    aA.C = At;
+    aB.C = Bt;
+    aC.C = Ct; aC.Cin = Ct; aC.alpha = -1.0;
+    run_bgemm(aA, dA, pool, st);
+    run_bgemm(aB, dB, pool, st);
+    run_bgemm(aC, dCl, pool, st);
+    run_bgemm(aC, dCr, pool, st);
+  }
 
   // ---- dichotomy tree (Algorithm 1 applied to the reduced system)
   P->nodes.clear();
@@ -672,6 +788,49 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
     }
     P->d_split = P->upload(split);
     P->d_comb = P->upload(comb);
+
+    if (P->dense) {
+      // G_i = D_i^{-1} F_i (B = F, M rows per block) into W for every interior row
+      std::vector<BDesc> gf, ftd;
+      for (int64_t s = 0; s < p; ++s)
+        for (int64_t i = ks[s] + 1; i < ks[s + 1]; ++i) {
+          BDesc d = desc0();
+          d.a_off = i * MM;
+          d.b_off = i * M;
+          d.c_off = i * Mp;
+          d.kd = d.segrows = (int32_t)Mp;
+          gf.push_back(d);
+        }
+      // F~_s += [A_k | B_k] [W_{k-1}; W_{k+1}] over the neighbours that are interior rows
+      for (int64_t s = 0; s < p; ++s) {
+        const int64_t kk = ks[s];
+        const bool left = s > 0 && kk - 1 > ks[s - 1];
+        const bool right = kk + 1 < ks[s + 1];
+        if (!left && !right) continue;
+        BDesc d = desc0();
+        d.c_off = d.cin_off = s * Mp;
+        d.segrows = (int32_t)Mp;
+        if (left && right) {
+          d.a_off = kk * 2 * MM;
+          d.kd = (int32_t)(2 * Mp);
+          d.b_off = (kk - 1) * Mp;
+          d.bseg = 2 * Mp;
+        } else if (left) {
+          d.a_off = kk * 2 * MM;
+          d.kd = (int32_t)Mp;
+          d.b_off = (kk - 1) * Mp;
+        } else {
+          d.a_off = kk * 2 * MM + MM;
+          d.kd = (int32_t)Mp;
+          d.b_off = (kk + 1) * Mp;
+        }
+        ftd.push_back(d);
+      }
+      P->n_gf = (int)gf.size();
+      P->d_gf = P->upload(gf);
+      P->n_ftd = (int)ftd.size();
+      P->d_ftd = P->upload(ftd);
+    }
   }
   // pivot check
   int32_t badv = INT_MAX;
@@ -739,8 +898,18 @@ void solve_pass(td_plan_s* P, const double* F, int64_t ldf, double* X, int64_t l
   const int64_t ldw = N * Mp, ldft = p * Mp, ldxi = (p + 2) * Mp, ldsp = (int64_t)P->nchunks * Mp;
   stage_mark(P, 0, st);
   if (P->prec == TD_PREC_F64) {
+    if (P->dense && P->n_gf > 0) {   // G_i = D_i^{-1} F_i, the forward sweep's inhomogeneous term
+      BArgs g = bargs_base((int)Mp);
+      g.descs = P->d_gf; g.nprob = P->n_gf;
+      g.A = P->Dinv; g.lda = Mp;
+      g.B = F; g.ldb = ldf; g.brows = (int32_t)M;
+      g.C = P->Wbuf; g.ldc = ldw;
+      g.ncols = (int32_t)K;
+      HIPCHK(launch_bgemm(g, st));
+    }
     SweepArgs sa;
     sa.ks = P->d_ks; sa.Dinv = P->Dinv; sa.alpha = P->alpha; sa.adiag = P->adiag;
+    sa.E = P->dense ? P->E : nullptr;
     sa.F = F; sa.ldf = ldf; sa.W = P->Wbuf; sa.ldw = ldw;
     sa.N = (int32_t)N; sa.M = (int32_t)M; sa.Mp = (int32_t)Mp; sa.p = (int32_t)p; sa.K = (int32_t)K;
     sa.ncoltiles = 0; sa.total = 0;
@@ -748,6 +917,16 @@ void solve_pass(td_plan_s* P, const double* F, int64_t ldf, double* X, int64_t l
     stage_mark(P, 1, st);
     HIPCHK(launch_ftilde(P->Ft, ldft, F, ldf, P->Wbuf, ldw, P->d_ks, P->adiag, P->bdiag, (int)p, (int)M, (int)Mp,
                          (int)K, st));
+    if (P->dense && P->n_ftd > 0) {
+      BArgs f = bargs_base((int)Mp);
+      f.descs = P->d_ftd; f.nprob = P->n_ftd;
+      f.A = P->ABd; f.lda = Mp;
+      f.B = P->Wbuf; f.ldb = ldw;
+      f.C = P->Ft; f.ldc = ldft;
+      f.Cin = P->Ft; f.ldcin = ldft;
+      f.ncols = (int32_t)K;
+      HIPCHK(launch_bgemm(f, st));
+    }
   } else {
     LpSweepArgs sa;
     sa.ks = P->d_ks; sa.Dinv = P->Dlp; sa.alpha = P->Alp; sa.adiag = P->adiag;
@@ -927,8 +1106,8 @@ td_status check_desc(const td_desc* d) {
   if (d->reserved != 0) return fail(TD_EINVAL, "reserved must be 0");
   if (d->M > 512) return fail(TD_ENOTSUP, "M > 512 is not supported");
   if (d->N > (int64_t)1 << 30) return fail(TD_ENOTSUP, "N too large");
-  if (d->fmt_A == TD_FMT_DENSE || d->fmt_B == TD_FMT_DENSE)
-    return fail(TD_ENOTSUP, "dense A/B blocks are not supported by this build");
+  if ((d->fmt_A == TD_FMT_DENSE || d->fmt_B == TD_FMT_DENSE) && d->sweep_prec != TD_PREC_F64)
+    return fail(TD_ENOTSUP, "dense A/B blocks need sweep_prec F64");
   return TD_OK;
 }
 
@@ -944,21 +1123,32 @@ int64_t factor_bytes(int64_t N, int64_t M, int64_t p, int fA, int fB, int fC, in
   b += (1 + N) * MM + p * MM;              // Gamma arena, Dwork (temporary)
   b += 3 * p * MM + p * (depth + 1) * MM + 2 * p * MM + (1 + 6 * p) * MM + p * MM;  // reduced, G, H, arenas
   if (prec != TD_PREC_F64) b += (4 * N * MM * (prec == TD_PREC_F32 ? 4 : 2) + 7) / 8;  // rounded copies
+  if (fA == TD_FMT_DENSE || fB == TD_FMT_DENSE) b += 3 * N * MM;                     // [A|B] blocks, E
   return b * 8;
 }
 
-// blocks of P^T (compact formats): C'_j = C_j^T, A'_j = B_{j-1}^T, B'_j = A_{j+1}^T
+// blocks of P^T (compact formats): C'_j = C_j^T, A'_j = B_{j-1}^T, B'_j = A_{j+1}^T; the transposed
+// system's A has B's format and its B has A's format
 void transpose_inputs(const td_plan_s* P, std::vector<double>& A2, std::vector<double>& B2, std::vector<double>& C2) {
   const int64_t N = P->N, M = P->M;
-  std::vector<double> a(N * M), b(N * M);
-  HIPCHK(hipMemcpy(a.data(), P->cA, N * M * 8, hipMemcpyDeviceToHost));
-  HIPCHK(hipMemcpy(b.data(), P->cB, N * M * 8, hipMemcpyDeviceToHost));
-  A2.assign(N * M, 0.0);
-  B2.assign(N * M, 0.0);
-  for (int64_t j = 1; j < N; ++j)
-    for (int64_t r = 0; r < M; ++r) A2[j * M + r] = b[(j - 1) * M + r];
-  for (int64_t j = 0; j + 1 < N; ++j)
-    for (int64_t r = 0; r < M; ++r) B2[j * M + r] = a[(j + 1) * M + r];
+  const int64_t sa = (P->fmtA == TD_FMT_DIAG) ? M : M * M;   // per-block sizes of the inputs
+  const int64_t sb = (P->fmtB == TD_FMT_DIAG) ? M : M * M;
+  std::vector<double> a(N * sa), b(N * sb);
+  HIPCHK(hipMemcpy(a.data(), P->cA, N * sa * 8, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(b.data(), P->cB, N * sb * 8, hipMemcpyDeviceToHost));
+  // A'_j = B_{j-1}^T (format of B), B'_j = A_{j+1}^T (format of A)
+  auto transpose_block = [M](const double* src, double* dst, bool diag) {
+    if (diag) {
+      for (int64_t r = 0; r < M; ++r) dst[r] = src[r];
+    } else {
+      for (int64_t r = 0; r < M; ++r)
+        for (int64_t q = 0; q < M; ++q) dst[q + r * M] = src[r + q * M];
+    }
+  };
+  A2.assign(N * sb, 0.0);
+  B2.assign(N * sa, 0.0);
+  for (int64_t j = 1; j < N; ++j) transpose_block(&b[(j - 1) * sb], &A2[j * sb], P->fmtB == TD_FMT_DIAG);
+  for (int64_t j = 0; j + 1 < N; ++j) transpose_block(&a[(j + 1) * sa], &B2[j * sa], P->fmtA == TD_FMT_DIAG);
   if (P->fmtC == TD_FMT_TRIDIAG) {
     std::vector<double> c(N * 3 * M);
     HIPCHK(hipMemcpy(c.data(), P->cC, N * 3 * M * 8, hipMemcpyDeviceToHost));
@@ -1043,6 +1233,8 @@ td_status factor_top(const td_desc* d, const double* A, const double* B, const d
       td_desc d2 = *d;
       d2.subdomains = P->p;
       d2.adjoint = 0;
+      d2.fmt_A = d->fmt_B;
+      d2.fmt_B = d->fmt_A;
       td_plan adj = nullptr;
       td_status s2 = factor_top(&d2, dA, dB, dC, st, &adj, false);
       (void)hipFree(dA); (void)hipFree(dB); (void)hipFree(dC);

@@ -43,7 +43,7 @@ __device__ __forceinline__ void bgemm_tile(const BArgs& args, int prob, int ct, 
       if (e < KC * KT) {
         const int k = e % KC, c = e / KC;
         const int col = col0 + c;
-        if (col < args.ncols) {
+        if (col < args.ncols && (args.brows <= 0 || kin + k < args.brows)) {
           v = Bq[k + (int64_t)col * args.ldb];
           if (args.bscale) v *= args.bscale[d.bs_off + k0 + k];
         }
@@ -435,8 +435,10 @@ __device__ __forceinline__ void sweep_f64_tile(const SweepArgs& a, int s, int ct
   // matrix.  Step order: forward rows first..last (D^{-1}), then backward rows
   // last-1..first (alpha).
   const int64_t nsteps = 2 * (last - first) + 1;
+  const bool dense = a.E != nullptr;
+  const double* __restrict__ fwdmat = dense ? a.E : a.Dinv;
   auto step_matrix = [&](int64_t q) -> const double* {
-    return (q <= last - first) ? a.Dinv + (first + q) * MM : a.alpha + (last - 1 - (q - (last - first + 1))) * MM;
+    return (q <= last - first) ? fwdmat + (first + q) * MM : a.alpha + (last - 1 - (q - (last - first + 1))) * MM;
   };
   const int64_t lane_off = rb + (L & 15) + (int64_t)(L >> 4) * Mp;
   double a0[KU][RT], a1[KU][RT];
@@ -462,10 +464,11 @@ __device__ __forceinline__ void sweep_f64_tile(const SweepArgs& a, int s, int ct
     }
   };
 
+  // first operand: F_first, or zero for the dense-A recurrence (beta_first = G_first)
   for (int e = tid; e < Mp * KT; e += nthr) {
     const int row = e % Mp, c = e / Mp;
     const int col = col0 + c;
-    In[row * SB + c] = (row < M && col < K) ? a.F[first * M + row + (int64_t)col * a.ldf] : 0.0;
+    In[row * SB + c] = (!dense && row < M && col < K) ? a.F[first * M + row + (int64_t)col * a.ldf] : 0.0;
   }
   loadA(a0, step_matrix(0), 0);
   __syncthreads();
@@ -486,9 +489,9 @@ __device__ __forceinline__ void sweep_f64_tile(const SweepArgs& a, int s, int ct
       compute(a1, kc + 1);
     }
     // operands of the epilogue, fetched before the last two chunks: F_{i+1} and a_{i+1}
-    // (forward) or beta_i (backward)
+    // (forward), G_i (forward, dense A) or beta_i (backward)
     double ex[RT][CT], an[RT];
-    const bool more = fwd && i < last;
+    const bool more = fwd && i < last && !dense;
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
       const int row = rb + 16 * t + out_row(L);
@@ -497,7 +500,7 @@ __device__ __forceinline__ void sweep_f64_tile(const SweepArgs& a, int s, int ct
       for (int c = 0; c < CT; ++c) {
         const int col = col0 + out_col(L) * CT + c;
         double v = 0.0;
-        if (fwd) {
+        if (fwd && !dense) {
           if (more && row < M && col < K) v = a.F[(i + 1) * M + row + (int64_t)col * a.ldf];
         } else if (col < K) {
           v = a.W[i * Mp + row + (int64_t)col * a.ldw];
@@ -518,8 +521,9 @@ __device__ __forceinline__ void sweep_f64_tile(const SweepArgs& a, int s, int ct
         const int lc = out_col(L) * CT + c;
         const int col = col0 + lc;
         // forward: beta_i; next operand F_{i+1} + a_{i+1} o beta_i (or beta_last = W_last)
+        // forward, dense A: beta_i = E_i beta_{i-1} + G_i; next operand beta_i
         // backward: W_i = alpha_i W_{i+1} + beta_i
-        const double v = fwd ? acc[t][c] : acc[t][c] + ex[t][c];
+        const double v = (fwd && !dense) ? acc[t][c] : acc[t][c] + ex[t][c];
         if (col < K) a.W[i * Mp + row + (int64_t)col * a.ldw] = v;
         In[row * SB + lc] = more ? ex[t][c] + an[t] * v : v;
       }
