@@ -201,6 +201,21 @@ td_status tridiag_batch_solve(td_batch batch, void* stream);
 td_status tridiag_batch_info(td_batch batch, td_info* infos);
 td_status tridiag_batch_destroy(td_batch batch);
 
+/*
+ * Band matrices (Sec. 3: the PML subdomain matrix and the probing preconditioner are band
+ * matrices, and a band matrix is block-tridiagonal with upper-triangular A_j and lower-
+ * triangular B_j).  Writes the blocks of the n x n band matrix with kl sub- and ku
+ * super-diagonals, given in general band storage (device, column-major, entry (i, j) at
+ * ab[ku + i - j + j * ldab], ldab >= kl + ku + 1), as DENSE blocks of size M >= max(kl, ku, 1):
+ * N = ceil(n / M) block rows, A, B, C each [N][M][M] (device, caller-allocated, column-major
+ * blocks), in the sign convention of tridiag_factor (the band entries left of the diagonal
+ * block are -A_I, right of it -B_I).  Rows at or beyond n get a unit diagonal and no couplings,
+ * so right-hand sides padded with zeros to N*M rows give solutions whose padded rows are zero.
+ * Asynchronous on `stream`; TD_EINVAL for inconsistent sizes or null pointers.
+ */
+td_status tridiag_band_to_blocks(int64_t n, int32_t kl, int32_t ku, const double* ab, int64_t ldab, int64_t M,
+                                 double* A, double* B, double* C, void* stream);
+
 const char* tridiag_status_string(td_status s);
 /* Text of the last error on the calling host thread ("" if none). */
 const char* tridiag_last_error(void);

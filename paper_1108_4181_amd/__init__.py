@@ -57,7 +57,7 @@ class _PlanInfo(ctypes.Structure):
 EXPORTS = ["tridiag_factor", "tridiag_solve", "tridiag_solve_adjoint", "tridiag_diag_grad", "tridiag_destroy",
            "tridiag_plan_info", "tridiag_set_profiling", "tridiag_stage_times", "tridiag_status_string",
            "tridiag_last_error", "tridiag_batch_create", "tridiag_batch_solve", "tridiag_batch_info",
-           "tridiag_batch_destroy", "tridiag_autotune"]
+           "tridiag_batch_destroy", "tridiag_autotune", "tridiag_band_to_blocks"]
 
 _lib = None
 
@@ -104,6 +104,8 @@ def load_library(path: str = LIB_PATH):
     lib.tridiag_batch_destroy.restype = i32
     lib.tridiag_autotune.argtypes = [i64, i64, i32, i64, pi64, ctypes.c_int, vp, pi64, ctypes.POINTER(dp)]
     lib.tridiag_autotune.restype = i32
+    lib.tridiag_band_to_blocks.argtypes = [i64, i32, i32, vp, i64, i64, vp, vp, vp, vp]
+    lib.tridiag_band_to_blocks.restype = i32
     _lib = lib
     return lib
 
@@ -323,6 +325,41 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class BandSolver:
+    """Solves with an n x n band matrix (kl sub-, ku super-diagonals) through its block-tridiagonal
+    form (tridiag_band_to_blocks, then a float64 plan with DENSE blocks of size M).
+
+    ab: float64 device tensor of shape (n, kl + ku + 1); row j holds column j of the general band
+    storage, i.e. ab[j, ku + i - j] = a(i, j).  Right-hand sides are (K, n) tensors; they are
+    padded with zeros to N*M rows for the solve and the solution is cut back to n rows."""
+
+    def __init__(self, ab, kl: int, ku: int, M: int = 0, subdomains: int = 0, adjoint: bool = False):
+        lib = load_library()
+        ab = _dev(ab, "ab")
+        self.n, self.kl, self.ku = int(ab.shape[0]), int(kl), int(ku)
+        if ab.dim() != 2 or ab.shape[1] != self.kl + self.ku + 1:
+            raise ValueError("ab must have shape (n, kl + ku + 1)")
+        self.M = int(M) if M else max(self.kl, self.ku, 1)
+        self.N = -(-self.n // self.M)
+        blocks = [torch.empty((self.N, self.M, self.M), dtype=torch.float64, device=ab.device) for _ in range(3)]
+        A, B, C = blocks
+        _check(lib.tridiag_band_to_blocks(self.n, self.kl, self.ku, ctypes.c_void_p(ab.data_ptr()), ab.shape[1],
+                                          self.M, ctypes.c_void_p(A.data_ptr()), ctypes.c_void_p(B.data_ptr()),
+                                          ctypes.c_void_p(C.data_ptr()), _stream()))
+        self.plan = Plan(A, B, C, self.N, self.M, "dense", "dense", "dense", subdomains=subdomains, adjoint=adjoint)
+
+    def _pad(self, F):
+        Fp = torch.zeros((F.shape[0], self.N * self.M), dtype=torch.float64, device=F.device)
+        Fp[:, : self.n] = F
+        return Fp
+
+    def solve(self, F, refine=None):
+        return self.plan.solve(self._pad(F), refine=refine)[:, : self.n]
+
+    def solve_adjoint(self, G, refine=None):
+        return self.plan.solve_adjoint(self._pad(G), refine=refine)[:, : self.n]
 
 
 def choose_subdomains(N: int, M: int, K: int, sweep_prec: str = "f64") -> int:

@@ -152,6 +152,8 @@ hipError_t launch_reduced(double* At, double* Ct, double* Bt, const int64_t* ks,
 hipError_t launch_pad_diag(double* dst, const double* src, int N, int M, int Mp, int zero_first,
                            int zero_last, hipStream_t st);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
+hipError_t launch_band_to_blocks(int64_t n, int kl, int ku, const double* ab, int64_t ldab, int M, int64_t N,
+                                 double* A, double* B, double* C, hipStream_t st);
 // [A_j | B_j] as one zero-padded Mp x 2Mp column-major matrix per block row (DIAG blocks on the
 // diagonal); A_0 and B_{N-1} are stored as zero
 hipError_t launch_expand_AB(double* ABd, const double* A, int fmtA, const double* B, int fmtB, int N, int M, int Mp,

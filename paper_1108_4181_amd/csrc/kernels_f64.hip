@@ -526,6 +526,42 @@ hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Band matrix (general band storage, column-major: a(i, j) at ab[ku + i - j + j * ldab]) as
+// block-tridiagonal blocks of size M >= max(kl, ku): with block rows I = i / M the entries of
+// block column I - 1 form -A_I (upper triangular), of block column I form C_I and of block
+// column I + 1 form -B_I (lower triangular).  Rows and columns at or beyond n get a unit
+// diagonal in C and no couplings.
+__global__ void k_band_to_blocks(int64_t n, int kl, int ku, const double* ab, int64_t ldab, int M, int64_t N,
+                                 double* A, double* B, double* C) {
+  const int64_t MM = (int64_t)M * M;
+  const int64_t total = 3 * N * MM;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int which = (int)(e / (N * MM));          // 0: A, 1: C, 2: B
+    const int64_t f = e - which * N * MM;
+    const int64_t I = f / MM;
+    const int r = (int)(f % M), c = (int)((f / M) % M);
+    const int64_t i = I * M + r, j = (I + which - 1) * M + c;
+    double v = 0.0;
+    if (j >= 0 && i < n && j < n && i - j <= kl && j - i <= ku) {
+      const double a = ab[ku + i - j + j * ldab];
+      v = (which == 1) ? a : -a;
+    } else if (which == 1 && r == c && i >= n) {
+      v = 1.0;
+    }
+    double* out = (which == 0) ? A : (which == 1 ? C : B);
+    out[f] = v;
+  }
+}
+
+hipError_t launch_band_to_blocks(int64_t n, int kl, int ku, const double* ab, int64_t ldab, int M, int64_t N,
+                                 double* A, double* B, double* C, hipStream_t st) {
+  const int64_t total = 3 * N * (int64_t)M * M;
+  int64_t bx = (total + 255) / 256;
+  if (bx > 16384) bx = 16384;
+  hipLaunchKernelGGL(k_band_to_blocks, dim3((unsigned)bx), dim3(256), 0, st, n, kl, ku, ab, ldab, M, N, A, B, C);
+  return hipGetLastError();
+}
+
 __global__ void k_expand_AB(double* ABd, const double* A, int fmtA, const double* B, int fmtB, int N, int M, int Mp) {
   const int64_t MM = (int64_t)Mp * Mp;
   for (int64_t j = blockIdx.y; j < N; j += gridDim.y)

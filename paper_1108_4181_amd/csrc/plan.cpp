@@ -1636,6 +1636,20 @@ const char* tridiag_status_string(td_status s) {
 
 const char* tridiag_last_error(void) { return g_err.c_str(); }
 
+td_status tridiag_band_to_blocks(int64_t n, int32_t kl, int32_t ku, const double* ab, int64_t ldab, int64_t M,
+                                 double* A, double* B, double* C, void* stream) {
+  g_err.clear();
+  if (n < 1 || kl < 0 || ku < 0) return fail(TD_EINVAL, "n must be >= 1 and kl, ku >= 0");
+  if (ldab < (int64_t)kl + ku + 1) return fail(TD_EINVAL, "ldab must be >= kl + ku + 1");
+  if (M < 1 || M < kl || M < ku) return fail(TD_EINVAL, "block size M must be >= max(kl, ku, 1)");
+  if (M > 512) return fail(TD_ENOTSUP, "M > 512 is not supported");
+  if (!ab || !A || !B || !C) return fail(TD_EINVAL, "null pointer");
+  const int64_t N = (n + M - 1) / M;
+  hipError_t e = launch_band_to_blocks(n, kl, ku, ab, ldab, (int)M, N, A, B, C, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(TD_EHIP, hipGetErrorString(e));
+  return TD_OK;
+}
+
 td_status tridiag_autotune(int64_t M, int64_t K, int32_t sweep_prec, int64_t probe_N, const int64_t* candidates,
                            int ncand, void* stream, int64_t* best_L, double* ms_per_solve) {
   g_err.clear();

@@ -94,3 +94,11 @@ def test_null_arguments_rejected(lib):
     assert lib.tridiag_solve_adjoint(None, None, 0, None, 0, 1, None, None, None) == 1
     assert lib.tridiag_diag_grad(None, 0, None, 0, 0, 0, None, None) == 1
     assert lib.tridiag_destroy(None) == 0
+
+
+@pytest.mark.parametrize("n,kl,ku,ldab,M,code", [
+    (0, 1, 1, 3, 2, 1), (10, -1, 1, 3, 2, 1), (10, 2, 2, 4, 2, 1), (10, 3, 1, 5, 2, 1), (10, 1, 1, 3, 600, 7),
+])
+def test_band_conversion_rejects_bad_sizes(lib, n, kl, ku, ldab, M, code):
+    dummy = ctypes.c_void_p(16)  # never dereferenced: validation fails first
+    assert lib.tridiag_band_to_blocks(n, kl, ku, dummy, ldab, M, dummy, dummy, dummy, None) == code
