@@ -88,8 +88,9 @@ def algorithmic_work(N, M, K, p):
         depth += 1
         q >>= 1
     dich_flops = 2.0 * M * M * K * p * (depth + 2)
+    dich_bytes = 8.0 * (M * M * p * depth + 3 * p * M * K)   # stored inverse rows once, F~ and X rows
     return dict(sweep_flops=sweep_flops, sweep_bytes=sweep_bytes, sup_flops=sup_flops, sup_bytes=sup_bytes,
-                dich_flops=dich_flops, total_flops=sweep_flops + sup_flops + dich_flops)
+                dich_flops=dich_flops, dich_bytes=dich_bytes, total_flops=sweep_flops + sup_flops + dich_flops)
 
 
 def cpu_baseline(w, rows, cols, threads):
@@ -200,6 +201,72 @@ def bench_batched(args):
     print(json.dumps(out))
 
 
+def band_storage(n, kl, ku, seed):
+    """General band storage (rows = diagonals, (kl+ku+1) x n) of a diagonally dominant band matrix."""
+    import numpy as np
+
+    import synth
+
+    ab = synth.uniform_range(seed, 11, 0, (kl + ku + 1) * n, -1.0, 1.0).reshape(kl + ku + 1, n)
+    ab[ku, :] = (kl + ku + 1) * 1.5 + np.abs(ab[ku, :])
+    j = np.arange(n)
+    for d in range(kl + ku + 1):
+        i = j - (ku - d)
+        ab[d, (i < 0) | (i >= n)] = 0.0
+    return ab
+
+
+def bench_band(args):
+    """A band matrix (n, kl, ku) solved through its block-tridiagonal form (blocks of size max(kl, ku),
+    dense triangular couplings, float64), K right-hand sides."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1108_4181_amd as td
+
+    n, kl, ku, K = (int(v) for v in args.band.split(","))
+    dev = torch.device("cuda:0")
+    ab = torch.as_tensor(np.ascontiguousarray(band_storage(n, kl, ku, 4242).T), device=dev)
+    F = synth.rhs_torch(4243, n, 1, K, dev)
+    M = max(kl, ku, 1)
+    N = -(-n // M)
+    p = args.subdomains or max(1, N // 32)
+    t0 = time.perf_counter()
+    solver = td.BandSolver(ab, kl, ku, subdomains=p)
+    torch.cuda.synchronize()
+    factor_ms = (time.perf_counter() - t0) * 1e3
+    Fp = solver._pad(F)
+    X = torch.empty_like(Fp)
+    _, info = solver.plan.solve(Fp, X, info=True)
+    for _ in range(args.warmup):
+        solver.plan.solve(Fp, X)
+    torch.cuda.synchronize()
+    solver.plan.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        solver.plan.solve(Fp, X)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    stages = solver.plan.stage_times()
+    # dense couplings: the forward sweep is G = D^{-1} F (2 M^2 K per interior row) plus the recurrence
+    # with E (2 M^2 K), the backward sweep 2 M^2 K, the superposition 4 M^2 K
+    work = algorithmic_work(N, M, K, p)
+    fwd = N - p
+    flops = work["total_flops"] + 2.0 * M * M * K * fwd
+    out = {
+        "metric": METRIC, "value": K / (ms / 1e3), "unit": "RHS/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "band", "n": n, "kl": kl, "ku": ku, "K": K, "block": M, "N": N, "subdomains": p},
+        "stages_ms": {k: v for k, v in stages.items() if k != "count"},
+        "whole_solve_tflops": flops / (ms * 1e-3) / 1e12,
+        "factor_ms": factor_ms, "max_col_rel_residual": info["max_col_rel_residual"],
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,6 +281,10 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="bytes of a plain device-to-device copy run before the timed region (counter calibration)")
     ap.add_argument("--batch-passes", type=int, default=3)
+    ap.add_argument("--subdomains", type=int, default=0,
+                    help="override the workload's subdomain count (= N: Algorithm 1 on the whole system)")
+    ap.add_argument("--band", default="65536,60,60,256",
+                    help="band workload n,kl,ku,K (with --workload band)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -222,6 +293,9 @@ def main():
 
     if args.workload == "batched_64":
         bench_batched(args)
+        return
+    if args.workload == "band":
+        bench_band(args)
         return
 
     import torch
@@ -232,6 +306,8 @@ def main():
     w = dict(synth.WORKLOADS[args.workload])
     w["name"] = args.workload
     N, M, K, p = w["N"], w["M"], w["K"], w["p"]
+    if args.subdomains:
+        p = min(N, args.subdomains)
     dev = torch.device("cuda:0")
     sysw = synth.workload_system(args.workload)
     F = synth.rhs_torch(w["seed"], N, M, K, dev)
@@ -267,11 +343,20 @@ def main():
     plan.set_profiling(False)
     ms_per_step = elapsed * 1e3 / args.steps
     value = K / (ms_per_step / 1e3)
+    # the same solves without stage events: the library replays them from a captured HIP graph
+    plan.solve(F, X)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.solve(F, X)
+    torch.cuda.synchronize()
+    graph_ms = (time.perf_counter() - t0) * 1e3 / args.steps
 
     work = algorithmic_work(N, M, K, p)
     kern = {
         "sweep": (stages["sweep"], work["sweep_flops"], work["sweep_bytes"]),
         "superposition": (stages["superposition"], work["sup_flops"], work["sup_bytes"]),
+        "dichotomy": (stages["dichotomy_partial"] + stages["dichotomy_levels"], work["dich_flops"], work["dich_bytes"]),
     }
     dom = max(kern, key=lambda k: kern[k][0])
     t_ms, fl, by = kern[dom]
@@ -302,6 +387,7 @@ def main():
         "kernels": other,
         "stages_ms": {k: v for k, v in stages.items() if k != "count"},
         "whole_solve_tflops": work["total_flops"] / (ms_per_step * 1e-3) / 1e12,
+        "graph_replay_ms_per_step": graph_ms,
         "factor_ms": factor_ms,
         "max_col_rel_residual": info["max_col_rel_residual"],
         "plan_device_bytes": pinfo["device_bytes"],

@@ -184,7 +184,9 @@ hipError_t launch_probe_inputs(double* A, double* B, double* C, double* F, int N
 // global counter; an item waits (bounded spin) until the counter of the stage it
 // depends on reaches the expected value, runs, and then increments its own counter.
 // ---------------------------------------------------------------------------
+constexpr int RES_CHUNK = 8192;      // rows of the stencil residual per work-group
 constexpr int BATCH_MAXDEPTH = 16;
+constexpr int BATCH_RESCOLS = 8;   // right-hand sides per residual item of the batched solve
 enum { BI_SWEEP = 0, BI_FTILDE = 1, BI_PART = 2, BI_LEVEL = 3, BI_SUP = 4, BI_RES = 5, BI_RFIN = 6 };
 
 struct BatchItem {

@@ -103,7 +103,7 @@ __device__ void run_item(const BatchItem& it, const BatchSys& S, uint4* lds, dou
     case BI_RES: {
       const int c1 = it.i1 + S.rescols < S.K ? it.i1 + S.rescols : S.K;
       for (int col = it.i1; col < c1; ++col)
-        residual_stencil_tile(S.R, S.ldr, S.F, S.ldf, S.X, S.ldx, S.cA, S.cB, S.cC, S.N, S.M, 8192, S.colpart,
+        residual_stencil_tile(S.R, S.ldr, S.F, S.ldf, S.X, S.ldx, S.cA, S.cB, S.cC, S.N, S.M, RES_CHUNK, S.colpart,
                               S.nchunk, it.i0, col, red);
       break;
     }

@@ -57,13 +57,13 @@ hipError_t launch_cast_rowmajor(int prec, void* dst, int64_t dstride, const doub
 // T (column-major, k contiguous), beta / W kept in float32 in the workspace, and the input
 // right-hand side read in float64 and rounded once.
 // ---------------------------------------------------------------------------
-template <int PREC, int RT, int CT>
+template <int PREC, int RT, int CT, int KU>
 __global__ void __launch_bounds__(512) k_sweep_lp(LpSweepArgs a) {
   extern __shared__ uint4 lds_raw[];
   const int lg = lp_xcd_remap(blockIdx.x, gridDim.x);
   if (lg >= a.total) return;
   const int s = lg / a.ncoltiles;
-  sweep_lp_tile<PREC, RT, CT>(a, s, lg - s * a.ncoltiles, lds_raw);
+  sweep_lp_tile<PREC, RT, CT, KU>(a, s, lg - s * a.ncoltiles, lds_raw);
 }
 
 // ---------------------------------------------------------------------------
@@ -71,13 +71,23 @@ __global__ void __launch_bounds__(512) k_sweep_lp(LpSweepArgs a) {
 // interface panel rounded to T in LDS and [U_i V_i] (row-major, T) streamed.  With
 // `accumulate` the result is added to X (refinement correction).
 // ---------------------------------------------------------------------------
-template <int PREC, int RT, int CT>
+template <int PREC, int RT, int CT, int KU>
 __global__ void __launch_bounds__(512) k_superpose_lp(LpSupArgs a) {
   extern __shared__ uint4 lds_raw[];
   const int lg = lp_xcd_remap(blockIdx.x, gridDim.x);
   if (lg >= a.total) return;
   const int s = lg / a.ncoltiles;
-  superpose_lp_tile<PREC, RT, CT>(a, s, lg - s * a.ncoltiles, lds_raw);
+  superpose_lp_tile<PREC, RT, CT, KU>(a, s, lg - s * a.ncoltiles, lds_raw);
+}
+
+// k-groups per register chunk of the streamed matrix: a float32 group (16 deep) is four MFMAs per
+// tile and one group of prefetch covers the load latency (longer chunks measured no faster); a
+// bfloat16 group (32 deep) is one MFMA, so bfloat16 loads four groups ahead (5% faster sweeps)
+template <int PREC>
+static inline int lp_chunk(int ngroups) {
+  if (PREC == 1) return 1;
+  if (ngroups % 4 == 0) return 4;
+  return (ngroups % 2 == 0) ? 2 : 1;
 }
 
 static inline int lp_choose_rt(int Mp) {
@@ -86,7 +96,7 @@ static inline int lp_choose_rt(int Mp) {
   return 1;
 }
 
-template <int PREC, int RT, int CT>
+template <int PREC, int RT, int CT, int KU>
 static hipError_t launch_sweep_lp_cfg(const LpSweepArgs& a0, hipStream_t st) {
   LpSweepArgs a = a0;
   constexpr int kt = 16 * CT;
@@ -96,18 +106,27 @@ static hipError_t launch_sweep_lp_cfg(const LpSweepArgs& a0, hipStream_t st) {
   const int nthr = a.Mp / (16 * RT) * 64;
   const size_t esz = (PREC == 1) ? 4 : 2;
   const size_t lds = (size_t)kt * ((size_t)a.Mp * esz + 16);
-  hipError_t e = hipFuncSetAttribute((const void*)k_sweep_lp<PREC, RT, CT>,
+  hipError_t e = hipFuncSetAttribute((const void*)k_sweep_lp<PREC, RT, CT, KU>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_sweep_lp<PREC, RT, CT>), dim3(lp_pad8(a.total)), dim3(nthr), lds, st, a);
+  hipLaunchKernelGGL((k_sweep_lp<PREC, RT, CT, KU>), dim3(lp_pad8(a.total)), dim3(nthr), lds, st, a);
   return hipGetLastError();
+}
+
+template <int PREC, int RT, int CT>
+static hipError_t launch_sweep_lp_ku(const LpSweepArgs& a, hipStream_t st) {
+  switch (lp_chunk<PREC>(a.Mp / LP<PREC>::KG)) {
+    case 4: return launch_sweep_lp_cfg<PREC, RT, CT, 4>(a, st);
+    case 2: return launch_sweep_lp_cfg<PREC, RT, CT, 2>(a, st);
+    default: return launch_sweep_lp_cfg<PREC, RT, CT, 1>(a, st);
+  }
 }
 
 template <int PREC, int RT>
 static hipError_t launch_sweep_lp_rt(const LpSweepArgs& a, hipStream_t st) {
-  if (a.K <= 16) return launch_sweep_lp_cfg<PREC, RT, 1>(a, st);
-  if (a.K <= 32 || RT == 4) return launch_sweep_lp_cfg<PREC, RT, 2>(a, st);
-  return launch_sweep_lp_cfg<PREC, RT, (RT == 4 ? 2 : 4)>(a, st);
+  if (a.K <= 16) return launch_sweep_lp_ku<PREC, RT, 1>(a, st);
+  if (a.K <= 32 || RT == 4) return launch_sweep_lp_ku<PREC, RT, 2>(a, st);
+  return launch_sweep_lp_ku<PREC, RT, (RT == 4 ? 2 : 4)>(a, st);
 }
 
 hipError_t launch_sweep_lp(int prec, const LpSweepArgs& a, hipStream_t st) {
@@ -123,7 +142,7 @@ hipError_t launch_sweep_lp(int prec, const LpSweepArgs& a, hipStream_t st) {
   return launch_sweep_lp_rt<2, 1>(a, st);
 }
 
-template <int PREC, int RT, int CT>
+template <int PREC, int RT, int CT, int KU>
 static hipError_t launch_sup_lp_cfg(const LpSupArgs& a0, hipStream_t st) {
   LpSupArgs a = a0;
   constexpr int kt = 16 * CT;
@@ -133,20 +152,34 @@ static hipError_t launch_sup_lp_cfg(const LpSupArgs& a0, hipStream_t st) {
   const int nthr = a.Mp / (16 * RT) * 64;
   const size_t esz = (PREC == 1) ? 4 : 2;
   const size_t lds = (size_t)kt * ((size_t)2 * a.Mp * esz + 16);
-  hipError_t e = hipFuncSetAttribute((const void*)k_superpose_lp<PREC, RT, CT>,
+  hipError_t e = hipFuncSetAttribute((const void*)k_superpose_lp<PREC, RT, CT, KU>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_superpose_lp<PREC, RT, CT>), dim3(lp_pad8(a.total)), dim3(nthr), lds, st, a);
+  hipLaunchKernelGGL((k_superpose_lp<PREC, RT, CT, KU>), dim3(lp_pad8(a.total)), dim3(nthr), lds, st, a);
   return hipGetLastError();
+}
+
+template <int PREC, int RT, int CT>
+static hipError_t launch_sup_lp_ku(const LpSupArgs& a, hipStream_t st) {
+  // the widest tile already holds 16 accumulators per lane: longer chunks would spill
+  if constexpr (RT * CT >= 16) {
+    return launch_sup_lp_cfg<PREC, RT, CT, 1>(a, st);
+  } else {
+    switch (lp_chunk<PREC>(2 * a.Mp / LP<PREC>::KG)) {
+      case 4: return launch_sup_lp_cfg<PREC, RT, CT, 4>(a, st);
+      case 2: return launch_sup_lp_cfg<PREC, RT, CT, 2>(a, st);
+      default: return launch_sup_lp_cfg<PREC, RT, CT, 1>(a, st);
+    }
+  }
 }
 
 template <int PREC, int RT>
 static hipError_t launch_sup_lp_rt(const LpSupArgs& a, hipStream_t st) {
   const size_t esz = (PREC == 1) ? 4 : 2;
   const size_t lds4 = (size_t)64 * ((size_t)2 * a.Mp * esz + 16);
-  if (a.K <= 16) return launch_sup_lp_cfg<PREC, RT, 1>(a, st);
-  if (a.K <= 32 || lds4 > 160 * 1024) return launch_sup_lp_cfg<PREC, RT, 2>(a, st);
-  return launch_sup_lp_cfg<PREC, RT, 4>(a, st);
+  if (a.K <= 16) return launch_sup_lp_ku<PREC, RT, 1>(a, st);
+  if (a.K <= 32 || lds4 > 160 * 1024) return launch_sup_lp_ku<PREC, RT, 2>(a, st);
+  return launch_sup_lp_ku<PREC, RT, 4>(a, st);
 }
 
 hipError_t launch_superpose_lp(int prec, const LpSupArgs& a, hipStream_t st) {
@@ -206,7 +239,7 @@ __global__ void __launch_bounds__(256) k_residual_stencil(double* R, int64_t ldr
   residual_stencil_tile(R, ldr, F, ldf, X, ldx, A, B, C, N, M, chunk, colpart, nchunk, blockIdx.x, blockIdx.y, red);
 }
 
-int residual_chunks(int64_t n) { return (int)((n + 8191) / 8192); }
+int residual_chunks(int64_t n) { return (int)((n + RES_CHUNK - 1) / RES_CHUNK); }
 
 hipError_t launch_residual_stencil(double* R, int64_t ldr, const double* F, int64_t ldf, const double* X, int64_t ldx,
                                    const double* A, const double* B, const double* C, int N, int M, int K,
@@ -215,7 +248,7 @@ hipError_t launch_residual_stencil(double* R, int64_t ldr, const double* F, int6
   const int64_t n = (int64_t)N * M;
   const int nchunk = residual_chunks(n);
   hipLaunchKernelGGL(k_residual_stencil, dim3(nchunk, K), dim3(256), 0, st, R, ldr, F, ldf, X, ldx, A, B, C, N, M, K,
-                     8192, colpart, nchunk);
+                     RES_CHUNK, colpart, nchunk);
   return hipGetLastError();
 }
 

@@ -126,7 +126,22 @@ struct td_plan_s {
     if (it != allocs.end()) allocs.erase(it);
     (void)hipFree(p);
   }
+  // the last plain solve (no refinement, no report, not profiled), captured as a HIP graph and
+  // replayed while the arguments and the workspace stay the same
+  struct {
+    const double* F = nullptr; int64_t ldf = 0;
+    double* X = nullptr; int64_t ldx = 0;
+    int64_t K = 0, ws_gen = -1;
+    hipGraph_t g = nullptr; hipGraphExec_t ex = nullptr;
+  } sg;
+  int64_t ws_gen = 0;           // incremented whenever the solve workspace is reallocated
+  void drop_graph() {
+    if (sg.ex) (void)hipGraphExecDestroy(sg.ex);
+    if (sg.g) (void)hipGraphDestroy(sg.g);
+    sg.ex = nullptr; sg.g = nullptr; sg.F = nullptr; sg.X = nullptr; sg.ws_gen = -1;
+  }
   ~td_plan_s() {
+    drop_graph();
     for (void* p : allocs) (void)hipFree(p);
     for (auto& s : evsets)
       for (auto& e : s.ev) (void)hipEventDestroy(e);
@@ -755,7 +770,8 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
         return (2 * Mp) % n == 0 && w % 16 == 0 && Mp % w == 0;
       };
       int ns = 1;
-      while (nl * ns < 16 && ns < 8 && slab_ok(2 * ns)) ns *= 2;
+      // (small blocks: the inner dimension is a few chunks and the extra launch would cost more)
+      while (Mp >= 64 && nl * ns < 16 && ns < 8 && slab_ok(2 * ns)) ns *= 2;
       P->lev_nslab[lv] = ns;
       P->split_begin[lv] = (int)split.size();
       P->comb_begin[lv] = (int)comb.size();
@@ -847,6 +863,7 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
 
 void ensure_workspace(td_plan_s* P, int64_t K, hipStream_t st) {
   if (K <= P->kcap) return;
+  ++P->ws_gen;
   const int64_t N = P->N, Mp = P->Mp, p = P->p;
   P->release(P->Wbuf); P->release(P->W32); P->release(P->Ft); P->release(P->Xi); P->release(P->Sp);
   P->release(P->Pbuf);
@@ -882,6 +899,15 @@ void ensure_refine_ws(td_plan_s* P, int64_t K) {
   P->rcap = K;
 }
 
+// plain solves replay a captured HIP graph unless TD_SOLVE_GRAPH=0
+bool solve_graphs_enabled() {
+  static const bool on = [] {
+    const char* v = std::getenv("TD_SOLVE_GRAPH");
+    return !(v && v[0] == '0');
+  }();
+  return on;
+}
+
 // stage boundaries are recorded for the first pass of a solve only
 void stage_mark(td_plan_s* P, int idx, hipStream_t st) {
   if (!P->prof || !P->se || !P->first_pass) return;
@@ -913,7 +939,7 @@ void solve_pass(td_plan_s* P, const double* F, int64_t ldf, double* X, int64_t l
     sa.F = F; sa.ldf = ldf; sa.W = P->Wbuf; sa.ldw = ldw;
     sa.N = (int32_t)N; sa.M = (int32_t)M; sa.Mp = (int32_t)Mp; sa.p = (int32_t)p; sa.K = (int32_t)K;
     sa.ncoltiles = 0; sa.total = 0;
-    HIPCHK(launch_sweep(sa, st));
+    if (N > p) HIPCHK(launch_sweep(sa, st));
     stage_mark(P, 1, st);
     HIPCHK(launch_ftilde(P->Ft, ldft, F, ldf, P->Wbuf, ldw, P->d_ks, P->adiag, P->bdiag, (int)p, (int)M, (int)Mp,
                          (int)K, st));
@@ -933,7 +959,7 @@ void solve_pass(td_plan_s* P, const double* F, int64_t ldf, double* X, int64_t l
     sa.F = F; sa.ldf = ldf; sa.W = P->W32; sa.ldw = ldw;
     sa.N = (int32_t)N; sa.M = (int32_t)M; sa.Mp = (int32_t)Mp; sa.p = (int32_t)p; sa.K = (int32_t)K;
     sa.ncoltiles = 0; sa.total = 0;
-    HIPCHK(launch_sweep_lp(P->prec, sa, st));
+    if (N > p) HIPCHK(launch_sweep_lp(P->prec, sa, st));
     stage_mark(P, 1, st);
     HIPCHK(launch_ftilde_f32(P->Ft, ldft, F, ldf, P->W32, ldw, P->d_ks, P->adiag, P->bdiag, (int)p, (int)M,
                              (int)Mp, (int)K, st));
@@ -993,7 +1019,7 @@ void solve_pass(td_plan_s* P, const double* F, int64_t ldf, double* X, int64_t l
     u.X = X; u.ldx = ldx;
     u.N = (int32_t)N; u.M = (int32_t)M; u.Mp = (int32_t)Mp; u.p = (int32_t)p; u.K = (int32_t)K;
     u.ncoltiles = 0; u.total = 0; u.accumulate = accumulate ? 1 : 0;
-    HIPCHK(launch_superpose(u, st));
+    if (N > p) HIPCHK(launch_superpose(u, st));
   } else {
     LpSupArgs u;
     u.ks = P->d_ks; u.UV = P->UVlp;
@@ -1002,7 +1028,7 @@ void solve_pass(td_plan_s* P, const double* F, int64_t ldf, double* X, int64_t l
     u.X = X; u.ldx = ldx;
     u.N = (int32_t)N; u.M = (int32_t)M; u.Mp = (int32_t)Mp; u.p = (int32_t)p; u.K = (int32_t)K;
     u.ncoltiles = 0; u.total = 0; u.accumulate = accumulate ? 1 : 0;
-    HIPCHK(launch_superpose_lp(P->prec, u, st));
+    if (N > p) HIPCHK(launch_superpose_lp(P->prec, u, st));
   }
   stage_mark(P, 5, st);
   P->first_pass = false;
@@ -1059,8 +1085,40 @@ td_status solve_impl(td_plan_s* P, const double* F, int64_t ldf, double* X, int6
   ensure_workspace(P, K, st);
   if (P->se) HIPCHK(hipEventRecord(P->se->ev[6], st));
   P->first_pass = true;
-  solve_pass(P, F, ldf, X, ldx, K, false, st);
   const bool refine = rf && rf->enable;
+  if (!refine && !info && !P->se && solve_graphs_enabled()) {
+    // a plain solve is a fixed sequence of launches: replay it from a HIP graph (captured on a
+    // private stream, so that a legacy default stream of the caller is never captured)
+    auto& g = P->sg;
+    if (!(g.ex && g.F == F && g.ldf == ldf && g.X == X && g.ldx == ldx && g.K == K && g.ws_gen == P->ws_gen)) {
+      P->drop_graph();
+      hipStream_t cs = nullptr;
+      HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+      hipError_t be = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+      hipGraph_t gr = nullptr;
+      hipError_t ce = hipSuccess;
+      if (be == hipSuccess) {
+        try {
+          solve_pass(P, F, ldf, X, ldx, K, false, cs);
+        } catch (...) {
+          (void)hipStreamEndCapture(cs, &gr);
+          if (gr) (void)hipGraphDestroy(gr);
+          (void)hipStreamDestroy(cs);
+          throw;
+        }
+        ce = hipStreamEndCapture(cs, &gr);
+      }
+      (void)hipStreamDestroy(cs);
+      HIPCHK(be);
+      HIPCHK(ce);
+      g.g = gr;
+      HIPCHK(hipGraphInstantiate(&g.ex, gr, nullptr, nullptr, 0));
+      g.F = F; g.ldf = ldf; g.X = X; g.ldx = ldx; g.K = K; g.ws_gen = P->ws_gen;
+    }
+    HIPCHK(hipGraphLaunch(g.ex, st));
+    return TD_OK;
+  }
+  solve_pass(P, F, ldf, X, ldx, K, false, st);
   td_status status = TD_OK;
   if (refine || info) {
     const double tol = (rf && rf->tol > 0.0) ? rf->tol : 1e-10;
@@ -1377,7 +1435,7 @@ td_status batch_create_impl(int n, const td_plan* plans, const double* const* F,
     S.resid = nullptr;  // set below
     S.N = (int32_t)N; S.M = (int32_t)M; S.Mp = (int32_t)Mp; S.p = (int32_t)p; S.K = (int32_t)Kq;
     S.rt = (int32_t)(Mp / 64);
-    S.rescols = 8;
+    S.rescols = BATCH_RESCOLS;
     S.tol = tol;
     nst[q] = 6 + P->depth;
     cbase[q] = nctr;
@@ -1413,7 +1471,7 @@ td_status batch_create_impl(int n, const td_plan* plans, const double* const* F,
     cnt_lev[q].resize(P->depth);
     for (int lv = 0; lv < P->depth; ++lv) cnt_lev[q][lv] = P->corr_count[lv] * nct_bg[q];
     cnt_sup[q] = (int)P->p * nct_sup[q];
-    cnt_res[q] = sys[q].nchunk * (int)((K[q] + 7) / 8);
+    cnt_res[q] = sys[q].nchunk * (int)((K[q] + BATCH_RESCOLS - 1) / BATCH_RESCOLS);
   }
   int maxdepth = 0;
   for (int q = 0; q < n; ++q) maxdepth = std::max(maxdepth, plans[q]->depth);
@@ -1469,7 +1527,7 @@ td_status batch_create_impl(int n, const td_plan* plans, const double* const* F,
     for (int q : order) {
       td_plan_s* P = plans[q];
       for (int ch = 0; ch < sys[q].nchunk; ++ch)
-        for (int c0 = 0; c0 < K[q]; c0 += 8)
+        for (int c0 = 0; c0 < K[q]; c0 += BATCH_RESCOLS)
           add(BI_RES, q, r, 0, ch, c0, ctr(q, r, 3 + P->depth), cnt_sup[q], ctr(q, r, 4 + P->depth));
     }
     stage();

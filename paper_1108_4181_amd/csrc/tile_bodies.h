@@ -138,7 +138,9 @@ __device__ __forceinline__ void bgemm_tile(const BArgs& args, int prob, int ct, 
   }
 }
 
-template <int PREC, int RT, int CT>
+// The step matrix streams through two register buffers of KU k-groups each (KU must divide the
+// number of k-groups, Mp / KG), each loaded one buffer ahead of its MFMAs.
+template <int PREC, int RT, int CT, int KU = 1>
 __device__ __forceinline__ void sweep_lp_tile(const LpSweepArgs& a, int s, int ct, uint4* lds_raw) {
   using Tr = LP<PREC>;
   using T = typename Tr::T;
@@ -155,7 +157,7 @@ __device__ __forceinline__ void sweep_lp_tile(const LpSweepArgs& a, int s, int c
   if (first > last) return;
   const int rb = w * 16 * RT;
   const int64_t MM = (int64_t)Mp * Mp;
-  const int ng = Mp / KG;   // k-groups per step
+  const int nkc = Mp / (KG * KU);   // chunks of KU k-groups per step
 
   const int64_t nsteps = 2 * (last - first) + 1;
   auto step_matrix = [&](int64_t q) -> const T* {
@@ -164,22 +166,28 @@ __device__ __forceinline__ void sweep_lp_tile(const LpSweepArgs& a, int s, int c
   };
   // lane's 16-byte slice of row (rb + 16t + L%16), k-group g
   const int64_t lane_off = (int64_t)(rb + (L & 15)) * Mp + (KG / 4) * (L >> 4);
-  uint4 a0[RT], a1[RT];
-  auto loadA = [&](uint4 (&dst)[RT], const T* __restrict__ Ab, int g) {
+  uint4 a0[KU][RT], a1[KU][RT];
+  auto loadA = [&](uint4 (&dst)[KU][RT], const T* __restrict__ Ab, int q) {
 #pragma unroll
-    for (int t = 0; t < RT; ++t)
-      dst[t] = *reinterpret_cast<const uint4*>(Ab + lane_off + (int64_t)16 * t * Mp + KG * g);
+    for (int u = 0; u < KU; ++u)
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+        dst[u][t] = *reinterpret_cast<const uint4*>(Ab + lane_off + (int64_t)16 * t * Mp + KG * (KU * q + u));
   };
   f32x4 acc[RT][CT];
-  auto compute = [&](const uint4 (&av)[RT], int g) {
-    uint4 b[CT];
+  auto compute = [&](const uint4 (&av)[KU][RT], int q) {
 #pragma unroll
-    for (int c = 0; c < CT; ++c)
-      b[c] = *reinterpret_cast<const uint4*>(In + (16 * c + (L & 15)) * SK + KG * g + (KG / 4) * (L >> 4));
+    for (int u = 0; u < KU; ++u) {
+      const int g = KU * q + u;
+      uint4 b[CT];
 #pragma unroll
-    for (int t = 0; t < RT; ++t)
+      for (int c = 0; c < CT; ++c)
+        b[c] = *reinterpret_cast<const uint4*>(In + (16 * c + (L & 15)) * SK + KG * g + (KG / 4) * (L >> 4));
 #pragma unroll
-      for (int c = 0; c < CT; ++c) Tr::mma(acc[t][c], av[t], b[c]);
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) Tr::mma(acc[t][c], av[u][t], b[c]);
+    }
   };
 
   for (int e = tid; e < Mp * KT; e += nthr) {
@@ -201,7 +209,7 @@ __device__ __forceinline__ void sweep_lp_tile(const LpSweepArgs& a, int s, int c
 #pragma unroll
       for (int c = 0; c < CT; ++c) acc[t][c] = (f32x4){0.f, 0.f, 0.f, 0.f};
     int g = 0;
-    for (; g + 2 < ng; g += 2) {
+    for (; g + 2 < nkc; g += 2) {
       loadA(a1, Ai, g + 1);
       compute(a0, g);
       loadA(a0, Ai, g + 2);
@@ -232,7 +240,7 @@ __device__ __forceinline__ void sweep_lp_tile(const LpSweepArgs& a, int s, int c
         }
       }
     }
-    if (ng - g == 2) {
+    if (nkc - g == 2) {
       loadA(a1, Ai, g + 1);
       compute(a0, g);
       loadA(a0, Anx, 0);
@@ -264,7 +272,7 @@ __device__ __forceinline__ void sweep_lp_tile(const LpSweepArgs& a, int s, int c
   }
 }
 
-template <int PREC, int RT, int CT>
+template <int PREC, int RT, int CT, int KU = 1>
 __device__ __forceinline__ void superpose_lp_tile(const LpSupArgs& a, int s, int ct, uint4* lds_raw) {
   using Tr = LP<PREC>;
   using T = typename Tr::T;
@@ -282,7 +290,7 @@ __device__ __forceinline__ void superpose_lp_tile(const LpSupArgs& a, int s, int
   if (first > last) return;
   const int rb = w * 16 * RT;
   const int64_t MM2 = (int64_t)Mp * kd;
-  const int ng = kd / KG;
+  const int nkc = kd / (KG * KU);
 
   for (int e = tid; e < kd * KT; e += nthr) {
     const int k = e % kd, c = e / kd;
@@ -292,22 +300,28 @@ __device__ __forceinline__ void superpose_lp_tile(const LpSupArgs& a, int s, int
   }
 
   const int64_t lane_off = (int64_t)(rb + (L & 15)) * kd + (KG / 4) * (L >> 4);
-  uint4 a0[RT], a1[RT];
-  auto loadA = [&](uint4 (&dst)[RT], const T* __restrict__ Ab, int g) {
+  uint4 a0[KU][RT], a1[KU][RT];
+  auto loadA = [&](uint4 (&dst)[KU][RT], const T* __restrict__ Ab, int q) {
 #pragma unroll
-    for (int t = 0; t < RT; ++t)
-      dst[t] = *reinterpret_cast<const uint4*>(Ab + lane_off + (int64_t)16 * t * kd + KG * g);
+    for (int u = 0; u < KU; ++u)
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+        dst[u][t] = *reinterpret_cast<const uint4*>(Ab + lane_off + (int64_t)16 * t * kd + KG * (KU * q + u));
   };
   f32x4 acc[RT][CT];
-  auto compute = [&](const uint4 (&av)[RT], int g) {
-    uint4 b[CT];
+  auto compute = [&](const uint4 (&av)[KU][RT], int q) {
 #pragma unroll
-    for (int c = 0; c < CT; ++c)
-      b[c] = *reinterpret_cast<const uint4*>(Xs + (16 * c + (L & 15)) * SK + KG * g + (KG / 4) * (L >> 4));
+    for (int u = 0; u < KU; ++u) {
+      const int g = KU * q + u;
+      uint4 b[CT];
 #pragma unroll
-    for (int t = 0; t < RT; ++t)
+      for (int c = 0; c < CT; ++c)
+        b[c] = *reinterpret_cast<const uint4*>(Xs + (16 * c + (L & 15)) * SK + KG * g + (KG / 4) * (L >> 4));
 #pragma unroll
-      for (int c = 0; c < CT; ++c) Tr::mma(acc[t][c], av[t], b[c]);
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) Tr::mma(acc[t][c], av[u][t], b[c]);
+    }
   };
 
   const T* UVb = (const T*)a.UV;
@@ -321,7 +335,7 @@ __device__ __forceinline__ void superpose_lp_tile(const LpSupArgs& a, int s, int
 #pragma unroll
       for (int c = 0; c < CT; ++c) acc[t][c] = (f32x4){0.f, 0.f, 0.f, 0.f};
     int g = 0;
-    for (; g + 2 < ng; g += 2) {
+    for (; g + 2 < nkc; g += 2) {
       loadA(a1, Ai, g + 1);
       compute(a0, g);
       loadA(a0, Ai, g + 2);
@@ -340,7 +354,7 @@ __device__ __forceinline__ void superpose_lp_tile(const LpSupArgs& a, int s, int
         for (int v = 0; v < 4; ++v) wv[t][c][v] = x[v];
       }
     }
-    if (ng - g == 2) {
+    if (nkc - g == 2) {
       loadA(a1, Ai, g + 1);
       compute(a0, g);
       loadA(a0, Anx, 0);

@@ -119,3 +119,29 @@ def test_zero_columns(td):
     plan = td.Plan.from_system(sys, subdomains=2)
     X = plan.solve(torch.empty((0, 256), dtype=torch.float64, device="cuda"))
     assert X.shape == (0, 256)
+
+
+def test_solve_graph_replays_match_eager(td):
+    """Plain solves replay a captured HIP graph: every replay, with eager work of the same plan
+    between replays, equals the eager solve bitwise; new arguments or more columns recapture."""
+    sys = synth.varcoef_system(96, 48, seed=71)
+    F1 = _dev(synth.rhs_columns(71, 96, 48, range(9)))
+    F2 = _dev(synth.rhs_columns(72, 96, 48, range(9)))
+    plan = td.Plan.from_system(sys, subdomains=6)
+    ref1, _ = plan.solve(F1, info=True)          # eager path (a report is requested)
+    ref2, _ = plan.solve(F2, info=True)
+    ref1, ref2 = ref1.clone(), ref2.clone()
+    X = torch.empty_like(F1)
+    for _ in range(3):
+        X.zero_()
+        plan.solve(F1, X)                         # captured once, then replayed
+        torch.cuda.synchronize()
+        assert torch.equal(X, ref1)
+        Y, _ = plan.solve(F2, info=True)          # eager work of the same plan in between
+        assert torch.equal(Y, ref2)
+    Z = plan.solve(F2)                            # other arguments: a new capture
+    assert torch.equal(Z, ref2)
+    F3 = _dev(synth.rhs_columns(73, 96, 48, range(20)))   # more columns: workspace grows, recapture
+    ref3, _ = plan.solve(F3, info=True)
+    assert torch.equal(plan.solve(F3), ref3)
+    assert rel_err(X.cpu().numpy(), oracle.solve(sys, F1.cpu().numpy())) <= TOL
