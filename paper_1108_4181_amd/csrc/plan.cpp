@@ -336,7 +336,7 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
       a.ncols = (int32_t)Mp;
       run_bgemm(a, da, pool, st);
     }
-    GJArgs g;
+    GJArgs g{};
     g.work = Dwork; g.work_off = nullptr; g.wstride = MM;
     g.out = P->Dinv; g.out_off = pool.put_vec(outoff);
     g.alpha = P->dense ? nullptr : P->alpha; g.bdiag = P->bdiag; g.bd_off = pool.put_vec(bdoff);
@@ -568,7 +568,7 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
     // invert the chain matrices in place in the arena (one launch for all nodes)
     const int nm = (int)woff.size();
     if (nm > 0) {
-      GJArgs g;
+      GJArgs g{};
       g.work = Da; g.work_off = pool.put_vec(woff); g.wstride = 0;
       g.out = P->G; g.out_off = pool.put_vec(outoff);
       g.alpha = nullptr; g.bdiag = nullptr; g.bd_off = nullptr;
@@ -620,7 +620,7 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
     run_bgemm(a2, d2, pool, st);
     std::vector<int64_t> woff;
     for (int n = 0; n < nn; ++n) woff.push_back(DWL(n));
-    GJArgs g;
+    GJArgs g{};
     g.work = Da; g.work_off = pool.put_vec(woff); g.wstride = 0;
     g.out = P->G; g.out_off = pool.put_vec(outoff);
     g.alpha = nullptr; g.bdiag = nullptr; g.bd_off = nullptr;
@@ -933,7 +933,7 @@ void solve_pass(td_plan_s* P, const double* F, int64_t ldf, double* X, int64_t l
       g.ncols = (int32_t)K;
       HIPCHK(launch_bgemm(g, st));
     }
-    SweepArgs sa;
+    SweepArgs sa{};
     sa.ks = P->d_ks; sa.Dinv = P->Dinv; sa.alpha = P->alpha; sa.adiag = P->adiag;
     sa.E = P->dense ? P->E : nullptr;
     sa.F = F; sa.ldf = ldf; sa.W = P->Wbuf; sa.ldw = ldw;
@@ -954,7 +954,7 @@ void solve_pass(td_plan_s* P, const double* F, int64_t ldf, double* X, int64_t l
       HIPCHK(launch_bgemm(f, st));
     }
   } else {
-    LpSweepArgs sa;
+    LpSweepArgs sa{};
     sa.ks = P->d_ks; sa.Dinv = P->Dlp; sa.alpha = P->Alp; sa.adiag = P->adiag;
     sa.F = F; sa.ldf = ldf; sa.W = P->W32; sa.ldw = ldw;
     sa.N = (int32_t)N; sa.M = (int32_t)M; sa.Mp = (int32_t)Mp; sa.p = (int32_t)p; sa.K = (int32_t)K;
@@ -1012,7 +1012,7 @@ void solve_pass(td_plan_s* P, const double* F, int64_t ldf, double* X, int64_t l
   }
   stage_mark(P, 4, st);
   if (P->prec == TD_PREC_F64) {
-    SupArgs u;
+    SupArgs u{};
     u.ks = P->d_ks; u.UV = P->UVa + 2 * Mp * Mp;
     u.Xi = P->Xi; u.ldxi = ldxi;
     u.W = P->Wbuf; u.ldw = ldw;
@@ -1021,7 +1021,7 @@ void solve_pass(td_plan_s* P, const double* F, int64_t ldf, double* X, int64_t l
     u.ncoltiles = 0; u.total = 0; u.accumulate = accumulate ? 1 : 0;
     if (N > p) HIPCHK(launch_superpose(u, st));
   } else {
-    LpSupArgs u;
+    LpSupArgs u{};
     u.ks = P->d_ks; u.UV = P->UVlp;
     u.Xi = P->Xi; u.ldxi = ldxi;
     u.W = P->W32; u.ldw = ldw;
