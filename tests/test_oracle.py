@@ -3,7 +3,8 @@
 Each pin reduces a case to a library routine or a closed form: numpy's dense LU
 solve of the matrix of eq. (main-eq) written out in full, the separable DST-I
 eigen-solution of the constant-coefficient 5-point operator, scipy's banded
-solver for M = 1, manufactured solutions, the adjoint identity, central finite
+solver for M = 1, SuperLU on the assembled sparse matrix up to the bench workload's
+size, manufactured solutions, linearity, the adjoint identity, central finite
 differences and the Schur-complement identity behind eq. (red1).  The last test
 plants mistakes in the oracle (a flipped sign, a dropped term, a transposed
 block, a wrong index, a missing row interchange) and checks that every planted
@@ -261,6 +262,63 @@ def test_superposition_parts_definitions(N, p):
         for i in range(ks[s], ks[s + 1]):
             rec[:, i, :] = Xi[:, s] @ parts["U"][i].T + Xi[:, s + 1] @ parts["V"][i].T + parts["W"][:, i]
     assert rel_err(rec, Xb) < 1e-13
+
+
+# ---------------------------------------------------------------- sparse direct solve at scale
+
+
+def _five_point_csr(sys):
+    """The matrix of eq. (main-eq) for DIAG A, B and TRIDIAG C, assembled entry by entry as a sparse
+    matrix (row j*M + r): -A_j on column (j-1)*M + r, C_j(r, r-1 / r / r+1), -B_j on (j+1)*M + r."""
+    import scipy.sparse
+
+    N, M = sys.N, sys.M
+    rows, cols, vals = [], [], []
+    for j in range(N):
+        for r in range(M):
+            g = j * M + r
+            rows.append(g); cols.append(g); vals.append(sys.C[j, 1, r])
+            if r > 0:
+                rows.append(g); cols.append(g - 1); vals.append(sys.C[j, 0, r])
+            if r < M - 1:
+                rows.append(g); cols.append(g + 1); vals.append(sys.C[j, 2, r])
+            if j > 0:
+                rows.append(g); cols.append(g - M); vals.append(-sys.A[j, r])
+            if j < N - 1:
+                rows.append(g); cols.append(g + M); vals.append(-sys.B[j, r])
+    return scipy.sparse.csc_matrix((vals, (rows, cols)), shape=(N * M, N * M))
+
+
+@pytest.mark.parametrize("N,M,family", [(256, 256, "varcoef"), (1024, 64, "nonsym")])
+def test_sparse_lu_at_scale(N, M, family):
+    """65k unknowns: the oracle against scipy's sparse LU (SuperLU) of the assembled matrix."""
+    import scipy.sparse.linalg
+
+    sys = synth.varcoef_system(N, M, seed=91) if family == "varcoef" else nonsym_tridiag_system(N, M, seed=92)
+    F = _rhs(93, sys, 4)
+    ref = scipy.sparse.linalg.splu(_five_point_csr(sys)).solve(np.ascontiguousarray(F.T)).T
+    assert rel_err(oracle.solve(sys, F), ref) <= 1e-12
+
+
+def test_sparse_lu_bench_workload():
+    """The bench workload itself (N=2048, M=256: 524k unknowns, variable coefficients, nonsymmetric):
+    the oracle against SuperLU on 4 of its right-hand sides (about 20 s)."""
+    import scipy.sparse.linalg
+
+    sys = synth.workload_system("varcoef_n2048_m256_k512")
+    F = synth.rhs_columns(synth.WORKLOADS["varcoef_n2048_m256_k512"]["seed"], sys.N, sys.M, range(4))
+    ref = scipy.sparse.linalg.splu(_five_point_csr(sys)).solve(np.ascontiguousarray(F.T)).T
+    assert rel_err(oracle.solve(sys, F), ref) <= 1e-12
+
+
+def test_linearity_and_column_independence():
+    """solve(F1 + F2) = solve(F1) + solve(F2), and K columns at once equal one column at a time."""
+    sys = nonsym_tridiag_system(40, 24, seed=95)
+    F1, F2 = _rhs(96, sys, 5), _rhs(97, sys, 5)
+    X1, X2 = oracle.solve(sys, F1), oracle.solve(sys, F2)
+    assert rel_err(oracle.solve(sys, F1 + F2), X1 + X2) <= 1e-14
+    cols = np.concatenate([oracle.solve(sys, F1[k:k + 1]) for k in range(5)])
+    assert np.array_equal(cols, X1)
 
 
 def test_partition_uneven():
