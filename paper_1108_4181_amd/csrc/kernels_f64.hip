@@ -203,15 +203,204 @@ hipError_t launch_superpose(const SupArgs& a, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // Batched Gauss-Jordan inversion with partial pivoting (row interchanges chosen
 // by the largest remaining entry of each column; ties go to the lowest row).
-// One work-group per matrix.  Columns are processed in panels of NB: the panel
-// is eliminated in LDS, then its combined transform (identity except in the NB
-// pivot-row columns) updates every other column as one rank-NB product on MFMA.
-// Rows are never physically swapped; the final inverse is read out through the
-// pivot permutation.  A pivot whose magnitude is not above 1e-14 times the
-// infinity norm of the matrix (or is NaN) marks the matrix singular.
+// One work-group per matrix; thread i < Mp owns row i.  Columns are processed in
+// panels of NB: during a panel every thread keeps its row of the panel in
+// registers and publishes it to one of two LDS copies (alternating by column),
+// so that one barrier per column suffices: the pivot row read from the copy of
+// the previous column is never the copy being written.  The panel's combined
+// transform (identity except in the NB pivot-row columns) then updates every
+// other column as one rank-NB product on MFMA, with the next column tile's
+// operands loaded before the current tile's products.  Rows are never
+// physically swapped; the inverse is read out through the pivot permutation.
+// A pivot whose magnitude is not above 1e-14 times the infinity norm of the
+// matrix (or is NaN) marks the matrix singular.
 // ---------------------------------------------------------------------------
+template <int RT, int NT>
+__global__ void __launch_bounds__(NT) k_gj(GJArgs g) {
+  constexpr int NB = 16;
+  constexpr int CT = 4;           // 16 columns per update tile
+  constexpr int KT = 4 * CT;
+  extern __shared__ double sm[];
+  const int Mp = g.Mp;
+  double* Pb = sm;                         // [2][NB][Mp]: published panel rows
+  double* Ys = Pb + NB * Mp;               // [NB][Mp]: pivot rows of W, all columns (after the
+                                           // panel's last column, in the copy it no longer uses)
+  double* wv = Pb + 2 * NB * Mp;           // [2][16] per-wave candidate values
+  int* wi = (int*)(wv + 32);               // [2][16] per-wave candidate rows
+  int* pivrow = wi + 32;                   // [Mp]
+  int* invpiv = pivrow + Mp;               // [Mp]
+
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int L = tid & 63, w = tid >> 6, nw = nthr >> 6;
+  const int q = blockIdx.x;
+  if (q >= g.nmat) return;
+  double* W = g.work + (g.work_off ? g.work_off[q] : q * g.wstride);
+  const int rb = w * 16 * RT;
+  const bool owner = tid < Mp;             // nthr >= Mp for every RT choice
+
+  // infinity norm (row sums), one row per thread
+  double rs = 0.0;
+  if (owner)
+    for (int c = 0; c < Mp; ++c) rs += fabs(W[tid + (int64_t)c * Mp]);
+  for (int off = 32; off > 0; off >>= 1) rs = fmax(rs, __shfl_xor(rs, off));
+  if (L == 0) wv[w] = rs;
+  __syncthreads();
+  double norm = 0.0;
+  for (int v = 0; v < nw; ++v) norm = fmax(norm, wv[v]);
+  const double tol = 1e-14 * norm;
+  __syncthreads();
+  bool singular = false;
+  bool used = false;
+
+  for (int p0 = 0; p0 < Mp; p0 += NB) {
+    double prv[NB];
+#pragma unroll
+    for (int jj = 0; jj < NB; ++jj) prv[jj] = owner ? W[tid + (int64_t)(p0 + jj) * Mp] : 0.0;
+    if (owner) {
+#pragma unroll
+      for (int jj = 0; jj < NB; ++jj) Pb[jj * Mp + tid] = prv[jj];
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int b = j & 1;
+      const double* cur = Pb + b * NB * Mp;        // rows after column j-1
+      double* nxt = Pb + (b ^ 1) * NB * Mp;        // rows after column j
+      // pivot search on the own row
+      double bv = -1.0;
+      int bi = INT_MAX;
+      if (owner && !used) {
+        const double v = fabs(prv[j]);
+        bv = (v == v) ? v : DBL_MAX;   // NaN ranks first so that it is reported
+        bi = tid;
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(bv, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+      }
+      if (L == 0) { wv[16 * b + w] = bv; wi[16 * b + w] = bi; }
+      __syncthreads();
+      double b2 = wv[16 * b];
+      int r = wi[16 * b];
+      for (int v = 1; v < nw; ++v) {
+        const double ov = wv[16 * b + v];
+        const int oi = wi[16 * b + v];
+        if (ov > b2 || (ov == b2 && oi < r)) { b2 = ov; r = oi; }
+      }
+      if (tid == 0) pivrow[p0 + j] = r;
+      const double pv = cur[j * Mp + r];
+      if (!(fabs(pv) > tol)) singular = true;
+      const double ipv = 1.0 / pv;
+      if (owner) {
+        if (tid == r) {
+#pragma unroll
+          for (int jj = 0; jj < NB; ++jj) prv[jj] = (jj == j) ? ipv : prv[jj] * ipv;
+          used = true;
+        } else {
+          const double f = prv[j];
+#pragma unroll
+          for (int jj = 0; jj < NB; ++jj) {
+            const double pr = (jj == j) ? ipv : cur[jj * Mp + r] * ipv;
+            prv[jj] = ((jj == j) ? 0.0 : prv[jj]) - f * pr;
+          }
+        }
+#pragma unroll
+        for (int jj = 0; jj < NB; ++jj) nxt[jj * Mp + tid] = prv[jj];
+      }
+    }
+    // the last column (NB - 1, odd) published into copy 0
+    __syncthreads();
+    const double* Pn = Pb;
+    for (int e = tid; e < NB * Mp; e += nthr) {
+      const int jj = e / Mp, c = e % Mp;
+      Ys[jj * Mp + c] = W[pivrow[p0 + jj] + (int64_t)c * Mp];
+    }
+    __syncthreads();
+    // rank-NB update of all other columns: W[:, c] += (Pn - E_R) * W[R, c]
+    double av[NB / 4][RT];
+#pragma unroll
+    for (int kk = 0; kk < NB / 4; ++kk) {
+      const int k = 4 * kk + (L >> 4);
+      const int pr = pivrow[p0 + k];
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int row = rb + 16 * t + (L & 15);
+        av[kk][t] = Pn[k * Mp + row] - (row == pr ? 1.0 : 0.0);
+      }
+    }
+    const int ntile = Mp / KT;
+    auto load_tile = [&](double (&acc)[RT][CT], int tile) {
+      const int c0 = tile * KT;
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int row = rb + 16 * t + out_row(L);
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[t][c] = W[row + (int64_t)(c0 + out_col(L) * CT + c) * Mp];
+      }
+    };
+    auto update_tile = [&](double (&acc)[RT][CT], int tile) {
+      const int c0 = tile * KT;
+#pragma unroll
+      for (int kk = 0; kk < NB / 4; ++kk) {
+        const int k = 4 * kk + (L >> 4);
+        const double* bp = &Ys[k * Mp + c0 + (L & 3) * CT];
+        double bb[CT];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) bb[c] = bp[c];
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+          for (int c = 0; c < CT; ++c) acc[t][c] = mfma4(av[kk][t], bb[c], acc[t][c]);
+      }
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int row = rb + 16 * t + out_row(L);
+#pragma unroll
+        for (int c = 0; c < CT; ++c) W[row + (int64_t)(c0 + out_col(L) * CT + c) * Mp] = acc[t][c];
+      }
+    };
+    const int ptile = p0 / KT;               // the panel's own tile (NB == KT) is skipped
+    double ta[RT][CT], tb[RT][CT];
+    int tile = (ptile == 0) ? 1 : 0;
+    if (tile < ntile) load_tile(ta, tile);
+    while (tile < ntile) {
+      int t2 = tile + 1;
+      if (t2 == ptile) ++t2;
+      if (t2 < ntile) load_tile(tb, t2);
+      update_tile(ta, tile);
+      if (t2 >= ntile) break;
+      int t3 = t2 + 1;
+      if (t3 == ptile) ++t3;
+      if (t3 < ntile) load_tile(ta, t3);
+      update_tile(tb, t2);
+      tile = t3;
+    }
+    for (int e = tid; e < NB * Mp; e += nthr) {
+      const int i = e % Mp, jj = e / Mp;
+      W[i + (int64_t)(p0 + jj) * Mp] = Pn[jj * Mp + i];
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && singular) atomicMin(g.bad, g.tag[q]);
+  // inverse: Dinv[c][pivrow[c']] = S[pivrow[c]][c']
+  for (int c = tid; c < Mp; c += nthr) invpiv[pivrow[c]] = c;
+  __syncthreads();
+  double* out = g.out + g.out_off[q];
+  double* al = g.alpha ? g.alpha + g.out_off[q] : nullptr;
+  const double* bd = g.alpha ? g.bdiag + g.bd_off[q] : nullptr;
+  for (int e = tid; e < Mp * Mp; e += nthr) {
+    const int row = e % Mp, oc = e / Mp;
+    const double v = W[pivrow[row] + (int64_t)invpiv[oc] * Mp];
+    out[row + (int64_t)oc * Mp] = v;
+    if (al) al[row + (int64_t)oc * Mp] = v * bd[oc];
+  }
+}
+
+// The same elimination for blocks above 256 rows, where two LDS copies of the panel and the
+// register-resident rows do not fit: the panel stays in one LDS copy, the pivot row is formed by
+// one thread between barriers, and each column tile of the update stages its pivot rows.
 template <int RT>
-__global__ void __launch_bounds__(512) k_gj(GJArgs g) {
+__global__ void __launch_bounds__(512) k_gj_big(GJArgs g) {
   constexpr int NB = 16;
   constexpr int CT = 4;           // 16 columns per update tile
   constexpr int KT = 4 * CT;
@@ -363,14 +552,32 @@ __global__ void __launch_bounds__(512) k_gj(GJArgs g) {
   }
 }
 
+template <int RT, int NT>
+static hipError_t launch_gj_cfg(const GJArgs& g, int nthr, hipStream_t st) {
+  const size_t lds = (size_t)(2 * 16 * g.Mp + 32) * sizeof(double) + (size_t)(32 + 2 * g.Mp) * sizeof(int);
+  hipError_t e = hipFuncSetAttribute((const void*)k_gj<RT, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_gj<RT, NT>), dim3(g.nmat), dim3(nthr), lds, st, g);
+  return hipGetLastError();
+}
+
+// work-groups of at most 256 threads get the larger register budget of that bound
 template <int RT>
 static hipError_t launch_gj_rt(const GJArgs& g, hipStream_t st) {
   const int nthr = g.Mp / (16 * RT) * 64;
-  const size_t lds = (size_t)(16 * g.Mp + 16 * 18 + 16 + 32) * sizeof(double) + (size_t)(2 * g.Mp + 16) * sizeof(int);
-  hipError_t e = hipFuncSetAttribute((const void*)k_gj<RT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_gj<RT>), dim3(g.nmat), dim3(nthr), lds, st, g);
-  return hipGetLastError();
+  if (g.Mp > 256) {
+    const size_t lds = (size_t)(16 * g.Mp + 16 * 18 + 16 + 32) * sizeof(double) + (size_t)(2 * g.Mp + 16) * sizeof(int);
+    hipError_t e = hipFuncSetAttribute((const void*)k_gj_big<RT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_gj_big<RT>), dim3(g.nmat), dim3(nthr), lds, st, g);
+    return hipGetLastError();
+  }
+  if constexpr (RT == 4) {   // Mp == 256 here: 256 threads
+    return launch_gj_cfg<RT, 256>(g, nthr, st);
+  } else {
+    if (nthr <= 256) return launch_gj_cfg<RT, 256>(g, nthr, st);
+    return launch_gj_cfg<RT, 512>(g, nthr, st);
+  }
 }
 
 hipError_t launch_gj(const GJArgs& g, hipStream_t st) {
