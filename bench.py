@@ -30,8 +30,8 @@ PEAK_HBM = 8000.0      # GB/s
 # (profiles/sweep_superposition_varcoef_n2048_m256_k512.md).
 MEASURED_TRAFFIC = {
     # kernel: (workload, source hash (kernel_source_hash), read bytes, write bytes)
-    "sweep": ("varcoef_n2048_m256_k512", "27ef6073d9b34cfd", 8.54126e9, 4.09364e9),
-    "superposition": ("varcoef_n2048_m256_k512", "27ef6073d9b34cfd", 4.42142e9, 2.08037e9),
+    "sweep": ("varcoef_n2048_m256_k512", "aa63dbcc8ffc4442", 7.64417e9, 4.09574e9),
+    "superposition": ("varcoef_n2048_m256_k512", "aa63dbcc8ffc4442", 4.39888e9, 2.08037e9),
 }
 KERNEL_SOURCES = ["kernels_f64.hip", "tile_bodies.h", "device_common.h", "internal.h"]
 

@@ -215,9 +215,8 @@ hipError_t launch_superpose(const SupArgs& a, hipStream_t st) {
 // A pivot whose magnitude is not above 1e-14 times the infinity norm of the
 // matrix (or is NaN) marks the matrix singular.
 // ---------------------------------------------------------------------------
-template <int RT, int NT>
+template <int RT, int NT, int NB>
 __global__ void __launch_bounds__(NT) k_gj(GJArgs g) {
-  constexpr int NB = 16;
   constexpr int CT = 4;           // 16 columns per update tile
   constexpr int KT = 4 * CT;
   extern __shared__ double sm[];
@@ -260,6 +259,8 @@ __global__ void __launch_bounds__(NT) k_gj(GJArgs g) {
 #pragma unroll
       for (int jj = 0; jj < NB; ++jj) Pb[jj * Mp + tid] = prv[jj];
     }
+    // unrolled so that the panel row stays in registers (faster even where the 512-thread
+    // register budget makes it spill)
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int b = j & 1;
@@ -268,8 +269,12 @@ __global__ void __launch_bounds__(NT) k_gj(GJArgs g) {
       // pivot search on the own row
       double bv = -1.0;
       int bi = INT_MAX;
+      // prv[j] by selection, so that a rolled loop would not place the array in scratch memory
+      double pj = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < NB; ++jj) pj = (jj == j) ? prv[jj] : pj;
       if (owner && !used) {
-        const double v = fabs(prv[j]);
+        const double v = fabs(pj);
         bv = (v == v) ? v : DBL_MAX;   // NaN ranks first so that it is reported
         bi = tid;
       }
@@ -297,7 +302,7 @@ __global__ void __launch_bounds__(NT) k_gj(GJArgs g) {
           for (int jj = 0; jj < NB; ++jj) prv[jj] = (jj == j) ? ipv : prv[jj] * ipv;
           used = true;
         } else {
-          const double f = prv[j];
+          const double f = pj;
 #pragma unroll
           for (int jj = 0; jj < NB; ++jj) {
             const double pr = (jj == j) ? ipv : cur[jj * Mp + r] * ipv;
@@ -359,21 +364,28 @@ __global__ void __launch_bounds__(NT) k_gj(GJArgs g) {
         for (int c = 0; c < CT; ++c) W[row + (int64_t)(c0 + out_col(L) * CT + c) * Mp] = acc[t][c];
       }
     };
-    const int ptile = p0 / KT;               // the panel's own tile (NB == KT) is skipped
-    double ta[RT][CT], tb[RT][CT];
-    int tile = (ptile == 0) ? 1 : 0;
-    if (tile < ntile) load_tile(ta, tile);
-    while (tile < ntile) {
-      int t2 = tile + 1;
-      if (t2 == ptile) ++t2;
-      if (t2 < ntile) load_tile(tb, t2);
-      update_tile(ta, tile);
-      if (t2 >= ntile) break;
-      int t3 = t2 + 1;
-      if (t3 == ptile) ++t3;
-      if (t3 < ntile) load_tile(ta, t3);
-      update_tile(tb, t2);
-      tile = t3;
+    // the column tiles other than the panel's own (NB a multiple of KT), in order; four register buffers
+    // rotate so that every tile's operands are requested three tiles ahead of their use
+    constexpr int PT = NB / KT;               // tiles covered by the panel
+    const int ptile = p0 / KT;
+    const int cnt = ntile - PT;
+    auto tile_of = [&](int n) { return n < ptile ? n : n + PT; };
+    double tb0[RT][CT], tb1[RT][CT], tb2[RT][CT], tb3[RT][CT];
+    if (cnt > 0) load_tile(tb0, tile_of(0));
+    if (cnt > 1) load_tile(tb1, tile_of(1));
+    if (cnt > 2) load_tile(tb2, tile_of(2));
+    for (int n = 0; n < cnt; n += 4) {
+      if (n + 3 < cnt) load_tile(tb3, tile_of(n + 3));
+      update_tile(tb0, tile_of(n));
+      if (n + 1 >= cnt) break;
+      if (n + 4 < cnt) load_tile(tb0, tile_of(n + 4));
+      update_tile(tb1, tile_of(n + 1));
+      if (n + 2 >= cnt) break;
+      if (n + 5 < cnt) load_tile(tb1, tile_of(n + 5));
+      update_tile(tb2, tile_of(n + 2));
+      if (n + 3 >= cnt) break;
+      if (n + 6 < cnt) load_tile(tb2, tile_of(n + 6));
+      update_tile(tb3, tile_of(n + 3));
     }
     for (int e = tid; e < NB * Mp; e += nthr) {
       const int i = e % Mp, jj = e / Mp;
@@ -552,12 +564,13 @@ __global__ void __launch_bounds__(512) k_gj_big(GJArgs g) {
   }
 }
 
-template <int RT, int NT>
+template <int RT, int NT, int NB>
 static hipError_t launch_gj_cfg(const GJArgs& g, int nthr, hipStream_t st) {
-  const size_t lds = (size_t)(2 * 16 * g.Mp + 32) * sizeof(double) + (size_t)(32 + 2 * g.Mp) * sizeof(int);
-  hipError_t e = hipFuncSetAttribute((const void*)k_gj<RT, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  const size_t lds = (size_t)(2 * NB * g.Mp + 32) * sizeof(double) + (size_t)(32 + 2 * g.Mp) * sizeof(int);
+  hipError_t e =
+      hipFuncSetAttribute((const void*)k_gj<RT, NT, NB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_gj<RT, NT>), dim3(g.nmat), dim3(nthr), lds, st, g);
+  hipLaunchKernelGGL((k_gj<RT, NT, NB>), dim3(g.nmat), dim3(nthr), lds, st, g);
   return hipGetLastError();
 }
 
@@ -572,11 +585,17 @@ static hipError_t launch_gj_rt(const GJArgs& g, hipStream_t st) {
     hipLaunchKernelGGL((k_gj_big<RT>), dim3(g.nmat), dim3(nthr), lds, st, g);
     return hipGetLastError();
   }
+  // panels of 32 columns halve the passes of the update over the matrix where the block size
+  // divides into them and the two LDS copies fit; 16 otherwise
   if constexpr (RT == 4) {   // Mp == 256 here: 256 threads
-    return launch_gj_cfg<RT, 256>(g, nthr, st);
+    return launch_gj_cfg<RT, 256, 32>(g, nthr, st);
   } else {
-    if (nthr <= 256) return launch_gj_cfg<RT, 256>(g, nthr, st);
-    return launch_gj_cfg<RT, 512>(g, nthr, st);
+    if (g.Mp % 32 == 0) {
+      if (nthr <= 256) return launch_gj_cfg<RT, 256, 32>(g, nthr, st);
+      return launch_gj_cfg<RT, 512, 32>(g, nthr, st);
+    }
+    if (nthr <= 256) return launch_gj_cfg<RT, 256, 16>(g, nthr, st);
+    return launch_gj_cfg<RT, 512, 16>(g, nthr, st);
   }
 }
 
