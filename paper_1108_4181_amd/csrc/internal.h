@@ -184,7 +184,7 @@ hipError_t launch_probe_inputs(double* A, double* B, double* C, double* F, int N
 // global counter; an item waits (bounded spin) until the counter of the stage it
 // depends on reaches the expected value, runs, and then increments its own counter.
 // ---------------------------------------------------------------------------
-constexpr int RES_CHUNK = 8192;      // rows of the stencil residual per work-group
+constexpr int RES_CHUNK = 8192;      // rows of a batched stencil residual item
 constexpr int BATCH_MAXDEPTH = 16;
 constexpr int BATCH_RESCOLS = 8;   // right-hand sides per residual item of the batched solve
 enum { BI_SWEEP = 0, BI_FTILDE = 1, BI_PART = 2, BI_LEVEL = 3, BI_SUP = 4, BI_RES = 5, BI_RFIN = 6 };
@@ -242,6 +242,11 @@ hipError_t launch_ftilde_f32(double* Ft, int64_t ldft, const double* F, int64_t 
                              const int64_t* ks, const double* adiag, const double* bdiag, int p, int M, int Mp, int K,
                              hipStream_t st);
 int residual_chunks(int64_t n);
+// rows x right-hand sides of one work-group of the single-plan stencil residual
+constexpr int RES_ROWS = 1024;
+constexpr int RES_COLS = 16;
+int residual_row_chunks(int64_t n);
+hipError_t launch_zero_absent(double* A, double* B, double* C, int N, int M, hipStream_t st);
 hipError_t launch_residual_stencil(double* R, int64_t ldr, const double* F, int64_t ldf, const double* X, int64_t ldx,
                                    const double* A, const double* B, const double* C, int N, int M, int K,
                                    double* colpart, hipStream_t st);

@@ -252,6 +252,8 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
   HIPCHK(hipMemcpyAsync(P->cA, A, nA * 8, hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(P->cB, B, nB * 8, hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(P->cC, C, nC * 8, hipMemcpyDeviceToDevice, st));
+  if (P->fmtA == TD_FMT_DIAG && P->fmtB == TD_FMT_DIAG && P->fmtC == TD_FMT_TRIDIAG)
+    HIPCHK(launch_zero_absent(P->cA, P->cB, P->cC, (int)N, (int)M, st));   // for the stencil residual
   P->adiag = P->alloc(N * Mp);
   P->bdiag = P->alloc(N * Mp);
   P->dense = (P->fmtA == TD_FMT_DENSE || P->fmtB == TD_FMT_DENSE);
@@ -886,7 +888,7 @@ bool stencil_formats(const td_plan_s* P) {
 }
 
 int residual_parts(const td_plan_s* P) {
-  return stencil_formats(P) ? residual_chunks(P->N * P->M) : (int)P->N;
+  return stencil_formats(P) ? residual_row_chunks(P->N * P->M) : (int)P->N;
 }
 
 void ensure_refine_ws(td_plan_s* P, int64_t K) {
