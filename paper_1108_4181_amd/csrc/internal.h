@@ -184,9 +184,7 @@ hipError_t launch_probe_inputs(double* A, double* B, double* C, double* F, int N
 // global counter; an item waits (bounded spin) until the counter of the stage it
 // depends on reaches the expected value, runs, and then increments its own counter.
 // ---------------------------------------------------------------------------
-constexpr int RES_CHUNK = 8192;      // rows of a batched stencil residual item
 constexpr int BATCH_MAXDEPTH = 16;
-constexpr int BATCH_RESCOLS = 8;   // right-hand sides per residual item of the batched solve
 enum { BI_SWEEP = 0, BI_FTILDE = 1, BI_PART = 2, BI_LEVEL = 3, BI_SUP = 4, BI_RES = 5, BI_RFIN = 6 };
 
 struct BatchItem {
@@ -241,8 +239,7 @@ hipError_t launch_superpose_lp(int prec, const LpSupArgs& a, hipStream_t st);
 hipError_t launch_ftilde_f32(double* Ft, int64_t ldft, const double* F, int64_t ldf, const float* W, int64_t ldw,
                              const int64_t* ks, const double* adiag, const double* bdiag, int p, int M, int Mp, int K,
                              hipStream_t st);
-int residual_chunks(int64_t n);
-// rows x right-hand sides of one work-group of the single-plan stencil residual
+// rows x right-hand sides of one work-group (or batched work item) of the stencil residual
 constexpr int RES_ROWS = 1024;
 constexpr int RES_COLS = 16;
 int residual_row_chunks(int64_t n);

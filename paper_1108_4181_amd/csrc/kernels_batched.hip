@@ -100,13 +100,10 @@ __device__ void run_item(const BatchItem& it, const BatchSys& S, uint4* lds, dou
       }
       break;
     }
-    case BI_RES: {
-      const int c1 = it.i1 + S.rescols < S.K ? it.i1 + S.rescols : S.K;
-      for (int col = it.i1; col < c1; ++col)
-        residual_stencil_tile(S.R, S.ldr, S.F, S.ldf, S.X, S.ldx, S.cA, S.cB, S.cC, S.N, S.M, RES_CHUNK, S.colpart,
-                              S.nchunk, it.i0, col, red);
+    case BI_RES:
+      residual_cols_tile(S.R, S.ldr, S.F, S.ldf, S.X, S.ldx, S.cA, S.cB, S.cC, S.N, S.M, S.K, S.colpart, S.nchunk,
+                         it.i0, it.i1, reinterpret_cast<double*>(lds), red);
       break;
-    }
     case BI_RFIN: {
       double worst = 0.0;
       for (int col = tid; col < S.K; col += BATCH_THREADS) {
@@ -140,7 +137,7 @@ __global__ void __launch_bounds__(BATCH_THREADS, 2) k_batched(const BatchItem* _
                                                            const BatchSys* __restrict__ sys, int32_t* counters,
                                                            int32_t* conv, BatchCtl* ctl, int64_t spin_limit) {
   extern __shared__ uint4 lds[];
-  __shared__ double red[2][4];
+  __shared__ double red[2 * RES_COLS][4];
   __shared__ int sh_idx, sh_ok;
   for (;;) {
     if (threadIdx.x == 0) sh_idx = atomicAdd(&ctl->head, 1);
@@ -178,7 +175,7 @@ __global__ void __launch_bounds__(BATCH_THREADS, 2) k_batched_stage(const BatchI
                                                                  int end, const BatchSys* __restrict__ sys,
                                                                  int32_t* conv, int32_t* head) {
   extern __shared__ uint4 lds[];
-  __shared__ double red[2][4];
+  __shared__ double red[2 * RES_COLS][4];
   __shared__ int sh_idx;
   for (;;) {
     if (threadIdx.x == 0) sh_idx = begin + atomicAdd(head, 1);

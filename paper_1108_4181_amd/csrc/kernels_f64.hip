@@ -945,23 +945,33 @@ hipError_t launch_residual(double* R, int64_t ldr, const double* F, int64_t ldf,
   return hipGetLastError();
 }
 
-// out[col] = sqrt(sum_blk colpart[..][0]) / sqrt(sum_blk colpart[..][1]) as (rnorm, fnorm) pairs:
-// out[2*col] = ||R_col||, out[2*col+1] = ||F_col||  (fixed summation order)
-__global__ void k_colnorm_finish(double* out, const double* colpart, int nblk, int K) {
-  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+// out[2*col] = ||R_col||, out[2*col+1] = ||F_col|| from the partial sums of squares
+// colpart[col][blk][2]: one wave per column, lanes striding over the blocks, then a fixed
+// shuffle tree (deterministic order)
+__global__ void __launch_bounds__(256) k_colnorm_finish(double* out, const double* colpart, int nblk, int K) {
+  const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int L = threadIdx.x & 63;
   if (col >= K) return;
+  const double2* cp = reinterpret_cast<const double2*>(colpart) + (int64_t)col * nblk;
   double a = 0.0, b = 0.0;
-  for (int j = 0; j < nblk; ++j) {
-    a += colpart[((int64_t)col * nblk + j) * 2 + 0];
-    b += colpart[((int64_t)col * nblk + j) * 2 + 1];
+  for (int j = L; j < nblk; j += 64) {
+    const double2 v = cp[j];
+    a += v.x;
+    b += v.y;
   }
-  out[2 * col] = sqrt(a);
-  out[2 * col + 1] = sqrt(b);
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_xor(a, off);
+    b += __shfl_xor(b, off);
+  }
+  if (L == 0) {
+    out[2 * col] = sqrt(a);
+    out[2 * col + 1] = sqrt(b);
+  }
 }
 
 hipError_t launch_colnorm_finish(double* out, const double* colpart, int nblk, int K, hipStream_t st) {
   if (K == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_colnorm_finish, dim3((K + 127) / 128), dim3(128), 0, st, out, colpart, nblk, K);
+  hipLaunchKernelGGL(k_colnorm_finish, dim3((K + 3) / 4), dim3(256), 0, st, out, colpart, nblk, K);
   return hipGetLastError();
 }
 

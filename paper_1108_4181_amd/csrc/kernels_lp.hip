@@ -227,114 +227,19 @@ hipError_t launch_ftilde_f32(double* Ft, int64_t ldft, const double* F, int64_t 
 }
 
 // ---------------------------------------------------------------------------
-// Float64 residual R = F - P X for diagonal A, B and tridiagonal C (a five-point stencil over
-// the rows).  A work-group takes RES_ROWS consecutive rows of up to RES_COLS right-hand sides.
-// The five coefficients of its rows stay in registers for all its columns; each column's x,
-// with one block of rows on either side, is staged once in LDS, so every neighbour is an LDS
-// read; the next column's x and f are loaded into registers while the current column is
-// computed.  The plan's coefficient copies hold zeros for absent neighbours (k_zero_absent at
-// factor), so the row formula has no branches, and halo rows outside the matrix are staged as
-// zeros.  Per (column, row chunk) sums of squares of R and F feed the column norms (fixed
-// order, no atomics).
+// Float64 stencil residual (residual_cols_tile): grid (row chunks of RES_ROWS, groups of
+// RES_COLS right-hand sides)
 // ---------------------------------------------------------------------------
-constexpr int RES_RPT = RES_ROWS / 256;   // rows per thread
-constexpr int RES_SPT = RES_RPT + 4;      // staged rows per thread: RES_ROWS + 2M with M <= 512
-
-__global__ void __launch_bounds__(256) k_residual_stencil(double* __restrict__ R, int64_t ldr,
-                                                          const double* __restrict__ F, int64_t ldf,
-                                                          const double* __restrict__ X, int64_t ldx,
-                                                          const double* __restrict__ A, const double* __restrict__ B,
-                                                          const double* __restrict__ C, int N, int M, int K,
-                                                          double* __restrict__ colpart, int nchunk) {
-  extern __shared__ double xs[];                 // [RES_ROWS + 2M]: rows g0 - M ..
-  __shared__ double red[2][RES_COLS][4];
-  const int tid = threadIdx.x;
-  const int q = blockIdx.x, c0 = blockIdx.y * RES_COLS;
-  const int ncol = (K - c0) < RES_COLS ? (K - c0) : RES_COLS;
-  const int64_t n = (int64_t)N * M;
-  const int64_t g0 = (int64_t)q * RES_ROWS;
-  const int cnt = (n - g0) < RES_ROWS ? (int)(n - g0) : RES_ROWS;
-  const int64_t jb = g0 / M;
-  const unsigned rb0 = (unsigned)(g0 - jb * M);
-  // own rows tid + 256 i (the tail chunk repeats its last row; those copies are not stored)
-  double cd[RES_RPT], cs[RES_RPT], cu[RES_RPT], av[RES_RPT], bv[RES_RPT];
-  int oc[RES_RPT];
-#pragma unroll
-  for (int i = 0; i < RES_RPT; ++i) {
-    const int o = tid + 256 * i;
-    oc[i] = o < cnt ? o : cnt - 1;
-    const unsigned u = rb0 + (unsigned)oc[i];
-    const unsigned jj = u / (unsigned)M;
-    const unsigned r = u - jj * (unsigned)M;
-    const double* t = C + (jb + jj) * 3 * M + r;
-    cs[i] = t[0];
-    cd[i] = t[M];
-    cu[i] = t[2 * M];
-    av[i] = A[g0 + oc[i]];
-    bv[i] = B[g0 + oc[i]];
-  }
-  const int span = cnt + 2 * M;
-  double xr[RES_SPT], fv[RES_RPT];
-  auto load_col = [&](int c) {
-    const double* x = X + (int64_t)(c0 + c) * ldx;
-    const double* f = F + (int64_t)(c0 + c) * ldf;
-#pragma unroll
-    for (int i = 0; i < RES_RPT; ++i) fv[i] = f[g0 + oc[i]];
-#pragma unroll
-    for (int k = 0; k < RES_SPT; ++k) {
-      const int i = tid + 256 * k;
-      const int64_t g = g0 - M + i;
-      xr[k] = (i < span && g >= 0 && g < n) ? x[g] : 0.0;
-    }
-  };
-  load_col(0);
-#pragma unroll 1
-  for (int c = 0; c < ncol; ++c) {
-#pragma unroll
-    for (int k = 0; k < RES_SPT; ++k) {
-      const int i = tid + 256 * k;
-      if (i < span) xs[i] = xr[k];
-    }
-    double fc[RES_RPT];
-#pragma unroll
-    for (int i = 0; i < RES_RPT; ++i) fc[i] = fv[i];
-    __syncthreads();
-    if (c + 1 < ncol) load_col(c + 1);
-    double sr = 0.0, sf = 0.0;
-#pragma unroll
-    for (int i = 0; i < RES_RPT; ++i) {
-      const double* xp = xs + M + oc[i];
-      double y = cd[i] * xp[0];
-      y += cs[i] * xp[-1];
-      y += cu[i] * xp[1];
-      y -= av[i] * xp[-M];
-      y -= bv[i] * xp[M];
-      const double rv = fc[i] - y;
-      if (tid + 256 * i < cnt) {
-        if (R) R[g0 + oc[i] + (int64_t)(c0 + c) * ldr] = rv;
-        sr += rv * rv;
-        sf += fc[i] * fc[i];
-      }
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-      sr += __shfl_xor(sr, off);
-      sf += __shfl_xor(sf, off);
-    }
-    if ((tid & 63) == 0) {
-      red[0][c][tid >> 6] = sr;
-      red[1][c][tid >> 6] = sf;
-    }
-    __syncthreads();   // LDS rows and partial sums are reused by the next column
-  }
-  if (tid < ncol) {
-    double a = 0.0, b = 0.0;
-    for (int v = 0; v < 4; ++v) { a += red[0][tid][v]; b += red[1][tid][v]; }
-    colpart[((int64_t)(c0 + tid) * nchunk + q) * 2 + 0] = a;
-    colpart[((int64_t)(c0 + tid) * nchunk + q) * 2 + 1] = b;
-  }
+__global__ void __launch_bounds__(256) k_residual_stencil(double* R, int64_t ldr, const double* F, int64_t ldf,
+                                                          const double* X, int64_t ldx, const double* A,
+                                                          const double* B, const double* C, int N, int M, int K,
+                                                          double* colpart, int nchunk) {
+  extern __shared__ double xs[];   // RES_ROWS + 2M
+  __shared__ double red[2 * RES_COLS][4];
+  residual_cols_tile(R, ldr, F, ldf, X, ldx, A, B, C, N, M, K, colpart, nchunk, blockIdx.x, blockIdx.y * RES_COLS,
+                     xs, red);
 }
 
-int residual_chunks(int64_t n) { return (int)((n + RES_CHUNK - 1) / RES_CHUNK); }
 int residual_row_chunks(int64_t n) { return (int)((n + RES_ROWS - 1) / RES_ROWS); }
 
 hipError_t launch_residual_stencil(double* R, int64_t ldr, const double* F, int64_t ldf, const double* X, int64_t ldx,

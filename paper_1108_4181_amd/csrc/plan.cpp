@@ -1432,12 +1432,12 @@ td_status batch_create_impl(int n, const td_plan* plans, const double* const* F,
     S.R = check ? B->dalloc<double>((size_t)(N * M * Kq)) : nullptr;
     S.ldr = N * M;
     S.cA = P->cA; S.cB = P->cB; S.cC = P->cC;
-    S.nchunk = residual_chunks(N * M);
+    S.nchunk = residual_row_chunks(N * M);
     S.colpart = check ? B->dalloc<double>((size_t)(S.nchunk * Kq * 2)) : nullptr;
     S.resid = nullptr;  // set below
     S.N = (int32_t)N; S.M = (int32_t)M; S.Mp = (int32_t)Mp; S.p = (int32_t)p; S.K = (int32_t)Kq;
     S.rt = (int32_t)(Mp / 64);
-    S.rescols = BATCH_RESCOLS;
+    S.rescols = RES_COLS;
     S.tol = tol;
     nst[q] = 6 + P->depth;
     cbase[q] = nctr;
@@ -1473,7 +1473,7 @@ td_status batch_create_impl(int n, const td_plan* plans, const double* const* F,
     cnt_lev[q].resize(P->depth);
     for (int lv = 0; lv < P->depth; ++lv) cnt_lev[q][lv] = P->corr_count[lv] * nct_bg[q];
     cnt_sup[q] = (int)P->p * nct_sup[q];
-    cnt_res[q] = sys[q].nchunk * (int)((K[q] + BATCH_RESCOLS - 1) / BATCH_RESCOLS);
+    cnt_res[q] = sys[q].nchunk * (int)((K[q] + RES_COLS - 1) / RES_COLS);
   }
   int maxdepth = 0;
   for (int q = 0; q < n; ++q) maxdepth = std::max(maxdepth, plans[q]->depth);
@@ -1529,7 +1529,7 @@ td_status batch_create_impl(int n, const td_plan* plans, const double* const* F,
     for (int q : order) {
       td_plan_s* P = plans[q];
       for (int ch = 0; ch < sys[q].nchunk; ++ch)
-        for (int c0 = 0; c0 < K[q]; c0 += BATCH_RESCOLS)
+        for (int c0 = 0; c0 < K[q]; c0 += RES_COLS)
           add(BI_RES, q, r, 0, ch, c0, ctr(q, r, 3 + P->depth), cnt_sup[q], ctr(q, r, 4 + P->depth));
     }
     stage();

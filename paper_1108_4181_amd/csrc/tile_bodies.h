@@ -384,47 +384,108 @@ __device__ __forceinline__ void superpose_lp_tile(const LpSupArgs& a, int s, int
   }
 }
 
-// one work-group of 256 threads: rows [q*chunk, (q+1)*chunk) of column col; red holds 8 doubles
-__device__ __forceinline__ void residual_stencil_tile(double* R, int64_t ldr, const double* F, int64_t ldf,
-                                                      const double* X, int64_t ldx, const double* A, const double* B,
-                                                      const double* C, int N, int M, int chunk, double* colpart,
-                                                      int nchunk, int q, int col, double (*red)[4]) {
+// Float64 residual R = F - P X for diagonal A, B and tridiagonal C (a five-point stencil over the
+// rows), one work-group of 256 threads: rows [q RES_ROWS, (q+1) RES_ROWS) of the right-hand sides
+// c0 .. c0 + RES_COLS - 1 (fewer at the end).  The five coefficients of the work-group's rows stay
+// in registers for all its columns; each column's x, with one block of rows on either side, is
+// staged once in LDS (xs: RES_ROWS + 2M doubles), so every neighbour is an LDS read; the next
+// column's x and f are loaded into registers while the current column is computed.  The
+// coefficients of absent neighbours must be zero (the plan's copies are), so the row formula has
+// no branches; halo rows outside the matrix are staged as zeros.  colpart[col][q] receives the sums
+// of squares of R and F over the rows (fixed order, no atomics); red holds 2 RES_COLS x 4 doubles.
+constexpr int RES_RPT = RES_ROWS / 256;   // rows per thread
+constexpr int RES_SPT = RES_RPT + 4;      // staged rows per thread: RES_ROWS + 2M with M <= 512
+
+__device__ __forceinline__ void residual_cols_tile(double* __restrict__ R, int64_t ldr, const double* __restrict__ F,
+                                                   int64_t ldf, const double* __restrict__ X, int64_t ldx,
+                                                   const double* __restrict__ A, const double* __restrict__ B,
+                                                   const double* __restrict__ C, int N, int M, int K,
+                                                   double* __restrict__ colpart, int nchunk, int q, int c0,
+                                                   double* xs, double (*red)[4]) {
+  const int tid = threadIdx.x;
+  const int ncol = (K - c0) < RES_COLS ? (K - c0) : RES_COLS;
   const int64_t n = (int64_t)N * M;
-  const int64_t g0 = (int64_t)q * chunk;
-  const int64_t g1 = g0 + chunk < n ? g0 + chunk : n;
-  const double* x = X + (int64_t)col * ldx;
-  const double* f = F + (int64_t)col * ldf;
-  double sr = 0.0, sf = 0.0;
-  for (int64_t g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
-    const int64_t j = g / M;
-    const int r = (int)(g - j * M);
-    const double* t = C + j * 3 * M;
-    double y = t[M + r] * x[g];
-    if (r > 0) y += t[r] * x[g - 1];
-    if (r < M - 1) y += t[2 * M + r] * x[g + 1];
-    if (j > 0) y -= A[g] * x[g - M];
-    if (j < N - 1) y -= B[g] * x[g + M];
-    const double fv = f[g];
-    const double rv = fv - y;
-    if (R) R[g + (int64_t)col * ldr] = rv;
-    sr += rv * rv;
-    sf += fv * fv;
+  const int64_t g0 = (int64_t)q * RES_ROWS;
+  const int cnt = (n - g0) < RES_ROWS ? (int)(n - g0) : RES_ROWS;
+  const int64_t jb = g0 / M;
+  const unsigned rb0 = (unsigned)(g0 - jb * M);
+  // own rows tid + 256 i (the tail chunk repeats its last row; those copies are not stored)
+  double cd[RES_RPT], cs[RES_RPT], cu[RES_RPT], av[RES_RPT], bv[RES_RPT];
+  int oc[RES_RPT];
+#pragma unroll
+  for (int i = 0; i < RES_RPT; ++i) {
+    const int o = tid + 256 * i;
+    oc[i] = o < cnt ? o : cnt - 1;
+    const unsigned u = rb0 + (unsigned)oc[i];
+    const unsigned jj = u / (unsigned)M;
+    const unsigned r = u - jj * (unsigned)M;
+    const double* t = C + (jb + jj) * 3 * M + r;
+    cs[i] = t[0];
+    cd[i] = t[M];
+    cu[i] = t[2 * M];
+    av[i] = A[g0 + oc[i]];
+    bv[i] = B[g0 + oc[i]];
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    sr += __shfl_xor(sr, off);
-    sf += __shfl_xor(sf, off);
+  const int span = cnt + 2 * M;
+  double xr[RES_SPT], fv[RES_RPT];
+  auto load_col = [&](int c) {
+    const double* x = X + (int64_t)(c0 + c) * ldx;
+    const double* f = F + (int64_t)(c0 + c) * ldf;
+#pragma unroll
+    for (int i = 0; i < RES_RPT; ++i) fv[i] = f[g0 + oc[i]];
+#pragma unroll
+    for (int k = 0; k < RES_SPT; ++k) {
+      const int i = tid + 256 * k;
+      const int64_t g = g0 - M + i;
+      xr[k] = (i < span && g >= 0 && g < n) ? x[g] : 0.0;
+    }
+  };
+  load_col(0);
+#pragma unroll 1
+  for (int c = 0; c < ncol; ++c) {
+#pragma unroll
+    for (int k = 0; k < RES_SPT; ++k) {
+      const int i = tid + 256 * k;
+      if (i < span) xs[i] = xr[k];
+    }
+    double fc[RES_RPT];
+#pragma unroll
+    for (int i = 0; i < RES_RPT; ++i) fc[i] = fv[i];
+    __syncthreads();
+    if (c + 1 < ncol) load_col(c + 1);
+    double sr = 0.0, sf = 0.0;
+#pragma unroll
+    for (int i = 0; i < RES_RPT; ++i) {
+      const double* xp = xs + M + oc[i];
+      double y = cd[i] * xp[0];
+      y += cs[i] * xp[-1];
+      y += cu[i] * xp[1];
+      y -= av[i] * xp[-M];
+      y -= bv[i] * xp[M];
+      const double rv = fc[i] - y;
+      if (tid + 256 * i < cnt) {
+        if (R) R[g0 + oc[i] + (int64_t)(c0 + c) * ldr] = rv;
+        sr += rv * rv;
+        sf += fc[i] * fc[i];
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      sr += __shfl_xor(sr, off);
+      sf += __shfl_xor(sf, off);
+    }
+    if ((tid & 63) == 0) {
+      red[c][tid >> 6] = sr;
+      red[RES_COLS + c][tid >> 6] = sf;
+    }
+    __syncthreads();   // LDS rows and partial sums are reused by the next column
   }
-  if ((threadIdx.x & 63) == 0) {
-    red[0][threadIdx.x >> 6] = sr;
-    red[1][threadIdx.x >> 6] = sf;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
+  if (tid < ncol) {
     double a = 0.0, b = 0.0;
-    for (int v = 0; v < 4; ++v) { a += red[0][v]; b += red[1][v]; }
-    colpart[((int64_t)col * nchunk + q) * 2 + 0] = a;
-    colpart[((int64_t)col * nchunk + q) * 2 + 1] = b;
+    for (int v = 0; v < 4; ++v) { a += red[tid][v]; b += red[RES_COLS + tid][v]; }
+    colpart[((int64_t)(c0 + tid) * nchunk + q) * 2 + 0] = a;
+    colpart[((int64_t)(c0 + tid) * nchunk + q) * 2 + 1] = b;
   }
+  __syncthreads();   // red is free again when the work-group goes on to other work
 }
 
 template <int RT, int CT, int KU = 2>
