@@ -98,15 +98,15 @@ struct td_plan_s {
   int prof_n = 0;
   StageEvents* se = nullptr;        // set of the solve in progress
   double factor_ms = 0.0;
-  int64_t bytes = 0;
-  std::vector<void*> allocs;
+  int64_t bytes = 0;                                   // device memory held now
+  std::vector<std::pair<void*, int64_t>> allocs;       // (pointer, bytes)
   hipStream_t last_stream = nullptr;
 
   double* alloc(int64_t n_doubles) {
     void* p = nullptr;
     if (n_doubles <= 0) n_doubles = 1;
     HIPCHK(hipMalloc(&p, (size_t)n_doubles * sizeof(double)));
-    allocs.push_back(p);
+    allocs.emplace_back(p, n_doubles * (int64_t)sizeof(double));
     bytes += n_doubles * (int64_t)sizeof(double);
     return (double*)p;
   }
@@ -115,15 +115,18 @@ struct td_plan_s {
     void* p = nullptr;
     size_t nb = std::max<size_t>(1, v.size()) * sizeof(T);
     HIPCHK(hipMalloc(&p, nb));
-    allocs.push_back(p);
+    allocs.emplace_back(p, (int64_t)nb);
     bytes += (int64_t)nb;
     if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
     return (T*)p;
   }
   void release(void* p) {
     if (!p) return;
-    auto it = std::find(allocs.begin(), allocs.end(), p);
-    if (it != allocs.end()) allocs.erase(it);
+    auto it = std::find_if(allocs.begin(), allocs.end(), [p](const std::pair<void*, int64_t>& a) { return a.first == p; });
+    if (it != allocs.end()) {
+      bytes -= it->second;
+      allocs.erase(it);
+    }
     (void)hipFree(p);
   }
   // the last plain solve (no refinement, no report, not profiled), captured as a HIP graph and
@@ -142,7 +145,7 @@ struct td_plan_s {
   }
   ~td_plan_s() {
     drop_graph();
-    for (void* p : allocs) (void)hipFree(p);
+    for (auto& a : allocs) (void)hipFree(a.first);
     for (auto& s : evsets)
       for (auto& e : s.ev) (void)hipEventDestroy(e);
     delete adj;

@@ -92,3 +92,12 @@ def test_noconvergence_reported(td):
     with pytest.raises(td.TridiagError) as e:
         plan.solve(_dev(F), refine={"tol": 1e-14, "max_iter": 1})
     assert e.value.code == 4
+
+
+def test_plan_bytes_count_released_buffers(td):
+    """A float32 plan releases its float64 sweep matrices after rounding them, so it holds less
+    device memory than the float64 plan of the same system (the report counts held memory)."""
+    sys = synth.varcoef_system(96, 64, seed=36)
+    b64 = td.Plan.from_system(sys, subdomains=6).plan_info()["device_bytes"]
+    b32 = td.Plan.from_system(sys, subdomains=6, sweep_prec="f32").plan_info()["device_bytes"]
+    assert 0 < b32 < b64
