@@ -6,7 +6,9 @@ import this package.  It wraps the plain float64 block-Thomas solver of
 Terekhov's paper) and adds the few other plain definitions the tests need:
 the product P X, the transposed system P^T, the diagonal-shift gradient and
 the sub-problem solutions U, V, W of eqs. (sub1)-(sub3) with the reduced
-matrix of eq. (red1) (Sec. 2.2).  It shares no code with the HIP library.
+matrix of eq. (red1) (Sec. 2.2), and the Schur complement on interface block
+rows with its right-hand side and back-substitution (Sec. 3, eqs.
+(schur_decomp), (domains_equation)).  It shares no code with the HIP library.
 """
 from __future__ import annotations
 
@@ -297,3 +299,58 @@ def superposition_parts(sys, p: int, F: np.ndarray):
             else:
                 Bt[s] = Bk
     return dict(ks=ks, U=U, V=V, W=W, At=At, Ct=Ct, Bt=Bt, Ft=Ft)
+
+
+# ---------------------------------------------------------------------------
+# Schur complement on interface block rows (Sec. 3, eqs. (linear_decomp),
+# (schur_decomp), (domains_equation)): the unknowns of the block rows listed in
+# `icol` form the interface set Gamma, all others the interior set I.  Small
+# sizes only: P is assembled densely and A_II^{-1} is numpy's dense solve.
+# ---------------------------------------------------------------------------
+
+def dense_P(sys) -> np.ndarray:
+    """P of eq. (main-eq) as a dense row-major (N M) x (N M) array."""
+    N, M = sys.N, sys.M
+    P = np.zeros((N * M, N * M))
+    for j in range(N):
+        r = slice(j * M, (j + 1) * M)
+        P[r, r] = _block(sys, "C", j)
+        if j > 0:
+            P[r, (j - 1) * M:j * M] = -_block(sys, "A", j)
+        if j + 1 < N:
+            P[r, (j + 1) * M:(j + 2) * M] = -_block(sys, "B", j)
+    return P
+
+
+def schur_sets(sys, icol):
+    """Unknown indices of the interface set (block rows icol, in that order) and of the interior set."""
+    M = sys.M
+    g = np.concatenate([np.arange(c * M, (c + 1) * M) for c in icol]) if len(icol) else np.zeros(0, int)
+    mask = np.ones(sys.N * M, bool)
+    mask[g] = False
+    return g, np.nonzero(mask)[0]
+
+
+def schur_complement(sys, icol) -> np.ndarray:
+    """S = A_GG - A_GI A_II^{-1} A_IG (eq. schur_decomp), dense (|G| x |G|)."""
+    P = dense_P(sys)
+    g, i = schur_sets(sys, icol)
+    return P[np.ix_(g, g)] - P[np.ix_(g, i)] @ np.linalg.solve(P[np.ix_(i, i)], P[np.ix_(i, g)])
+
+
+def schur_rhs(sys, icol, F: np.ndarray) -> np.ndarray:
+    """Right-hand side f_G - A_GI A_II^{-1} f_I of eq. (schur_decomp) for every row of F ([K][N M])."""
+    P = dense_P(sys)
+    g, i = schur_sets(sys, icol)
+    Y = np.linalg.solve(P[np.ix_(i, i)], F[:, i].T)
+    return F[:, g] - (P[np.ix_(g, i)] @ Y).T
+
+
+def schur_interior(sys, icol, F: np.ndarray, xG: np.ndarray) -> np.ndarray:
+    """Full solution from the interface values: x_I = A_II^{-1}(f_I - A_IG x_G) (eq. domains_equation)."""
+    P = dense_P(sys)
+    g, i = schur_sets(sys, icol)
+    X = np.zeros_like(F)
+    X[:, g] = xG
+    X[:, i] = np.linalg.solve(P[np.ix_(i, i)], (F[:, i] - xG @ P[np.ix_(i, g)].T).T).T
+    return X

@@ -350,6 +350,30 @@ def _pins_pass(lib_path):
     return True
 
 
+@pytest.mark.parametrize("N,M,icol,family", [
+    (13, 6, [4, 8], "laplace"), (20, 5, [3, 9, 14], "varcoef"), (9, 1, [2, 6], "laplace"), (12, 4, [5], "nonsym"),
+])
+def test_schur_complement_pins(N, M, icol, family):
+    """Sec. 3: the interface values of the block-Thomas solution solve S x_G = f_G - A_GI A_II^{-1} f_I
+    (eq. schur_decomp), S^{-1} is the interface block of P^{-1} (block inversion), and eq.
+    (domains_equation) rebuilds the interior rows; for symmetric P, S is symmetric positive definite."""
+    sys = {"laplace": lambda: synth.laplace_system(N, M, 4.5),
+           "varcoef": lambda: synth.varcoef_system(N, M, seed=61),
+           "nonsym": lambda: nonsym_tridiag_system(N, M, 62)}[family]()
+    F = _rhs(63, sys, 4)
+    X = oracle.solve(sys, F)
+    S = oracle.schur_complement(sys, icol)
+    g, _ = oracle.schur_sets(sys, icol)
+    assert S.shape == (len(icol) * M, len(icol) * M)
+    assert rel_err(X[:, g] @ S.T, oracle.schur_rhs(sys, icol, F)) <= 1e-12
+    Pinv = np.linalg.inv(dense_matrix(sys))
+    assert rel_err(np.linalg.inv(S), Pinv[np.ix_(g, g)]) <= 1e-11
+    assert rel_err(oracle.schur_interior(sys, icol, F, X[:, g]), X) <= 1e-12
+    if family == "laplace":
+        assert np.allclose(S, S.T, rtol=0, atol=1e-13)
+        assert np.linalg.eigvalsh(S).min() > 0
+
+
 @pytest.mark.parametrize("mutant", [1, 2, 3, 4, 5, 6])
 def test_planted_mistakes_are_caught(mutant):
     with tempfile.TemporaryDirectory() as d:
