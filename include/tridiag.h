@@ -216,6 +216,45 @@ td_status tridiag_batch_destroy(td_batch batch);
 td_status tridiag_band_to_blocks(int64_t n, int32_t kl, int32_t ku, const double* ab, int64_t ldab, int64_t M,
                                  double* A, double* B, double* C, void* stream);
 
+/*
+ * Schur-complement solver on interface block rows (Sec. 3: eq. (linear_decomp) orders the
+ * unknowns as interiors of the subdomains, then interfaces; eq. (schur_decomp) defines the
+ * Schur complement S = A_GG - A_GI A_II^{-1} A_IG and the interface system
+ * S x_G = f_G - A_GI A_II^{-1} f_I, solved by conjugate gradients with a probing preconditioner;
+ * eq. (domains_equation) gives x_I = A_II^{-1}(f_I - A_IG x_G)).  Here the whole problem is one
+ * block-tridiagonal P (N block rows of size M, diagonal A and B, tridiagonal C; device, the
+ * layouts of tridiag_factor) whose block rows icol[0..nif) (host array) are the interfaces: they
+ * must increase, lie in [1, N-2] and leave at least one interior block row between two of them,
+ * so the interior rows fall into nif + 1 strips.  CG needs P symmetric (A_{j+1} = B_j and every
+ * C_j symmetric; checked, else TD_EINVAL) and positive definite (else CG fails: TD_ENOCONV).
+ * The interior rows of all strips are factored as one block-tridiagonal plan; every product
+ * with A_II^{-1} is one solve of it.  band >= 0 builds the probing preconditioner: S applied to
+ * 2 (2 band + 1) probe vectors gives a symmetric band matrix of half-width `band` per interface
+ * (couplings between interfaces dropped), factored through tridiag_band_to_blocks; band = -1
+ * runs plain CG.  tridiag_schur_create synchronises `stream` and keeps copies of A, B, C.
+ *
+ * tridiag_schur_apply: Y = S V for K interface vectors (device, column-major nif*M x K,
+ * ldv, ldy >= nif*M; the rows of interface k are block row icol[k]).  Asynchronous.
+ * tridiag_schur_solve: X = P^{-1} F through the interface system (F, X device, column-major
+ * (N*M) x K, ld >= N*M, no overlap), one CG per column, stopping when every column has
+ * ||r_k|| <= tol ||g_k|| (tol <= 0: 1e-10) or after max_iter iterations (<= 0: 500,
+ * TD_ENOCONV).  Synchronises `stream` once per iteration.  info (host, may be NULL):
+ * iterations done, columns still above tol, largest ||r_k|| / ||g_k||.
+ */
+typedef struct td_schur_s* td_schur;
+typedef struct {
+  int32_t iterations;
+  int32_t active;
+  double max_rel_residual;
+} td_schur_info;
+td_status tridiag_schur_create(int64_t N, int64_t M, const double* A, const double* B, const double* C, int64_t nif,
+                               const int64_t* icol, int32_t band, void* stream, td_schur* out);
+td_status tridiag_schur_apply(td_schur s, const double* V, int64_t ldv, double* Y, int64_t ldy, int64_t K,
+                              void* stream);
+td_status tridiag_schur_solve(td_schur s, const double* F, int64_t ldf, double* X, int64_t ldx, int64_t K, double tol,
+                              int32_t max_iter, td_schur_info* info, void* stream);
+td_status tridiag_schur_destroy(td_schur s);
+
 const char* tridiag_status_string(td_status s);
 /* Text of the last error on the calling host thread ("" if none). */
 const char* tridiag_last_error(void);

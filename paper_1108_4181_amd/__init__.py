@@ -57,7 +57,12 @@ class _PlanInfo(ctypes.Structure):
 EXPORTS = ["tridiag_factor", "tridiag_solve", "tridiag_solve_adjoint", "tridiag_diag_grad", "tridiag_destroy",
            "tridiag_plan_info", "tridiag_set_profiling", "tridiag_stage_times", "tridiag_status_string",
            "tridiag_last_error", "tridiag_batch_create", "tridiag_batch_solve", "tridiag_batch_info",
-           "tridiag_batch_destroy", "tridiag_autotune", "tridiag_band_to_blocks"]
+           "tridiag_batch_destroy", "tridiag_autotune", "tridiag_band_to_blocks", "tridiag_schur_create",
+           "tridiag_schur_apply", "tridiag_schur_solve", "tridiag_schur_destroy"]
+
+class _SchurInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("active", ctypes.c_int32), ("max_rel_residual", ctypes.c_double)]
+
 
 _lib = None
 
@@ -106,6 +111,14 @@ def load_library(path: str = LIB_PATH):
     lib.tridiag_autotune.restype = i32
     lib.tridiag_band_to_blocks.argtypes = [i64, i32, i32, vp, i64, i64, vp, vp, vp, vp]
     lib.tridiag_band_to_blocks.restype = i32
+    lib.tridiag_schur_create.argtypes = [i64, i64, vp, vp, vp, i64, pi64, i32, vp, ctypes.POINTER(vp)]
+    lib.tridiag_schur_create.restype = i32
+    lib.tridiag_schur_apply.argtypes = [vp, vp, i64, vp, i64, i64, vp]
+    lib.tridiag_schur_apply.restype = i32
+    lib.tridiag_schur_solve.argtypes = [vp, vp, i64, vp, i64, i64, dp, i32, ctypes.POINTER(_SchurInfo), vp]
+    lib.tridiag_schur_solve.restype = i32
+    lib.tridiag_schur_destroy.argtypes = [vp]
+    lib.tridiag_schur_destroy.restype = i32
     _lib = lib
     return lib
 
@@ -360,6 +373,59 @@ class BandSolver:
 
     def solve_adjoint(self, G, refine=None):
         return self.plan.solve_adjoint(self._pad(G), refine=refine)[:, : self.n]
+
+
+class SchurSolver:
+    """Schur-complement solver on interface block rows (tridiag_schur_*): the block rows `icol`
+    of the system (diagonal A, B; tridiagonal C; symmetric) are the interfaces, solved by
+    conjugate gradients on S = A_GG - A_GI A_II^{-1} A_IG with a probing preconditioner of
+    half-bandwidth `band` (-1: none); the interiors by the stacked interior plan.
+
+    A, B: (N, M) and C: (N, 3, M) float64 device tensors.  Vectors are (K, rows) tensors:
+    full vectors have N*M rows, interface vectors len(icol)*M rows."""
+
+    def __init__(self, A, B, C, icol, band: int = 4):
+        lib = load_library()
+        A, B, C = _dev(A, "A"), _dev(B, "B"), _dev(C, "C")
+        self.N, self.M = int(A.shape[0]), int(A.shape[1])
+        self.icol = [int(c) for c in icol]
+        arr = (ctypes.c_int64 * len(self.icol))(*self.icol)
+        h = ctypes.c_void_p()
+        _check(lib.tridiag_schur_create(self.N, self.M, ctypes.c_void_p(A.data_ptr()), ctypes.c_void_p(B.data_ptr()),
+                                        ctypes.c_void_p(C.data_ptr()), len(self.icol), arr, int(band), _stream(),
+                                        ctypes.byref(h)))
+        self.lib, self.h = lib, h
+
+    def apply(self, V):
+        V = _dev(V, "V")
+        Y = torch.empty_like(V)
+        _check(self.lib.tridiag_schur_apply(self.h, ctypes.c_void_p(V.data_ptr()), V.shape[1],
+                                            ctypes.c_void_p(Y.data_ptr()), Y.shape[1], V.shape[0], _stream()))
+        return Y
+
+    def solve(self, F, tol: float = 1e-10, max_iter: int = 500, info: bool = False):
+        F = _dev(F, "F")
+        X = torch.empty_like(F)
+        inf = _SchurInfo()
+        st = self.lib.tridiag_schur_solve(self.h, ctypes.c_void_p(F.data_ptr()), F.shape[1],
+                                          ctypes.c_void_p(X.data_ptr()), X.shape[1], F.shape[0], float(tol),
+                                          int(max_iter), ctypes.byref(inf), _stream())
+        rep = {"iterations": inf.iterations, "active": inf.active, "max_rel_residual": inf.max_rel_residual,
+               "converged": st == 0}
+        if st != 4 or not info:
+            _check(st)
+        return (X, rep) if info else X
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tridiag_schur_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def choose_subdomains(N: int, M: int, K: int, sweep_prec: str = "f64") -> int:

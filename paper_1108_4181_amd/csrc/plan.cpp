@@ -50,6 +50,9 @@ struct StageEvents {
 
 }  // namespace
 
+// error text for the library's other host source files
+td_status td_set_error(td_status s, const char* msg) { return fail(s, msg ? msg : ""); }
+
 struct td_plan_s {
   int64_t N = 0, M = 0, Mp = 0, p = 0;
   int fmtA = 1, fmtB = 1, fmtC = 2, prec = 0, adjoint = 0;

@@ -102,3 +102,24 @@ def test_null_arguments_rejected(lib):
 def test_band_conversion_rejects_bad_sizes(lib, n, kl, ku, ldab, M, code):
     dummy = ctypes.c_void_p(16)  # never dereferenced: validation fails first
     assert lib.tridiag_band_to_blocks(n, kl, ku, dummy, ldab, M, dummy, dummy, dummy, None) == code
+
+
+@pytest.mark.parametrize("N,M,icol,band,code", [
+    (10, 4, [0], 2, 1), (10, 4, [3, 4], 2, 1), (10, 4, [9], 2, 1), (10, 4, [4], 65, 1), (10, 4, [4], -2, 1),
+    (10, 513, [4], 2, 7), (2, 4, [1], 2, 1), (10, 4, [2, 4, 6, 8, 8], 2, 1),
+])
+def test_schur_create_rejects_bad_arguments_on_host(lib, N, M, icol, band, code):
+    dummy = ctypes.c_void_p(16)  # never dereferenced: validation fails first
+    arr = (ctypes.c_int64 * len(icol))(*icol)
+    out = ctypes.c_void_p()
+    lib.tridiag_schur_create.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+    assert lib.tridiag_schur_create(N, M, dummy, dummy, dummy, len(icol), arr, band, None, ctypes.byref(out)) == code
+    assert out.value is None
+
+
+def test_schur_null_handles(lib):
+    assert lib.tridiag_schur_solve(None, None, 0, None, 0, 1, ctypes.c_double(0.0), 0, None, None) == 1
+    assert lib.tridiag_schur_apply(None, None, 0, None, 0, 1, None) == 1
+    assert lib.tridiag_schur_destroy(None) == 0
