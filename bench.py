@@ -267,6 +267,73 @@ def bench_band(args):
     print(json.dumps(out))
 
 
+def bench_schur(args):
+    """Schur-complement CG on interface block rows (Sec. 3): a 2-D five-point operator
+    (C_j = tridiag(-1, 4 + s, -1), A = B = I, s = 0.01) on a rectangle of N columns of M nodes cut
+    into strips by interface columns; probing preconditioner of half-bandwidth `band`.  Compared
+    with the direct float64 solve of the whole system by one plan."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1108_4181_amd as td
+
+    N, M, nstrip, K, band = (int(v) for v in args.schur.split(","))
+    width = (N - (nstrip - 1)) // nstrip
+    icol = [(k + 1) * width + k for k in range(nstrip - 1)]
+    dev = torch.device("cuda:0")
+    sysw = synth.laplace_system(N, M, 4.01)
+    A, B, C = (torch.as_tensor(np.ascontiguousarray(x), device=dev) for x in (sysw.A, sysw.B, sysw.C))
+    F = synth.rhs_torch(4251, N, M, K, dev)
+    t0 = time.perf_counter()
+    solver = td.SchurSolver(A, B, C, icol, band=band)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    X, info = solver.solve(F, tol=1e-10, info=True)
+    for _ in range(args.warmup):
+        solver.solve(F, tol=1e-10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        solver.solve(F, tol=1e-10)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    # one application of S to K interface vectors (scatter, interior solve, gather)
+    V = torch.ones((K, len(icol) * M), dtype=torch.float64, device=dev)
+    solver.apply(V)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        solver.apply(V)
+    torch.cuda.synchronize()
+    apply_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    # the same system by one plan (direct Algorithm 2 on the whole domain)
+    plan = td.Plan.from_system(sysw, device=dev, subdomains=max(1, N // 32))
+    Xd = torch.empty_like(F)
+    plan.solve(F, Xd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.solve(F, Xd)
+    torch.cuda.synchronize()
+    direct_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    diff = float(torch.linalg.norm(X - Xd) / torch.linalg.norm(Xd))
+    out = {
+        "metric": METRIC, "value": K / (ms / 1e3), "unit": "RHS/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "schur_cg", "N": N, "M": M, "strips": nstrip, "interfaces": len(icol), "K": K,
+                   "probe_band": band, "shift": 0.01},
+        "cg_iterations": info["iterations"], "cg_max_rel_residual": info["max_rel_residual"],
+        "apply_ms": apply_ms, "setup_ms": setup_ms,
+        "direct_plan_ms": direct_ms, "direct_plan_rhs_per_s": K / (direct_ms / 1e3),
+        "rel_diff_vs_direct": diff,
+    }
+    solver.close()
+    plan.close()
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -285,6 +352,8 @@ def main():
                     help="override the workload's subdomain count (= N: Algorithm 1 on the whole system)")
     ap.add_argument("--band", default="65536,60,60,256",
                     help="band workload n,kl,ku,K (with --workload band)")
+    ap.add_argument("--schur", default="2047,256,16,64,4",
+                    help="Schur-complement workload N,M,strips,K,probe band (with --workload schur)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -296,6 +365,9 @@ def main():
         return
     if args.workload == "band":
         bench_band(args)
+        return
+    if args.workload == "schur":
+        bench_schur(args)
         return
 
     import torch
