@@ -220,7 +220,8 @@ td_status schur_create(int64_t N, int64_t M, const double* A, const double* B, c
       double* Cb = S->dalloc<double>(bb, tmp);
       TDCHK(tridiag_band_to_blocks(S->ng, band, band, ab, w, S->Mb, Ab, Bb, Cb, st));
       td_desc e{};
-      e.N = S->Nb; e.M = S->Mb; e.subdomains = std::max<int64_t>(1, S->Nb / 32);
+      // short subdomains: the band system is small, its sweeps are latency-bound, not MFMA-bound
+      e.N = S->Nb; e.M = S->Mb; e.subdomains = std::max<int64_t>(1, S->Nb / 8);
       e.fmt_A = TD_FMT_DENSE; e.fmt_B = TD_FMT_DENSE; e.fmt_C = TD_FMT_DENSE; e.sweep_prec = TD_PREC_F64;
       fs = tridiag_factor(&e, Ab, Bb, Cb, st, &S->precond);
       SCHK(hipStreamSynchronize(st));
