@@ -10,7 +10,7 @@
 // with their leading dimensions; interface vectors are column-major nGp x K (nGp >= nif M,
 // rows beyond nif M are padding and stay zero).  The coupling of block row c to c-1 is -A_c,
 // to c+1 is -B_c (DIAG [N][M]); C is TRIDIAG [N][3][M].
-#include "internal.h"
+#include "schur_kernels.h"
 
 namespace td {
 

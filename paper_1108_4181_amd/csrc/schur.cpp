@@ -10,7 +10,7 @@
 //     (tridiag_band_to_blocks), as the paper proposes;
 //   * preconditioned CG runs one independent iteration per right-hand side on the device; the
 //     host reads two numbers per iteration (active columns, largest relative residual).
-#include "internal.h"
+#include "schur_kernels.h"
 #include "tridiag.h"
 
 #include <algorithm>
