@@ -45,6 +45,17 @@ struct SchurFail {
     if (s_ != TD_OK) throw SchurFail{s_, std::string(#x) + ": " + tridiag_last_error()};               \
   } while (0)
 
+// device buffers of one construction step; freed on every exit path (hipFree waits for the
+// device, so kernels still reading them finish first)
+struct TmpBufs {
+  std::vector<void*> v;
+  void release() {
+    for (void* ptr : v) (void)hipFree(ptr);
+    v.clear();
+  }
+  ~TmpBufs() { release(); }
+};
+
 }  // namespace
 
 struct td_schur_s {
@@ -188,17 +199,16 @@ td_status schur_create(int64_t N, int64_t M, const double* A, const double* B, c
     SCHK(hipMemcpyAsync(S->cC, C, N * 3 * M * 8, hipMemcpyDeviceToDevice, st));
 
     // A_II: the stacked interior rows, one plan
-    std::vector<void*> tmp;
-    double* Ai = S->dalloc<double>(S->Nint * M, tmp);
-    double* Bi = S->dalloc<double>(S->Nint * M, tmp);
-    double* Ci = S->dalloc<double>(S->Nint * 3 * M, tmp);
+    TmpBufs tmp;
+    double* Ai = S->dalloc<double>(S->Nint * M, tmp.v);
+    double* Bi = S->dalloc<double>(S->Nint * M, tmp.v);
+    double* Ci = S->dalloc<double>(S->Nint * 3 * M, tmp.v);
     SCHK(launch_schur_interior_coeffs(Ai, Bi, Ci, S->cA, S->cB, S->cC, S->d_intcol, S->Nint, (int)M, st));
     td_desc d{};
     d.N = S->Nint; d.M = M; d.subdomains = std::max<int64_t>(1, S->Nint / 32);
     d.fmt_A = TD_FMT_DIAG; d.fmt_B = TD_FMT_DIAG; d.fmt_C = TD_FMT_TRIDIAG; d.sweep_prec = TD_PREC_F64;
     td_status fs = tridiag_factor(&d, Ai, Bi, Ci, st, &S->interior);
-    for (void* ptr : tmp) (void)hipFree(ptr);
-    tmp.clear();
+    tmp.release();
     if (fs != TD_OK) throw SchurFail{fs, std::string("interior factor: ") + tridiag_last_error()};
 
     // probing preconditioner: band blocks of size Mb (>= d) over the padded interface vector
@@ -208,24 +218,23 @@ td_status schur_create(int64_t N, int64_t M, const double* A, const double* B, c
       S->nGp = S->Nb * S->Mb;
       const int w = 2 * band + 1;
       S->ensure_ws(2 * w);
-      double* V = S->dalloc<double>(S->nGp * 2 * w, tmp);
-      double* Yp = S->dalloc<double>(S->nGp * 2 * w, tmp);
-      double* ab = S->dalloc<double>(S->ng * w, tmp);
+      double* V = S->dalloc<double>(S->nGp * 2 * w, tmp.v);
+      double* Yp = S->dalloc<double>(S->nGp * 2 * w, tmp.v);
+      double* ab = S->dalloc<double>(S->ng * w, tmp.v);
       SCHK(launch_probe_vectors(V, S->nGp, S->nGp, S->ng, (int)M, band, st));
       S->apply(V, S->nGp, Yp, S->nGp, S->nGp, 2 * w, st);
       SCHK(launch_probe_band(ab, w, Yp, S->nGp, S->ng, (int)M, band, st));
       const int64_t bb = S->Nb * S->Mb * S->Mb;
-      double* Ab = S->dalloc<double>(bb, tmp);
-      double* Bb = S->dalloc<double>(bb, tmp);
-      double* Cb = S->dalloc<double>(bb, tmp);
+      double* Ab = S->dalloc<double>(bb, tmp.v);
+      double* Bb = S->dalloc<double>(bb, tmp.v);
+      double* Cb = S->dalloc<double>(bb, tmp.v);
       TDCHK(tridiag_band_to_blocks(S->ng, band, band, ab, w, S->Mb, Ab, Bb, Cb, st));
       td_desc e{};
       // short subdomains: the band system is small, its sweeps are latency-bound, not MFMA-bound
       e.N = S->Nb; e.M = S->Mb; e.subdomains = std::max<int64_t>(1, S->Nb / 8);
       e.fmt_A = TD_FMT_DENSE; e.fmt_B = TD_FMT_DENSE; e.fmt_C = TD_FMT_DENSE; e.sweep_prec = TD_PREC_F64;
       fs = tridiag_factor(&e, Ab, Bb, Cb, st, &S->precond);
-      SCHK(hipStreamSynchronize(st));
-      for (void* ptr : tmp) (void)hipFree(ptr);
+      tmp.release();
       if (fs != TD_OK) throw SchurFail{fs, std::string("probed preconditioner factor: ") + tridiag_last_error()};
     } else {
       S->nGp = S->ng;
