@@ -401,28 +401,27 @@ def main():
     pinfo = plan.plan_info()
 
     _, info = plan.solve(F, X, info=True)
+    # timed: plain solves, as a caller runs them (the library replays a captured HIP graph)
     for _ in range(args.warmup):
         plan.solve(F, X)
-    torch.cuda.synchronize()
-    plan.set_profiling(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         plan.solve(F, X)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    stages = plan.stage_times()
-    plan.set_profiling(False)
     ms_per_step = elapsed * 1e3 / args.steps
     value = K / (ms_per_step / 1e3)
-    # the same solves without stage events: the library replays them from a captured HIP graph
-    plan.solve(F, X)
+    # the same solves launched eagerly with HIP events around every stage (per-kernel times)
+    plan.set_profiling(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         plan.solve(F, X)
     torch.cuda.synchronize()
-    graph_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    eager_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    stages = plan.stage_times()
+    plan.set_profiling(False)
 
     work = algorithmic_work(N, M, K, p)
     kern = {
@@ -459,7 +458,7 @@ def main():
         "kernels": other,
         "stages_ms": {k: v for k, v in stages.items() if k != "count"},
         "whole_solve_tflops": work["total_flops"] / (ms_per_step * 1e-3) / 1e12,
-        "graph_replay_ms_per_step": graph_ms,
+        "eager_profiled_ms_per_step": eager_ms,
         "factor_ms": factor_ms,
         "max_col_rel_residual": info["max_col_rel_residual"],
         "plan_device_bytes": pinfo["device_bytes"],
