@@ -37,7 +37,8 @@ def _colres(sys, X, F):
 
 
 @pytest.mark.parametrize("prec,maxit", [("f32", 3), ("bf16", 10)])
-@pytest.mark.parametrize("N,M,K,p", [(128, 64, 20, 8), (64, 16, 8, 4), (96, 48, 37, 6)])
+@pytest.mark.parametrize("N,M,K,p", [(128, 64, 20, 8), (64, 16, 8, 4), (96, 48, 37, 6), (48, 256, 70, 4),
+                                     (40, 224, 33, 5), (24, 320, 17, 3)])
 def test_refined_to_1e10(td, prec, maxit, N, M, K, p):
     sys = synth.varcoef_system(N, M, seed=200 + N + M)
     F = synth.rhs_columns(200 + N, N, M, range(K))
