@@ -59,7 +59,7 @@ __device__ void run_item(const BatchItem& it, const BatchSys& S, uint4* lds, dou
       const int64_t* ks = S.sweep.ks;
       const float* W32 = S.sweep.W;
       const double* W64 = S.sweep64.W;
-      const int64_t ldw = S.sweep.ldw;
+      const int64_t ldw = S.sweep64.ldw;   // float64 workspace; the float32 one uses w32_off
       for (int64_t e = e0 + tid; e < e1; e += BATCH_THREADS) {
         const int r = (int)(e % S.Mp);
         const int64_t sc = e / S.Mp;
@@ -68,12 +68,12 @@ __device__ void run_item(const BatchItem& it, const BatchSys& S, uint4* lds, dou
         const int64_t k = ks[s];
         double v = (r < S.M) ? F[k * S.M + r + col * ldf] : 0.0;
         if (s > 0 && k - 1 > ks[s - 1]) {
-          const int64_t o = (k - 1) * S.Mp + r + col * ldw;
-          v += S.adiag[k * S.Mp + r] * (S.prec == 0 ? W64[o] : (double)W32[o]);
+          const double wv = S.prec == 0 ? W64[(k - 1) * S.Mp + r + col * ldw] : (double)W32[w32_off(S.N, S.Mp, k - 1, r, col)];
+          v += S.adiag[k * S.Mp + r] * wv;
         }
         if (k + 1 < ks[s + 1]) {
-          const int64_t o = (k + 1) * S.Mp + r + col * ldw;
-          v += S.bdiag[k * S.Mp + r] * (S.prec == 0 ? W64[o] : (double)W32[o]);
+          const double wv = S.prec == 0 ? W64[(k + 1) * S.Mp + r + col * ldw] : (double)W32[w32_off(S.N, S.Mp, k + 1, r, col)];
+          v += S.bdiag[k * S.Mp + r] * wv;
         }
         S.Ft[(int64_t)s * S.Mp + r + col * S.ldft] = v;
       }

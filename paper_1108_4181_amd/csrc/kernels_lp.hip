@@ -202,7 +202,7 @@ hipError_t launch_superpose_lp(int prec, const LpSupArgs& a, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // Right-hand side of the reduced system from a float32 W (see k_ftilde)
 // ---------------------------------------------------------------------------
-__global__ void k_ftilde_f32(double* Ft, int64_t ldft, const double* F, int64_t ldf, const float* W, int64_t ldw,
+__global__ void k_ftilde_f32(double* Ft, int64_t ldft, const double* F, int64_t ldf, const float* W, int64_t N,
                              const int64_t* ks, const double* adiag, const double* bdiag, int p, int M, int Mp, int K) {
   const int64_t n = (int64_t)p * Mp * K;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
@@ -212,20 +212,20 @@ __global__ void k_ftilde_f32(double* Ft, int64_t ldft, const double* F, int64_t 
     const int64_t col = sc / p;
     const int64_t k = ks[s];
     double v = (r < M) ? F[k * M + r + col * ldf] : 0.0;
-    if (s > 0 && k - 1 > ks[s - 1]) v += adiag[k * Mp + r] * (double)W[(k - 1) * Mp + r + col * ldw];
-    if (k + 1 < ks[s + 1]) v += bdiag[k * Mp + r] * (double)W[(k + 1) * Mp + r + col * ldw];
+    if (s > 0 && k - 1 > ks[s - 1]) v += adiag[k * Mp + r] * (double)W[w32_off(N, Mp, k - 1, r, col)];
+    if (k + 1 < ks[s + 1]) v += bdiag[k * Mp + r] * (double)W[w32_off(N, Mp, k + 1, r, col)];
     Ft[(int64_t)s * Mp + r + col * ldft] = v;
   }
 }
 
-hipError_t launch_ftilde_f32(double* Ft, int64_t ldft, const double* F, int64_t ldf, const float* W, int64_t ldw,
+hipError_t launch_ftilde_f32(double* Ft, int64_t ldft, const double* F, int64_t ldf, const float* W, int64_t N,
                              const int64_t* ks, const double* adiag, const double* bdiag, int p, int M, int Mp, int K,
                              hipStream_t st) {
   const int64_t n = (int64_t)p * Mp * K;
   if (n == 0) return hipSuccess;
   int bx = (int)((n + 255) / 256);
   if (bx > 8192) bx = 8192;
-  hipLaunchKernelGGL(k_ftilde_f32, dim3(bx), dim3(256), 0, st, Ft, ldft, F, ldf, W, ldw, ks, adiag, bdiag, p, M, Mp,
+  hipLaunchKernelGGL(k_ftilde_f32, dim3(bx), dim3(256), 0, st, Ft, ldft, F, ldf, W, N, ks, adiag, bdiag, p, M, Mp,
                      K);
   return hipGetLastError();
 }

@@ -880,7 +880,7 @@ void ensure_workspace(td_plan_s* P, int64_t K, hipStream_t st) {
   if (P->prec == TD_PREC_F64)
     P->Wbuf = P->alloc(N * Mp * K);
   else
-    P->W32 = (float*)P->alloc((N * Mp * K + 1) / 2);
+    P->W32 = (float*)P->alloc((w32_floats(N, Mp, K) + 1) / 2);
   P->Ft = P->alloc(p * Mp * K);
   P->Xi = P->alloc((p + 2) * Mp * K);
   P->Sp = P->alloc((int64_t)P->nchunks * Mp * K);
@@ -964,12 +964,12 @@ void solve_pass(td_plan_s* P, const double* F, int64_t ldf, double* X, int64_t l
   } else {
     LpSweepArgs sa{};
     sa.ks = P->d_ks; sa.Dinv = P->Dlp; sa.alpha = P->Alp; sa.adiag = P->adiag;
-    sa.F = F; sa.ldf = ldf; sa.W = P->W32; sa.ldw = ldw;
+    sa.F = F; sa.ldf = ldf; sa.W = P->W32;
     sa.N = (int32_t)N; sa.M = (int32_t)M; sa.Mp = (int32_t)Mp; sa.p = (int32_t)p; sa.K = (int32_t)K;
     sa.ncoltiles = 0; sa.total = 0;
     if (N > p) HIPCHK(launch_sweep_lp(P->prec, sa, st));
     stage_mark(P, 1, st);
-    HIPCHK(launch_ftilde_f32(P->Ft, ldft, F, ldf, P->W32, ldw, P->d_ks, P->adiag, P->bdiag, (int)p, (int)M,
+    HIPCHK(launch_ftilde_f32(P->Ft, ldft, F, ldf, P->W32, N, P->d_ks, P->adiag, P->bdiag, (int)p, (int)M,
                              (int)Mp, (int)K, st));
   }
   stage_mark(P, 2, st);
@@ -1032,7 +1032,7 @@ void solve_pass(td_plan_s* P, const double* F, int64_t ldf, double* X, int64_t l
     LpSupArgs u{};
     u.ks = P->d_ks; u.UV = P->UVlp;
     u.Xi = P->Xi; u.ldxi = ldxi;
-    u.W = P->W32; u.ldw = ldw;
+    u.W = P->W32;
     u.X = X; u.ldx = ldx;
     u.N = (int32_t)N; u.M = (int32_t)M; u.Mp = (int32_t)Mp; u.p = (int32_t)p; u.K = (int32_t)K;
     u.ncoltiles = 0; u.total = 0; u.accumulate = accumulate ? 1 : 0;
@@ -1404,11 +1404,11 @@ td_status batch_create_impl(int n, const td_plan* plans, const double* const* F,
     BatchSys& S = sys[q];
     std::memset(&S, 0, sizeof(S));
     S.sweep.ks = P->d_ks; S.sweep.Dinv = P->Dlp; S.sweep.alpha = P->Alp; S.sweep.adiag = P->adiag;
-    S.sweep.F = F[q]; S.sweep.ldf = ldf[q]; S.sweep.W = P->W32; S.sweep.ldw = ldw;
+    S.sweep.F = F[q]; S.sweep.ldf = ldf[q]; S.sweep.W = P->W32;
     S.sweep.N = (int32_t)N; S.sweep.M = (int32_t)M; S.sweep.Mp = (int32_t)Mp; S.sweep.p = (int32_t)p;
     S.sweep.K = (int32_t)Kq;
     S.sup.ks = P->d_ks; S.sup.UV = P->UVlp; S.sup.Xi = P->Xi; S.sup.ldxi = ldxi;
-    S.sup.W = P->W32; S.sup.ldw = ldw; S.sup.X = X[q]; S.sup.ldx = ldx[q];
+    S.sup.W = P->W32; S.sup.X = X[q]; S.sup.ldx = ldx[q];
     S.sup.N = (int32_t)N; S.sup.M = (int32_t)M; S.sup.Mp = (int32_t)Mp; S.sup.p = (int32_t)p; S.sup.K = (int32_t)Kq;
     S.sweep64.ks = P->d_ks; S.sweep64.Dinv = P->Dinv; S.sweep64.alpha = P->alpha; S.sweep64.adiag = P->adiag;
     S.sweep64.F = F[q]; S.sweep64.ldf = ldf[q]; S.sweep64.W = P->Wbuf; S.sweep64.ldw = ldw;

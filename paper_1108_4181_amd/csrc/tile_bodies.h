@@ -146,6 +146,7 @@ __device__ __forceinline__ void sweep_lp_tile(const LpSweepArgs& a, int s, int c
   using T = typename Tr::T;
   constexpr int KG = Tr::KG;
   constexpr int KT = 16 * CT;
+  static_assert(W32_PANEL % KT == 0, "a column tile must lie in one workspace panel");
   T* In = reinterpret_cast<T*>(lds_raw);     // [KT][SK]
   const int Mp = a.Mp, M = a.M, K = a.K;
   const int SK = Mp + 16 / (int)sizeof(T);   // column stride (elements), padded by 16 bytes
@@ -158,6 +159,9 @@ __device__ __forceinline__ void sweep_lp_tile(const LpSweepArgs& a, int s, int c
   const int rb = w * 16 * RT;
   const int64_t MM = (int64_t)Mp * Mp;
   const int nkc = Mp / (KG * KU);   // chunks of KU k-groups per step
+  // the tile's columns lie in one panel of the float32 workspace (KT divides W32_PANEL)
+  float* const Wp = a.W + (int64_t)(col0 / W32_PANEL) * a.N * W32_PANEL * Mp;
+  const int cp0 = col0 % W32_PANEL;
 
   const int64_t nsteps = 2 * (last - first) + 1;
   auto step_matrix = [&](int64_t q) -> const T* {
@@ -234,7 +238,7 @@ __device__ __forceinline__ void sweep_lp_tile(const LpSweepArgs& a, int s, int c
           if (fwd) {
             if (more && row < M && col < K) x = (float)a.F[(i + 1) * M + row + (int64_t)col * a.ldf];
           } else if (col < K) {
-            x = a.W[i * Mp + row + (int64_t)col * a.ldw];
+            x = Wp[i * (W32_PANEL * Mp) + (int64_t)(cp0 + 16 * c + (L & 15)) * Mp + row];
           }
           ex[t][c][v] = x;
         }
@@ -260,7 +264,7 @@ __device__ __forceinline__ void sweep_lp_tile(const LpSweepArgs& a, int s, int c
         f32x4 vv;
 #pragma unroll
         for (int v = 0; v < 4; ++v) vv[v] = fwd ? acc[t][c][v] : acc[t][c][v] + ex[t][c][v];
-        if (col < K) *reinterpret_cast<f32x4*>(a.W + i * Mp + row0 + (int64_t)col * a.ldw) = vv;
+        if (col < K) *reinterpret_cast<f32x4*>(Wp + i * (W32_PANEL * Mp) + (int64_t)(cp0 + lc) * Mp + row0) = vv;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const float nxt = more ? ex[t][c][v] + an[t][v] * vv[v] : vv[v];
@@ -278,6 +282,7 @@ __device__ __forceinline__ void superpose_lp_tile(const LpSupArgs& a, int s, int
   using T = typename Tr::T;
   constexpr int KG = Tr::KG;
   constexpr int KT = 16 * CT;
+  static_assert(W32_PANEL % KT == 0, "a column tile must lie in one workspace panel");
   T* Xs = reinterpret_cast<T*>(lds_raw);   // [KT][SK]
   const int Mp = a.Mp, M = a.M, K = a.K;
   const int kd = 2 * Mp;
@@ -291,6 +296,9 @@ __device__ __forceinline__ void superpose_lp_tile(const LpSupArgs& a, int s, int
   const int rb = w * 16 * RT;
   const int64_t MM2 = (int64_t)Mp * kd;
   const int nkc = kd / (KG * KU);
+  // the tile's columns lie in one panel of the float32 workspace (KT divides W32_PANEL)
+  const float* const Wp = a.W + (int64_t)(col0 / W32_PANEL) * a.N * W32_PANEL * Mp;
+  const int cp0 = col0 % W32_PANEL;
 
   for (int e = tid; e < kd * KT; e += nthr) {
     const int k = e % kd, c = e / kd;
@@ -349,7 +357,7 @@ __device__ __forceinline__ void superpose_lp_tile(const LpSupArgs& a, int s, int
       for (int c = 0; c < CT; ++c) {
         const int col = col0 + 16 * c + (L & 15);
         f32x4 x = (f32x4){0.f, 0.f, 0.f, 0.f};
-        if (col < K) x = *reinterpret_cast<const f32x4*>(a.W + i * Mp + row0 + (int64_t)col * a.ldw);
+        if (col < K) x = *reinterpret_cast<const f32x4*>(Wp + i * (W32_PANEL * Mp) + (int64_t)(cp0 + 16 * c + (L & 15)) * Mp + row0);
 #pragma unroll
         for (int v = 0; v < 4; ++v) wv[t][c][v] = x[v];
       }
