@@ -71,13 +71,13 @@ __global__ void __launch_bounds__(512) k_sweep_lp(LpSweepArgs a) {
 // interface panel rounded to T in LDS and [U_i V_i] (row-major, T) streamed.  With
 // `accumulate` the result is added to X (refinement correction).
 // ---------------------------------------------------------------------------
-template <int PREC, int RT, int CT, int KU>
+template <int PREC, int RT, int CT, int KU, int ACC>
 __global__ void __launch_bounds__(512) k_superpose_lp(LpSupArgs a) {
   extern __shared__ uint4 lds_raw[];
   const int lg = lp_xcd_remap(blockIdx.x, gridDim.x);
   if (lg >= a.total) return;
   const int s = lg / a.ncoltiles;
-  superpose_lp_tile<PREC, RT, CT, KU>(a, s, lg - s * a.ncoltiles, lds_raw);
+  superpose_lp_tile<PREC, RT, CT, KU, ACC>(a, s, lg - s * a.ncoltiles, lds_raw);
 }
 
 // k-groups per register chunk of the streamed matrix: a float32 group (16 deep) is four MFMAs per
@@ -156,10 +156,15 @@ static hipError_t launch_sup_lp_cfg(const LpSupArgs& a0, hipStream_t st) {
   const int nthr = a.Mp / (16 * RT) * 64;
   const size_t esz = (PREC == 1) ? 4 : 2;
   const size_t lds = (size_t)kt * ((size_t)2 * a.Mp * esz + 16);
-  hipError_t e = hipFuncSetAttribute((const void*)k_superpose_lp<PREC, RT, CT, KU>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  // separate kernels for writing and for adding to X (the first pass of a solve writes)
+  const void* fn = a.accumulate ? (const void*)k_superpose_lp<PREC, RT, CT, KU, 1>
+                                : (const void*)k_superpose_lp<PREC, RT, CT, KU, 0>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_superpose_lp<PREC, RT, CT, KU>), dim3(lp_pad8(a.total)), dim3(nthr), lds, st, a);
+  if (a.accumulate)
+    hipLaunchKernelGGL((k_superpose_lp<PREC, RT, CT, KU, 1>), dim3(lp_pad8(a.total)), dim3(nthr), lds, st, a);
+  else
+    hipLaunchKernelGGL((k_superpose_lp<PREC, RT, CT, KU, 0>), dim3(lp_pad8(a.total)), dim3(nthr), lds, st, a);
   return hipGetLastError();
 }
 

@@ -220,27 +220,52 @@ __device__ __forceinline__ void sweep_lp_tile(const LpSweepArgs& a, int s, int c
       compute(a1, g + 1);
     }
     // epilogue operands: rows 4(L/16)..+3 of column L%16 of each tile
+    // Unconditional loads (out-of-range lanes read element 0 and discard it): a load under a
+    // per-lane branch makes the compiler wait for every outstanding load before the next one.
     const bool more = fwd && i < last;
     float ex[RT][CT][4];
     float an[RT][4];
+    const double* __restrict__ asrc = a.adiag + (more ? (i + 1) * Mp : 0);
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
       const int row0 = rb + 16 * t + 4 * (L >> 4);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) an[t][v] = more ? (float)a.adiag[(i + 1) * Mp + row0 + v] : 0.f;
+      for (int v = 0; v < 4; ++v) {
+        const double av = asrc[row0 + v];
+        an[t][v] = more ? (float)av : 0.f;
+      }
+    }
+    if (fwd) {
+      // row and column indices clamped into the operand (the values read there are discarded)
+      const double* __restrict__ fsrc = a.F + (more ? (i + 1) * M : 0);
+      const int frows = more ? M : 0;
+      const int rmax = more ? M - 1 : 0;
 #pragma unroll
-      for (int c = 0; c < CT; ++c) {
-        const int col = col0 + 16 * c + (L & 15);
+      for (int t = 0; t < RT; ++t) {
+        const int row0 = rb + 16 * t + 4 * (L >> 4);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = row0 + v;
-          float x = 0.f;
-          if (fwd) {
-            if (more && row < M && col < K) x = (float)a.F[(i + 1) * M + row + (int64_t)col * a.ldf];
-          } else if (col < K) {
-            x = Wp[i * (W32_PANEL * Mp) + (int64_t)(cp0 + 16 * c + (L & 15)) * Mp + row];
+        for (int c = 0; c < CT; ++c) {
+          const int col = col0 + 16 * c + (L & 15);
+          const double* __restrict__ fc = fsrc + (int64_t)min(col, K - 1) * a.ldf;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const bool ok = row0 + v < frows && col < K;
+            const double x = fc[min(row0 + v, rmax)];
+            ex[t][c][v] = ok ? (float)x : 0.f;
           }
-          ex[t][c][v] = x;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int row0 = rb + 16 * t + 4 * (L >> 4);
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+          const bool ok = col0 + 16 * c + (L & 15) < K;
+          const f32x4 x = *reinterpret_cast<const f32x4*>(
+              Wp + (ok ? i * (W32_PANEL * Mp) + (int64_t)(cp0 + 16 * c + (L & 15)) * Mp + row0 : 0));
+#pragma unroll
+          for (int v = 0; v < 4; ++v) ex[t][c][v] = ok ? x[v] : 0.f;
         }
       }
     }
@@ -276,7 +301,8 @@ __device__ __forceinline__ void sweep_lp_tile(const LpSweepArgs& a, int s, int c
   }
 }
 
-template <int PREC, int RT, int CT, int KU = 1>
+// ACC: 0 writes X_i, 1 adds to X_i, -1 follows a.accumulate at run time.
+template <int PREC, int RT, int CT, int KU = 1, int ACC = -1>
 __device__ __forceinline__ void superpose_lp_tile(const LpSupArgs& a, int s, int ct, uint4* lds_raw) {
   using Tr = LP<PREC>;
   using T = typename Tr::T;
@@ -371,20 +397,49 @@ __device__ __forceinline__ void superpose_lp_tile(const LpSupArgs& a, int s, int
       compute(a0, g);
       loadA(a0, Anx, 0);
     }
+    if constexpr (ACC == 1 && RT <= 2) {
+      // X_i += result: per row tile, all loads of X_i (unconditional), then the stores.  (With
+      // four row tiles the registers are short; those take the combined loop below.)
 #pragma unroll
-    for (int t = 0; t < RT; ++t) {
-      const int row0 = rb + 16 * t + 4 * (L >> 4);
+      for (int t = 0; t < RT; ++t) {
+        const int row0 = rb + 16 * t + 4 * (L >> 4);
+        double d[CT][4];
 #pragma unroll
-      for (int c = 0; c < CT; ++c) {
-        const int col = col0 + 16 * c + (L & 15);
-        if (col >= K) continue;
+        for (int c = 0; c < CT; ++c) {
+          const int col = col0 + 16 * c + (L & 15);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = row0 + v;
-          if (row < M) {
-            double* xp = a.X + i * M + row + (int64_t)col * a.ldx;
-            const double d = (double)acc[t][c][v] + (double)wv[t][c][v];
-            *xp = a.accumulate ? *xp + d : d;
+          for (int v = 0; v < 4; ++v) {
+            const bool ok = row0 + v < M && col < K;
+            const double x = a.X[ok ? i * M + row0 + v + (int64_t)col * a.ldx : 0];
+            d[c][v] = ok ? x : 0.0;
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+          const int col = col0 + 16 * c + (L & 15);
+          if (col >= K) continue;
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (row0 + v < M)
+              a.X[i * M + row0 + v + (int64_t)col * a.ldx] = d[c][v] + ((double)acc[t][c][v] + (double)wv[t][c][v]);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int row0 = rb + 16 * t + 4 * (L >> 4);
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+          const int col = col0 + 16 * c + (L & 15);
+          if (col >= K) continue;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int row = row0 + v;
+            if (row < M) {
+              double* xp = a.X + i * M + row + (int64_t)col * a.ldx;
+              const double d = (double)acc[t][c][v] + (double)wv[t][c][v];
+              *xp = (ACC == 1 || (ACC < 0 && a.accumulate)) ? *xp + d : d;
+            }
           }
         }
       }
@@ -573,22 +628,28 @@ __device__ __forceinline__ void sweep_f64_tile(const SweepArgs& a, int s, int ct
     }
     // operands of the epilogue, fetched before the last two chunks: F_{i+1} and a_{i+1}
     // (forward), G_i (forward, dense A) or beta_i (backward)
+    // The loads are unconditional (lanes outside the matrix read element 0 of the source and
+    // discard it): a load under a per-lane branch makes the compiler wait for every
+    // outstanding load, the prefetched matrix chunks included, before the next one.
     double ex[RT][CT], an[RT];
     const bool more = fwd && i < last && !dense;
+    const bool useF = fwd && !dense;
+    const double* __restrict__ esrc = useF ? (more ? a.F + (i + 1) * M : a.F) : a.W + i * Mp;
+    const int64_t eld = useF ? a.ldf : a.ldw;
+    const int erows = useF ? (more ? M : 0) : Mp;
+    const int rmax = erows > 0 ? erows - 1 : 0;   // indices clamped into the operand
+    const double* __restrict__ asrc = a.adiag + (more ? (i + 1) * Mp : 0);
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
       const int row = rb + 16 * t + out_row(L);
-      an[t] = more ? a.adiag[(i + 1) * Mp + row] : 0.0;
+      const double av = asrc[row];
+      an[t] = more ? av : 0.0;
 #pragma unroll
       for (int c = 0; c < CT; ++c) {
         const int col = col0 + out_col(L) * CT + c;
-        double v = 0.0;
-        if (fwd && !dense) {
-          if (more && row < M && col < K) v = a.F[(i + 1) * M + row + (int64_t)col * a.ldf];
-        } else if (col < K) {
-          v = a.W[i * Mp + row + (int64_t)col * a.ldw];
-        }
-        ex[t][c] = v;
+        const bool ok = row < erows && col < K;
+        const double v = esrc[min(row, rmax) + (int64_t)min(col, K - 1) * eld];
+        ex[t][c] = ok ? v : 0.0;
       }
     }
     loadA(a1, Ai, nkc - 1);
@@ -704,6 +765,8 @@ __device__ __forceinline__ void superpose_f64_tile(const SupArgs& a, int s, int 
       loadA(a0, Ai, kc + 2);
       compute(a1, kc + 1, false);
     }
+    // W_i (and X_i when accumulating) fetched before the last two chunks, by unconditional
+    // loads (out-of-range lanes read element 0 and discard it; see the sweep's epilogue)
     double ex[RT][CT];
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
@@ -711,13 +774,28 @@ __device__ __forceinline__ void superpose_f64_tile(const SupArgs& a, int s, int 
 #pragma unroll
       for (int c = 0; c < CT; ++c) {
         const int col = col0 + out_col(L) * CT + c;
-        ex[t][c] = (col < K) ? a.W[i * Mp + row + (int64_t)col * a.ldw] : 0.0;
+        const bool ok = col < K;
+        const double v = a.W[ok ? i * Mp + row + (int64_t)col * a.ldw : 0];
+        ex[t][c] = ok ? v : 0.0;
       }
     }
     loadA(a1, Ai, nkc - 1);
     compute(a0, nkc - 2, false);
     loadA(a0, Anx, 0);
     compute(a1, nkc - 1, true);
+    if (a.accumulate) {   // X_i += result: all loads of X_i first (unconditional), then the stores
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int row = rb + 16 * t + out_row(L);
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+          const int col = col0 + out_col(L) * CT + c;
+          const bool ok = row < M && col < K;
+          const double v = a.X[ok ? i * M + row + (int64_t)col * a.ldx : 0];
+          ex[t][c] += ok ? v : 0.0;
+        }
+      }
+    }
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
       const int row = rb + 16 * t + out_row(L);
@@ -725,11 +803,7 @@ __device__ __forceinline__ void superpose_f64_tile(const SupArgs& a, int s, int 
 #pragma unroll
         for (int c = 0; c < CT; ++c) {
           const int col = col0 + out_col(L) * CT + c;
-          if (col < K) {
-            double* xp = a.X + i * M + row + (int64_t)col * a.ldx;
-            const double d = acc[t][c] + ex[t][c];
-            *xp = a.accumulate ? *xp + d : d;
-          }
+          if (col < K) a.X[i * M + row + (int64_t)col * a.ldx] = acc[t][c] + ex[t][c];
         }
       }
     }
