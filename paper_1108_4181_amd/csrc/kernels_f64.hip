@@ -65,6 +65,7 @@ template <int RT>
 static hipError_t launch_bgemm_rt(const BArgs& a0, hipStream_t st) {
   BArgs a = a0;
   const int nthr = a.Mp / (16 * RT) * 64;
+  if (nthr < 64 * RT) return hipErrorInvalidValue;   // the tile stages B with at least 64 RT threads
   const int kt = bgemm_coltile(a.ncols);
   a.ncoltiles = (a.ncols + kt - 1) / kt;
   a.total = a.nprob * a.ncoltiles;

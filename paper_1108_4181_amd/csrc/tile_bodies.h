@@ -12,7 +12,8 @@ __device__ __forceinline__ void bgemm_tile(const BArgs& args, int prob, int ct, 
   constexpr int KC = 16;
   constexpr int KT = 4 * CT;
   constexpr int SB = KT + 2;
-  constexpr int NSTG = (KC * KT + 63) / 64;
+  // staging slots per thread for one B chunk; every caller runs at least 64 RT threads
+  constexpr int NSTG = (KC * KT + 64 * RT - 1) / (64 * RT);
   double* Bs0 = lds;              // [2][KC * SB]
 
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -31,25 +32,34 @@ __device__ __forceinline__ void bgemm_tile(const BArgs& args, int prob, int ct, 
 
   const int nch = d.kd / KC;
   double stg[NSTG];
+  // B chunk loads are unconditional, their indices clamped into the operand (values read there
+  // are discarded): a load under a per-lane branch makes the compiler wait for every outstanding
+  // load, the prefetched A chunks included, before the next one.
+  const int krows = args.brows > 0 ? args.brows : d.segrows;
   auto gload = [&](int q) {
     const int k0 = q * KC;
     const int seg = k0 / d.segrows;
     const int kin = k0 - seg * d.segrows;
     const double* Bq = args.B + d.b_off + (int64_t)seg * d.bseg + kin;
+    bool ok[NSTG];
 #pragma unroll
     for (int u = 0; u < NSTG; ++u) {
       const int e = tid + u * nthr;
-      double v = 0.0;
-      if (e < KC * KT) {
-        const int k = e % KC, c = e / KC;
-        const int col = col0 + c;
-        if (col < args.ncols && (args.brows <= 0 || kin + k < args.brows)) {
-          v = Bq[k + (int64_t)col * args.ldb];
-          if (args.bscale) v *= args.bscale[d.bs_off + k0 + k];
-        }
-      }
-      stg[u] = v;
+      const int ec = min(e, KC * KT - 1);
+      const int k = ec % KC, c = ec / KC;
+      const int col = col0 + c;
+      ok[u] = e < KC * KT && col < args.ncols && kin + k < krows;
+      stg[u] = Bq[(int64_t)min(col, args.ncols - 1) * args.ldb + min(k, krows - 1 - kin)];
     }
+    if (args.bscale) {
+#pragma unroll
+      for (int u = 0; u < NSTG; ++u) {
+        const int k = min(tid + u * nthr, KC * KT - 1) % KC;
+        stg[u] *= args.bscale[d.bs_off + k0 + k];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NSTG; ++u) stg[u] = ok[u] ? stg[u] : 0.0;
   };
   auto lstore = [&](int buf) {
 #pragma unroll
@@ -113,26 +123,62 @@ __device__ __forceinline__ void bgemm_tile(const BArgs& args, int prob, int ct, 
 #pragma unroll
       for (int c = 0; c < CT; ++c) {
         const int col = col0 + out_col(L) * CT + c;
-        pv[c] = (col < args.ncols) ? sp[rb + 16 * t + out_row(L) + (int64_t)col * args.ldsp] : 0.0;
+        const double v = sp[rb + 16 * t + out_row(L) + (int64_t)min(col, args.ncols - 1) * args.ldsp];
+        pv[c] = (col < args.ncols) ? v : 0.0;
       }
 #pragma unroll
       for (int c = 0; c < CT; ++c) acc[t][c] += pv[c];
     }
   }
+  // epilogue: the addends (Cin, and X2 when accumulating) are loaded for the whole tile first, by
+  // unconditional loads with clamped indices, then the stores
 #pragma unroll
-  for (int t = 0; t < RT; ++t) {
-    const int row = rb + 16 * t + out_row(L);
+  for (int t = 0; t < RT; ++t)
 #pragma unroll
-    for (int c = 0; c < CT; ++c) {
-      const int col = col0 + out_col(L) * CT + c;
-      if (col < args.ncols) {
-        double v = args.alpha * acc[t][c];
-        if (args.Cin) v += args.Cin[d.cin_off + row + (int64_t)col * args.ldcin];
-        if (args.C) args.C[d.c_off + row + (int64_t)col * args.ldc] = v;
-        if (args.X2 && row < args.x2rows) {
-          double* xp = args.X2 + d.x2_off + row + (int64_t)col * args.ldx2;
-          *xp = args.x2accum ? *xp + v : v;
+    for (int c = 0; c < CT; ++c) acc[t][c] *= args.alpha;
+  if (args.Cin) {
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int row = rb + 16 * t + out_row(L);
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const int col = col0 + out_col(L) * CT + c;
+        const double v = args.Cin[d.cin_off + row + (int64_t)min(col, args.ncols - 1) * args.ldcin];
+        acc[t][c] += (col < args.ncols) ? v : 0.0;
+      }
+    }
+  }
+  if (args.C) {
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int row = rb + 16 * t + out_row(L);
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const int col = col0 + out_col(L) * CT + c;
+        if (col < args.ncols) args.C[d.c_off + row + (int64_t)col * args.ldc] = acc[t][c];
+      }
+    }
+  }
+  if (args.X2) {
+    if (args.x2accum) {
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int row = rb + 16 * t + out_row(L);
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+          const int col = col0 + out_col(L) * CT + c;
+          const double v = args.X2[d.x2_off + min(row, args.x2rows - 1) + (int64_t)min(col, args.ncols - 1) * args.ldx2];
+          acc[t][c] += (row < args.x2rows && col < args.ncols) ? v : 0.0;
         }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int row = rb + 16 * t + out_row(L);
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const int col = col0 + out_col(L) * CT + c;
+        if (col < args.ncols && row < args.x2rows) args.X2[d.x2_off + row + (int64_t)col * args.ldx2] = acc[t][c];
       }
     }
   }
