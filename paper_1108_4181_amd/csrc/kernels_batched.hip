@@ -35,7 +35,9 @@ __device__ __forceinline__ bool wait_counter(const int32_t* c, int32_t need, int
 }
 
 template <int RT>
-__device__ void run_item(const BatchItem& it, const BatchSys& S, uint4* lds, double (*red)[4], int32_t* conv) {
+// kept out of line: the three instances inlined into one kernel would share one register budget
+__device__ __attribute__((noinline)) void run_item(const BatchItem& it, const BatchSys& S, uint4* lds, double (*red)[4],
+                                                   int32_t* conv) {
   const int tid = threadIdx.x;
   switch (it.type) {
     case BI_SWEEP: {

@@ -119,6 +119,11 @@ static hipError_t launch_sweep_lp_cfg(const LpSweepArgs& a0, hipStream_t st) {
 
 template <int PREC, int RT, int CT>
 static hipError_t launch_sweep_lp_ku(const LpSweepArgs& a, hipStream_t st) {
+  // four row tiles of two or more column tiles: chunks of four k-groups would spill registers
+  if constexpr (RT == 4 && CT >= 2) {
+    if (lp_chunk<PREC>(a.Mp / LP<PREC>::KG) >= 2) return launch_sweep_lp_cfg<PREC, RT, CT, 2>(a, st);
+    return launch_sweep_lp_cfg<PREC, RT, CT, 1>(a, st);
+  }
   switch (lp_chunk<PREC>(a.Mp / LP<PREC>::KG)) {
     case 4: return launch_sweep_lp_cfg<PREC, RT, CT, 4>(a, st);
     case 2: return launch_sweep_lp_cfg<PREC, RT, CT, 2>(a, st);

@@ -49,7 +49,9 @@ __device__ __forceinline__ void bgemm_tile(const BArgs& args, int prob, int ct, 
       const int k = ec % KC, c = ec / KC;
       const int col = col0 + c;
       ok[u] = e < KC * KT && col < args.ncols && kin + k < krows;
-      stg[u] = Bq[(int64_t)min(col, args.ncols - 1) * args.ldb + min(k, krows - 1 - kin)];
+      stg[u] = 0.0;
+      // (uniform: slots beyond the chunk exist only with more than 64 RT threads)
+      if (u == 0 || u * nthr < KC * KT) stg[u] = Bq[(int64_t)min(col, args.ncols - 1) * args.ldb + min(k, krows - 1 - kin)];
     }
     if (args.bscale) {
 #pragma unroll
