@@ -119,12 +119,18 @@ static hipError_t launch_sweep_lp_cfg(const LpSweepArgs& a0, hipStream_t st) {
 
 template <int PREC, int RT, int CT>
 static hipError_t launch_sweep_lp_ku(const LpSweepArgs& a, hipStream_t st) {
+  const int ngroups = a.Mp / LP<PREC>::KG;
   // four row tiles of two or more column tiles: chunks of four k-groups would spill registers
   if constexpr (RT == 4 && CT >= 2) {
-    if (lp_chunk<PREC>(a.Mp / LP<PREC>::KG) >= 2) return launch_sweep_lp_cfg<PREC, RT, CT, 2>(a, st);
+    if (lp_chunk<PREC>(ngroups) >= 2) return launch_sweep_lp_cfg<PREC, RT, CT, 2>(a, st);
     return launch_sweep_lp_cfg<PREC, RT, CT, 1>(a, st);
   }
-  switch (lp_chunk<PREC>(a.Mp / LP<PREC>::KG)) {
+  // float32 sweeps of at most two row tiles: four groups ahead (the epilogue's loads then
+  // stay in flight together; 3.31 -> 3.16 ms at 2048x256)
+  if constexpr (PREC == 1 && RT <= 2 && CT == 4) {
+    if (ngroups % 4 == 0) return launch_sweep_lp_cfg<PREC, RT, CT, 4>(a, st);
+  }
+  switch (lp_chunk<PREC>(ngroups)) {
     case 4: return launch_sweep_lp_cfg<PREC, RT, CT, 4>(a, st);
     case 2: return launch_sweep_lp_cfg<PREC, RT, CT, 2>(a, st);
     default: return launch_sweep_lp_cfg<PREC, RT, CT, 1>(a, st);
