@@ -83,6 +83,29 @@ def test_f64_plan_refine_is_noop(td):
     assert info["iterations"] == 0 and info["max_col_rel_residual"] < 1e-14
 
 
+def test_f64_correction_pass_adds_to_x(td):
+    """An unreachable tolerance forces one correction pass on a float64 plan: the superposition and
+    the dichotomy's last level then add to X (their accumulating forms), and X must stay the
+    float64 solution."""
+    sys = synth.varcoef_system(70, 40, seed=36)
+    F = synth.rhs_columns(36, 70, 40, range(37))
+    plan = td.Plan.from_system(sys, subdomains=6)
+    X, info = plan.solve(_dev(F), refine={"tol": 1e-300, "max_iter": 1}, info=True)
+    assert info["iterations"] == 1 and not info["converged"]
+    assert rel_err(X.cpu().numpy(), oracle.solve(sys, F)) < 1e-12
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("N,M,K,p", [(3, 1, 1, 1), (9, 5, 1, 3), (12, 33, 2, 4)])
+def test_refined_degenerate_sizes(td, prec, N, M, K, p):
+    sys = synth.varcoef_system(N, M, seed=300 + N + M)
+    F = synth.rhs_columns(300 + N + M, N, M, range(K))
+    plan = td.Plan.from_system(sys, subdomains=p, sweep_prec=prec)
+    X, info = plan.solve(_dev(F), refine={"tol": 1e-10, "max_iter": 12}, info=True)
+    assert info["converged"] and info["max_col_rel_residual"] <= 1e-10
+    assert rel_err(X.cpu().numpy(), oracle.solve(sys, F)) < 1e-9
+
+
 def test_noconvergence_reported(td):
     """max_iter = 1 with a bfloat16 plan cannot reach 1e-14: TD_ENOCONV (reported through info)."""
     sys = synth.varcoef_system(64, 32, seed=35)

@@ -59,6 +59,20 @@ def test_varcoef_shapes(td, N, M, K, p):
     assert rel_err(X, oracle.solve(sys, F)) < TOL
 
 
+@pytest.mark.parametrize("N,M,K,p", [
+    (1, 1, 1, 1),        # one block row: the reduced system is the whole problem
+    (2, 1, 1, 2),        # scalar blocks, every row an interface
+    (3, 1, 2, 1),        # scalar blocks, one subdomain with interior rows
+    (5, 3, 1, 2),        # one right-hand side (column indices clamp to 0 in the epilogues)
+    (7, 17, 1, 3),       # one row beyond a 16-row tile (padded to 32)
+])
+def test_degenerate_sizes(td, N, M, K, p):
+    sys = synth.varcoef_system(N, M, seed=200 + N + M)
+    F = synth.rhs_columns(200 + N + M, N, M, range(K))
+    _, X = _solve(td, sys, F, p)
+    assert rel_err(X, oracle.solve(sys, F)) < TOL
+
+
 def test_block_150(td):
     """M = 150 (one of the paper's block sizes): padded to 160."""
     sys = synth.varcoef_system(48, 150, seed=7)
