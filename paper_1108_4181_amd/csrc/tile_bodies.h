@@ -7,6 +7,22 @@
 
 namespace td {
 
+// Position of column c in a row of a 4 CT-column float64 operand staged in LDS.  A lane reads the
+// CT columns of block L % 4 of a row, 16 bytes at a time; the four blocks are interleaved in
+// 16-byte pairs so that the lanes of one read touch one 64-byte span (with the blocks side by side
+// they sit 64 bytes apart and two of them share LDS banks).  The epilogue's writes of column pairs
+// are 16-byte stores that are conflict-free too.
+template <int CT>
+__device__ __forceinline__ int lds_col(int c) {
+  static_assert(CT % 2 == 0, "column blocks are stored in pairs");
+  return ((c % CT) >> 1) * 8 + 2 * (c / CT) + (c & 1);
+}
+
+// Physical row of row k of such an operand (rows come in groups of 16).  One MFMA k-step reads
+// rows 4m .. 4m+3; they are stored 4 rows apart (row 4m+j at 16 (m/4) + 4 j + m % 4), which puts
+// the sixteen 16-byte pieces a k-step reads (four rows, four column blocks) in distinct LDS banks.
+__device__ __forceinline__ int lds_row(int k) { return (k & ~15) + 4 * (k & 3) + ((k >> 2) & 3); }
+
 template <int RT, int CT>
 __device__ __forceinline__ void bgemm_tile(const BArgs& args, int prob, int ct, double* lds) {
   constexpr int KC = 16;
@@ -69,7 +85,7 @@ __device__ __forceinline__ void bgemm_tile(const BArgs& args, int prob, int ct, 
       const int e = tid + u * nthr;
       if (e < KC * KT) {
         const int k = e % KC, c = e / KC;
-        Bs0[buf * KC * SB + k * SB + c] = stg[u];
+        Bs0[buf * KC * SB + lds_row(k) * SB + lds_col<CT>(c)] = stg[u];
       }
     }
   };
@@ -88,10 +104,15 @@ __device__ __forceinline__ void bgemm_tile(const BArgs& args, int prob, int ct, 
   auto compute = [&](const double (&av)[2][RT], int buf, int half) {
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      const double* bp = &Bs0[buf * KC * SB + (8 * half + 4 * u + (L >> 4)) * SB + (L & 3) * CT];
+      // rows 4m + L/16 of the chunk, m = 2 half + u (see lds_row, lds_col)
+      const double* bp = &Bs0[buf * KC * SB + (4 * (L >> 4) + 2 * half + u) * SB + 2 * (L & 3)];
       double b[CT];
 #pragma unroll
-      for (int c = 0; c < CT; ++c) b[c] = bp[c];
+      for (int c = 0; c < CT; c += 2) {
+        const double2 v = *reinterpret_cast<const double2*>(bp + (c >> 1) * 8);
+        b[c] = v.x;
+        b[c + 1] = v.y;
+      }
 #pragma unroll
       for (int t = 0; t < RT; ++t)
 #pragma unroll
@@ -639,10 +660,15 @@ __device__ __forceinline__ void sweep_f64_tile(const SweepArgs& a, int s, int ct
   auto compute = [&](const double (&av)[KU][RT], int q) {
 #pragma unroll
     for (int u = 0; u < KU; ++u) {
-      const double* bp = &In[(4 * KU * q + 4 * u + (L >> 4)) * SB + (L & 3) * CT];
+      const int m = KU * q + u;   // rows 4m + L/16 (see lds_row)
+      const double* bp = &In[(16 * (m >> 2) + 4 * (L >> 4) + (m & 3)) * SB + 2 * (L & 3)];
       double b[CT];
 #pragma unroll
-      for (int c = 0; c < CT; ++c) b[c] = bp[c];
+      for (int c = 0; c < CT; c += 2) {
+        const double2 v = *reinterpret_cast<const double2*>(bp + (c >> 1) * 8);
+        b[c] = v.x;
+        b[c + 1] = v.y;
+      }
 #pragma unroll
       for (int t = 0; t < RT; ++t)
 #pragma unroll
@@ -654,7 +680,7 @@ __device__ __forceinline__ void sweep_f64_tile(const SweepArgs& a, int s, int ct
   for (int e = tid; e < Mp * KT; e += nthr) {
     const int row = e % Mp, c = e / Mp;
     const int col = col0 + c;
-    In[row * SB + c] = (!dense && row < M && col < K) ? a.F[first * M + row + (int64_t)col * a.ldf] : 0.0;
+    In[lds_row(row) * SB + lds_col<CT>(c)] = (!dense && row < M && col < K) ? a.F[first * M + row + (int64_t)col * a.ldf] : 0.0;
   }
   loadA(a0, step_matrix(0), 0);
   __syncthreads();
@@ -708,17 +734,20 @@ __device__ __forceinline__ void sweep_f64_tile(const SweepArgs& a, int s, int ct
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
       const int row = rb + 16 * t + out_row(L);
+      double nx[CT];
 #pragma unroll
       for (int c = 0; c < CT; ++c) {
-        const int lc = out_col(L) * CT + c;
-        const int col = col0 + lc;
+        const int col = col0 + out_col(L) * CT + c;
         // forward: beta_i; next operand F_{i+1} + a_{i+1} o beta_i (or beta_last = W_last)
         // forward, dense A: beta_i = E_i beta_{i-1} + G_i; next operand beta_i
         // backward: W_i = alpha_i W_{i+1} + beta_i
         const double v = (fwd && !dense) ? acc[t][c] : acc[t][c] + ex[t][c];
         if (col < K) a.W[i * Mp + row + (int64_t)col * a.ldw] = v;
-        In[row * SB + lc] = more ? ex[t][c] + an[t] * v : v;
+        nx[c] = more ? ex[t][c] + an[t] * v : v;
       }
+      double* ip = &In[lds_row(row) * SB + 2 * out_col(L)];
+#pragma unroll
+      for (int c = 0; c < CT; c += 2) *reinterpret_cast<double2*>(ip + (c >> 1) * 8) = make_double2(nx[c], nx[c + 1]);
     }
     __syncthreads();
   }
@@ -748,7 +777,7 @@ __device__ __forceinline__ void superpose_f64_tile(const SupArgs& a, int s, int 
   for (int e = tid; e < kd * KT; e += nthr) {
     const int k = e % kd, c = e / kd;
     const int col = col0 + c;
-    Xs[k * SB + c] = (col < K) ? a.Xi[(int64_t)(s + 1) * Mp + k + (int64_t)col * a.ldxi] : 0.0;
+    Xs[lds_row(k) * SB + lds_col<CT>(c)] = (col < K) ? a.Xi[(int64_t)(s + 1) * Mp + k + (int64_t)col * a.ldxi] : 0.0;
   }
 
   const int64_t lane_off = rb + (L & 15) + (int64_t)(L >> 4) * Mp;
@@ -760,12 +789,16 @@ __device__ __forceinline__ void superpose_f64_tile(const SupArgs& a, int s, int 
 #pragma unroll
       for (int t = 0; t < RT; ++t) dst[u][t] = pa[16 * t + (int64_t)(4 * u) * Mp];
   };
-  const double* Bl = &Xs[(L >> 4) * SB + (L & 3) * CT];
+  const double* Bl = &Xs[4 * (L >> 4) * SB + 2 * (L & 3)];   // block L % 4 (see lds_col, lds_row)
   double b0[CT], b1[CT];
-  auto ldB = [&](double (&b)[CT], int ks) {
-    const double* bp = Bl + 4 * ks * SB;
+  auto ldB = [&](double (&b)[CT], int ks) {   // rows 4 ks .. 4 ks + 3
+    const double* bp = Bl + (16 * (ks >> 2) + (ks & 3)) * SB;
 #pragma unroll
-    for (int c = 0; c < CT; ++c) b[c] = bp[c];
+    for (int c = 0; c < CT; c += 2) {
+      const double2 v = *reinterpret_cast<const double2*>(bp + (c >> 1) * 8);
+      b[c] = v.x;
+      b[c + 1] = v.y;
+    }
   };
   double acc[RT][CT];
   auto mm = [&](const double (&av)[RT], const double (&b)[CT]) {
