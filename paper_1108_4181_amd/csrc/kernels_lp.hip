@@ -109,7 +109,7 @@ static hipError_t launch_sweep_lp_cfg(const LpSweepArgs& a0, hipStream_t st) {
   if (a.total == 0) return hipSuccess;
   const int nthr = a.Mp / (16 * RT) * 64;
   const size_t esz = (PREC == 1) ? 4 : 2;
-  const size_t lds = (size_t)kt * ((size_t)a.Mp * esz + 16);
+  const size_t lds = (size_t)kt * ((size_t)a.Mp * esz + 32);
   hipError_t e = hipFuncSetAttribute((const void*)k_sweep_lp<PREC, RT, CT, KU>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -166,7 +166,7 @@ static hipError_t launch_sup_lp_cfg(const LpSupArgs& a0, hipStream_t st) {
   if (a.total == 0) return hipSuccess;
   const int nthr = a.Mp / (16 * RT) * 64;
   const size_t esz = (PREC == 1) ? 4 : 2;
-  const size_t lds = (size_t)kt * ((size_t)2 * a.Mp * esz + 16);
+  const size_t lds = (size_t)kt * ((size_t)2 * a.Mp * esz + 32);
   // separate kernels for writing and for adding to X (the first pass of a solve writes)
   const void* fn = a.accumulate ? (const void*)k_superpose_lp<PREC, RT, CT, KU, 1>
                                 : (const void*)k_superpose_lp<PREC, RT, CT, KU, 0>;
@@ -196,7 +196,7 @@ static hipError_t launch_sup_lp_ku(const LpSupArgs& a, hipStream_t st) {
 template <int PREC, int RT>
 static hipError_t launch_sup_lp_rt(const LpSupArgs& a, hipStream_t st) {
   const size_t esz = (PREC == 1) ? 4 : 2;
-  const size_t lds4 = (size_t)64 * ((size_t)2 * a.Mp * esz + 16);
+  const size_t lds4 = (size_t)64 * ((size_t)2 * a.Mp * esz + 32);
   if (a.K <= 16) return launch_sup_lp_ku<PREC, RT, 1>(a, st);
   if (a.K <= 32 || lds4 > 160 * 1024) return launch_sup_lp_ku<PREC, RT, 2>(a, st);
   return launch_sup_lp_ku<PREC, RT, 4>(a, st);

@@ -218,7 +218,9 @@ __device__ __forceinline__ void sweep_lp_tile(const LpSweepArgs& a, int s, int c
   static_assert(W32_PANEL % KT == 0, "a column tile must lie in one workspace panel");
   T* In = reinterpret_cast<T*>(lds_raw);     // [KT][SK]
   const int Mp = a.Mp, M = a.M, K = a.K;
-  const int SK = Mp + 16 / (int)sizeof(T);   // column stride (elements), padded by 16 bytes
+  // column stride (elements), padded by 32 bytes: with a stride of 32 (mod 64) bytes the 16-byte
+  // pieces that 32 lanes read of 16 columns and two k-groups lie in distinct LDS banks
+  const int SK = Mp + 32 / (int)sizeof(T);
 
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int L = tid & 63, w = tid >> 6;
@@ -381,7 +383,7 @@ __device__ __forceinline__ void superpose_lp_tile(const LpSupArgs& a, int s, int
   T* Xs = reinterpret_cast<T*>(lds_raw);   // [KT][SK]
   const int Mp = a.Mp, M = a.M, K = a.K;
   const int kd = 2 * Mp;
-  const int SK = kd + 16 / (int)sizeof(T);
+  const int SK = kd + 32 / (int)sizeof(T);   // padded by 32 bytes (see the sweep tile)
 
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int L = tid & 63, w = tid >> 6;
