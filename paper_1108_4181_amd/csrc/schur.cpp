@@ -205,7 +205,10 @@ td_status schur_create(int64_t N, int64_t M, const double* A, const double* B, c
     double* Ci = S->dalloc<double>(S->Nint * 3 * M, tmp.v);
     SCHK(launch_schur_interior_coeffs(Ai, Bi, Ci, S->cA, S->cB, S->cC, S->d_intcol, S->Nint, (int)M, st));
     td_desc d{};
-    d.N = S->Nint; d.M = M; d.subdomains = std::max<int64_t>(1, S->Nint / 32);
+    // subdomains of 16 rows: CG applies S to few columns (tens), so the sweeps need many
+    // subdomains to fill the GPU (2047x256, K = 64: 28 ms per CG solve against 41 ms with 32 rows
+    // and 31 ms with 8)
+    d.N = S->Nint; d.M = M; d.subdomains = std::max<int64_t>(1, S->Nint / 16);
     d.fmt_A = TD_FMT_DIAG; d.fmt_B = TD_FMT_DIAG; d.fmt_C = TD_FMT_TRIDIAG; d.sweep_prec = TD_PREC_F64;
     td_status fs = tridiag_factor(&d, Ai, Bi, Ci, st, &S->interior);
     tmp.release();
