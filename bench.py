@@ -231,7 +231,7 @@ def bench_band(args):
     F = synth.rhs_torch(4243, n, 1, K, dev)
     M = max(kl, ku, 1)
     N = -(-n // M)
-    p = args.subdomains or max(1, N // 32)
+    p = args.subdomains or td.choose_subdomains(N, M, K)
     t0 = time.perf_counter()
     solver = td.BandSolver(ab, kl, ku, subdomains=p)
     torch.cuda.synchronize()

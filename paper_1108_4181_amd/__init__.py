@@ -428,10 +428,22 @@ class SchurSolver:
             pass
 
 
+def default_length(N: int, K: int) -> int:
+    """Subdomain length without an autotuned entry: the longest of 32, 16, 8 rows that still gives
+    the sweeps about 512 work-groups (two per compute unit; one per subdomain and 32-column tile),
+    so that few right-hand sides still fill the GPU."""
+    tiles = max(1, (K + 31) // 32)
+    for L in (32, 16):
+        if (N // L) * tiles >= 512:
+            return L
+    return 8
+
+
 def choose_subdomains(N: int, M: int, K: int, sweep_prec: str = "f64") -> int:
     """Subdomain count for an N x M system with K right-hand sides: N / L with the subdomain length
-    L chosen by the autotuner's cached result for (M, K bucket, precision) when present, else 32."""
-    L = autotuned_length(M, K, sweep_prec)
+    L chosen by the autotuner's cached result for (M, K bucket, precision) when present, else
+    default_length(N, K)."""
+    L = autotuned_length(M, K, sweep_prec, default=default_length(N, K))
     return max(1, min(N, N // L))
 
 

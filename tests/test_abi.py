@@ -123,3 +123,17 @@ def test_schur_null_handles(lib):
     assert lib.tridiag_schur_solve(None, None, 0, None, 0, 1, ctypes.c_double(0.0), 0, None, None) == 1
     assert lib.tridiag_schur_apply(None, None, 0, None, 0, 1, None) == 1
     assert lib.tridiag_schur_destroy(None) == 0
+
+
+def test_default_subdomain_length_fills_the_gpu(tmp_path, monkeypatch):
+    """Without an autotuned entry the subdomain length is the longest of 32, 16, 8 rows that gives
+    the sweeps about 512 work-groups (subdomains x 32-column tiles)."""
+    import paper_1108_4181_amd as td
+
+    monkeypatch.setenv("TD_AUTOTUNE_CACHE", str(tmp_path / "none.json"))
+    assert td.default_length(2048, 512) == 32      # 64 subdomains x 16 tiles
+    assert td.default_length(1093, 256) == 16      # 34 x 8 would be 272 work-groups
+    assert td.default_length(2032, 64) == 8
+    assert td.default_length(64, 8) == 8
+    assert td.choose_subdomains(1093, 60, 256) == 1093 // 16
+    assert td.choose_subdomains(4, 16, 1) == 1
