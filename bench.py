@@ -356,8 +356,8 @@ def main():
                     help="Schur-complement workload N,M,strips,K,probe band (with --workload schur)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is a design note, not part of this build", file=sys.stderr)
+        print(f"bench.py: the solver runs on one GPU (asked for --gpus {args.gpus}); sharding over "
+              "several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "batched_64":
