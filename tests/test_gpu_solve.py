@@ -73,6 +73,19 @@ def test_degenerate_sizes(td, N, M, K, p):
     assert rel_err(X, oracle.solve(sys, F)) < TOL
 
 
+@pytest.mark.parametrize("M", [16, 48, 96, 256])
+@pytest.mark.parametrize("K", [8, 16, 17, 64])
+def test_tile_forms(td, M, K):
+    """Every (row tiles, column tiles) form of the sweep and superposition kernels: blocks padded to
+    16, 48, 96 and 256 rows (one, two and four row tiles per wave) and 8, 16, 17 and 64 columns
+    (8-, 16- and 32-column tiles, one ragged); the LDS operand layout of each form is exercised."""
+    N, p = 24, 4
+    sys = synth.varcoef_system(N, M, seed=400 + M + K)
+    F = synth.rhs_columns(400 + M + K, N, M, range(K))
+    _, X = _solve(td, sys, F, p)
+    assert rel_err(X, oracle.solve(sys, F)) < TOL
+
+
 def test_block_150(td):
     """M = 150 (one of the paper's block sizes): padded to 160."""
     sys = synth.varcoef_system(48, 150, seed=7)
