@@ -216,6 +216,36 @@ hipError_t launch_superpose(const SupArgs& a, hipStream_t st) {
 // A pivot whose magnitude is not above 1e-14 times the infinity norm of the
 // matrix (or is NaN) marks the matrix singular.
 // ---------------------------------------------------------------------------
+// One step of a wave-wide arg-max: (v, i) against the (v, i) of the lane that the DPP control
+// CTRL selects (rows outside ROWMASK keep their own); larger v wins, ties go to the smaller i.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ void argmax_dpp_step(double& v, int& i) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int olo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xF, false);
+  const int ohi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xF, false);
+  const int oi = __builtin_amdgcn_update_dpp(i, i, CTRL, ROWMASK, 0xF, false);
+  const double ov = __hiloint2double(ohi, olo);
+  const bool take = (ov > v) | ((ov == v) & (oi < i));
+  v = take ? ov : v;
+  i = take ? oi : i;
+}
+
+// Wave-wide arg-max with DPP lane moves instead of LDS permutes (the pivot search sits on the
+// column-to-column critical path of the elimination): swaps within quads, half-row and row
+// mirrors, then row broadcasts leave the result in lane 63, which every lane reads.
+__device__ __forceinline__ void wave_argmax(double& v, int& i) {
+  argmax_dpp_step<0xB1, 0xF>(v, i);    // quad_perm [1,0,3,2]
+  argmax_dpp_step<0x4E, 0xF>(v, i);    // quad_perm [2,3,0,1]
+  argmax_dpp_step<0x141, 0xF>(v, i);   // row_half_mirror
+  argmax_dpp_step<0x140, 0xF>(v, i);   // row_mirror
+  argmax_dpp_step<0x142, 0xA>(v, i);   // row_bcast:15 into rows 1 and 3
+  argmax_dpp_step<0x143, 0xC>(v, i);   // row_bcast:31 into rows 2 and 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  v = __hiloint2double(hi, lo);
+  i = __builtin_amdgcn_readlane(i, 63);
+}
+
 template <int RT, int NT, int NB>
 __global__ void __launch_bounds__(NT) k_gj(GJArgs g) {
   constexpr int CT = 4;           // 16 columns per update tile
@@ -279,11 +309,7 @@ __global__ void __launch_bounds__(NT) k_gj(GJArgs g) {
         bv = (v == v) ? v : DBL_MAX;   // NaN ranks first so that it is reported
         bi = tid;
       }
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(bv, off);
-        const int oi = __shfl_xor(bi, off);
-        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-      }
+      wave_argmax(bv, bi);
       if (L == 0) { wv[16 * b + w] = bv; wi[16 * b + w] = bi; }
       __syncthreads();
       double b2 = wv[16 * b];
@@ -467,11 +493,7 @@ __global__ void __launch_bounds__(512) k_gj_big(GJArgs g) {
           if (vv > bv || (vv == bv && i < bi)) { bv = vv; bi = i; }
         }
       }
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(bv, off);
-        const int oi = __shfl_xor(bi, off);
-        if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-      }
+      wave_argmax(bv, bi);
       if (L == 0) { redv[w] = bv; redi[w] = bi; }
       __syncthreads();
       if (tid == 0) {
