@@ -30,8 +30,8 @@ PEAK_HBM = 8000.0      # GB/s
 # (profiles/sweep_superposition_varcoef_n2048_m256_k512.md).
 MEASURED_TRAFFIC = {
     # kernel: (workload, source hash (kernel_source_hash), read bytes, write bytes)
-    "sweep": ("varcoef_n2048_m256_k512", "901131aae1902c3f", 6.61146e9, 4.09993e9),
-    "superposition": ("varcoef_n2048_m256_k512", "901131aae1902c3f", 4.40890e9, 2.08037e9),
+    "sweep": ("varcoef_n2048_m256_k512", "acc9770f3ef82867", 6.61451e9, 4.09993e9),
+    "superposition": ("varcoef_n2048_m256_k512", "acc9770f3ef82867", 4.41027e9, 2.08037e9),
 }
 KERNEL_SOURCES = ["kernels_f64.hip", "tile_bodies.h", "device_common.h", "internal.h"]
 
