@@ -93,8 +93,23 @@ def algorithmic_work(N, M, K, p):
                 dich_flops=dich_flops, dich_bytes=dich_bytes, total_flops=sweep_flops + sup_flops + dich_flops)
 
 
-def cpu_baseline(w, rows, cols, threads):
-    """The CPU oracle (plain float64 block Thomas) on the leading `rows` block rows with `cols` RHS."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, rows, cols, cols_1t, threads):
+    """The CPU oracle (plain float64 block Thomas, OpenMP over right-hand sides) on a bounded sample of
+    the workload: the leading `rows` block rows of the same matrix (a truncated system; the oracle's
+    solve cost per right-hand side is linear in the number of block rows, so its time is scaled by
+    N / rows), with `cols` right-hand sides on `threads` threads and `cols_1t` on one thread.  The
+    factor (not part of the metric) is timed once, on `threads` threads."""
     import numpy as np
 
     import oracle
@@ -104,20 +119,43 @@ def cpu_baseline(w, rows, cols, threads):
     N, M = full.N, full.M
     rows = N if rows <= 0 else min(rows, N)
     sub = synth.System(rows, M, full.A[:rows], full.B[:rows], full.C[:rows], full.fmt_A, full.fmt_B, full.fmt_C)
-    F = synth.rhs_columns(w["seed"], N, M, range(cols))[:, : rows * M]
-    F = np.ascontiguousarray(F)
-    tf, ts, _ = oracle.timed_factor_solve(sub, F, threads)
+    F = np.ascontiguousarray(synth.rhs_columns(w["seed"], N, M, range(cols))[:, : rows * M])
+    t0 = time.perf_counter()
+    fac = oracle.Factor(sub, threads)
+    tf = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    fac.solve(F)
+    ts = time.perf_counter() - t0
+    fac.threads = 1
+    F1 = np.ascontiguousarray(F[:cols_1t])
+    t0 = time.perf_counter()
+    fac.solve(F1)
+    ts1 = time.perf_counter() - t0
     scale = N / rows
-    rhs_per_s = cols / (ts * scale)
+    per_rhs = ts * scale / cols
+    per_rhs_1t = ts1 * scale / cols_1t
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
     return {
-        "value": rhs_per_s,
+        "value": 1.0 / per_rhs,
         "unit": "RHS/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": (f"oracle block-Thomas factor + solve of {rows} of {N} block rows (M={M}) with {cols} of "
-                   f"{w['K']} right-hand sides" + (f"; solve time per RHS scaled x{scale:g} to N={N}" if rows < N else "")
-                   + f"; factor {tf:.2f} s, solve {ts:.2f} s; value = solved RHS / solve seconds"),
+        "sample": (f"oracle block-Thomas solve of the leading {rows} of {N} block rows (M={M}; same coefficients) "
+                   f"with {cols} of {w['K']} right-hand sides on {threads} threads and {cols_1t} on 1 thread; "
+                   f"solve seconds per right-hand side scaled x{scale:g} to N={N}"
+                   + (" (extrapolated)" if rows < N else "") + "; factor timed separately"),
+        "extrapolated": rows < N,
+        "value_1thread": 1.0 / per_rhs_1t,
+        "solve_s_per_rhs": per_rhs,
+        "solve_s_per_rhs_1thread": per_rhs_1t,
+        "sample_factor_s": tf,
         "factor_s_scaled": tf * scale,
+        "nproc": os.cpu_count(),
+        "affinity_cpus": affinity,
+        "cpu_model": _cpu_model(),
     }
 
 
@@ -339,10 +377,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="varcoef_n2048_m256_k512")
+    ap.add_argument("--workload", default="mixed_n4096_m512_k1024")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=0, help="block rows of the oracle sample (0 = all)")
+    ap.add_argument("--cpu-rows", type=int, default=256, help="block rows of the oracle sample (0 = all)")
     ap.add_argument("--cpu-cols", type=int, default=128, help="right-hand sides of the oracle sample")
+    ap.add_argument("--cpu-cols-1t", type=int, default=16, help="right-hand sides of the one-thread oracle sample")
     ap.add_argument("--mixed", default="f32,bf16",
                     help="low-precision sweep types to time with float64 refinement ('' = none)")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -415,11 +454,12 @@ def main():
     # the same solves launched eagerly with HIP events around every stage (per-kernel times)
     plan.set_profiling(True)
     torch.cuda.synchronize()
+    n_prof = max(1, min(args.steps, 10))
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(n_prof):
         plan.solve(F, X)
     torch.cuda.synchronize()
-    eager_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    eager_ms = (time.perf_counter() - t0) * 1e3 / n_prof
     stages = plan.stage_times()
     plan.set_profiling(False)
 
@@ -505,19 +545,24 @@ def main():
         _, minfo = mplan.solve(F, X, refine=ref, info=True)
         for _ in range(args.warmup):
             mplan.solve(F, X, refine=ref)
-        mplan.set_profiling(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
             mplan.solve(F, X, refine=ref)
         torch.cuda.synchronize()
         mel = time.perf_counter() - t0
-        mst = mplan.stage_times()
         mms = mel * 1e3 / args.steps
+        # stage times from separate, untimed solves with HIP events around every stage
+        mplan.set_profiling(True)
+        for _ in range(max(1, min(args.steps, 5))):
+            mplan.solve(F, X, refine=ref)
+        torch.cuda.synchronize()
+        mst = mplan.stage_times()
+        mplan.set_profiling(False)
         mixed[prec] = {"value": K / (mms / 1e3), "unit": "RHS/s", "ms_per_step": mms,
                        "speedup_vs_f64": ms_per_step / mms, "iterations": minfo["iterations"],
                        "max_col_rel_residual": minfo["max_col_rel_residual"], "factor_ms": mfac,
-                       "first_pass_stages_ms": {k: v for k, v in mst.items() if k != "count"}}
+                       "last_pass_stages_ms": {k: v for k, v in mst.items() if k != "count"}}
         mplan.close()
         del mplan
         plan = None
@@ -525,7 +570,8 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
 
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_rows, args.cpu_cols, oracle.default_threads())
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_rows, args.cpu_cols, args.cpu_cols_1t,
+                                           oracle.default_threads())
     print(json.dumps(out))
 
 

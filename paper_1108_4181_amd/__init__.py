@@ -155,9 +155,13 @@ class Plan:
     """A factored block-tridiagonal matrix (tridiag_factor) reusable for many right-hand sides."""
 
     def __init__(self, A, B, C, N, M, fmt_A="diag", fmt_B="diag", fmt_C="tridiag", subdomains=0,
-                 sweep_prec="f64", adjoint=False):
+                 sweep_prec="f64", adjoint=False, k_hint=512):
+        """subdomains = 0: choose_subdomains(N, M, k_hint, sweep_prec) (the autotuned length for the
+        expected number of right-hand sides per solve, else the library's default rule)."""
         self.lib = load_library()
         self.N, self.M = int(N), int(M)
+        if not subdomains:
+            subdomains = choose_subdomains(self.N, self.M, int(k_hint), sweep_prec)
         d = _Desc(self.N, self.M, int(subdomains), FMT[fmt_A], FMT[fmt_B], FMT[fmt_C], PREC[sweep_prec],
                   1 if adjoint else 0, 0)
         A, B, C = _dev(A, "A"), _dev(B, "B"), _dev(C, "C")

@@ -48,6 +48,43 @@ def make(name):
     print(f"{name}: oracle {time.time() - t0:.1f} s -> {path}")
 
 
+BATCH_LARGEST = 8        # systems of the batched workload with the most sweep work (N M^2 K)
+
+
+def largest_batch_shapes(count=BATCH_LARGEST):
+    """The `count` systems of the 64-system batched workload with the largest N M^2 K, in that order."""
+    return sorted(synth.batch_shapes(), key=lambda t: -t[0] * t[1] * t[1] * t[2])[:count]
+
+
+def make_batched(samples=500):
+    """Oracle samples for the largest systems of the batched workload (coefficients of the tiny
+    workload, C = tridiag(-1, 4.5, -1), A = B = I; right-hand sides from each system's seed):
+    columns 0, K//2 and K-1 of each."""
+    out = {"workload": "batched_64_largest", "generator": "tests/golden/make_golden.py (oracle block-Thomas, float64)",
+           "systems": []}
+    rng = np.random.default_rng(54321)
+    t0 = time.time()
+    for N, M, K, seed in largest_batch_shapes():
+        sys_ = synth.laplace_system(N, M, 4.5)
+        n = N * M
+        cols = [0, K // 2, K - 1]
+        F = synth.rhs_columns(seed, N, M, cols)
+        X = oracle.solve(sys_, F)
+        ent = {"N": N, "M": M, "K": K, "seed": seed, "samples": []}
+        for t, k in enumerate(cols):
+            idx = np.unique(np.concatenate([np.sort(rng.choice(n, samples, replace=False)), [0, n - 1]]))
+            ent["samples"].append({"column": k, "index": idx.tolist(), "value": [repr(float(v)) for v in X[t, idx]]})
+        out["systems"].append(ent)
+        print(f"  N={N} M={M} K={K}: {time.time() - t0:.1f} s", flush=True)
+    path = os.path.join(HERE, "batched_64_largest.json")
+    with open(path, "w") as f:
+        json.dump(out, f)
+    print(f"batched_64_largest -> {path}")
+
+
 if __name__ == "__main__":
     for name in (sys.argv[1:] or ["varcoef_n2048_m256_k512", "adjoint_n1024_m256_k256"]):
-        make(name)
+        if name == "batched_64_largest":
+            make_batched()
+        else:
+            make(name)

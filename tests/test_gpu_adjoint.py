@@ -128,3 +128,14 @@ def test_float32_gradient_refined(td, grad64):
     _, gs32, gF32 = _loss_grad(td, sigma, base, F, Xt, w["p"], prec="f32", refine={"tol": 1e-12, "max_iter": 10})
     assert rel_err(gs32, gs) <= 1e-8
     assert rel_err(gF32, gF) <= 1e-8
+
+
+def test_float32_gradient_unrefined(td, grad64):
+    """Float32 sweeps without refinement (forward and adjoint solves each carry float32 rounding of
+    the factor): gradients within 1e-4 of the float64 adjoint (finite differences at h = 1e-6 are
+    meaningless at float32 resolution, so the float64 gradient is the reference)."""
+    w, sigma, base, F, Xt, X, gs, gF = grad64
+    X32, gs32, gF32 = _loss_grad(td, sigma, base, F, Xt, w["p"], prec="f32", refine=None)
+    assert rel_err(X32, X) <= 1e-5
+    assert rel_err(gs32, gs) <= 1e-4
+    assert rel_err(gF32, gF) <= 1e-4

@@ -126,3 +126,60 @@ def test_batched_rejects_bf16_plans(td):
     with pytest.raises(td.TridiagError) as e:
         td.Batch([plan], [F], [torch.zeros_like(F)])
     assert e.value.code == 7
+
+
+def _stencil_residual(sysq, X, F):
+    """max over columns of ||F - P X|| / ||F|| for diagonal A, B and tridiagonal C, in plain torch
+    float64 on the device (written from the definition of P, independent of the library)."""
+    N, M = sysq.N, sysq.M
+    K = X.shape[0]
+    x = X.view(K, N, M)
+    a = torch.as_tensor(sysq.A, device=X.device)
+    b = torch.as_tensor(sysq.B, device=X.device)
+    c = torch.as_tensor(sysq.C, device=X.device)
+    px = c[:, 1, :] * x
+    px[:, :, 1:] += c[:, 0, 1:] * x[:, :, :-1]
+    px[:, :, :-1] += c[:, 2, :-1] * x[:, :, 1:]
+    px[:, 1:, :] -= a[1:] * x[:, :-1, :]
+    px[:, :-1, :] -= b[:-1] * x[:, 1:, :]
+    r = F.view(K, N, M) - px
+    return float((r.reshape(K, -1).norm(dim=1) / F.norm(dim=1)).max())
+
+
+def test_batched_largest_systems(td):
+    """The eight systems of the 64-system batched workload with the most sweep work (all M = 256;
+    N up to 3600, K up to 478) in one batch, float32 sweeps with float64 refinement, default
+    subdomain counts: every column's residual <= 1e-10 (plain torch stencil), and samples of
+    columns 0, K/2 and K-1 within 1e-9 of the oracle (tests/golden/batched_64_largest.json)."""
+    import json
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batched_64_largest.json")
+    with open(path) as f:
+        gold = json.load(f)
+    plans, Fs, Xs, systems = [], [], [], []
+    for ent in gold["systems"]:
+        N, M, K, seed = ent["N"], ent["M"], ent["K"], ent["seed"]
+        sysq = synth.laplace_system(N, M, 4.5)
+        plans.append(td.Plan.from_system(sysq, subdomains=td.choose_subdomains(N, M, K, "f32"), sweep_prec="f32"))
+        Fs.append(synth.rhs_torch(seed, N, M, K, "cuda"))
+        Xs.append(torch.zeros_like(Fs[-1]))
+        systems.append(sysq)
+    batch = td.Batch(plans, Fs, Xs, passes=3, tol=1e-10)
+    batch.solve()
+    infos, ok = batch.info()
+    assert ok, infos
+    worst = 0.0
+    for q, ent in enumerate(gold["systems"]):
+        assert infos[q]["max_col_rel_residual"] <= 1e-10
+        assert _stencil_residual(systems[q], Xs[q], Fs[q]) <= 1e-10
+        for smp in ent["samples"]:
+            idx = torch.as_tensor(smp["index"], dtype=torch.int64, device="cuda")
+            got = Xs[q][smp["column"]].index_select(0, idx).cpu().numpy()
+            ref = np.array([float(v) for v in smp["value"]])
+            worst = max(worst, float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
+    assert worst <= 1e-9, worst
+    batch.close()
+    for p in plans:
+        p.close()
+    del plans, Fs, Xs
+    torch.cuda.empty_cache()

@@ -89,6 +89,26 @@ def test_adjoint_workload_fullsize_forward_and_transpose(td):
     _check_samples(Lam, gold, 1e-12)
 
 
+def test_mixed_workload_fullsize_f64(td):
+    """The 4096 x 512 workload (K = 1024, 128 subdomains) solved in float64 as bench.py times it
+    (plain solve, replayed graph): samples against the oracle <= 1e-12, every column's residual
+    <= 1e-13 (checked by an eager solve with a report on the same plan)."""
+    name = "mixed_n4096_m512_k1024"
+    gold = _golden(name)
+    w, sys, F = _inputs(name)
+    plan = td.Plan.from_system(sys, subdomains=w["p"])
+    X = torch.empty_like(F)
+    plan.solve(F, X)                       # captured
+    plan.solve(F, X)                       # replayed
+    torch.cuda.synchronize()
+    _check_samples(X, gold, 1e-12)
+    Y, info = plan.solve(F, info=True)
+    assert info["max_col_rel_residual"] <= 1e-13 and info["nonfinite"] == 0
+    assert torch.equal(X, Y)
+    del plan, X, Y, F
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 def test_mixed_fullsize_refined(td, prec):
     name = "mixed_n4096_m512_k1024"

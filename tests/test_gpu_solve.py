@@ -172,3 +172,25 @@ def test_solve_graph_replays_match_eager(td):
     ref3, _ = plan.solve(F3, info=True)
     assert torch.equal(plan.solve(F3), ref3)
     assert rel_err(X.cpu().numpy(), oracle.solve(sys, F1.cpu().numpy())) <= TOL
+
+
+@pytest.mark.parametrize("M", [288, 384, 448, 512])
+@pytest.mark.parametrize("K", [17, 40])
+def test_large_blocks_f64(td, M, K):
+    """Block sizes above 256 (padded to 320, 384, 448 and 512): the superposition's four-row-tile
+    form and the sweep with five to eight waves of 64 rows, which the 4096 x 512 workload's float64
+    solve runs; one full and one ragged 32-column tile."""
+    N, p = 20, 4
+    sys = synth.varcoef_system(N, M, seed=500 + M + K)
+    F = synth.rhs_columns(500 + M + K, N, M, range(K))
+    _, X = _solve(td, sys, F, p)
+    assert rel_err(X, oracle.solve(sys, F)) < TOL
+
+
+def test_large_block_laplace_f64(td):
+    """The 4096 x 512 workload's coefficients (C = tridiag(-1, 4.5, -1), A = B = I) at a small N with
+    the same subdomain length (32 rows) and 64 right-hand sides."""
+    sys = synth.laplace_system(96, 512, 4.5)
+    F = synth.rhs_columns(31, 96, 512, range(64))
+    _, X = _solve(td, sys, F, 3)
+    assert rel_err(X, oracle.solve(sys, F)) < TOL
