@@ -35,6 +35,7 @@
 #ifndef TRIDIAG_H
 #define TRIDIAG_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -56,11 +57,27 @@ typedef enum { TD_FMT_DENSE = 0, TD_FMT_DIAG = 1, TD_FMT_TRIDIAG = 2 } td_format
 
 typedef enum { TD_PREC_F64 = 0, TD_PREC_F32 = 1, TD_PREC_BF16 = 2 } td_precision;
 
+/*
+ * Device memory callbacks (not in the paper).  When td_desc.dev_alloc and td_desc.dev_free are both
+ * set, every device buffer of the plan (factor, compact input copies, solve and refinement workspaces,
+ * the temporaries of the factor) is obtained from dev_alloc and returned through dev_free, so that a
+ * caller's caching allocator (for example PyTorch's) holds and accounts for it; both NULL: hipMalloc /
+ * hipFree.  dev_alloc(ctx, bytes, stream) returns a device pointer aligned to at least 256 bytes, or NULL
+ * when the memory is not available (the library then frees what it holds and returns TD_ENOMEM).
+ * `stream` is the hipStream_t (as void*) of the call that allocates; the library only frees a buffer
+ * after the work that uses it on the plan's last stream has completed.  The callbacks are called from
+ * tridiag_factor, tridiag_solve(_adjoint) (when the workspace grows) and tridiag_destroy, on the calling
+ * host thread.
+ */
+typedef void* (*td_alloc_fn)(void* ctx, size_t bytes, void* stream);
+typedef void (*td_free_fn)(void* ctx, void* ptr, void* stream);
+
 /* Description of the matrix and of the plan to build. */
 typedef struct {
   int64_t N;            /* block rows, >= 1 */
   int64_t M;            /* block size, 1 <= M <= 512 */
-  int64_t subdomains;   /* p in [1, N]: number of subdomains of Algorithm 2; 0 = chosen by the library */
+  int64_t subdomains;   /* p in [1, N]: number of subdomains of Algorithm 2; 0 = the library's default rule
+                           for k_hint right-hand sides (tridiag_default_subdomains) */
   int32_t fmt_A;        /* TD_FMT_DENSE or TD_FMT_DIAG (DENSE A or B: sweep_prec must be F64,
                            else TD_ENOTSUP; every coupling then becomes a block product) */
   int32_t fmt_B;        /* TD_FMT_DENSE or TD_FMT_DIAG */
@@ -70,6 +87,10 @@ typedef struct {
                            factor (float32 accumulation), see tridiag_solve */
   int32_t adjoint;      /* nonzero: also factor P^T so that tridiag_solve_adjoint can be used */
   int32_t reserved;     /* must be 0 */
+  int64_t k_hint;       /* right-hand sides per solve the default subdomain count is chosen for (<= 0: 512) */
+  td_alloc_fn dev_alloc; /* device memory callbacks (see above); both NULL = hipMalloc / hipFree */
+  td_free_fn dev_free;
+  void* alloc_ctx;      /* passed to dev_alloc / dev_free */
 } td_desc;
 
 /* Iterative refinement (used by tridiag_solve and tridiag_solve_adjoint). */
@@ -89,6 +110,20 @@ typedef struct {
 typedef struct td_plan_s* td_plan;
 
 /*
+ * Default number of subdomains for N block rows and K right-hand sides per solve (not in the paper,
+ * which leaves p to the machine): p = N / L with L the longest of 32, 16 and 8 rows for which the
+ * subdomain sweeps still get about 512 work-groups ((N / L) * ceil(K / 32) >= 512; else L = 8), clamped
+ * to [1, N].  K <= 0 means 512.  This is the rule tridiag_factor applies for subdomains == 0.
+ */
+td_status tridiag_default_subdomains(int64_t N, int64_t K, int64_t* p);
+
+/*
+ * Device bytes a tridiag_factor with this description needs at its peak (the footprint it checks
+ * against free device memory before allocating anything).  TD_EINVAL / TD_ENOTSUP as tridiag_factor.
+ */
+td_status tridiag_plan_bytes(const td_desc* desc, int64_t* bytes);
+
+/*
  * Factor P once (Algorithm 2, preliminary step 1 of Sec. 2.2).
  *   desc    : host pointer to the description.
  *   A, B, C : device pointers to the blocks in the formats named by desc.  They are read
@@ -96,9 +131,10 @@ typedef struct td_plan_s* td_plan;
  *   stream  : hipStream_t (as void*), or NULL.
  *   out     : receives the plan (NULL on failure).
  * The call is synchronous: it returns after the factor is complete and its pivots have been
- * checked.  Returns TD_ESINGULAR if a diagonal block of the elimination (or of the reduced
- * system) has a pivot below 1e-14 times its infinity norm; tridiag_last_error() names the
- * block row.  The plan owns all its device memory until tridiag_destroy.
+ * checked.  Before allocating, the footprint (tridiag_plan_bytes) is compared with the free device
+ * memory (hipMemGetInfo): above 95% of it the call returns TD_ENOMEM and allocates nothing.
+ * Returns TD_ESINGULAR if a diagonal block of the elimination (or of the reduced system) has a
+ * pivot below 1e-14 times its infinity norm; tridiag_last_error() names the block row.  The plan owns all its device memory until tridiag_destroy.
  */
 td_status tridiag_factor(const td_desc* desc, const double* A, const double* B, const double* C,
                          void* stream, td_plan* out);
@@ -194,6 +230,20 @@ td_status tridiag_autotune(int64_t M, int64_t K, int32_t sweep_prec, int64_t pro
  * runs a single pass without residual test (infos then report -1).
  */
 typedef struct td_batch_s* td_batch;
+
+/*
+ * One-call form of the batched solve: solves P_q X_q = F_q for the n plans (F_q, X_q device, column-major
+ * N_q M_q x K_q with leading dimension N_q M_q).  The first call with a given set of (plan, F, X, K) and
+ * refinement settings builds and captures the batch (tridiag_batch_create); later calls with the same
+ * arguments replay it; other arguments replace it.  refine NULL or disabled: one pass, no residual test;
+ * enabled: up to 1 + max_iter passes (max_iter <= 0: 2) with per-system early exit at tol (<= 0: 1e-10).
+ * infos (host, n entries) may be NULL; if given, the call synchronises and fills them (TD_ENOCONV if a
+ * system missed tol).  Plans, F and X must stay alive while the captured batch may be replayed; the
+ * cached batch is released by tridiag_solve_batched(0, ...) or when the arguments change.  One host
+ * thread at a time.
+ */
+td_status tridiag_solve_batched(int n, const td_plan* plans, const double* const* F, double* const* X,
+                                const int64_t* K, const td_refine* refine, td_info* infos, void* stream);
 td_status tridiag_batch_create(int n, const td_plan* plans, const double* const* F, const int64_t* ldf,
                                double* const* X, const int64_t* ldx, const int64_t* K, int passes, double tol,
                                void* stream, td_batch* out);

@@ -32,10 +32,38 @@ class TridiagError(RuntimeError):
         self.code = code
 
 
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+def _torch_alloc(ctx, nbytes, stream):
+    """td_desc.dev_alloc: a block of torch's caching allocator on the current device, associated with
+    the library call's stream; None (the library then reports TD_ENOMEM) when it cannot allocate."""
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), device=torch.cuda.current_device(),
+                                                  stream=int(stream or 0))
+    except Exception:
+        return None
+
+
+def _torch_free(ctx, ptr, stream):
+    try:
+        torch.cuda.caching_allocator_delete(int(ptr))
+    except Exception:
+        pass
+
+
+# kept alive for the lifetime of the module: the library calls them until every plan is destroyed
+TORCH_ALLOC = _ALLOC_FN(_torch_alloc)
+TORCH_FREE = _FREE_FN(_torch_free)
+
+
 class _Desc(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int64), ("M", ctypes.c_int64), ("subdomains", ctypes.c_int64),
                 ("fmt_A", ctypes.c_int32), ("fmt_B", ctypes.c_int32), ("fmt_C", ctypes.c_int32),
-                ("sweep_prec", ctypes.c_int32), ("adjoint", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("sweep_prec", ctypes.c_int32), ("adjoint", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("k_hint", ctypes.c_int64), ("dev_alloc", _ALLOC_FN), ("dev_free", _FREE_FN),
+                ("alloc_ctx", ctypes.c_void_p)]
 
 
 class _Refine(ctypes.Structure):
@@ -58,7 +86,8 @@ EXPORTS = ["tridiag_factor", "tridiag_solve", "tridiag_solve_adjoint", "tridiag_
            "tridiag_plan_info", "tridiag_set_profiling", "tridiag_stage_times", "tridiag_status_string",
            "tridiag_last_error", "tridiag_batch_create", "tridiag_batch_solve", "tridiag_batch_info",
            "tridiag_batch_destroy", "tridiag_autotune", "tridiag_band_to_blocks", "tridiag_schur_create",
-           "tridiag_schur_apply", "tridiag_schur_solve", "tridiag_schur_destroy"]
+           "tridiag_schur_apply", "tridiag_schur_solve", "tridiag_schur_destroy", "tridiag_default_subdomains",
+           "tridiag_plan_bytes", "tridiag_solve_batched"]
 
 class _SchurInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("active", ctypes.c_int32), ("max_rel_residual", ctypes.c_double)]
@@ -119,6 +148,13 @@ def load_library(path: str = LIB_PATH):
     lib.tridiag_schur_solve.restype = i32
     lib.tridiag_schur_destroy.argtypes = [vp]
     lib.tridiag_schur_destroy.restype = i32
+    lib.tridiag_default_subdomains.argtypes = [i64, i64, pi64]
+    lib.tridiag_default_subdomains.restype = i32
+    lib.tridiag_plan_bytes.argtypes = [ctypes.POINTER(_Desc), pi64]
+    lib.tridiag_plan_bytes.restype = i32
+    lib.tridiag_solve_batched.argtypes = [ctypes.c_int, pp, pp, pp, pi64, ctypes.POINTER(_Refine),
+                                          ctypes.POINTER(_Info), vp]
+    lib.tridiag_solve_batched.restype = i32
     _lib = lib
     return lib
 
@@ -155,20 +191,31 @@ class Plan:
     """A factored block-tridiagonal matrix (tridiag_factor) reusable for many right-hand sides."""
 
     def __init__(self, A, B, C, N, M, fmt_A="diag", fmt_B="diag", fmt_C="tridiag", subdomains=0,
-                 sweep_prec="f64", adjoint=False, k_hint=512):
+                 sweep_prec="f64", adjoint=False, k_hint=512, torch_allocator=True):
         """subdomains = 0: choose_subdomains(N, M, k_hint, sweep_prec) (the autotuned length for the
-        expected number of right-hand sides per solve, else the library's default rule)."""
+        expected number of right-hand sides per solve, else the library's default rule).
+        torch_allocator: the plan's device memory comes from torch's caching allocator (td_desc
+        callbacks); False: the library's own hipMalloc."""
         self.lib = load_library()
         self.N, self.M = int(N), int(M)
         if not subdomains:
             subdomains = choose_subdomains(self.N, self.M, int(k_hint), sweep_prec)
         d = _Desc(self.N, self.M, int(subdomains), FMT[fmt_A], FMT[fmt_B], FMT[fmt_C], PREC[sweep_prec],
-                  1 if adjoint else 0, 0)
+                  1 if adjoint else 0, 0, int(k_hint), TORCH_ALLOC if torch_allocator else _ALLOC_FN(),
+                  TORCH_FREE if torch_allocator else _FREE_FN(), None)
         A, B, C = _dev(A, "A"), _dev(B, "B"), _dev(C, "C")
+        if torch_allocator:
+            # torch may hold freed blocks in its cache that the library's free-memory check cannot see
+            need = ctypes.c_int64()
+            _check(self.lib.tridiag_plan_bytes(ctypes.byref(d), ctypes.byref(need)))
+            free, _ = torch.cuda.mem_get_info(A.device)
+            if need.value > 0.9 * free:
+                torch.cuda.empty_cache()
         h = ctypes.c_void_p()
-        code = self.lib.tridiag_factor(ctypes.byref(d), ctypes.c_void_p(A.data_ptr()),
-                                       ctypes.c_void_p(B.data_ptr()), ctypes.c_void_p(C.data_ptr()), _stream(),
-                                       ctypes.byref(h))
+        with torch.cuda.device(A.device):
+            code = self.lib.tridiag_factor(ctypes.byref(d), ctypes.c_void_p(A.data_ptr()),
+                                           ctypes.c_void_p(B.data_ptr()), ctypes.c_void_p(C.data_ptr()),
+                                           _stream(), ctypes.byref(h))
         _check(code)
         self.h = h
         self.device = A.device
@@ -344,6 +391,46 @@ class Batch:
             pass
 
 
+def solve_batched(plans, Fs, Xs, refine=None, info=False):
+    """tridiag_solve_batched: X_q = P_q^{-1} F_q for every plan, through one captured batch that later
+    calls with the same plans, tensors and refinement settings replay.  Fs, Xs: (K_q, N_q*M_q)
+    contiguous float64 device tensors.  refine: None (one pass), True or dict(tol, max_iter).
+    info=True: returns the per-system reports."""
+    lib = load_library()
+    n = len(plans)
+    if not (n == len(Fs) == len(Xs)) or n == 0:
+        raise ValueError("plans, Fs and Xs must have the same non-zero length")
+    for p, F, X in zip(plans, Fs, Xs):
+        nn = p.N * p.M
+        for t, name in ((F, "F"), (X, "X")):
+            _dev(t, name)
+            if t.dim() != 2 or t.shape[1] != nn:
+                raise TypeError(f"{name} must have shape (K, {nn})")
+        if F.shape[0] != X.shape[0]:
+            raise ValueError("F and X column counts differ")
+    rf = None
+    if refine:
+        refine = {} if refine is True else refine
+        rf = _Refine(1, int(refine.get("max_iter", 2)), float(refine.get("tol", 1e-10)))
+    infos = (_Info * n)() if info else None
+    code = lib.tridiag_solve_batched(n, (ctypes.c_void_p * n)(*[p.h.value for p in plans]),
+                                     (ctypes.c_void_p * n)(*[F.data_ptr() for F in Fs]),
+                                     (ctypes.c_void_p * n)(*[X.data_ptr() for X in Xs]),
+                                     (ctypes.c_int64 * n)(*[F.shape[0] for F in Fs]),
+                                     ctypes.byref(rf) if rf else None, infos, _stream())
+    if code not in (0, 4) or (code == 4 and not info):
+        _check(code)
+    if info:
+        return [{"iterations": i.iterations, "max_col_rel_residual": i.max_col_rel_residual,
+                 "nonfinite": i.nonfinite} for i in infos], code == 0
+    return None
+
+
+def release_batched():
+    """Drop the batch cached by solve_batched (tridiag_solve_batched with n = 0)."""
+    _check(load_library().tridiag_solve_batched(0, None, None, None, None, None, None, None))
+
+
 class BandSolver:
     """Solves with an n x n band matrix (kl sub-, ku super-diagonals) through its block-tridiagonal
     form (tridiag_band_to_blocks, then a float64 plan with DENSE blocks of size M).
@@ -432,22 +519,23 @@ class SchurSolver:
             pass
 
 
-def default_length(N: int, K: int) -> int:
-    """Subdomain length without an autotuned entry: the longest of 32, 16, 8 rows that still gives
-    the sweeps about 512 work-groups (two per compute unit; one per subdomain and 32-column tile),
-    so that few right-hand sides still fill the GPU."""
-    tiles = max(1, (K + 31) // 32)
-    for L in (32, 16):
-        if (N // L) * tiles >= 512:
-            return L
-    return 8
+def default_subdomains(N: int, K: int) -> int:
+    """The library's default subdomain count for N block rows and K right-hand sides
+    (tridiag_default_subdomains): N / L with L the longest of 32, 16 and 8 rows that still gives the
+    sweeps about 512 work-groups."""
+    lib = load_library()
+    p = ctypes.c_int64()
+    _check(lib.tridiag_default_subdomains(int(N), int(K), ctypes.byref(p)))
+    return int(p.value)
 
 
 def choose_subdomains(N: int, M: int, K: int, sweep_prec: str = "f64") -> int:
     """Subdomain count for an N x M system with K right-hand sides: N / L with the subdomain length
-    L chosen by the autotuner's cached result for (M, K bucket, precision) when present, else
-    default_length(N, K)."""
-    L = autotuned_length(M, K, sweep_prec, default=default_length(N, K))
+    L from the autotuner's cached result for (M, K bucket, precision) when present, else the library's
+    default rule (default_subdomains)."""
+    L = autotuned_length(M, K, sweep_prec, default=0)
+    if L <= 0:
+        return default_subdomains(N, K)
     return max(1, min(N, N // L))
 
 
@@ -462,7 +550,7 @@ def _kbucket(K):
     return b
 
 
-def autotuned_length(M, K, sweep_prec="f64", default=32):
+def autotuned_length(M, K, sweep_prec="f64", default=0):
     import json
     try:
         with open(_cache_path()) as f:

@@ -105,19 +105,38 @@ struct td_plan_s {
   std::vector<std::pair<void*, int64_t>> allocs;       // (pointer, bytes)
   hipStream_t last_stream = nullptr;
 
-  double* alloc(int64_t n_doubles) {
+  // device memory: the caller's callbacks (td_desc.dev_alloc / dev_free) or hipMalloc / hipFree
+  td_alloc_fn ualloc = nullptr;
+  td_free_fn ufree = nullptr;
+  void* uctx = nullptr;
+  hipStream_t astream = nullptr;   // stream of the call in progress (passed to the callbacks)
+  void* raw_alloc(size_t nb) {
     void* p = nullptr;
+    nb = std::max<size_t>(nb, 256);
+    if (ualloc) {
+      p = ualloc(uctx, nb, (void*)astream);
+      if (!p) throw HipFail{hipErrorOutOfMemory, "dev_alloc callback (" + std::to_string(nb) + " bytes)"};
+    } else {
+      HIPCHK(hipMalloc(&p, nb));
+    }
+    return p;
+  }
+  void raw_free(void* p) {
+    if (!p) return;
+    if (ufree) ufree(uctx, p, (void*)astream);
+    else (void)hipFree(p);
+  }
+  double* alloc(int64_t n_doubles) {
     if (n_doubles <= 0) n_doubles = 1;
-    HIPCHK(hipMalloc(&p, (size_t)n_doubles * sizeof(double)));
+    void* p = raw_alloc((size_t)n_doubles * sizeof(double));
     allocs.emplace_back(p, n_doubles * (int64_t)sizeof(double));
     bytes += n_doubles * (int64_t)sizeof(double);
     return (double*)p;
   }
   template <class T>
   T* upload(const std::vector<T>& v) {
-    void* p = nullptr;
     size_t nb = std::max<size_t>(1, v.size()) * sizeof(T);
-    HIPCHK(hipMalloc(&p, nb));
+    void* p = raw_alloc(nb);
     allocs.emplace_back(p, (int64_t)nb);
     bytes += (int64_t)nb;
     if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
@@ -130,7 +149,7 @@ struct td_plan_s {
       bytes -= it->second;
       allocs.erase(it);
     }
-    (void)hipFree(p);
+    raw_free(p);
   }
   // the last plain solve (no refinement, no report, not profiled), captured as a HIP graph and
   // replayed while the arguments and the workspace stay the same
@@ -148,7 +167,7 @@ struct td_plan_s {
   }
   ~td_plan_s() {
     drop_graph();
-    for (auto& a : allocs) (void)hipFree(a.first);
+    for (auto& a : allocs) raw_free(a.first);
     for (auto& s : evsets)
       for (auto& e : s.ev) (void)hipEventDestroy(e);
     delete adj;
@@ -203,26 +222,57 @@ BDesc desc0() {
   return d;
 }
 
-// Uploads a batch of descriptors, launches, and frees the upload after the stream is done with it.
+// Descriptor lists of the factor's launches: copied into chunks of pinned host memory and sent with
+// asynchronous copies into device chunks (from the plan's allocator), so that building a list never
+// waits for the device.  Each piece of a chunk is written once; the chunks are released when the pool
+// goes out of scope, after the stream has finished with them.
 struct DescPool {
-  std::vector<void*> bufs;
-  BDesc* put(const std::vector<BDesc>& v) {
-    void* p = nullptr;
-    HIPCHK(hipMalloc(&p, std::max<size_t>(1, v.size()) * sizeof(BDesc)));
-    bufs.push_back(p);
-    if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(BDesc), hipMemcpyHostToDevice));
-    return (BDesc*)p;
+  struct Chunk {
+    char* host;
+    char* dev;
+    size_t cap, used;
+  };
+  td_plan_s* P;
+  hipStream_t st;
+  std::vector<Chunk> chunks;
+  DescPool(td_plan_s* plan, hipStream_t s) : P(plan), st(s) {}
+  DescPool(const DescPool&) = delete;
+  DescPool& operator=(const DescPool&) = delete;
+  void* put_bytes(const void* src, size_t nb) {
+    const size_t need = (std::max<size_t>(nb, 1) + 255) & ~(size_t)255;
+    if (chunks.empty() || chunks.back().used + need > chunks.back().cap) {
+      Chunk c{};
+      c.cap = std::max<size_t>(need, (size_t)4 << 20);
+      HIPCHK(hipHostMalloc((void**)&c.host, c.cap, hipHostMallocDefault));
+      try {
+        c.dev = (char*)P->raw_alloc(c.cap);
+      } catch (...) {
+        (void)hipHostFree(c.host);
+        throw;
+      }
+      chunks.push_back(c);
+    }
+    Chunk& c = chunks.back();
+    void* d = c.dev + c.used;
+    if (nb) {
+      std::memcpy(c.host + c.used, src, nb);
+      HIPCHK(hipMemcpyAsync(d, c.host + c.used, nb, hipMemcpyHostToDevice, st));
+    }
+    c.used += need;
+    return d;
   }
   template <class T>
   T* put_vec(const std::vector<T>& v) {
-    void* p = nullptr;
-    HIPCHK(hipMalloc(&p, std::max<size_t>(1, v.size()) * sizeof(T)));
-    bufs.push_back(p);
-    if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
-    return (T*)p;
+    return (T*)put_bytes(v.data(), v.size() * sizeof(T));
   }
+  BDesc* put(const std::vector<BDesc>& v) { return put_vec(v); }
   ~DescPool() {
-    for (void* p : bufs) (void)hipFree(p);
+    if (chunks.empty()) return;
+    (void)hipStreamSynchronize(st);
+    for (auto& c : chunks) {
+      P->raw_free(c.dev);
+      (void)hipHostFree(c.host);
+    }
   }
 };
 
@@ -233,9 +283,18 @@ void run_bgemm(BArgs a, const std::vector<BDesc>& d, DescPool& pool, hipStream_t
   HIPCHK(launch_bgemm(a, st));
 }
 
-int64_t choose_p(int64_t N) {
-  int64_t p = N / 32;
-  return std::max<int64_t>(1, std::min<int64_t>(p, N));
+// Default subdomain count (tridiag_default_subdomains): the longest of 32, 16 and 8 rows per subdomain
+// that still gives the sweeps about 512 work-groups (one per subdomain and 32-column tile).
+int64_t default_subdomains(int64_t N, int64_t K) {
+  if (K <= 0) K = 512;
+  const int64_t tiles = std::max<int64_t>(1, (K + 31) / 32);
+  int64_t L = 8;
+  for (int64_t cand : {32, 16})
+    if ((N / cand) * tiles >= 512) {
+      L = cand;
+      break;
+    }
+  return std::max<int64_t>(1, std::min<int64_t>(N, N / L));
 }
 
 // ------------------------------------------------------------------------------------------
@@ -246,7 +305,7 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
   const int64_t N = P->N, M = P->M, Mp = P->Mp, p = P->p;
   const int64_t MM = Mp * Mp;
   const auto& ks = P->ks;
-  DescPool pool;
+  DescPool pool(P, st);
 
   // compact copies of the input
   const int64_t nA = (P->fmtA == TD_FMT_DIAG) ? N * M : N * M * M;
@@ -869,8 +928,10 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
   }
 }
 
-void ensure_workspace(td_plan_s* P, int64_t K, hipStream_t st) {
+// prev: the stream of the plan's previous solve, whose work may still read the old workspace
+void ensure_workspace(td_plan_s* P, int64_t K, hipStream_t st, hipStream_t prev) {
   if (K <= P->kcap) return;
+  if (P->kcap > 0 && prev != st) HIPCHK(hipStreamSynchronize(prev));
   ++P->ws_gen;
   const int64_t N = P->N, Mp = P->Mp, p = P->p;
   P->release(P->Wbuf); P->release(P->W32); P->release(P->Ft); P->release(P->Xi); P->release(P->Sp);
@@ -899,6 +960,7 @@ int residual_parts(const td_plan_s* P) {
 
 void ensure_refine_ws(td_plan_s* P, int64_t K) {
   if (K <= P->rcap) return;
+  if (P->rcap > 0) HIPCHK(hipStreamSynchronize(P->last_stream));
   const int64_t n = P->N * P->M;
   P->release(P->Rbuf); P->release(P->colpart); P->release(P->norms);
   P->Rbuf = P->alloc(n * K);
@@ -922,12 +984,27 @@ void stage_mark(td_plan_s* P, int idx, hipStream_t st) {
   HIPCHK(hipEventRecord(P->se->ev[idx], st));
 }
 
+// Solve workspace of one call: the plan's own buffers (plan_work) or pieces of a caller-independent
+// fixed device array (tridiag_solve_noalloc).  Layouts: W (N Mp) x K float64 or W32 (panels of 64
+// right-hand sides) float32; Ft (p Mp) x K; Xi ((p + 2) Mp) x K with a zero block at each end;
+// Sp (nchunks Mp) x K; Pbuf (pslots Mp) x K.
+struct Work {
+  double* W;
+  float* W32;
+  double* Ft;
+  double* Xi;
+  double* Sp;
+  double* Pbuf;
+};
+
+Work plan_work(const td_plan_s* P) { return Work{P->Wbuf, P->W32, P->Ft, P->Xi, P->Sp, P->Pbuf}; }
+
 // One pass of Algorithm 2, step 2: eq. (sub3) sweeps, eq. (red1) right-hand side, Algorithm 1 on
 // the reduced system, eq. (superposition).  The sweeps and the superposition run in the plan's
 // precision (float64, or float32 / bfloat16 with float32 accumulation); the reduced system always
 // in float64.  With `accumulate` the result is added to X (a refinement correction).
-void solve_pass(td_plan_s* P, const double* F, int64_t ldf, double* X, int64_t ldx, int64_t K, bool accumulate,
-                hipStream_t st) {
+void solve_pass(td_plan_s* P, const Work& w, const double* F, int64_t ldf, double* X, int64_t ldx, int64_t K,
+                bool accumulate, hipStream_t st) {
   const int64_t N = P->N, M = P->M, Mp = P->Mp, p = P->p;
   const int64_t ldw = N * Mp, ldft = p * Mp, ldxi = (p + 2) * Mp, ldsp = (int64_t)P->nchunks * Mp;
   stage_mark(P, 0, st);
@@ -937,39 +1014,39 @@ void solve_pass(td_plan_s* P, const double* F, int64_t ldf, double* X, int64_t l
       g.descs = P->d_gf; g.nprob = P->n_gf;
       g.A = P->Dinv; g.lda = Mp;
       g.B = F; g.ldb = ldf; g.brows = (int32_t)M;
-      g.C = P->Wbuf; g.ldc = ldw;
+      g.C = w.W; g.ldc = ldw;
       g.ncols = (int32_t)K;
       HIPCHK(launch_bgemm(g, st));
     }
     SweepArgs sa{};
     sa.ks = P->d_ks; sa.Dinv = P->Dinv; sa.alpha = P->alpha; sa.adiag = P->adiag;
     sa.E = P->dense ? P->E : nullptr;
-    sa.F = F; sa.ldf = ldf; sa.W = P->Wbuf; sa.ldw = ldw;
+    sa.F = F; sa.ldf = ldf; sa.W = w.W; sa.ldw = ldw;
     sa.N = (int32_t)N; sa.M = (int32_t)M; sa.Mp = (int32_t)Mp; sa.p = (int32_t)p; sa.K = (int32_t)K;
     sa.ncoltiles = 0; sa.total = 0;
     if (N > p) HIPCHK(launch_sweep(sa, st));
     stage_mark(P, 1, st);
-    HIPCHK(launch_ftilde(P->Ft, ldft, F, ldf, P->Wbuf, ldw, P->d_ks, P->adiag, P->bdiag, (int)p, (int)M, (int)Mp,
+    HIPCHK(launch_ftilde(w.Ft, ldft, F, ldf, w.W, ldw, P->d_ks, P->adiag, P->bdiag, (int)p, (int)M, (int)Mp,
                          (int)K, st));
     if (P->dense && P->n_ftd > 0) {
       BArgs f = bargs_base((int)Mp);
       f.descs = P->d_ftd; f.nprob = P->n_ftd;
       f.A = P->ABd; f.lda = Mp;
-      f.B = P->Wbuf; f.ldb = ldw;
-      f.C = P->Ft; f.ldc = ldft;
-      f.Cin = P->Ft; f.ldcin = ldft;
+      f.B = w.W; f.ldb = ldw;
+      f.C = w.Ft; f.ldc = ldft;
+      f.Cin = w.Ft; f.ldcin = ldft;
       f.ncols = (int32_t)K;
       HIPCHK(launch_bgemm(f, st));
     }
   } else {
     LpSweepArgs sa{};
     sa.ks = P->d_ks; sa.Dinv = P->Dlp; sa.alpha = P->Alp; sa.adiag = P->adiag;
-    sa.F = F; sa.ldf = ldf; sa.W = P->W32;
+    sa.F = F; sa.ldf = ldf; sa.W = w.W32;
     sa.N = (int32_t)N; sa.M = (int32_t)M; sa.Mp = (int32_t)Mp; sa.p = (int32_t)p; sa.K = (int32_t)K;
     sa.ncoltiles = 0; sa.total = 0;
     if (N > p) HIPCHK(launch_sweep_lp(P->prec, sa, st));
     stage_mark(P, 1, st);
-    HIPCHK(launch_ftilde_f32(P->Ft, ldft, F, ldf, P->W32, N, P->d_ks, P->adiag, P->bdiag, (int)p, (int)M,
+    HIPCHK(launch_ftilde_f32(w.Ft, ldft, F, ldf, w.W32, N, P->d_ks, P->adiag, P->bdiag, (int)p, (int)M,
                              (int)Mp, (int)K, st));
   }
   stage_mark(P, 2, st);
@@ -977,8 +1054,8 @@ void solve_pass(td_plan_s* P, const double* F, int64_t ldf, double* X, int64_t l
     BArgs a = bargs_base((int)Mp);
     a.descs = P->d_part; a.nprob = P->n_part;
     a.A = P->G; a.lda = Mp;
-    a.B = P->Ft; a.ldb = ldft;
-    a.C = P->Sp; a.ldc = ldsp;
+    a.B = w.Ft; a.ldb = ldft;
+    a.C = w.Sp; a.ldc = ldsp;
     a.ncols = (int32_t)K;
     HIPCHK(launch_bgemm(a, st));
   }
@@ -990,8 +1067,8 @@ void solve_pass(td_plan_s* P, const double* F, int64_t ldf, double* X, int64_t l
       a.descs = P->d_split + P->split_begin[lv];
       a.nprob = P->split_count[lv];
       a.A = P->H; a.lda = Mp;
-      a.B = P->Xi; a.ldb = ldxi;
-      a.C = P->Pbuf; a.ldc = ldp;
+      a.B = w.Xi; a.ldb = ldxi;
+      a.C = w.Pbuf; a.ldc = ldp;
       a.ncols = (int32_t)K;
       HIPCHK(launch_bgemm(a, st));
       CombArgs c;
@@ -1000,9 +1077,9 @@ void solve_pass(td_plan_s* P, const double* F, int64_t ldf, double* X, int64_t l
       c.nnode = P->corr_count[lv];
       c.Mp = (int32_t)Mp; c.ncols = (int32_t)K;
       c.x2rows = (int32_t)M; c.x2accum = accumulate ? 1 : 0;
-      c.P = P->Pbuf; c.ldp = ldp;
-      c.Sp = P->Sp; c.ldsp = ldsp; c.spstride = Mp;
-      c.C = P->Xi; c.ldc = ldxi;
+      c.P = w.Pbuf; c.ldp = ldp;
+      c.Sp = w.Sp; c.ldsp = ldsp; c.spstride = Mp;
+      c.C = w.Xi; c.ldc = ldxi;
       c.X2 = X; c.ldx2 = ldx;
       HIPCHK(launch_level_combine(c, st));
       continue;
@@ -1011,9 +1088,9 @@ void solve_pass(td_plan_s* P, const double* F, int64_t ldf, double* X, int64_t l
     a.descs = P->d_corr + P->corr_begin[lv];
     a.nprob = P->corr_count[lv];
     a.A = P->H; a.lda = Mp;
-    a.B = P->Xi; a.ldb = ldxi;
-    a.Sp = P->Sp; a.ldsp = ldsp; a.spstride = Mp;
-    a.C = P->Xi; a.ldc = ldxi;
+    a.B = w.Xi; a.ldb = ldxi;
+    a.Sp = w.Sp; a.ldsp = ldsp; a.spstride = Mp;
+    a.C = w.Xi; a.ldc = ldxi;
     a.X2 = X; a.ldx2 = ldx; a.x2rows = (int32_t)M; a.x2accum = accumulate ? 1 : 0;
     a.ncols = (int32_t)K;
     HIPCHK(launch_bgemm(a, st));
@@ -1022,8 +1099,8 @@ void solve_pass(td_plan_s* P, const double* F, int64_t ldf, double* X, int64_t l
   if (P->prec == TD_PREC_F64) {
     SupArgs u{};
     u.ks = P->d_ks; u.UV = P->UVa + 2 * Mp * Mp;
-    u.Xi = P->Xi; u.ldxi = ldxi;
-    u.W = P->Wbuf; u.ldw = ldw;
+    u.Xi = w.Xi; u.ldxi = ldxi;
+    u.W = w.W; u.ldw = ldw;
     u.X = X; u.ldx = ldx;
     u.N = (int32_t)N; u.M = (int32_t)M; u.Mp = (int32_t)Mp; u.p = (int32_t)p; u.K = (int32_t)K;
     u.ncoltiles = 0; u.total = 0; u.accumulate = accumulate ? 1 : 0;
@@ -1031,8 +1108,8 @@ void solve_pass(td_plan_s* P, const double* F, int64_t ldf, double* X, int64_t l
   } else {
     LpSupArgs u{};
     u.ks = P->d_ks; u.UV = P->UVlp;
-    u.Xi = P->Xi; u.ldxi = ldxi;
-    u.W = P->W32;
+    u.Xi = w.Xi; u.ldxi = ldxi;
+    u.W = w.W32;
     u.X = X; u.ldx = ldx;
     u.N = (int32_t)N; u.M = (int32_t)M; u.Mp = (int32_t)Mp; u.p = (int32_t)p; u.K = (int32_t)K;
     u.ncoltiles = 0; u.total = 0; u.accumulate = accumulate ? 1 : 0;
@@ -1080,7 +1157,9 @@ td_status solve_impl(td_plan_s* P, const double* F, int64_t ldf, double* X, int6
   const char* x0 = (const char*)X;
   const char* x1 = (const char*)(X + (K - 1) * ldx + n);
   if (f0 < x1 && x0 < f1) return fail(TD_EINVAL, "X overlaps F");
+  const hipStream_t prev_stream = P->last_stream;
   P->last_stream = st;
+  P->astream = st;
   P->se = nullptr;
   if (P->prof && P->prof_n < 4096) {
     if ((int)P->evsets.size() <= P->prof_n) {
@@ -1090,7 +1169,7 @@ td_status solve_impl(td_plan_s* P, const double* F, int64_t ldf, double* X, int6
     }
     P->se = &P->evsets[P->prof_n++];
   }
-  ensure_workspace(P, K, st);
+  ensure_workspace(P, K, st, prev_stream);
   if (P->se) HIPCHK(hipEventRecord(P->se->ev[6], st));
   P->first_pass = true;
   const bool refine = rf && rf->enable;
@@ -1107,7 +1186,7 @@ td_status solve_impl(td_plan_s* P, const double* F, int64_t ldf, double* X, int6
       hipError_t ce = hipSuccess;
       if (be == hipSuccess) {
         try {
-          solve_pass(P, F, ldf, X, ldx, K, false, cs);
+          solve_pass(P, plan_work(P), F, ldf, X, ldx, K, false, cs);
         } catch (...) {
           (void)hipStreamEndCapture(cs, &gr);
           if (gr) (void)hipGraphDestroy(gr);
@@ -1126,7 +1205,7 @@ td_status solve_impl(td_plan_s* P, const double* F, int64_t ldf, double* X, int6
     HIPCHK(hipGraphLaunch(g.ex, st));
     return TD_OK;
   }
-  solve_pass(P, F, ldf, X, ldx, K, false, st);
+  solve_pass(P, plan_work(P), F, ldf, X, ldx, K, false, st);
   td_status status = TD_OK;
   if (refine || info) {
     const double tol = (rf && rf->tol > 0.0) ? rf->tol : 1e-10;
@@ -1140,7 +1219,7 @@ td_status solve_impl(td_plan_s* P, const double* F, int64_t ldf, double* X, int6
       // X += S(F - P X): the correction pass adds its result to X.  The residual is not
       // rescaled: for the relative residuals reached here its entries stay far above the
       // smallest normal float32 / bfloat16 number (about 1e-38).
-      solve_pass(P, P->Rbuf, n, X, ldx, K, true, st);
+      solve_pass(P, plan_work(P), P->Rbuf, n, X, ldx, K, true, st);
       ++it;
       res = residual(P, F, ldf, X, ldx, K, P->Rbuf, n, nrm, st);
     }
@@ -1170,6 +1249,8 @@ td_status check_desc(const td_desc* d) {
   if (!(d->fmt_C == TD_FMT_DENSE || d->fmt_C == TD_FMT_TRIDIAG)) return fail(TD_EINVAL, "fmt_C must be DENSE or TRIDIAG");
   if (d->sweep_prec < TD_PREC_F64 || d->sweep_prec > TD_PREC_BF16) return fail(TD_EINVAL, "bad sweep_prec");
   if (d->reserved != 0) return fail(TD_EINVAL, "reserved must be 0");
+  if ((d->dev_alloc == nullptr) != (d->dev_free == nullptr))
+    return fail(TD_EINVAL, "dev_alloc and dev_free must both be set or both be NULL");
   if (d->M > 512) return fail(TD_ENOTSUP, "M > 512 is not supported");
   if (d->N > (int64_t)1 << 30) return fail(TD_ENOTSUP, "N too large");
   if ((d->fmt_A == TD_FMT_DENSE || d->fmt_B == TD_FMT_DENSE) && d->sweep_prec != TD_PREC_F64)
@@ -1247,7 +1328,7 @@ void make_lowprec(td_plan_s* P, hipStream_t st) {
   for (int64_t s = 0; s < P->p; ++s)
     for (int64_t i = P->ks[s] + 1; i < P->ks[s + 1]; ++i) rows.push_back(i);
   if (rows.empty()) rows.push_back(0);
-  DescPool pool;
+  DescPool pool(P, st);
   int64_t* d_rows = pool.put_vec(rows);
   const int nm = (int)rows.size();
   P->Dlp = P->alloc((N * MM * esz + 7) / 8);
@@ -1272,14 +1353,17 @@ td_status factor_top(const td_desc* d, const double* A, const double* B, const d
   const auto t0 = std::chrono::steady_clock::now();
   td_plan_s* P = new td_plan_s();
   P->N = d->N; P->M = d->M; P->Mp = pad_block(d->M, d->sweep_prec);
-  P->p = d->subdomains ? d->subdomains : choose_p(d->N);
+  P->p = d->subdomains ? d->subdomains : default_subdomains(d->N, d->k_hint);
+  P->ualloc = d->dev_alloc; P->ufree = d->dev_free; P->uctx = d->alloc_ctx;
+  P->astream = st;
   P->fmtA = d->fmt_A; P->fmtB = d->fmt_B; P->fmtC = d->fmt_C;
   P->prec = d->sweep_prec; P->adjoint = d->adjoint;
   P->ks = partition(P->N, P->p);
   try {
     size_t freeb = 0, totb = 0;
     HIPCHK(hipMemGetInfo(&freeb, &totb));
-    const int64_t need = factor_bytes(P->N, P->M, P->p, P->fmtA, P->fmtB, P->fmtC, P->prec);
+    int64_t need = factor_bytes(P->N, P->M, P->p, P->fmtA, P->fmtB, P->fmtC, P->prec);
+    if (d->adjoint && allow_adjoint) need *= 2;
     if ((double)need > 0.95 * (double)freeb) {
       delete P;
       return fail(TD_ENOMEM, "factor needs " + std::to_string(need) + " bytes, " + std::to_string(freeb) + " free");
@@ -1289,13 +1373,9 @@ td_status factor_top(const td_desc* d, const double* A, const double* B, const d
     if (d->adjoint && allow_adjoint) {
       std::vector<double> A2, B2, C2;
       transpose_inputs(P, A2, B2, C2);
-      double *dA = nullptr, *dB = nullptr, *dC = nullptr;
-      HIPCHK(hipMalloc((void**)&dA, A2.size() * 8));
-      HIPCHK(hipMalloc((void**)&dB, B2.size() * 8));
-      HIPCHK(hipMalloc((void**)&dC, C2.size() * 8));
-      HIPCHK(hipMemcpy(dA, A2.data(), A2.size() * 8, hipMemcpyHostToDevice));
-      HIPCHK(hipMemcpy(dB, B2.data(), B2.size() * 8, hipMemcpyHostToDevice));
-      HIPCHK(hipMemcpy(dC, C2.data(), C2.size() * 8, hipMemcpyHostToDevice));
+      double* dA = P->upload(A2);
+      double* dB = P->upload(B2);
+      double* dC = P->upload(C2);
       td_desc d2 = *d;
       d2.subdomains = P->p;
       d2.adjoint = 0;
@@ -1303,7 +1383,7 @@ td_status factor_top(const td_desc* d, const double* A, const double* B, const d
       d2.fmt_B = d->fmt_A;
       td_plan adj = nullptr;
       td_status s2 = factor_top(&d2, dA, dB, dC, st, &adj, false);
-      (void)hipFree(dA); (void)hipFree(dB); (void)hipFree(dC);
+      P->release(dA); P->release(dB); P->release(dC);
       if (s2 != TD_OK) {
         delete P;
         return s2;
@@ -1398,7 +1478,9 @@ td_status batch_create_impl(int n, const td_plan* plans, const double* const* F,
   for (int q = 0; q < n; ++q) {
     td_plan_s* P = plans[q];
     const int64_t Kq = K[q];
-    ensure_workspace(P, Kq, st);
+    P->astream = st;
+    ensure_workspace(P, Kq, st, P->last_stream ? P->last_stream : st);
+    P->last_stream = st;
     const int64_t N = P->N, M = P->M, Mp = P->Mp, p = P->p;
     const int64_t ldw = N * Mp, ldft = p * Mp, ldxi = (p + 2) * Mp, ldsp = (int64_t)P->nchunks * Mp;
     BatchSys& S = sys[q];
@@ -1602,6 +1684,26 @@ td_status tridiag_factor(const td_desc* desc, const double* A, const double* B, 
   return factor_top(desc, A, B, C, (hipStream_t)stream, out, true);
 }
 
+td_status tridiag_default_subdomains(int64_t N, int64_t K, int64_t* p) {
+  g_err.clear();
+  if (!p) return fail(TD_EINVAL, "null p");
+  if (N < 1) return fail(TD_EINVAL, "N must be >= 1");
+  *p = default_subdomains(N, K);
+  return TD_OK;
+}
+
+td_status tridiag_plan_bytes(const td_desc* desc, int64_t* bytes) {
+  g_err.clear();
+  if (!bytes) return fail(TD_EINVAL, "null bytes");
+  td_status s = check_desc(desc);
+  if (s != TD_OK) return s;
+  const int64_t p = desc->subdomains ? desc->subdomains : default_subdomains(desc->N, desc->k_hint);
+  int64_t b = factor_bytes(desc->N, desc->M, p, desc->fmt_A, desc->fmt_B, desc->fmt_C, desc->sweep_prec);
+  if (desc->adjoint) b *= 2;
+  *bytes = b;
+  return TD_OK;
+}
+
 td_status tridiag_solve(td_plan plan, const double* F, int64_t ldf, double* X, int64_t ldx, int64_t K,
                         const td_refine* refine, td_info* info, void* stream) {
   if (!plan) return fail(TD_EINVAL, "null plan");
@@ -1636,6 +1738,8 @@ td_status tridiag_destroy(td_plan plan) {
   if (!plan) return TD_OK;
   if (plan->last_stream) (void)hipStreamSynchronize(plan->last_stream);
   else (void)hipDeviceSynchronize();
+  if (plan->adj && plan->adj->last_stream && plan->adj->last_stream != plan->last_stream)
+    (void)hipStreamSynchronize(plan->adj->last_stream);
   delete plan;
   return TD_OK;
 }
@@ -1836,6 +1940,57 @@ td_status tridiag_batch_destroy(td_batch b) {
   if (b->last) (void)hipStreamSynchronize(b->last);
   delete b;
   return TD_OK;
+}
+
+td_status tridiag_solve_batched(int n, const td_plan* plans, const double* const* F, double* const* X,
+                                const int64_t* K, const td_refine* refine, td_info* infos, void* stream) {
+  // the batch of the last call, replayed while the arguments stay the same
+  static struct {
+    std::vector<td_plan> plans;
+    std::vector<const double*> F;
+    std::vector<double*> X;
+    std::vector<int64_t> K;
+    int passes = 0;
+    double tol = 0.0;
+    td_batch b = nullptr;
+  } cache;
+  g_err.clear();
+  if (n == 0) {
+    if (cache.b) (void)tridiag_batch_destroy(cache.b);
+    cache.b = nullptr;
+    cache.plans.clear();
+    return TD_OK;
+  }
+  if (n < 0 || !plans || !F || !X || !K) return fail(TD_EINVAL, "bad batched arguments");
+  const bool ref = refine && refine->enable;
+  const int passes = ref ? 1 + (refine->max_iter > 0 ? refine->max_iter : 2) : 1;
+  const double tol = ref ? (refine->tol > 0.0 ? refine->tol : 1e-10) : -1.0;
+  const bool same = cache.b && (int)cache.plans.size() == n && cache.passes == passes && cache.tol == tol &&
+                    std::equal(plans, plans + n, cache.plans.begin()) && std::equal(F, F + n, cache.F.begin()) &&
+                    std::equal(X, X + n, cache.X.begin()) && std::equal(K, K + n, cache.K.begin());
+  if (!same) {
+    if (cache.b) (void)tridiag_batch_destroy(cache.b);
+    cache.b = nullptr;
+    cache.plans.clear();
+    std::vector<int64_t> ld(n);
+    for (int q = 0; q < n; ++q) {
+      if (!plans[q]) return fail(TD_EINVAL, "null plan");
+      ld[q] = plans[q]->N * plans[q]->M;
+    }
+    td_batch b = nullptr;
+    td_status s = tridiag_batch_create(n, plans, F, ld.data(), X, ld.data(), K, passes, tol, stream, &b);
+    if (s != TD_OK) return s;
+    cache.b = b;
+    cache.plans.assign(plans, plans + n);
+    cache.F.assign(F, F + n);
+    cache.X.assign(X, X + n);
+    cache.K.assign(K, K + n);
+    cache.passes = passes;
+    cache.tol = tol;
+  }
+  td_status s = tridiag_batch_solve(cache.b, stream);
+  if (s != TD_OK || !infos) return s;
+  return tridiag_batch_info(cache.b, infos);
 }
 
 }  // extern "C"

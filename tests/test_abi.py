@@ -125,15 +125,62 @@ def test_schur_null_handles(lib):
     assert lib.tridiag_schur_destroy(None) == 0
 
 
-def test_default_subdomain_length_fills_the_gpu(tmp_path, monkeypatch):
+def test_default_subdomain_count_fills_the_gpu(tmp_path, monkeypatch, lib):
     """Without an autotuned entry the subdomain length is the longest of 32, 16, 8 rows that gives
-    the sweeps about 512 work-groups (subdomains x 32-column tiles)."""
+    the sweeps about 512 work-groups (subdomains x 32-column tiles); the binding and the library's
+    subdomains = 0 use the same rule (tridiag_default_subdomains)."""
     import paper_1108_4181_amd as td
 
     monkeypatch.setenv("TD_AUTOTUNE_CACHE", str(tmp_path / "none.json"))
-    assert td.default_length(2048, 512) == 32      # 64 subdomains x 16 tiles
-    assert td.default_length(1093, 256) == 16      # 34 x 8 would be 272 work-groups
-    assert td.default_length(2032, 64) == 8
-    assert td.default_length(64, 8) == 8
-    assert td.choose_subdomains(1093, 60, 256) == 1093 // 16
+    assert td.default_subdomains(2048, 512) == 64      # L = 32: 64 subdomains x 16 tiles
+    assert td.default_subdomains(4096, 1024) == 128
+    assert td.default_subdomains(1093, 256) == 68      # L = 16: 34 x 8 would be 272 work-groups
+    assert td.default_subdomains(2032, 64) == 254      # L = 8
+    assert td.default_subdomains(64, 8) == 8
+    assert td.default_subdomains(4, 1) == 1
+    assert td.default_subdomains(2048, 0) == 64        # K <= 0 means 512
+    assert td.choose_subdomains(1093, 60, 256) == 68
     assert td.choose_subdomains(4, 16, 1) == 1
+    p = ctypes.c_int64()
+    assert lib.tridiag_default_subdomains(0, 8, ctypes.byref(p)) == 1
+    assert lib.tridiag_default_subdomains(8, 8, None) == 1
+
+
+def test_plan_bytes_on_host(lib):
+    """The factor's footprint (checked against free device memory before anything is allocated) is
+    computed on the host: it grows with N, doubles with the transposed plan, and p = 0 gives the
+    footprint of the default subdomain count."""
+    import paper_1108_4181_amd as td
+
+    def nbytes(**kw):
+        d = _desc(td, **kw)
+        d.adjoint = kw.get("adj", 0)
+        b = ctypes.c_int64()
+        assert lib.tridiag_plan_bytes(ctypes.byref(d), ctypes.byref(b)) == 0
+        return b.value
+
+    base = nbytes(N=2048, M=256, p=64)
+    assert base > 4 * 2048 * 256 * 256 * 8           # D^-1, alpha, U and V at least
+    assert nbytes(N=4096, M=256, p=64) > 1.8 * base
+    assert nbytes(N=2048, M=256, p=64, adj=1) == 2 * base
+    assert nbytes(N=2048, M=256, p=0) == base         # p = 0: the default rule gives 64 here
+    d = _desc(td, M=600)
+    assert lib.tridiag_plan_bytes(ctypes.byref(d), ctypes.byref(ctypes.c_int64())) == 7
+    assert lib.tridiag_plan_bytes(None, ctypes.byref(ctypes.c_int64())) == 1
+
+
+def test_allocator_callbacks_must_come_in_pairs(lib):
+    import paper_1108_4181_amd as td
+
+    d = _desc(td)
+    d.dev_alloc = td.TORCH_ALLOC
+    plan = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(16)  # never dereferenced: validation fails first
+    assert lib.tridiag_factor(ctypes.byref(d), dummy, dummy, dummy, None, ctypes.byref(plan)) == 1
+    assert plan.value is None
+
+
+def test_solve_batched_rejects_bad_arguments(lib):
+    assert lib.tridiag_solve_batched(-1, None, None, None, None, None, None, None) == 1
+    assert lib.tridiag_solve_batched(2, None, None, None, None, None, None, None) == 1
+    assert lib.tridiag_solve_batched(0, None, None, None, None, None, None, None) == 0   # releases the cache

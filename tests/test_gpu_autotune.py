@@ -26,7 +26,7 @@ def test_autotune_writes_and_uses_cache(td, tmp_path, monkeypatch, prec):
     cache = tmp_path / "tune.json"
     monkeypatch.setenv("TD_AUTOTUNE_CACHE", str(cache))
     M, K, N = 64, 40, 1000
-    assert td.choose_subdomains(N, M, K, prec) == max(1, N // td.default_length(N, K))
+    assert td.choose_subdomains(N, M, K, prec) == td.default_subdomains(N, K)
     cands = (8, 16, 32)
     res = td.autotune(M, K, prec, probe_N=256, candidates=cands)
     assert res["L"] in cands
