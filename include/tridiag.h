@@ -155,6 +155,22 @@ td_status tridiag_solve(td_plan plan, const double* F, int64_t ldf, double* X, i
                         const td_refine* refine, td_info* info, void* stream);
 
 /*
+ * tridiag_solve without any device memory allocation, for callers that cannot allocate (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same kernels as a plain
+ * tridiag_solve (no refinement, no report), with the solve workspace placed in a fixed device array of
+ * 64 MiB that the library holds on each GPU it runs on until the process ends, instead of the plan's
+ * workspace.  F, X, ldf, ldx, K as in tridiag_solve; the result equals tridiag_solve's.  The workspace
+ * a solve needs is ((p + 2) + p + chunks + slab slots) * Mp * K float64 words plus the sweep workspace
+ * (N * Mp * K float64 words, or float32 words in panels of 64 columns for low-precision plans); above
+ * 64 MiB the call returns TD_EINVAL and launches nothing.  Every call on one GPU shares that array
+ * (it keeps the last call's contents; each call clears what must start at zero), so calls on one GPU
+ * must not overlap: order them on one stream or synchronise between them.  Asynchronous on `stream`;
+ * calls no hipMalloc / hipFree and no allocation callback.
+ */
+td_status tridiag_solve_noalloc(td_plan plan, const double* F, int64_t ldf, double* X, int64_t ldx, int64_t K,
+                                void* stream);
+
+/*
  * Solve P^T Lam = G (same conventions as tridiag_solve).  The transposed matrix is again
  * block tridiagonal with blocks C'_j = C_j^T, A'_j = B_{j-1}^T, B'_j = A_{j+1}^T.
  * Returns TD_ENOADJ if the plan was factored with desc.adjoint == 0.

@@ -87,7 +87,7 @@ EXPORTS = ["tridiag_factor", "tridiag_solve", "tridiag_solve_adjoint", "tridiag_
            "tridiag_last_error", "tridiag_batch_create", "tridiag_batch_solve", "tridiag_batch_info",
            "tridiag_batch_destroy", "tridiag_autotune", "tridiag_band_to_blocks", "tridiag_schur_create",
            "tridiag_schur_apply", "tridiag_schur_solve", "tridiag_schur_destroy", "tridiag_default_subdomains",
-           "tridiag_plan_bytes", "tridiag_solve_batched"]
+           "tridiag_plan_bytes", "tridiag_solve_batched", "tridiag_solve_noalloc"]
 
 class _SchurInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("active", ctypes.c_int32), ("max_rel_residual", ctypes.c_double)]
@@ -155,6 +155,8 @@ def load_library(path: str = LIB_PATH):
     lib.tridiag_solve_batched.argtypes = [ctypes.c_int, pp, pp, pp, pi64, ctypes.POINTER(_Refine),
                                           ctypes.POINTER(_Info), vp]
     lib.tridiag_solve_batched.restype = i32
+    lib.tridiag_solve_noalloc.argtypes = [vp, vp, i64, vp, i64, i64, vp]
+    lib.tridiag_solve_noalloc.restype = i32
     _lib = lib
     return lib
 
@@ -254,6 +256,17 @@ class Plan:
     def solve(self, F, X=None, refine=None, info=False):
         """X = P^{-1} F.  F: (K, N*M) float64 on the device.  refine: None, True or dict(tol, max_iter)."""
         return self._solve(self.lib.tridiag_solve, F, X, refine, info)
+
+    def solve_noalloc(self, F, X):
+        """tridiag_solve_noalloc: X = P^{-1} F with the workspace in the library's fixed device array
+        (no allocation; TD_EINVAL above its 64 MiB).  X must be given (K, N*M), like F."""
+        n = self.N * self.M
+        fp, ldf, K = _rhs(F, n, "F")
+        xp, ldx, K2 = _rhs(X, n, "X")
+        if K2 != K:
+            raise ValueError("F and X have different numbers of columns")
+        _check(self.lib.tridiag_solve_noalloc(self.h, fp, ldf, xp, ldx, K, _stream()))
+        return X
 
     def solve_adjoint(self, G, Lam=None, refine=None, info=False):
         """Lam = P^{-T} G (needs adjoint=True at factor time)."""

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1674,6 +1675,62 @@ td_status batch_create_impl(int n, const td_plan* plans, const double* const* F,
 
 }  // namespace
 
+// ------------------------------------------------------------------------------------------
+// Fixed device workspace of tridiag_solve_noalloc: one array per GPU, held from the library's load
+// until the process ends, shared by every no-allocation solve on that GPU (so such calls must not
+// overlap on one GPU).  Host code never uses the array's name as a device address: the address of
+// each device's copy comes from hipGetSymbolAddress, once per device, with that device current.
+// ------------------------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// address of the current device's scratch array (looked up on the first call on that device)
+hipError_t scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// pieces of a solve's workspace in the scratch array, each 256-byte aligned; returns the bytes used
+int64_t scratch_layout(const td_plan_s* P, int64_t K, char* base, Work* w, int64_t* clear_doubles) {
+  const int64_t N = P->N, Mp = P->Mp, p = P->p;
+  auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
+  // Xi, Ft, Sp and Pbuf first (cleared on every call), then W
+  const int64_t bXi = up((p + 2) * Mp * K * 8), bFt = up(p * Mp * K * 8), bSp = up((int64_t)P->nchunks * Mp * K * 8);
+  const int64_t bP = up((int64_t)P->pslots * Mp * K * 8);
+  const int64_t bW = (P->prec == TD_PREC_F64) ? up(N * Mp * K * 8) : up(w32_floats(N, Mp, K) * 4);
+  if (w) {
+    w->Xi = (double*)base;
+    w->Ft = (double*)(base + bXi);
+    w->Sp = (double*)(base + bXi + bFt);
+    w->Pbuf = P->pslots > 0 ? (double*)(base + bXi + bFt + bSp) : nullptr;
+    char* wb = base + bXi + bFt + bSp + bP;
+    w->W = (P->prec == TD_PREC_F64) ? (double*)wb : nullptr;
+    w->W32 = (P->prec == TD_PREC_F64) ? nullptr : (float*)wb;
+  }
+  if (clear_doubles) *clear_doubles = (bXi + bFt + bSp + bP) / 8;
+  return bXi + bFt + bSp + bP + bW;
+}
+
+}  // namespace
+
 extern "C" {
 
 td_status tridiag_factor(const td_desc* desc, const double* A, const double* B, const double* C, void* stream,
@@ -1714,6 +1771,44 @@ td_status tridiag_solve(td_plan plan, const double* F, int64_t ldf, double* X, i
     const td_status code = (e.e == hipErrorOutOfMemory) ? TD_ENOMEM : TD_EHIP;
     return fail(code, std::string("HIP error ") + hipGetErrorString(e.e) + " in " + e.where);
   }
+}
+
+td_status tridiag_solve_noalloc(td_plan plan, const double* F, int64_t ldf, double* X, int64_t ldx, int64_t K,
+                                void* stream) {
+  if (!plan) return fail(TD_EINVAL, "null plan");
+  g_err.clear();
+  td_plan_s* P = plan;
+  const int64_t n = P->N * P->M;
+  if (K < 0 || ldf < n || ldx < n) return fail(TD_EINVAL, "K < 0 or leading dimension below N*M");
+  if (K > INT_MAX / 2) return fail(TD_EINVAL, "K too large");
+  if (K == 0) return TD_OK;
+  if (!F || !X) return fail(TD_EINVAL, "null F or X");
+  const char* f0 = (const char*)F;
+  const char* f1 = (const char*)(F + (K - 1) * ldf + n);
+  const char* x0 = (const char*)X;
+  const char* x1 = (const char*)(X + (K - 1) * ldx + n);
+  if (f0 < x1 && x0 < f1) return fail(TD_EINVAL, "X overlaps F");
+  const int64_t need = scratch_layout(P, K, nullptr, nullptr, nullptr);
+  if (need > (int64_t)kScratchBytes)
+    return fail(TD_EINVAL, "the solve needs " + std::to_string(need) + " bytes of workspace, above the fixed " +
+                               std::to_string(kScratchBytes) + "-byte scratch array of tridiag_solve_noalloc");
+  const hipStream_t st = (hipStream_t)stream;
+  try {
+    void* base = nullptr;
+    HIPCHK(scratch_address(&base));
+    Work w{};
+    int64_t nclear = 0;
+    scratch_layout(P, K, (char*)base, &w, &nclear);
+    // the array keeps the previous call's contents: the interface solution's zero end blocks and
+    // the pieces a pass reads before writing (padded rows) start from zero
+    HIPCHK(launch_fill((double*)base, nclear, 0.0, st));
+    P->last_stream = st;
+    P->first_pass = false;
+    solve_pass(P, w, F, ldf, X, ldx, K, false, st);
+  } catch (const HipFail& e) {
+    return fail(TD_EHIP, std::string("HIP error ") + hipGetErrorString(e.e) + " in " + e.where);
+  }
+  return TD_OK;
 }
 
 td_status tridiag_solve_adjoint(td_plan plan, const double* G, int64_t ldg, double* Lam, int64_t ldl, int64_t K,
