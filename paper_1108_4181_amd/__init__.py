@@ -319,20 +319,17 @@ class ShiftedSolve(torch.autograd.Function):
 
     Backward: Lam = P^{-T} dL/dX (the factored transpose), dL/dF = Lam and
     dL/dsigma = -sum_k Lam o X (the diagonal entries of dL/dP = -Lam X^T).
+    The plan comes from `solver` (a ShiftedSolver), which refactors only when sigma changes.
     """
 
     @staticmethod
-    def forward(ctx, F, sigma, base_C, A, B, subdomains, sweep_prec, refine):
-        N, M = sigma.shape
-        C = base_C.clone()
-        C[:, 1, :] += sigma
-        plan = Plan(A, B, C.contiguous(), N, M, "diag", "diag", "tridiag", subdomains=subdomains,
-                    sweep_prec=sweep_prec, adjoint=True)
-        X = plan.solve(F.contiguous(), refine=refine)
-        ctx.plan = plan
-        ctx.refine = refine
+    def forward(ctx, F, sigma, solver):
+        plan = solver.plan_for(sigma)
+        X = plan.solve(F.contiguous(), refine=solver.refine)
+        ctx.plan = plan                 # kept alive until backward, even if the solver refactors
+        ctx.refine = solver.refine
         ctx.save_for_backward(X)
-        ctx.NM = (N, M)
+        ctx.NM = tuple(sigma.shape)
         return X
 
     @staticmethod
@@ -340,11 +337,42 @@ class ShiftedSolve(torch.autograd.Function):
         (X,) = ctx.saved_tensors
         Lam = ctx.plan.solve_adjoint(gX.contiguous(), refine=ctx.refine)
         dsig = diag_grad(Lam, X).view(*ctx.NM)
-        return Lam, dsig, None, None, None, None, None, None
+        return Lam, dsig, None
+
+
+class ShiftedSolver:
+    """Differentiable X = P(sigma)^{-1} F for the shifted system C_j = tridiag(sub_j, base_j + sigma_j,
+    super_j), A_j, B_j fixed (diagonal; base_C tridiagonal [N][3][M]).  The plan, with its transposed
+    factor for the backward pass, is kept between calls and rebuilt only when sigma changes (compared
+    by value on the device), so repeated gradient steps at one sigma pay one factor."""
+
+    def __init__(self, base_C, A, B, subdomains=0, sweep_prec="f64", refine=None, k_hint=512):
+        self.base_C, self.A, self.B = _dev(base_C, "base_C"), _dev(A, "A"), _dev(B, "B")
+        self.subdomains, self.sweep_prec, self.refine, self.k_hint = subdomains, sweep_prec, refine, k_hint
+        self._sigma = None
+        self._plan = None
+        self.factors = 0                # number of factorizations done
+
+    def plan_for(self, sigma):
+        sigma = sigma.detach()
+        if self._plan is None or self._sigma.shape != sigma.shape or not torch.equal(self._sigma, sigma):
+            N, M = sigma.shape
+            C = self.base_C.clone()
+            C[:, 1, :] += sigma
+            self._plan = Plan(self.A, self.B, C.contiguous(), N, M, "diag", "diag", "tridiag",
+                              subdomains=self.subdomains, sweep_prec=self.sweep_prec, adjoint=True,
+                              k_hint=self.k_hint)
+            self._sigma = sigma.clone()
+            self.factors += 1
+        return self._plan
+
+    def __call__(self, F, sigma):
+        return ShiftedSolve.apply(F, sigma, self)
 
 
 def shifted_solve(F, sigma, base_C, A, B, subdomains=0, sweep_prec="f64", refine=None):
-    return ShiftedSolve.apply(F, sigma, base_C, A, B, subdomains, sweep_prec, refine)
+    """One-shot form of ShiftedSolver (factors P(sigma) on every call)."""
+    return ShiftedSolver(base_C, A, B, subdomains, sweep_prec, refine)(F, sigma)
 
 
 class Batch:

@@ -12,7 +12,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libtridiag.so")
 
-SOURCES = ["kernels_f64.hip", "kernels_lp.hip", "kernels_batched.hip", "kernels_schur.hip", "plan.cpp", "schur.cpp"]
+SOURCES = ["kernels_f64.hip", "kernels_gj.hip", "kernels_lp.hip", "kernels_batched.hip", "kernels_schur.hip", "plan.cpp", "schur.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -27,9 +27,13 @@ FLAGS = [
 ]
 
 
+# per-file extra flags (none at present)
+FILE_FLAGS: dict = {}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *FILE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")

@@ -151,6 +151,12 @@ hipError_t launch_level_combine(const CombArgs& a, hipStream_t st);
 hipError_t launch_sweep(const SweepArgs& a, hipStream_t st);
 hipError_t launch_superpose(const SupArgs& a, hipStream_t st);
 hipError_t launch_gj(const GJArgs& a, hipStream_t st);
+// compact inputs of P^T from those of P (formats: A' has B's, B' has A's, C' has C's)
+hipError_t launch_transpose_inputs(double* At, double* Bt, double* Ct, const double* A, int fmtA, const double* B,
+                                   int fmtB, const double* C, int fmtC, int N, int M, hipStream_t st);
+// Dinv_t[row] = Dinv[row]^T, alpha_t[row] = Dinv_t[row] diag(bdiag_t[row])
+hipError_t launch_transpose_scale(double* Dinv_t, double* alpha_t, const double* Dinv, const double* bdiag_t,
+                                  const int64_t* rows, int nrows, int Mp, hipStream_t st);
 int bgemm_coltile(int ncols);    // columns per work-group chosen for ncols
 int sweep_coltile(int Mp, int K);
 

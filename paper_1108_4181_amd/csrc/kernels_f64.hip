@@ -202,436 +202,6 @@ hipError_t launch_superpose(const SupArgs& a, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// Batched Gauss-Jordan inversion with partial pivoting (row interchanges chosen
-// by the largest remaining entry of each column; ties go to the lowest row).
-// One work-group per matrix; thread i < Mp owns row i.  Columns are processed in
-// panels of NB: during a panel every thread keeps its row of the panel in
-// registers and publishes it to one of two LDS copies (alternating by column),
-// so that one barrier per column suffices: the pivot row read from the copy of
-// the previous column is never the copy being written.  The panel's combined
-// transform (identity except in the NB pivot-row columns) then updates every
-// other column as one rank-NB product on MFMA, with the next column tile's
-// operands loaded before the current tile's products.  Rows are never
-// physically swapped; the inverse is read out through the pivot permutation.
-// A pivot whose magnitude is not above 1e-14 times the infinity norm of the
-// matrix (or is NaN) marks the matrix singular.
-// ---------------------------------------------------------------------------
-// One step of a wave-wide arg-max: (v, i) against the (v, i) of the lane that the DPP control
-// CTRL selects (rows outside ROWMASK keep their own); larger v wins, ties go to the smaller i.
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ void argmax_dpp_step(double& v, int& i) {
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  const int olo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xF, false);
-  const int ohi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xF, false);
-  const int oi = __builtin_amdgcn_update_dpp(i, i, CTRL, ROWMASK, 0xF, false);
-  const double ov = __hiloint2double(ohi, olo);
-  const bool take = (ov > v) | ((ov == v) & (oi < i));
-  v = take ? ov : v;
-  i = take ? oi : i;
-}
-
-// Wave-wide arg-max with DPP lane moves instead of LDS permutes (the pivot search sits on the
-// column-to-column critical path of the elimination): swaps within quads, half-row and row
-// mirrors, then row broadcasts leave the result in lane 63, which every lane reads.
-__device__ __forceinline__ void wave_argmax(double& v, int& i) {
-  argmax_dpp_step<0xB1, 0xF>(v, i);    // quad_perm [1,0,3,2]
-  argmax_dpp_step<0x4E, 0xF>(v, i);    // quad_perm [2,3,0,1]
-  argmax_dpp_step<0x141, 0xF>(v, i);   // row_half_mirror
-  argmax_dpp_step<0x140, 0xF>(v, i);   // row_mirror
-  argmax_dpp_step<0x142, 0xA>(v, i);   // row_bcast:15 into rows 1 and 3
-  argmax_dpp_step<0x143, 0xC>(v, i);   // row_bcast:31 into rows 2 and 3
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
-  v = __hiloint2double(hi, lo);
-  i = __builtin_amdgcn_readlane(i, 63);
-}
-
-template <int RT, int NT, int NB>
-__global__ void __launch_bounds__(NT) k_gj(GJArgs g) {
-  constexpr int CT = 4;           // 16 columns per update tile
-  constexpr int KT = 4 * CT;
-  extern __shared__ double sm[];
-  const int Mp = g.Mp;
-  double* Pb = sm;                         // [2][NB][Mp]: published panel rows
-  double* Ys = Pb + NB * Mp;               // [NB][Mp]: pivot rows of W, all columns (after the
-                                           // panel's last column, in the copy it no longer uses)
-  double* wv = Pb + 2 * NB * Mp;           // [2][16] per-wave candidate values
-  int* wi = (int*)(wv + 32);               // [2][16] per-wave candidate rows
-  int* pivrow = wi + 32;                   // [Mp]
-  int* invpiv = pivrow + Mp;               // [Mp]
-
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int L = tid & 63, w = tid >> 6, nw = nthr >> 6;
-  const int q = blockIdx.x;
-  if (q >= g.nmat) return;
-  double* W = g.work + (g.work_off ? g.work_off[q] : q * g.wstride);
-  const int rb = w * 16 * RT;
-  const bool owner = tid < Mp;             // nthr >= Mp for every RT choice
-
-  // infinity norm (row sums), one row per thread
-  double rs = 0.0;
-  if (owner)
-    for (int c = 0; c < Mp; ++c) rs += fabs(W[tid + (int64_t)c * Mp]);
-  for (int off = 32; off > 0; off >>= 1) rs = fmax(rs, __shfl_xor(rs, off));
-  if (L == 0) wv[w] = rs;
-  __syncthreads();
-  double norm = 0.0;
-  for (int v = 0; v < nw; ++v) norm = fmax(norm, wv[v]);
-  const double tol = 1e-14 * norm;
-  __syncthreads();
-  bool singular = false;
-  bool used = false;
-
-  for (int p0 = 0; p0 < Mp; p0 += NB) {
-    double prv[NB];
-#pragma unroll
-    for (int jj = 0; jj < NB; ++jj) prv[jj] = owner ? W[tid + (int64_t)(p0 + jj) * Mp] : 0.0;
-    if (owner) {
-#pragma unroll
-      for (int jj = 0; jj < NB; ++jj) Pb[jj * Mp + tid] = prv[jj];
-    }
-    // unrolled so that the panel row stays in registers (faster even where the 512-thread
-    // register budget makes it spill)
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int b = j & 1;
-      const double* cur = Pb + b * NB * Mp;        // rows after column j-1
-      double* nxt = Pb + (b ^ 1) * NB * Mp;        // rows after column j
-      // pivot search on the own row
-      double bv = -1.0;
-      int bi = INT_MAX;
-      // prv[j] by selection, so that a rolled loop would not place the array in scratch memory
-      double pj = 0.0;
-#pragma unroll
-      for (int jj = 0; jj < NB; ++jj) pj = (jj == j) ? prv[jj] : pj;
-      if (owner && !used) {
-        const double v = fabs(pj);
-        bv = (v == v) ? v : DBL_MAX;   // NaN ranks first so that it is reported
-        bi = tid;
-      }
-      wave_argmax(bv, bi);
-      if (L == 0) { wv[16 * b + w] = bv; wi[16 * b + w] = bi; }
-      __syncthreads();
-      double b2 = wv[16 * b];
-      int r = wi[16 * b];
-      for (int v = 1; v < nw; ++v) {
-        const double ov = wv[16 * b + v];
-        const int oi = wi[16 * b + v];
-        if (ov > b2 || (ov == b2 && oi < r)) { b2 = ov; r = oi; }
-      }
-      if (tid == 0) pivrow[p0 + j] = r;
-      const double pv = cur[j * Mp + r];
-      if (!(fabs(pv) > tol)) singular = true;
-      const double ipv = 1.0 / pv;
-      if (owner) {
-        if (tid == r) {
-#pragma unroll
-          for (int jj = 0; jj < NB; ++jj) prv[jj] = (jj == j) ? ipv : prv[jj] * ipv;
-          used = true;
-        } else {
-          const double f = pj;
-#pragma unroll
-          for (int jj = 0; jj < NB; ++jj) {
-            const double pr = (jj == j) ? ipv : cur[jj * Mp + r] * ipv;
-            prv[jj] = ((jj == j) ? 0.0 : prv[jj]) - f * pr;
-          }
-        }
-#pragma unroll
-        for (int jj = 0; jj < NB; ++jj) nxt[jj * Mp + tid] = prv[jj];
-      }
-    }
-    // the last column (NB - 1, odd) published into copy 0
-    __syncthreads();
-    const double* Pn = Pb;
-    for (int e = tid; e < NB * Mp; e += nthr) {
-      const int jj = e / Mp, c = e % Mp;
-      Ys[jj * Mp + c] = W[pivrow[p0 + jj] + (int64_t)c * Mp];
-    }
-    __syncthreads();
-    // rank-NB update of all other columns: W[:, c] += (Pn - E_R) * W[R, c]
-    double av[NB / 4][RT];
-#pragma unroll
-    for (int kk = 0; kk < NB / 4; ++kk) {
-      const int k = 4 * kk + (L >> 4);
-      const int pr = pivrow[p0 + k];
-#pragma unroll
-      for (int t = 0; t < RT; ++t) {
-        const int row = rb + 16 * t + (L & 15);
-        av[kk][t] = Pn[k * Mp + row] - (row == pr ? 1.0 : 0.0);
-      }
-    }
-    const int ntile = Mp / KT;
-    auto load_tile = [&](double (&acc)[RT][CT], int tile) {
-      const int c0 = tile * KT;
-#pragma unroll
-      for (int t = 0; t < RT; ++t) {
-        const int row = rb + 16 * t + out_row(L);
-#pragma unroll
-        for (int c = 0; c < CT; ++c) acc[t][c] = W[row + (int64_t)(c0 + out_col(L) * CT + c) * Mp];
-      }
-    };
-    auto update_tile = [&](double (&acc)[RT][CT], int tile) {
-      const int c0 = tile * KT;
-#pragma unroll
-      for (int kk = 0; kk < NB / 4; ++kk) {
-        const int k = 4 * kk + (L >> 4);
-        const double* bp = &Ys[k * Mp + c0 + (L & 3) * CT];
-        double bb[CT];
-#pragma unroll
-        for (int c = 0; c < CT; ++c) bb[c] = bp[c];
-#pragma unroll
-        for (int t = 0; t < RT; ++t)
-#pragma unroll
-          for (int c = 0; c < CT; ++c) acc[t][c] = mfma4(av[kk][t], bb[c], acc[t][c]);
-      }
-#pragma unroll
-      for (int t = 0; t < RT; ++t) {
-        const int row = rb + 16 * t + out_row(L);
-#pragma unroll
-        for (int c = 0; c < CT; ++c) W[row + (int64_t)(c0 + out_col(L) * CT + c) * Mp] = acc[t][c];
-      }
-    };
-    // the column tiles other than the panel's own (NB a multiple of KT), in order; four register buffers
-    // rotate so that every tile's operands are requested three tiles ahead of their use
-    constexpr int PT = NB / KT;               // tiles covered by the panel
-    const int ptile = p0 / KT;
-    const int cnt = ntile - PT;
-    auto tile_of = [&](int n) { return n < ptile ? n : n + PT; };
-    double tb0[RT][CT], tb1[RT][CT], tb2[RT][CT], tb3[RT][CT];
-    if (cnt > 0) load_tile(tb0, tile_of(0));
-    if (cnt > 1) load_tile(tb1, tile_of(1));
-    if (cnt > 2) load_tile(tb2, tile_of(2));
-    for (int n = 0; n < cnt; n += 4) {
-      if (n + 3 < cnt) load_tile(tb3, tile_of(n + 3));
-      update_tile(tb0, tile_of(n));
-      if (n + 1 >= cnt) break;
-      if (n + 4 < cnt) load_tile(tb0, tile_of(n + 4));
-      update_tile(tb1, tile_of(n + 1));
-      if (n + 2 >= cnt) break;
-      if (n + 5 < cnt) load_tile(tb1, tile_of(n + 5));
-      update_tile(tb2, tile_of(n + 2));
-      if (n + 3 >= cnt) break;
-      if (n + 6 < cnt) load_tile(tb2, tile_of(n + 6));
-      update_tile(tb3, tile_of(n + 3));
-    }
-    for (int e = tid; e < NB * Mp; e += nthr) {
-      const int i = e % Mp, jj = e / Mp;
-      W[i + (int64_t)(p0 + jj) * Mp] = Pn[jj * Mp + i];
-    }
-    __syncthreads();
-  }
-  if (tid == 0 && singular) atomicMin(g.bad, g.tag[q]);
-  // inverse: Dinv[c][pivrow[c']] = S[pivrow[c]][c']
-  for (int c = tid; c < Mp; c += nthr) invpiv[pivrow[c]] = c;
-  __syncthreads();
-  double* out = g.out + g.out_off[q];
-  double* al = g.alpha ? g.alpha + g.out_off[q] : nullptr;
-  const double* bd = g.alpha ? g.bdiag + g.bd_off[q] : nullptr;
-  for (int e = tid; e < Mp * Mp; e += nthr) {
-    const int row = e % Mp, oc = e / Mp;
-    const double v = W[pivrow[row] + (int64_t)invpiv[oc] * Mp];
-    out[row + (int64_t)oc * Mp] = v;
-    if (al) al[row + (int64_t)oc * Mp] = v * bd[oc];
-  }
-}
-
-// The same elimination for blocks above 256 rows, where two LDS copies of the panel and the
-// register-resident rows do not fit: the panel stays in one LDS copy, the pivot row is formed by
-// one thread between barriers, and each column tile of the update stages its pivot rows.
-template <int RT>
-__global__ void __launch_bounds__(512) k_gj_big(GJArgs g) {
-  constexpr int NB = 16;
-  constexpr int CT = 4;           // 16 columns per update tile
-  constexpr int KT = 4 * CT;
-  constexpr int SBY = KT + 2;
-  extern __shared__ double sm[];
-  const int Mp = g.Mp;
-  double* Pn = sm;                         // [NB][Mp]
-  double* Ys = Pn + NB * Mp;               // [NB][SBY]
-  double* prow = Ys + NB * SBY;            // [NB]
-  double* redv = prow + NB;                // [32]: per-wave reduction values, [16] = singular flag
-  int* pivrow = (int*)(redv + 32);         // [Mp]
-  int* used = pivrow + Mp;                 // [Mp]
-  int* redi = used + Mp;                   // [16]
-
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int L = tid & 63, w = tid >> 6, nw = nthr >> 6;
-  const int q = blockIdx.x;
-  if (q >= g.nmat) return;
-  double* W = g.work + (g.work_off ? g.work_off[q] : q * g.wstride);
-  const int rb = w * 16 * RT;
-
-  // infinity norm (row sums), one row per thread (nthr >= Mp)
-  double rs = 0.0;
-  if (tid < Mp) {
-    for (int c = 0; c < Mp; ++c) rs += fabs(W[tid + (int64_t)c * Mp]);
-    used[tid] = 0;
-  }
-  for (int off = 32; off > 0; off >>= 1) rs = fmax(rs, __shfl_xor(rs, off));
-  if (L == 0) redv[w] = rs;
-  __syncthreads();
-  double norm = 0.0;
-  for (int v = 0; v < nw; ++v) norm = fmax(norm, redv[v]);
-  const double tol = 1e-14 * norm;
-  __syncthreads();
-  bool singular = false;
-
-  for (int p0 = 0; p0 < Mp; p0 += NB) {
-    for (int e = tid; e < NB * Mp; e += nthr) {
-      const int i = e % Mp, jj = e / Mp;
-      Pn[jj * Mp + i] = W[i + (int64_t)(p0 + jj) * Mp];
-    }
-    __syncthreads();
-    for (int j = 0; j < NB; ++j) {
-      // pivot search over unused rows
-      double bv = -1.0;
-      int bi = INT_MAX;
-      for (int i = tid; i < Mp; i += nthr) {
-        if (!used[i]) {
-          const double v = fabs(Pn[j * Mp + i]);
-          const double vv = (v == v) ? v : DBL_MAX;  // NaN ranks first so that it is reported
-          if (vv > bv || (vv == bv && i < bi)) { bv = vv; bi = i; }
-        }
-      }
-      wave_argmax(bv, bi);
-      if (L == 0) { redv[w] = bv; redi[w] = bi; }
-      __syncthreads();
-      if (tid == 0) {
-        double b2 = redv[0];
-        int i2 = redi[0];
-        for (int v = 1; v < nw; ++v)
-          if (redv[v] > b2 || (redv[v] == b2 && redi[v] < i2)) { b2 = redv[v]; i2 = redi[v]; }
-        pivrow[p0 + j] = i2;
-        used[i2] = 1;
-        const double pv = Pn[j * Mp + i2];
-        redv[16] = (fabs(pv) > tol) ? 0.0 : 1.0;
-        for (int jj = 0; jj < NB; ++jj) prow[jj] = (jj == j) ? 1.0 / pv : Pn[jj * Mp + i2] / pv;
-      }
-      __syncthreads();
-      if (redv[16] != 0.0) singular = true;
-      const int r = pivrow[p0 + j];
-      if (tid < Mp) {
-        const int i = tid;
-        if (i == r) {
-#pragma unroll
-          for (int jj = 0; jj < NB; ++jj) Pn[jj * Mp + i] = prow[jj];
-        } else {
-          const double f = Pn[j * Mp + i];
-#pragma unroll
-          for (int jj = 0; jj < NB; ++jj) Pn[jj * Mp + i] = (jj == j ? 0.0 : Pn[jj * Mp + i]) - f * prow[jj];
-        }
-      }
-      __syncthreads();
-    }
-    // rank-NB update of all other columns: W[:, c] += (Pn - E_R) * W[R, c]
-    for (int c0 = 0; c0 < Mp; c0 += KT) {
-      if (c0 + KT > p0 && c0 < p0 + NB) continue;  // tile lies inside the panel (NB == KT)
-      for (int e = tid; e < NB * KT; e += nthr) {
-        const int jj = e / KT, c = e % KT;
-        Ys[jj * SBY + c] = W[pivrow[p0 + jj] + (int64_t)(c0 + c) * Mp];
-      }
-      __syncthreads();
-      double acc[RT][CT];
-#pragma unroll
-      for (int t = 0; t < RT; ++t) {
-        const int row = rb + 16 * t + out_row(L);
-#pragma unroll
-        for (int c = 0; c < CT; ++c) acc[t][c] = W[row + (int64_t)(c0 + out_col(L) * CT + c) * Mp];
-      }
-#pragma unroll
-      for (int kk = 0; kk < NB / 4; ++kk) {
-        const int k = 4 * kk + (L >> 4);
-        const int pr = pivrow[p0 + k];
-        double av[RT];
-#pragma unroll
-        for (int t = 0; t < RT; ++t) {
-          const int row = rb + 16 * t + (L & 15);
-          av[t] = Pn[k * Mp + row] - (row == pr ? 1.0 : 0.0);
-        }
-        const double* bp = &Ys[k * SBY + (L & 3) * CT];
-        double b[CT];
-#pragma unroll
-        for (int c = 0; c < CT; ++c) b[c] = bp[c];
-#pragma unroll
-        for (int t = 0; t < RT; ++t)
-#pragma unroll
-          for (int c = 0; c < CT; ++c) acc[t][c] = mfma4(av[t], b[c], acc[t][c]);
-      }
-#pragma unroll
-      for (int t = 0; t < RT; ++t) {
-        const int row = rb + 16 * t + out_row(L);
-#pragma unroll
-        for (int c = 0; c < CT; ++c) W[row + (int64_t)(c0 + out_col(L) * CT + c) * Mp] = acc[t][c];
-      }
-      __syncthreads();
-    }
-    for (int e = tid; e < NB * Mp; e += nthr) {
-      const int i = e % Mp, jj = e / Mp;
-      W[i + (int64_t)(p0 + jj) * Mp] = Pn[jj * Mp + i];
-    }
-    __syncthreads();
-  }
-  if (tid == 0 && singular) atomicMin(g.bad, g.tag[q]);
-  // inverse: Dinv[c][pivrow[c']] = S[pivrow[c]][c']
-  int* invpiv = used;  // reuse
-  for (int c = tid; c < Mp; c += nthr) invpiv[pivrow[c]] = c;
-  __syncthreads();
-  double* out = g.out + g.out_off[q];
-  double* al = g.alpha ? g.alpha + g.out_off[q] : nullptr;
-  const double* bd = g.alpha ? g.bdiag + g.bd_off[q] : nullptr;
-  for (int e = tid; e < Mp * Mp; e += nthr) {
-    const int row = e % Mp, oc = e / Mp;
-    const double v = W[pivrow[row] + (int64_t)invpiv[oc] * Mp];
-    out[row + (int64_t)oc * Mp] = v;
-    if (al) al[row + (int64_t)oc * Mp] = v * bd[oc];
-  }
-}
-
-template <int RT, int NT, int NB>
-static hipError_t launch_gj_cfg(const GJArgs& g, int nthr, hipStream_t st) {
-  const size_t lds = (size_t)(2 * NB * g.Mp + 32) * sizeof(double) + (size_t)(32 + 2 * g.Mp) * sizeof(int);
-  hipError_t e =
-      hipFuncSetAttribute((const void*)k_gj<RT, NT, NB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_gj<RT, NT, NB>), dim3(g.nmat), dim3(nthr), lds, st, g);
-  return hipGetLastError();
-}
-
-// work-groups of at most 256 threads get the larger register budget of that bound
-template <int RT>
-static hipError_t launch_gj_rt(const GJArgs& g, hipStream_t st) {
-  const int nthr = g.Mp / (16 * RT) * 64;
-  if (g.Mp > 256) {
-    const size_t lds = (size_t)(16 * g.Mp + 16 * 18 + 16 + 32) * sizeof(double) + (size_t)(2 * g.Mp + 16) * sizeof(int);
-    hipError_t e = hipFuncSetAttribute((const void*)k_gj_big<RT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_gj_big<RT>), dim3(g.nmat), dim3(nthr), lds, st, g);
-    return hipGetLastError();
-  }
-  // panels of 32 columns halve the passes of the update over the matrix where the block size
-  // divides into them and the two LDS copies fit; 16 otherwise
-  if constexpr (RT == 4) {   // Mp == 256 here: 256 threads
-    return launch_gj_cfg<RT, 256, 32>(g, nthr, st);
-  } else {
-    if (g.Mp % 32 == 0) {
-      if (nthr <= 256) return launch_gj_cfg<RT, 256, 32>(g, nthr, st);
-      return launch_gj_cfg<RT, 512, 32>(g, nthr, st);
-    }
-    if (nthr <= 256) return launch_gj_cfg<RT, 256, 16>(g, nthr, st);
-    return launch_gj_cfg<RT, 512, 16>(g, nthr, st);
-  }
-}
-
-hipError_t launch_gj(const GJArgs& g, hipStream_t st) {
-  if (g.nmat == 0) return hipSuccess;
-  switch (choose_rt(g.Mp)) {
-    case 4: return launch_gj_rt<4>(g, st);
-    case 2: return launch_gj_rt<2>(g, st);
-    default: return launch_gj_rt<1>(g, st);
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Element-wise helpers of the factor
 // ---------------------------------------------------------------------------
 

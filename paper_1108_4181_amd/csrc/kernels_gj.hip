@@ -1,0 +1,810 @@
+// Batched Gauss-Jordan inversion of the factor's diagonal blocks (gfx950): the block inverses
+// D_i^{-1} of the subdomain elimination and the chain inverses of the dichotomy tree, with partial
+// pivoting inside each block.  Float64 products on v_mfma_f64_4x4x4f64 used as 16 x 4 output tiles
+// (lane layout as in kernels_f64.hip: A[L%16][L/16], B[L/16][L%4], D[4*((L/4)%4) + L/16][L%4]).
+#include "device_common.h"
+#include "internal.h"
+
+#include <algorithm>
+#include <cfloat>
+#include <climits>
+#include <cstdlib>
+
+namespace td {
+
+// ---------------------------------------------------------------------------
+// Batched Gauss-Jordan inversion with partial pivoting (row interchanges chosen
+// by the largest remaining entry of each column; ties go to the lowest row).
+// One work-group per matrix; thread i < Mp owns row i.  Columns are processed in
+// panels of NB: during a panel every thread keeps its row of the panel in
+// registers and publishes it to one of two LDS copies (alternating by column),
+// so that one barrier per column suffices: the pivot row read from the copy of
+// the previous column is never the copy being written.  The panel's combined
+// transform (identity except in the NB pivot-row columns) then updates every
+// other column as one rank-NB product on MFMA, with the next column tile's
+// operands loaded before the current tile's products.  Rows are never
+// physically swapped; the inverse is read out through the pivot permutation.
+// A pivot whose magnitude is not above 1e-14 times the infinity norm of the
+// matrix (or is NaN) marks the matrix singular.
+// ---------------------------------------------------------------------------
+// One step of a wave-wide arg-max: (v, i) against the (v, i) of the lane that the DPP control
+// CTRL selects (rows outside ROWMASK keep their own); larger v wins, ties go to the smaller i.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ void argmax_dpp_step(double& v, int& i) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int olo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xF, false);
+  const int ohi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xF, false);
+  const int oi = __builtin_amdgcn_update_dpp(i, i, CTRL, ROWMASK, 0xF, false);
+  const double ov = __hiloint2double(ohi, olo);
+  const bool take = (ov > v) | ((ov == v) & (oi < i));
+  v = take ? ov : v;
+  i = take ? oi : i;
+}
+
+// Wave-wide arg-max with DPP lane moves instead of LDS permutes (the pivot search sits on the
+// column-to-column critical path of the elimination): swaps within quads, half-row and row
+// mirrors, then row broadcasts leave the result in lane 63, which every lane reads.
+__device__ __forceinline__ void wave_argmax(double& v, int& i) {
+  argmax_dpp_step<0xB1, 0xF>(v, i);    // quad_perm [1,0,3,2]
+  argmax_dpp_step<0x4E, 0xF>(v, i);    // quad_perm [2,3,0,1]
+  argmax_dpp_step<0x141, 0xF>(v, i);   // row_half_mirror
+  argmax_dpp_step<0x140, 0xF>(v, i);   // row_mirror
+  argmax_dpp_step<0x142, 0xA>(v, i);   // row_bcast:15 into rows 1 and 3
+  argmax_dpp_step<0x143, 0xC>(v, i);   // row_bcast:31 into rows 2 and 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  v = __hiloint2double(hi, lo);
+  i = __builtin_amdgcn_readlane(i, 63);
+}
+
+template <int RT, int NT, int NB>
+__global__ void __launch_bounds__(NT) k_gj(GJArgs g) {
+  constexpr int CT = 4;           // 16 columns per update tile
+  constexpr int KT = 4 * CT;
+  extern __shared__ double sm[];
+  const int Mp = g.Mp;
+  double* Pb = sm;                         // [2][NB][Mp]: published panel rows
+  double* Ys = Pb + NB * Mp;               // [NB][Mp]: pivot rows of W, all columns (after the
+                                           // panel's last column, in the copy it no longer uses)
+  double* wv = Pb + 2 * NB * Mp;           // [2][16] per-wave candidate values
+  int* wi = (int*)(wv + 32);               // [2][16] per-wave candidate rows
+  int* pivrow = wi + 32;                   // [Mp]
+  int* invpiv = pivrow + Mp;               // [Mp]
+
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int L = tid & 63, w = tid >> 6, nw = nthr >> 6;
+  const int q = blockIdx.x;
+  if (q >= g.nmat) return;
+  double* W = g.work + (g.work_off ? g.work_off[q] : q * g.wstride);
+  const int rb = w * 16 * RT;
+  const bool owner = tid < Mp;             // nthr >= Mp for every RT choice
+
+  // infinity norm (row sums), one row per thread
+  double rs = 0.0;
+  if (owner) {
+    // eight loads in flight per thread (Mp is a multiple of 16)
+#pragma unroll 1
+    for (int c0 = 0; c0 < Mp; c0 += 8) {
+      double t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = W[tid + (int64_t)(c0 + u) * Mp];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) rs += fabs(t[u]);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) rs = fmax(rs, __shfl_xor(rs, off));
+  if (L == 0) wv[w] = rs;
+  __syncthreads();
+  double norm = 0.0;
+  for (int v = 0; v < nw; ++v) norm = fmax(norm, wv[v]);
+  const double tol = 1e-14 * norm;
+  __syncthreads();
+  bool singular = false;
+  bool used = false;
+
+  for (int p0 = 0; p0 < Mp; p0 += NB) {
+    double prv[NB];
+#pragma unroll
+    for (int jj = 0; jj < NB; ++jj) prv[jj] = owner ? W[tid + (int64_t)(p0 + jj) * Mp] : 0.0;
+    if (owner) {
+#pragma unroll
+      for (int jj = 0; jj < NB; ++jj) Pb[jj * Mp + tid] = prv[jj];
+    }
+    // unrolled so that the panel row stays in registers (faster even where the 512-thread
+    // register budget makes it spill)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int b = j & 1;
+      const double* cur = Pb + b * NB * Mp;        // rows after column j-1
+      double* nxt = Pb + (b ^ 1) * NB * Mp;        // rows after column j
+      // pivot search on the own row
+      double bv = -1.0;
+      int bi = INT_MAX;
+      // prv[j] by selection, so that a rolled loop would not place the array in scratch memory
+      double pj = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < NB; ++jj) pj = (jj == j) ? prv[jj] : pj;
+      if (owner && !used) {
+        const double v = fabs(pj);
+        bv = (v == v) ? v : DBL_MAX;   // NaN ranks first so that it is reported
+        bi = tid;
+      }
+      wave_argmax(bv, bi);
+      if (L == 0) { wv[16 * b + w] = bv; wi[16 * b + w] = bi; }
+      __syncthreads();
+      double b2 = wv[16 * b];
+      int r = wi[16 * b];
+      for (int v = 1; v < nw; ++v) {
+        const double ov = wv[16 * b + v];
+        const int oi = wi[16 * b + v];
+        if (ov > b2 || (ov == b2 && oi < r)) { b2 = ov; r = oi; }
+      }
+      if (tid == 0) pivrow[p0 + j] = r;
+      const double pv = cur[j * Mp + r];
+      if (!(fabs(pv) > tol)) singular = true;
+      const double ipv = 1.0 / pv;
+      if (owner) {
+        if (tid == r) {
+#pragma unroll
+          for (int jj = 0; jj < NB; ++jj) prv[jj] = (jj == j) ? ipv : prv[jj] * ipv;
+          used = true;
+        } else {
+          const double fi = pj * ipv;   // row -= pj * (pivot row / pivot); column j <- -pj / pivot
+#pragma unroll
+          for (int jj = 0; jj < NB; ++jj) prv[jj] = (jj == j) ? -fi : prv[jj] - fi * cur[jj * Mp + r];
+        }
+#pragma unroll
+        for (int jj = 0; jj < NB; ++jj) nxt[jj * Mp + tid] = prv[jj];
+      }
+    }
+    // the last column (NB - 1, odd) published into copy 0
+    __syncthreads();
+    const double* Pn = Pb;
+    // pivot rows of W: four loads in flight per thread (clamped in-range indices, guarded stores)
+#pragma unroll 1
+    for (int e0 = tid; e0 < NB * Mp; e0 += 4 * nthr) {
+      double t[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = min(e0 + u * nthr, NB * Mp - 1);
+        t[u] = W[pivrow[p0 + e / Mp] + (int64_t)(e % Mp) * Mp];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * nthr;
+        if (e < NB * Mp) Ys[e] = t[u];
+      }
+    }
+    __syncthreads();
+    // rank-NB update of all other columns: W[:, c] += (Pn - E_R) * W[R, c]
+    double av[NB / 4][RT];
+#pragma unroll
+    for (int kk = 0; kk < NB / 4; ++kk) {
+      const int k = 4 * kk + (L >> 4);
+      const int pr = pivrow[p0 + k];
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int row = rb + 16 * t + (L & 15);
+        av[kk][t] = Pn[k * Mp + row] - (row == pr ? 1.0 : 0.0);
+      }
+    }
+    const int ntile = Mp / KT;
+    auto load_tile = [&](double (&acc)[RT][CT], int tile) {
+      const int c0 = tile * KT;
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int row = rb + 16 * t + out_row(L);
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[t][c] = W[row + (int64_t)(c0 + out_col(L) * CT + c) * Mp];
+      }
+    };
+    auto update_tile = [&](double (&acc)[RT][CT], int tile) {
+      const int c0 = tile * KT;
+#pragma unroll
+      for (int kk = 0; kk < NB / 4; ++kk) {
+        const int k = 4 * kk + (L >> 4);
+        const double* bp = &Ys[k * Mp + c0 + (L & 3) * CT];
+        double bb[CT];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) bb[c] = bp[c];
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+          for (int c = 0; c < CT; ++c) acc[t][c] = mfma4(av[kk][t], bb[c], acc[t][c]);
+      }
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int row = rb + 16 * t + out_row(L);
+#pragma unroll
+        for (int c = 0; c < CT; ++c) W[row + (int64_t)(c0 + out_col(L) * CT + c) * Mp] = acc[t][c];
+      }
+    };
+    // the column tiles other than the panel's own (NB a multiple of KT), in order; four register buffers
+    // rotate so that every tile's operands are requested three tiles ahead of their use
+    constexpr int PT = NB / KT;               // tiles covered by the panel
+    const int ptile = p0 / KT;
+    const int cnt = ntile - PT;
+    auto tile_of = [&](int n) { return n < ptile ? n : n + PT; };
+    double tb0[RT][CT], tb1[RT][CT], tb2[RT][CT], tb3[RT][CT];
+    if (cnt > 0) load_tile(tb0, tile_of(0));
+    if (cnt > 1) load_tile(tb1, tile_of(1));
+    if (cnt > 2) load_tile(tb2, tile_of(2));
+    for (int n = 0; n < cnt; n += 4) {
+      if (n + 3 < cnt) load_tile(tb3, tile_of(n + 3));
+      update_tile(tb0, tile_of(n));
+      if (n + 1 >= cnt) break;
+      if (n + 4 < cnt) load_tile(tb0, tile_of(n + 4));
+      update_tile(tb1, tile_of(n + 1));
+      if (n + 2 >= cnt) break;
+      if (n + 5 < cnt) load_tile(tb1, tile_of(n + 5));
+      update_tile(tb2, tile_of(n + 2));
+      if (n + 3 >= cnt) break;
+      if (n + 6 < cnt) load_tile(tb2, tile_of(n + 6));
+      update_tile(tb3, tile_of(n + 3));
+    }
+    for (int e = tid; e < NB * Mp; e += nthr) {
+      const int i = e % Mp, jj = e / Mp;
+      W[i + (int64_t)(p0 + jj) * Mp] = Pn[jj * Mp + i];
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && singular) atomicMin(g.bad, g.tag[q]);
+  // inverse: Dinv[c][pivrow[c']] = S[pivrow[c]][c']
+  for (int c = tid; c < Mp; c += nthr) invpiv[pivrow[c]] = c;
+  __syncthreads();
+  double* out = g.out + g.out_off[q];
+  double* al = g.alpha ? g.alpha + g.out_off[q] : nullptr;
+  const double* bd = g.alpha ? g.bdiag + g.bd_off[q] : nullptr;
+  // eight loads in flight per thread (clamped in-range indices, guarded stores)
+  const int MM = Mp * Mp;
+#pragma unroll 1
+  for (int e0 = tid; e0 < MM; e0 += 8 * nthr) {
+    double t[8], bb[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = min(e0 + u * nthr, MM - 1);
+      t[u] = W[pivrow[e % Mp] + (int64_t)invpiv[e / Mp] * Mp];
+      bb[u] = al ? bd[e / Mp] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * nthr;
+      if (e < MM) {
+        out[e] = t[u];
+        if (al) al[e] = t[u] * bb[u];
+      }
+    }
+  }
+}
+
+// The same elimination for blocks above 256 rows, where two LDS copies of the panel and the
+// register-resident rows do not fit: the panel stays in one LDS copy, the pivot row is formed by
+// one thread between barriers, and each column tile of the update stages its pivot rows.
+template <int RT>
+__global__ void __launch_bounds__(512) k_gj_big(GJArgs g) {
+  constexpr int NB = 16;
+  constexpr int CT = 4;           // 16 columns per update tile
+  constexpr int KT = 4 * CT;
+  constexpr int SBY = KT + 2;
+  extern __shared__ double sm[];
+  const int Mp = g.Mp;
+  double* Pn = sm;                         // [NB][Mp]
+  double* Ys = Pn + NB * Mp;               // [NB][SBY]
+  double* prow = Ys + NB * SBY;            // [NB]
+  double* redv = prow + NB;                // [32]: per-wave reduction values, [16] = singular flag
+  int* pivrow = (int*)(redv + 32);         // [Mp]
+  int* used = pivrow + Mp;                 // [Mp]
+  int* redi = used + Mp;                   // [16]
+
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int L = tid & 63, w = tid >> 6, nw = nthr >> 6;
+  const int q = blockIdx.x;
+  if (q >= g.nmat) return;
+  double* W = g.work + (g.work_off ? g.work_off[q] : q * g.wstride);
+  const int rb = w * 16 * RT;
+
+  // infinity norm (row sums), one row per thread (nthr >= Mp)
+  double rs = 0.0;
+  if (tid < Mp) {
+    for (int c = 0; c < Mp; ++c) rs += fabs(W[tid + (int64_t)c * Mp]);
+    used[tid] = 0;
+  }
+  for (int off = 32; off > 0; off >>= 1) rs = fmax(rs, __shfl_xor(rs, off));
+  if (L == 0) redv[w] = rs;
+  __syncthreads();
+  double norm = 0.0;
+  for (int v = 0; v < nw; ++v) norm = fmax(norm, redv[v]);
+  const double tol = 1e-14 * norm;
+  __syncthreads();
+  bool singular = false;
+
+  for (int p0 = 0; p0 < Mp; p0 += NB) {
+    for (int e = tid; e < NB * Mp; e += nthr) {
+      const int i = e % Mp, jj = e / Mp;
+      Pn[jj * Mp + i] = W[i + (int64_t)(p0 + jj) * Mp];
+    }
+    __syncthreads();
+    for (int j = 0; j < NB; ++j) {
+      // pivot search over unused rows
+      double bv = -1.0;
+      int bi = INT_MAX;
+      for (int i = tid; i < Mp; i += nthr) {
+        if (!used[i]) {
+          const double v = fabs(Pn[j * Mp + i]);
+          const double vv = (v == v) ? v : DBL_MAX;  // NaN ranks first so that it is reported
+          if (vv > bv || (vv == bv && i < bi)) { bv = vv; bi = i; }
+        }
+      }
+      wave_argmax(bv, bi);
+      if (L == 0) { redv[w] = bv; redi[w] = bi; }
+      __syncthreads();
+      if (tid == 0) {
+        double b2 = redv[0];
+        int i2 = redi[0];
+        for (int v = 1; v < nw; ++v)
+          if (redv[v] > b2 || (redv[v] == b2 && redi[v] < i2)) { b2 = redv[v]; i2 = redi[v]; }
+        pivrow[p0 + j] = i2;
+        used[i2] = 1;
+        const double pv = Pn[j * Mp + i2];
+        redv[16] = (fabs(pv) > tol) ? 0.0 : 1.0;
+        for (int jj = 0; jj < NB; ++jj) prow[jj] = (jj == j) ? 1.0 / pv : Pn[jj * Mp + i2] / pv;
+      }
+      __syncthreads();
+      if (redv[16] != 0.0) singular = true;
+      const int r = pivrow[p0 + j];
+      if (tid < Mp) {
+        const int i = tid;
+        if (i == r) {
+#pragma unroll
+          for (int jj = 0; jj < NB; ++jj) Pn[jj * Mp + i] = prow[jj];
+        } else {
+          const double f = Pn[j * Mp + i];
+#pragma unroll
+          for (int jj = 0; jj < NB; ++jj) Pn[jj * Mp + i] = (jj == j ? 0.0 : Pn[jj * Mp + i]) - f * prow[jj];
+        }
+      }
+      __syncthreads();
+    }
+    // rank-NB update of all other columns: W[:, c] += (Pn - E_R) * W[R, c]
+    for (int c0 = 0; c0 < Mp; c0 += KT) {
+      if (c0 + KT > p0 && c0 < p0 + NB) continue;  // tile lies inside the panel (NB == KT)
+      for (int e = tid; e < NB * KT; e += nthr) {
+        const int jj = e / KT, c = e % KT;
+        Ys[jj * SBY + c] = W[pivrow[p0 + jj] + (int64_t)(c0 + c) * Mp];
+      }
+      __syncthreads();
+      double acc[RT][CT];
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int row = rb + 16 * t + out_row(L);
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[t][c] = W[row + (int64_t)(c0 + out_col(L) * CT + c) * Mp];
+      }
+#pragma unroll
+      for (int kk = 0; kk < NB / 4; ++kk) {
+        const int k = 4 * kk + (L >> 4);
+        const int pr = pivrow[p0 + k];
+        double av[RT];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          const int row = rb + 16 * t + (L & 15);
+          av[t] = Pn[k * Mp + row] - (row == pr ? 1.0 : 0.0);
+        }
+        const double* bp = &Ys[k * SBY + (L & 3) * CT];
+        double b[CT];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) b[c] = bp[c];
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+          for (int c = 0; c < CT; ++c) acc[t][c] = mfma4(av[t], b[c], acc[t][c]);
+      }
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int row = rb + 16 * t + out_row(L);
+#pragma unroll
+        for (int c = 0; c < CT; ++c) W[row + (int64_t)(c0 + out_col(L) * CT + c) * Mp] = acc[t][c];
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < NB * Mp; e += nthr) {
+      const int i = e % Mp, jj = e / Mp;
+      W[i + (int64_t)(p0 + jj) * Mp] = Pn[jj * Mp + i];
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && singular) atomicMin(g.bad, g.tag[q]);
+  // inverse: Dinv[c][pivrow[c']] = S[pivrow[c]][c']
+  int* invpiv = used;  // reuse
+  for (int c = tid; c < Mp; c += nthr) invpiv[pivrow[c]] = c;
+  __syncthreads();
+  double* out = g.out + g.out_off[q];
+  double* al = g.alpha ? g.alpha + g.out_off[q] : nullptr;
+  const double* bd = g.alpha ? g.bdiag + g.bd_off[q] : nullptr;
+  for (int e = tid; e < Mp * Mp; e += nthr) {
+    const int row = e % Mp, oc = e / Mp;
+    const double v = W[pivrow[row] + (int64_t)invpiv[oc] * Mp];
+    out[row + (int64_t)oc * Mp] = v;
+    if (al) al[row + (int64_t)oc * Mp] = v * bd[oc];
+  }
+}
+
+// Gauss-Jordan inversion for block sizes that are multiples of 64 (64 ... 512): one thread per row
+// (Mp threads), the panel's NB columns of the thread's row in registers.  Per column every wave
+// finds its best candidate with a DPP arg-max, and the winning lane of each wave publishes that row
+// (NB values) next to its magnitude; after one work-group barrier every thread picks the overall
+// pivot among the waves' candidates (larger magnitude, then smaller row) and reads the pivot row from
+// the winning wave's slot.  Slots alternate between two copies, so one barrier per column suffices and
+// the LDS traffic per column is one row per wave (the all-thread kernel above publishes every row).
+// After the panel, all waves apply the rank-NB update to the other columns on MFMA with four row tiles
+// of 16 rows per wave and tile operands loaded three tiles ahead.
+template <int NB, int NT>
+__global__ void __launch_bounds__(NT) k_gj_cand(GJArgs g) {
+  constexpr int RT = 4;           // 64 rows per wave
+  constexpr int CT = 4;           // 16 columns per update tile
+  constexpr int KT = 4 * CT;
+  extern __shared__ double sm[];
+  const int Mp = g.Mp;                     // a multiple of 64, blockDim.x == Mp
+  double* Pn = sm;                         // [NB][Mp]: the eliminated panel
+  double* Ys = Pn + NB * Mp;               // [NB][Mp]: pivot rows of W, all columns
+  double* cand = Ys + NB * Mp;             // [2][8][NB]: candidate pivot rows of the waves
+  double* cv = cand + 2 * 8 * NB;          // [2][8]: their magnitudes; [16 .. 23]: row-sum maxima
+  int* ci = (int*)(cv + 24);               // [2][8]: their rows
+  int* pivrow = ci + 16;                   // [Mp]
+  int* invpiv = pivrow + Mp;               // [Mp]
+
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int L = tid & 63, w = tid >> 6, nw = nthr >> 6;
+  const int q = blockIdx.x;
+  if (q >= g.nmat) return;
+  double* W = g.work + (g.work_off ? g.work_off[q] : q * g.wstride);
+  const int rb = w * 16 * RT;
+
+  // infinity norm (row sums), one row per thread; eight loads in flight per thread (a loop that
+  // waits for each load before the next spends a memory latency per column)
+  double rs = 0.0;
+#pragma unroll 1
+  for (int c0 = 0; c0 < Mp; c0 += 8) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = W[tid + (int64_t)(c0 + u) * Mp];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) rs += fabs(t[u]);
+  }
+  for (int off = 32; off > 0; off >>= 1) rs = fmax(rs, __shfl_xor(rs, off));
+  if (L == 0) cv[16 + w] = rs;
+  __syncthreads();
+  double norm = 0.0;
+  for (int u = 0; u < nw; ++u) norm = fmax(norm, cv[16 + u]);
+  const double tol = 1e-14 * norm;
+  bool singular = false;
+  bool used = false;
+
+  for (int p0 = 0; p0 < Mp; p0 += NB) {
+    double v[NB];
+#pragma unroll
+    for (int jj = 0; jj < NB; ++jj) v[jj] = W[tid + (int64_t)(p0 + jj) * Mp];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int slot = j & 1;
+      // v[j] by selection, so that a loop the compiler leaves rolled keeps v in registers
+      double vj = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < NB; ++jj) vj = (jj == j) ? v[jj] : vj;
+      double bv = -1.0;
+      int bi = INT_MAX;
+      if (!used) {
+        const double a = fabs(vj);
+        bv = (a == a) ? a : DBL_MAX;   // NaN ranks first so that it is reported
+        bi = tid;
+      }
+      wave_argmax(bv, bi);
+      if (tid == bi) {
+        double* cp = cand + (slot * 8 + w) * NB;
+#pragma unroll
+        for (int jj = 0; jj < NB; ++jj) cp[jj] = v[jj];
+      }
+      if (L == 0) { cv[slot * 8 + w] = bv; ci[slot * 8 + w] = bi; }
+      __syncthreads();
+      double b2 = cv[slot * 8];
+      int r = ci[slot * 8], wr = 0;
+      for (int u = 1; u < nw; ++u) {
+        const double ov = cv[slot * 8 + u];
+        const int oi = ci[slot * 8 + u];
+        if (ov > b2 || (ov == b2 && oi < r)) { b2 = ov; r = oi; wr = u; }
+      }
+      const double* pr = cand + (slot * 8 + wr) * NB;
+      const double pv = pr[j];
+      if (!(fabs(pv) > tol)) singular = true;
+      const double ipv = 1.0 / pv;
+      if (tid == r) {
+#pragma unroll
+        for (int jj = 0; jj < NB; ++jj) v[jj] = (jj == j) ? ipv : v[jj] * ipv;
+        used = true;
+      } else {
+        const double fi = vj * ipv;   // v <- v - v_j * (pivot row / pivot), column j <- -v_j / pivot
+#pragma unroll
+        for (int jj = 0; jj < NB; ++jj) v[jj] = (jj == j) ? -fi : v[jj] - fi * pr[jj];
+      }
+      if (tid == 0) pivrow[p0 + j] = r;
+    }
+#pragma unroll
+    for (int jj = 0; jj < NB; ++jj) Pn[jj * Mp + tid] = v[jj];
+    __syncthreads();
+    // pivot rows of W, column tid of each: eight loads issued before their LDS stores
+#pragma unroll 1
+    for (int j0 = 0; j0 < NB; j0 += 8) {
+      double t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = W[pivrow[p0 + j0 + u] + (int64_t)tid * Mp];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) Ys[(j0 + u) * Mp + tid] = t[u];
+    }
+    __syncthreads();
+    // rank-NB update of all other columns: W[:, c] += (Pn - E_R) * W[R, c]
+    double av[NB / 4][RT];
+#pragma unroll
+    for (int kk = 0; kk < NB / 4; ++kk) {
+      const int k = 4 * kk + (L >> 4);
+      const int prw = pivrow[p0 + k];
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int row = rb + 16 * t + (L & 15);
+        av[kk][t] = Pn[k * Mp + row] - (row == prw ? 1.0 : 0.0);
+      }
+    }
+    const int ntile = Mp / KT;
+    auto load_tile = [&](double (&acc)[RT][CT], int tile) {
+      const int c0 = tile * KT;
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int row = rb + 16 * t + out_row(L);
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[t][c] = W[row + (int64_t)(c0 + out_col(L) * CT + c) * Mp];
+      }
+    };
+    auto update_tile = [&](double (&acc)[RT][CT], int tile) {
+      const int c0 = tile * KT;
+#pragma unroll
+      for (int kk = 0; kk < NB / 4; ++kk) {
+        const int k = 4 * kk + (L >> 4);
+        const double* bp = &Ys[k * Mp + c0 + (L & 3) * CT];
+        double bb[CT];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) bb[c] = bp[c];
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+          for (int c = 0; c < CT; ++c) acc[t][c] = mfma4(av[kk][t], bb[c], acc[t][c]);
+      }
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int row = rb + 16 * t + out_row(L);
+#pragma unroll
+        for (int c = 0; c < CT; ++c) W[row + (int64_t)(c0 + out_col(L) * CT + c) * Mp] = acc[t][c];
+      }
+    };
+    constexpr int PT = NB / KT;               // tiles covered by the panel
+    const int ptile = p0 / KT;
+    const int cnt = ntile - PT;               // >= 2 for Mp >= 64 (NB = 16) or Mp >= 128 (NB = 32)
+    auto tile_of = [&](int n) { return n < ptile ? n : n + PT; };
+    double tb0[RT][CT], tb1[RT][CT], tb2[RT][CT], tb3[RT][CT];
+    if (cnt > 0) load_tile(tb0, tile_of(0));
+    if (cnt > 1) load_tile(tb1, tile_of(1));
+    if (cnt > 2) load_tile(tb2, tile_of(2));
+    for (int n = 0; n < cnt; n += 4) {
+      if (n + 3 < cnt) load_tile(tb3, tile_of(n + 3));
+      update_tile(tb0, tile_of(n));
+      if (n + 1 >= cnt) break;
+      if (n + 4 < cnt) load_tile(tb0, tile_of(n + 4));
+      update_tile(tb1, tile_of(n + 1));
+      if (n + 2 >= cnt) break;
+      if (n + 5 < cnt) load_tile(tb1, tile_of(n + 5));
+      update_tile(tb2, tile_of(n + 2));
+      if (n + 3 >= cnt) break;
+      if (n + 6 < cnt) load_tile(tb2, tile_of(n + 6));
+      update_tile(tb3, tile_of(n + 3));
+    }
+    for (int e = tid; e < NB * Mp; e += nthr) {   // stores only: no load latency to hide
+      const int i = e % Mp, jj = e / Mp;
+      W[i + (int64_t)(p0 + jj) * Mp] = Pn[jj * Mp + i];
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && singular) atomicMin(g.bad, g.tag[q]);
+  // inverse: Dinv[c][pivrow[c']] = S[pivrow[c]][c']
+  invpiv[pivrow[tid]] = tid;
+  __syncthreads();
+  double* out = g.out + g.out_off[q];
+  double* al = g.alpha ? g.alpha + g.out_off[q] : nullptr;
+  const double* bd = g.alpha ? g.bdiag + g.bd_off[q] : nullptr;
+  // thread tid writes row tid of every column; eight columns' loads in flight at a time
+  const int prow_t = pivrow[tid];
+#pragma unroll 1
+  for (int oc0 = 0; oc0 < Mp; oc0 += 8) {
+    double t[8], b[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = W[prow_t + (int64_t)invpiv[oc0 + u] * Mp];
+    if (al) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) b[u] = bd[oc0 + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) out[tid + (int64_t)(oc0 + u) * Mp] = t[u];
+    if (al) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) al[tid + (int64_t)(oc0 + u) * Mp] = t[u] * b[u];
+    }
+  }
+}
+
+template <int NB, int NT>
+static hipError_t launch_gj_cand(const GJArgs& g, hipStream_t st) {
+  const size_t lds = (size_t)(2 * NB * g.Mp + 2 * 8 * NB + 24) * sizeof(double) + (size_t)(16 + 2 * g.Mp) * sizeof(int);
+  hipError_t e = hipFuncSetAttribute((const void*)k_gj_cand<NB, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_gj_cand<NB, NT>), dim3(g.nmat), dim3(g.Mp), lds, st, g);
+  return hipGetLastError();
+}
+
+// TD_GJ_CAND=0 selects the earlier all-thread panel kernels (for comparison)
+static bool gj_cand_disabled() {
+  static const bool off = [] {
+    const char* v = std::getenv("TD_GJ_CAND");
+    return v && v[0] == '0';
+  }();
+  return off;
+}
+
+template <int RT, int NT, int NB>
+static hipError_t launch_gj_cfg(const GJArgs& g, int nthr, hipStream_t st) {
+  const size_t lds = (size_t)(2 * NB * g.Mp + 32) * sizeof(double) + (size_t)(32 + 2 * g.Mp) * sizeof(int);
+  hipError_t e =
+      hipFuncSetAttribute((const void*)k_gj<RT, NT, NB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_gj<RT, NT, NB>), dim3(g.nmat), dim3(nthr), lds, st, g);
+  return hipGetLastError();
+}
+
+// work-groups of at most 256 threads get the larger register budget of that bound
+template <int RT>
+static hipError_t launch_gj_rt(const GJArgs& g, hipStream_t st) {
+  const int nthr = g.Mp / (16 * RT) * 64;
+  if (g.Mp > 256) {
+    const size_t lds = (size_t)(16 * g.Mp + 16 * 18 + 16 + 32) * sizeof(double) + (size_t)(2 * g.Mp + 16) * sizeof(int);
+    hipError_t e = hipFuncSetAttribute((const void*)k_gj_big<RT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_gj_big<RT>), dim3(g.nmat), dim3(nthr), lds, st, g);
+    return hipGetLastError();
+  }
+  // panels of 32 columns halve the passes of the update over the matrix where the block size
+  // divides into them and the two LDS copies fit; 16 otherwise
+  if constexpr (RT == 4) {   // Mp == 256 here: 256 threads
+    return launch_gj_cfg<RT, 256, 32>(g, nthr, st);
+  } else {
+    if (g.Mp % 32 == 0) {
+      if (nthr <= 256) return launch_gj_cfg<RT, 256, 32>(g, nthr, st);
+      return launch_gj_cfg<RT, 512, 32>(g, nthr, st);
+    }
+    if (nthr <= 256) return launch_gj_cfg<RT, 256, 16>(g, nthr, st);
+    return launch_gj_cfg<RT, 512, 16>(g, nthr, st);
+  }
+}
+
+hipError_t launch_gj(const GJArgs& g, hipStream_t st) {
+  if (g.nmat == 0) return hipSuccess;
+  // block sizes that are multiples of 64: candidate-row kernel (32-column panels up to 256 rows,
+  // where four waves get the register budget of 256-thread work-groups; 16-column panels above)
+  if (!gj_cand_disabled() && g.Mp % 64 == 0 && g.Mp >= 128 && g.Mp <= 512)
+    return g.Mp <= 256 ? launch_gj_cand<32, 256>(g, st) : launch_gj_cand<16, 512>(g, st);
+  switch (choose_rt(g.Mp)) {
+    case 4: return launch_gj_rt<4>(g, st);
+    case 2: return launch_gj_rt<2>(g, st);
+    default: return launch_gj_rt<1>(g, st);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Transposed system P^T (blocks C'_j = C_j^T, A'_j = B_{j-1}^T, B'_j = A_{j+1}^T), built on the
+// device from the plan's compact copies of P, and the block inverses of its subdomain elimination
+// taken from those of P: within a subdomain the transposed elimination's pivot blocks are
+// D'_i = D_i^T (induction on C'_i - A'_i D'_{i-1}^{-1} B'_{i-1} = (C_i - A_i D_{i-1}^{-1} B_{i-1})^T),
+// so D'_i^{-1} = (D_i^{-1})^T and alpha'_i = D'_i^{-1} diag(b'_i).
+// ---------------------------------------------------------------------------
+// A' (format fmtB), B' (format fmtA), C' (format fmtC) from A, B, C; one thread per entry
+__global__ void k_transpose_inputs(double* At, double* Bt, double* Ct, const double* A, int fmtA, const double* B,
+                                   int fmtB, const double* C, int fmtC, int N, int M) {
+  const int64_t MM = (int64_t)M * M;
+  const int64_t nA = (fmtB == 1) ? (int64_t)N * M : N * MM;   // A' has B's format
+  const int64_t nB = (fmtA == 1) ? (int64_t)N * M : N * MM;   // B' has A's format
+  const int64_t nC = (fmtC == 2) ? (int64_t)N * 3 * M : N * MM;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nA + nB + nC;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    if (e < nA) {                     // A'_j = B_{j-1}^T, A'_0 = 0
+      if (fmtB == 1) {
+        const int64_t j = e / M, r = e % M;
+        At[e] = j > 0 ? B[(j - 1) * M + r] : 0.0;
+      } else {
+        const int64_t j = e / MM, q = e % MM, r = q % M, c = q / M;   // A'_j(r, c) = B_{j-1}(c, r)
+        At[e] = j > 0 ? B[(j - 1) * MM + c + r * M] : 0.0;
+      }
+    } else if (e < nA + nB) {         // B'_j = A_{j+1}^T, B'_{N-1} = 0
+      const int64_t f = e - nA;
+      if (fmtA == 1) {
+        const int64_t j = f / M, r = f % M;
+        Bt[f] = j + 1 < N ? A[(j + 1) * M + r] : 0.0;
+      } else {
+        const int64_t j = f / MM, q = f % MM, r = q % M, c = q / M;
+        Bt[f] = j + 1 < N ? A[(j + 1) * MM + c + r * M] : 0.0;
+      }
+    } else {                          // C'_j = C_j^T
+      const int64_t f = e - nA - nB;
+      if (fmtC == 2) {                // (sub', diag', super')(r) = (super(r-1), diag(r), sub(r+1))
+        const int64_t j = f / (3 * M), q = f % (3 * M), part = q / M, r = q % M;
+        const double* t = C + j * 3 * M;
+        double v;
+        if (part == 1) v = t[M + r];
+        else if (part == 0) v = r > 0 ? t[2 * M + r - 1] : 0.0;
+        else v = r + 1 < M ? t[r + 1] : 0.0;
+        Ct[f] = v;
+      } else {
+        const int64_t j = f / MM, q = f % MM, r = q % M, c = q / M;
+        Ct[f] = C[j * MM + c + r * M];
+      }
+    }
+  }
+}
+
+hipError_t launch_transpose_inputs(double* At, double* Bt, double* Ct, const double* A, int fmtA, const double* B,
+                                   int fmtB, const double* C, int fmtC, int N, int M, hipStream_t st) {
+  const int64_t MM = (int64_t)M * M;
+  const int64_t tot = ((fmtB == 1) ? (int64_t)N * M : N * MM) + ((fmtA == 1) ? (int64_t)N * M : N * MM) +
+                      ((fmtC == 2) ? (int64_t)N * 3 * M : N * MM);
+  int bx = (int)std::min<int64_t>((tot + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_transpose_inputs, dim3(bx), dim3(256), 0, st, At, Bt, Ct, A, fmtA, B, fmtB, C, fmtC, N, M);
+  return hipGetLastError();
+}
+
+// Dinv_t[row] = Dinv[row]^T and alpha_t[row] = Dinv_t[row] diag(bdiag_t[row]) for the listed rows
+// (Mp x Mp column-major blocks at row * Mp^2); 32 x 32 tiles through LDS so that both the reads and
+// the writes are coalesced (edge tiles guarded when Mp is not a multiple of 32).  Grid: (tiles of
+// the block, rows).
+__global__ void __launch_bounds__(256) k_transpose_scale(double* Dinv_t, double* alpha_t, const double* Dinv,
+                                                         const double* bdiag_t, const int64_t* rows, int Mp) {
+  __shared__ double tile[32][33];
+  const int64_t row = rows[blockIdx.y];
+  const int nt = (Mp + 31) / 32;
+  const int ti = blockIdx.x % nt, tj = blockIdx.x / nt;     // source tile (rows ti, columns tj)
+  const int64_t MM = (int64_t)Mp * Mp;
+  const double* src = Dinv + row * MM;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8 threads
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int c = tj * 32 + ty + 8 * k, r = ti * 32 + tx;
+    if (r < Mp && c < Mp) tile[ty + 8 * k][tx] = src[r + (int64_t)c * Mp];   // tile[c - 32 tj][r - 32 ti]
+  }
+  __syncthreads();
+  // destination: transposed tile at (rows tj, columns ti): out(r', c') = in(c', r')
+  const double* bt = bdiag_t + row * Mp;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int cp = ti * 32 + ty + 8 * k, rp = tj * 32 + tx;
+    if (rp < Mp && cp < Mp) {
+      const double v = tile[tx][ty + 8 * k];
+      Dinv_t[row * MM + rp + (int64_t)cp * Mp] = v;
+      alpha_t[row * MM + rp + (int64_t)cp * Mp] = v * bt[cp];
+    }
+  }
+}
+
+hipError_t launch_transpose_scale(double* Dinv_t, double* alpha_t, const double* Dinv, const double* bdiag_t,
+                                  const int64_t* rows, int nrows, int Mp, hipStream_t st) {
+  if (nrows == 0) return hipSuccess;
+  const int nt = (Mp + 31) / 32;
+  hipLaunchKernelGGL(k_transpose_scale, dim3(nt * nt, nrows), dim3(256), 0, st, Dinv_t, alpha_t, Dinv, bdiag_t, rows,
+                     Mp);
+  return hipGetLastError();
+}
+
+}  // namespace td

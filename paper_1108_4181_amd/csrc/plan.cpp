@@ -302,7 +302,11 @@ int64_t default_subdomains(int64_t N, int64_t K) {
 // Factor: Algorithm 2, step 1 (sub-problems (sub1), (sub2); reduced matrix (red1); rows of the
 // inverse of the reduced matrix for Algorithm 1).
 // ------------------------------------------------------------------------------------------
-void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C, hipStream_t st) {
+// fwd (optional): P is the transposed plan of the factored plan fwd (same partition, diagonal
+// couplings): its compact inputs are transposed on the device from fwd's, and its subdomain block
+// inverses are the transposes of fwd's (no elimination of its own); the rest is factored as usual.
+void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C, hipStream_t st,
+                 const td_plan_s* fwd = nullptr) {
   const int64_t N = P->N, M = P->M, Mp = P->Mp, p = P->p;
   const int64_t MM = Mp * Mp;
   const auto& ks = P->ks;
@@ -315,9 +319,14 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
   P->cA = P->alloc(nA);
   P->cB = P->alloc(nB);
   P->cC = P->alloc(nC);
-  HIPCHK(hipMemcpyAsync(P->cA, A, nA * 8, hipMemcpyDeviceToDevice, st));
-  HIPCHK(hipMemcpyAsync(P->cB, B, nB * 8, hipMemcpyDeviceToDevice, st));
-  HIPCHK(hipMemcpyAsync(P->cC, C, nC * 8, hipMemcpyDeviceToDevice, st));
+  if (fwd) {
+    HIPCHK(launch_transpose_inputs(P->cA, P->cB, P->cC, fwd->cA, fwd->fmtA, fwd->cB, fwd->fmtB, fwd->cC, fwd->fmtC,
+                                   (int)N, (int)M, st));
+  } else {
+    HIPCHK(hipMemcpyAsync(P->cA, A, nA * 8, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(P->cB, B, nB * 8, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(P->cC, C, nC * 8, hipMemcpyDeviceToDevice, st));
+  }
   if (P->fmtA == TD_FMT_DIAG && P->fmtB == TD_FMT_DIAG && P->fmtC == TD_FMT_TRIDIAG)
     HIPCHK(launch_zero_absent(P->cA, P->cB, P->cC, (int)N, (int)M, st));   // for the stencil residual
   P->adiag = P->alloc(N * Mp);
@@ -358,6 +367,15 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
     maxn = std::max(maxn, nint[s]);
   }
 
+  const bool reuse = fwd != nullptr && !P->dense;
+  if (reuse) {   // D'_i^{-1} = (D_i^{-1})^T and alpha'_i for every interior row at once
+    std::vector<int64_t> rows;
+    for (int64_t s = 0; s < p; ++s)
+      for (int64_t i = ks[s] + 1; i < ks[s + 1]; ++i) rows.push_back(i);
+    HIPCHK(launch_transpose_scale(P->Dinv, P->alpha, fwd->Dinv, P->bdiag, pool.put_vec(rows), (int)rows.size(),
+                                  (int)Mp, st));
+  }
+
   // ---- forward elimination inside every subdomain: D_i, D_i^{-1}, alpha_i, Gamma_i
   for (int64_t t = 0; t < maxn; ++t) {
     std::vector<int64_t> rows, outoff, bdoff;
@@ -381,36 +399,38 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
       gam.push_back(d);
     }
     const int nm = (int)rows.size();
-    int64_t* d_rows = pool.put_vec(rows);
-    int32_t* d_first = pool.put_vec(first);
-    HIPCHK(launch_build_D(Dwork, MM, nm, d_rows, d_first, P->cC, P->fmtC, P->adiag, P->alpha, (int)M, (int)Mp, st));
-    if (P->dense && t > 0) {   // D_i -= A_i alpha_{i-1}
-      std::vector<BDesc> da;
-      for (int q = 0; q < nm; ++q) {
-        const int64_t i = rows[q];
-        BDesc d = desc0();
-        d.a_off = i * 2 * MM;
-        d.b_off = (i - 1) * MM;
-        d.c_off = d.cin_off = q * MM;
-        d.kd = d.segrows = (int32_t)Mp;
-        da.push_back(d);
+    if (!reuse) {
+      int64_t* d_rows = pool.put_vec(rows);
+      int32_t* d_first = pool.put_vec(first);
+      HIPCHK(launch_build_D(Dwork, MM, nm, d_rows, d_first, P->cC, P->fmtC, P->adiag, P->alpha, (int)M, (int)Mp, st));
+      if (P->dense && t > 0) {   // D_i -= A_i alpha_{i-1}
+        std::vector<BDesc> da;
+        for (int q = 0; q < nm; ++q) {
+          const int64_t i = rows[q];
+          BDesc d = desc0();
+          d.a_off = i * 2 * MM;
+          d.b_off = (i - 1) * MM;
+          d.c_off = d.cin_off = q * MM;
+          d.kd = d.segrows = (int32_t)Mp;
+          da.push_back(d);
+        }
+        BArgs a = bargs_base((int)Mp);
+        a.alpha = -1.0;
+        a.A = P->ABd; a.lda = Mp;
+        a.B = P->alpha; a.ldb = Mp;
+        a.C = Dwork; a.ldc = Mp;
+        a.Cin = Dwork; a.ldcin = Mp;
+        a.ncols = (int32_t)Mp;
+        run_bgemm(a, da, pool, st);
       }
-      BArgs a = bargs_base((int)Mp);
-      a.alpha = -1.0;
-      a.A = P->ABd; a.lda = Mp;
-      a.B = P->alpha; a.ldb = Mp;
-      a.C = Dwork; a.ldc = Mp;
-      a.Cin = Dwork; a.ldcin = Mp;
-      a.ncols = (int32_t)Mp;
-      run_bgemm(a, da, pool, st);
+      GJArgs g{};
+      g.work = Dwork; g.work_off = nullptr; g.wstride = MM;
+      g.out = P->Dinv; g.out_off = pool.put_vec(outoff);
+      g.alpha = P->dense ? nullptr : P->alpha; g.bdiag = P->bdiag; g.bd_off = pool.put_vec(bdoff);
+      g.tag = pool.put_vec(tag); g.bad = bad;
+      g.nmat = nm; g.Mp = (int32_t)Mp;
+      HIPCHK(launch_gj(g, st));
     }
-    GJArgs g{};
-    g.work = Dwork; g.work_off = nullptr; g.wstride = MM;
-    g.out = P->Dinv; g.out_off = pool.put_vec(outoff);
-    g.alpha = P->dense ? nullptr : P->alpha; g.bdiag = P->bdiag; g.bd_off = pool.put_vec(bdoff);
-    g.tag = pool.put_vec(tag); g.bad = bad;
-    g.nmat = nm; g.Mp = (int32_t)Mp;
-    HIPCHK(launch_gj(g, st));
     if (P->dense) {   // alpha_i = D_i^{-1} B_i, E_i = D_i^{-1} A_i, Gamma_i = E_i Gamma_{i-1}
       std::vector<BDesc> dal, de;
       for (int q = 0; q < nm; ++q) {
@@ -1275,51 +1295,6 @@ int64_t factor_bytes(int64_t N, int64_t M, int64_t p, int fA, int fB, int fC, in
   return b * 8;
 }
 
-// blocks of P^T (compact formats): C'_j = C_j^T, A'_j = B_{j-1}^T, B'_j = A_{j+1}^T; the transposed
-// system's A has B's format and its B has A's format
-void transpose_inputs(const td_plan_s* P, std::vector<double>& A2, std::vector<double>& B2, std::vector<double>& C2) {
-  const int64_t N = P->N, M = P->M;
-  const int64_t sa = (P->fmtA == TD_FMT_DIAG) ? M : M * M;   // per-block sizes of the inputs
-  const int64_t sb = (P->fmtB == TD_FMT_DIAG) ? M : M * M;
-  std::vector<double> a(N * sa), b(N * sb);
-  HIPCHK(hipMemcpy(a.data(), P->cA, N * sa * 8, hipMemcpyDeviceToHost));
-  HIPCHK(hipMemcpy(b.data(), P->cB, N * sb * 8, hipMemcpyDeviceToHost));
-  // A'_j = B_{j-1}^T (format of B), B'_j = A_{j+1}^T (format of A)
-  auto transpose_block = [M](const double* src, double* dst, bool diag) {
-    if (diag) {
-      for (int64_t r = 0; r < M; ++r) dst[r] = src[r];
-    } else {
-      for (int64_t r = 0; r < M; ++r)
-        for (int64_t q = 0; q < M; ++q) dst[q + r * M] = src[r + q * M];
-    }
-  };
-  A2.assign(N * sb, 0.0);
-  B2.assign(N * sa, 0.0);
-  for (int64_t j = 1; j < N; ++j) transpose_block(&b[(j - 1) * sb], &A2[j * sb], P->fmtB == TD_FMT_DIAG);
-  for (int64_t j = 0; j + 1 < N; ++j) transpose_block(&a[(j + 1) * sa], &B2[j * sa], P->fmtA == TD_FMT_DIAG);
-  if (P->fmtC == TD_FMT_TRIDIAG) {
-    std::vector<double> c(N * 3 * M);
-    HIPCHK(hipMemcpy(c.data(), P->cC, N * 3 * M * 8, hipMemcpyDeviceToHost));
-    C2.assign(N * 3 * M, 0.0);
-    for (int64_t j = 0; j < N; ++j) {
-      const double* t = &c[j * 3 * M];
-      double* u = &C2[j * 3 * M];
-      for (int64_t r = 0; r < M; ++r) {
-        u[M + r] = t[M + r];
-        if (r > 0) u[r] = t[2 * M + r - 1];        // (C^T)(r, r-1) = C(r-1, r)
-        if (r + 1 < M) u[2 * M + r] = t[r + 1];    // (C^T)(r, r+1) = C(r+1, r)
-      }
-    }
-  } else {
-    std::vector<double> c(N * M * M);
-    HIPCHK(hipMemcpy(c.data(), P->cC, N * M * M * 8, hipMemcpyDeviceToHost));
-    C2.assign(N * M * M, 0.0);
-    for (int64_t j = 0; j < N; ++j)
-      for (int64_t r = 0; r < M; ++r)
-        for (int64_t q = 0; q < M; ++q) C2[j * M * M + q + r * M] = c[j * M * M + r + q * M];
-  }
-}
-
 // Rounded copies of D^{-1}, alpha and [U V] for the low-precision sweeps and superposition
 // (row-major, k contiguous); the float64 originals are then released.
 void make_lowprec(td_plan_s* P, hipStream_t st) {
@@ -1370,13 +1345,36 @@ td_status factor_top(const td_desc* d, const double* A, const double* B, const d
       return fail(TD_ENOMEM, "factor needs " + std::to_string(need) + " bytes, " + std::to_string(freeb) + " free");
     }
     factor_impl(P, A, B, C, st);
+    if (d->adjoint && allow_adjoint && !P->dense) {
+      // the transposed plan from this one's compact inputs and block inverses (before the rounded
+      // copies of a low-precision plan release them)
+      td_plan_s* Q = new td_plan_s();
+      Q->N = P->N; Q->M = P->M; Q->Mp = P->Mp; Q->p = P->p;
+      Q->fmtA = P->fmtB; Q->fmtB = P->fmtA; Q->fmtC = P->fmtC;
+      Q->prec = P->prec; Q->adjoint = 0;
+      Q->ks = P->ks;
+      Q->ualloc = P->ualloc; Q->ufree = P->ufree; Q->uctx = P->uctx; Q->astream = st;
+      try {
+        factor_impl(Q, nullptr, nullptr, nullptr, st, P);
+        if (Q->prec != TD_PREC_F64) make_lowprec(Q, st);
+      } catch (...) {
+        delete Q;
+        throw;
+      }
+      Q->last_stream = st;
+      P->adj = Q;
+    }
     if (P->prec != TD_PREC_F64) make_lowprec(P, st);
-    if (d->adjoint && allow_adjoint) {
-      std::vector<double> A2, B2, C2;
-      transpose_inputs(P, A2, B2, C2);
-      double* dA = P->upload(A2);
-      double* dB = P->upload(B2);
-      double* dC = P->upload(C2);
+    if (d->adjoint && allow_adjoint && P->dense) {
+      // dense couplings: the transposed plan is factored on its own from P^T's blocks, formed on
+      // the device from this plan's compact copies
+      const int64_t N = P->N, M = P->M;
+      const int64_t sa = (P->fmtA == TD_FMT_DIAG) ? M : M * M, sb = (P->fmtB == TD_FMT_DIAG) ? M : M * M;
+      const int64_t sc = (P->fmtC == TD_FMT_TRIDIAG) ? 3 * M : M * M;
+      double* dA = P->alloc(N * sb);   // A' has B's format, B' has A's
+      double* dB = P->alloc(N * sa);
+      double* dC = P->alloc(N * sc);
+      HIPCHK(launch_transpose_inputs(dA, dB, dC, P->cA, P->fmtA, P->cB, P->fmtB, P->cC, P->fmtC, (int)N, (int)M, st));
       td_desc d2 = *d;
       d2.subdomains = P->p;
       d2.adjoint = 0;
@@ -1384,6 +1382,7 @@ td_status factor_top(const td_desc* d, const double* A, const double* B, const d
       d2.fmt_B = d->fmt_A;
       td_plan adj = nullptr;
       td_status s2 = factor_top(&d2, dA, dB, dC, st, &adj, false);
+      HIPCHK(hipStreamSynchronize(st));
       P->release(dA); P->release(dB); P->release(dC);
       if (s2 != TD_OK) {
         delete P;

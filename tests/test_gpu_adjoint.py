@@ -139,3 +139,29 @@ def test_float32_gradient_unrefined(td, grad64):
     assert rel_err(X32, X) <= 1e-5
     assert rel_err(gs32, gs) <= 1e-4
     assert rel_err(gF32, gF) <= 1e-4
+
+
+def test_shifted_solver_reuses_its_plan(td):
+    """ShiftedSolver factors once per distinct sigma: two gradient steps at one sigma reuse the plan
+    (same gradients as a one-shot solve), a changed sigma refactors."""
+    N, M, K = 64, 32, 6
+    sigma = synth.shift_sigma(N, M, 41)
+    base = synth.shift_system(np.zeros((N, M)))
+    F = synth.rhs_columns(41, N, M, range(K))
+    Xt = synth.rhs_columns(42, N, M, range(K))
+    solver = td.ShiftedSolver(_dev(base.C), _dev(base.A), _dev(base.B), subdomains=4)
+    grads = []
+    for step in range(3):
+        sig = _dev(sigma if step < 2 else sigma * 1.5).requires_grad_(True)
+        Ft = _dev(F).requires_grad_(True)
+        X = solver(Ft, sig)
+        (0.5 * ((X - _dev(Xt)) ** 2).sum()).backward()
+        grads.append(sig.grad.cpu().numpy())
+        assert solver.factors == (1 if step < 2 else 2)
+    assert np.array_equal(grads[0], grads[1])
+    _, gs_ref, _ = _loss_grad(td, sigma, base, F, Xt, 4)
+    assert rel_err(grads[0], gs_ref) <= 1e-12
+    sys2 = synth.shift_system(sigma * 1.5)
+    Xo = oracle.solve(sys2, F)
+    Lam = oracle.solve_adjoint(sys2, Xo - Xt)
+    assert rel_err(grads[2], oracle.diag_shift_grad(Lam, Xo, N, M)) <= 1e-12

@@ -194,3 +194,38 @@ def test_large_block_laplace_f64(td):
     F = synth.rhs_columns(31, 96, 512, range(64))
     _, X = _solve(td, sys, F, 3)
     assert rel_err(X, oracle.solve(sys, F)) < TOL
+
+
+def _pivoting_system(N, M, seed):
+    """Dense blocks whose elimination needs row interchanges: C_j is a strictly diagonally dominant
+    matrix with its rows cyclically shifted by M // 3 (so its diagonal is small and every pivot comes
+    from another row), A_j and B_j small dense blocks (entries U[-1, 1] / (8 M))."""
+    base = synth.dense_system(N, M, seed, dominance=2.0)
+    C = np.empty_like(base.C)
+    for j in range(N):
+        rowmajor = base.C[j].T                     # stored column-major
+        C[j] = np.roll(rowmajor, M // 3, axis=0).T
+    return synth.System(N, M, base.A / 8.0, base.B / 8.0, np.ascontiguousarray(C), "dense", "dense", "dense")
+
+
+@pytest.mark.parametrize("M", [64, 128, 256, 320, 512])
+def test_row_interchanges_in_block_inverses(td, M):
+    """Every diagonal block of the elimination needs row interchanges (Gauss-Jordan with partial
+    pivoting inside each block), at block sizes handled by the candidate-row Gauss-Jordan kernel."""
+    N, K, p = 9, 6, 3
+    sys = _pivoting_system(N, M, 700 + M)
+    F = synth.rhs_columns(700 + M, N, M, range(K))
+    _, X = _solve(td, sys, F, p)
+    assert rel_err(X, oracle.solve(sys, F)) < 1e-11
+
+
+@pytest.mark.parametrize("M", [64, 256, 512])
+def test_singular_block_large(td, M):
+    """A zero C block that opens a subdomain: TD_ESINGULAR with its block row, at block sizes of the
+    candidate-row Gauss-Jordan kernel."""
+    sys = synth.varcoef_system(12, M, seed=20 + M)
+    C = sys.C.copy()
+    C[7] = 0.0                     # p = 2: interface rows 0 and 6, row 7 opens subdomain 1
+    with pytest.raises(td.TridiagError) as e:
+        td.Plan.from_system(synth.System(12, M, sys.A, sys.B, C), subdomains=2)
+    assert e.value.code == 3 and "block row 7" in str(e.value)
