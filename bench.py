@@ -464,20 +464,42 @@ def main():
     plan.set_profiling(False)
 
     work = algorithmic_work(N, M, K, p)
-    kern = {
-        "sweep": (stages["sweep"], work["sweep_flops"], work["sweep_bytes"]),
-        "superposition": (stages["superposition"], work["sup_flops"], work["sup_bytes"]),
-        "dichotomy": (stages["dichotomy_partial"] + stages["dichotomy_levels"], work["dich_flops"], work["dich_bytes"]),
-    }
-    dom = max(kern, key=lambda k: kern[k][0])
-    t_ms, fl, by = kern[dom]
-    achieved = fl / (t_ms * 1e-3) / 1e12
-    roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": PEAK_F64_MFMA, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_F64_MFMA, "traffic": measured_traffic(dom, args.workload),
-                "algorithmic_flops_per_launch": fl, "algorithmic_bytes_per_launch": by,
-                "avg_launch_ms": t_ms}
-    other = {k: {"avg_launch_ms": v[0], "tflops": v[1] / (v[0] * 1e-3) / 1e12,
-                 "frac_f64_peak": v[1] / (v[0] * 1e-3) / 1e12 / PEAK_F64_MFMA} for k, v in kern.items()}
+    scalar = M == 1 and p == N
+    if scalar:
+        # Algorithm 1 on the scalar system: the subtree kernel reads F and writes X once (the HBM
+        # bound; the stored inverse rows, 8 (depth) N bytes, stay in cache across column groups);
+        # the top levels' kernels read F once more for the subtree parts of the top nodes' sums
+        depth = max(1, int(N).bit_length())
+        sub_bytes = 2.0 * 8 * N * K
+        top_bytes = 8.0 * N * K
+        sub_flops = 2.0 * N * K * depth
+        kern = {"scalar_subtrees": (stages["dichotomy_levels"], sub_flops, sub_bytes),
+                "scalar_top_levels": (stages["dichotomy_partial"], 2.0 * N * K * depth, top_bytes)}
+        dom = "scalar_subtrees"
+        t_ms, fl, by = kern[dom]
+        achieved = by / (t_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM, "unit": "GB/s",
+                    "frac": achieved / PEAK_HBM, "traffic": None,
+                    "algorithmic_flops_per_launch": fl, "algorithmic_bytes_per_launch": by,
+                    "avg_launch_ms": t_ms}
+        other = {k: {"avg_launch_ms": v[0], "gbs": v[2] / (v[0] * 1e-3) / 1e9} for k, v in kern.items()}
+        args.mixed = ""
+    else:
+        kern = {
+            "sweep": (stages["sweep"], work["sweep_flops"], work["sweep_bytes"]),
+            "superposition": (stages["superposition"], work["sup_flops"], work["sup_bytes"]),
+            "dichotomy": (stages["dichotomy_partial"] + stages["dichotomy_levels"], work["dich_flops"],
+                          work["dich_bytes"]),
+        }
+        dom = max(kern, key=lambda k: kern[k][0])
+        t_ms, fl, by = kern[dom]
+        achieved = fl / (t_ms * 1e-3) / 1e12
+        roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": PEAK_F64_MFMA, "unit": "TFLOP/s",
+                    "frac": achieved / PEAK_F64_MFMA, "traffic": measured_traffic(dom, args.workload),
+                    "algorithmic_flops_per_launch": fl, "algorithmic_bytes_per_launch": by,
+                    "avg_launch_ms": t_ms}
+        other = {k: {"avg_launch_ms": v[0], "tflops": v[1] / (v[0] * 1e-3) / 1e12,
+                     "frac_f64_peak": v[1] / (v[0] * 1e-3) / 1e12 / PEAK_F64_MFMA} for k, v in kern.items()}
 
     out = {
         "metric": METRIC,
@@ -497,7 +519,7 @@ def main():
         "roofline": roofline,
         "kernels": other,
         "stages_ms": {k: v for k, v in stages.items() if k != "count"},
-        "whole_solve_tflops": work["total_flops"] / (ms_per_step * 1e-3) / 1e12,
+        "whole_solve_tflops": (None if scalar else work["total_flops"] / (ms_per_step * 1e-3) / 1e12),
         "eager_profiled_ms_per_step": eager_ms,
         "factor_ms": factor_ms,
         "max_col_rel_residual": info["max_col_rel_residual"],
@@ -570,8 +592,9 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
 
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_rows, args.cpu_cols, args.cpu_cols_1t,
-                                           oracle.default_threads())
+        # the scalar system's oracle (the Thomas algorithm) solves every row of the sample quickly
+        rows = 0 if M == 1 else args.cpu_rows
+        out["cpu_baseline"] = cpu_baseline(w, rows, args.cpu_cols, args.cpu_cols_1t, oracle.default_threads())
     print(json.dumps(out))
 
 

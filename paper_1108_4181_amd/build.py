@@ -12,7 +12,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libtridiag.so")
 
-SOURCES = ["kernels_f64.hip", "kernels_gj.hip", "kernels_lp.hip", "kernels_batched.hip", "kernels_schur.hip", "plan.cpp", "schur.cpp"]
+SOURCES = ["kernels_f64.hip", "kernels_gj.hip", "kernels_scalar.hip", "kernels_lp.hip", "kernels_batched.hip", "kernels_schur.hip", "plan.cpp", "schur.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -125,6 +125,48 @@ struct GJArgs {
   int32_t nmat, Mp;
 };
 
+// Algorithm 1 on a scalar tridiagonal system (kernels_scalar.hip): subtrees of at most SC_SUB rows,
+// SC_CPW right-hand sides per work-group.
+constexpr int SC_SUB = 1024;
+constexpr int SC_CPW = 4;
+struct ScalarArgs {
+  int N, K, L0, ndeep, nsub, ntop, maxsub, accumulate;
+  int64_t ldf, ldx;
+  const double* G;         // [depth][N]: row m of the inverse of each node's submatrix, by level
+  const double* hl;        // [N] (by split row m): g_m[l] a_l
+  const double* hr;        // [N]: g_m[r] b_r
+  const int* lo;           // [N]: node range of split row m
+  const int* hi;
+  const double* F;
+  double* X;
+  double* Pt;              // [L0][nsub][K]: subtree parts of the top nodes' sums
+  double* Xt;              // [ntop][K]: x at the top rows (top list order)
+  // subtrees (nodes of level L0, by row)
+  const int* sub_lo;
+  const int* sub_hi;
+  const int* sub_left;     // top-list position of row sub_lo - 1, or -1
+  const int* sub_right;    // top-list position of row sub_hi + 1, or -1
+  const int* sub_order;    // the subtrees' nodes, each subtree's in level order
+  const int* sub_off;      // [nsub]: start of subtree s in sub_order
+  const int* sub_lvoff;    // [nsub][ndeep + 1]: level starts within the subtree's part of sub_order
+  // top nodes (levels < L0), in level order
+  const int* top_m;
+  const int* top_lvl;
+  const int* top_s0;       // subtrees inside the node: [top_s0, top_s1)
+  const int* top_s1;
+  const int* top_t0;       // top rows inside the node: toprow_sorted[top_t0 .. top_t1)
+  const int* top_t1;
+  const int* top_left;     // top-list position of row l - 1, or -1
+  const int* top_right;    // top-list position of row r + 1, or -1
+  const int* toprow_sorted;
+};
+hipError_t launch_scalar_factor(const double* a, const double* b, const double* cdiag, int cs, int N, const int* lo,
+                                const int* hi, const int* lvl, double* G, double* hl, double* hr, int32_t* bad,
+                                hipStream_t st);
+// the top levels (subtree parts of the top nodes' sums, then the top nodes) and the subtrees
+hipError_t launch_scalar_top(const ScalarArgs& A, hipStream_t st);
+hipError_t launch_scalar_sub(const ScalarArgs& A, hipStream_t st);
+
 // Launch wrappers (kernels_f64.hip)
 hipError_t launch_bgemm(const BArgs& a, hipStream_t st);
 

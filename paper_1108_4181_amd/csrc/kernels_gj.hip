@@ -277,158 +277,6 @@ __global__ void __launch_bounds__(NT) k_gj(GJArgs g) {
   }
 }
 
-// The same elimination for blocks above 256 rows, where two LDS copies of the panel and the
-// register-resident rows do not fit: the panel stays in one LDS copy, the pivot row is formed by
-// one thread between barriers, and each column tile of the update stages its pivot rows.
-template <int RT>
-__global__ void __launch_bounds__(512) k_gj_big(GJArgs g) {
-  constexpr int NB = 16;
-  constexpr int CT = 4;           // 16 columns per update tile
-  constexpr int KT = 4 * CT;
-  constexpr int SBY = KT + 2;
-  extern __shared__ double sm[];
-  const int Mp = g.Mp;
-  double* Pn = sm;                         // [NB][Mp]
-  double* Ys = Pn + NB * Mp;               // [NB][SBY]
-  double* prow = Ys + NB * SBY;            // [NB]
-  double* redv = prow + NB;                // [32]: per-wave reduction values, [16] = singular flag
-  int* pivrow = (int*)(redv + 32);         // [Mp]
-  int* used = pivrow + Mp;                 // [Mp]
-  int* redi = used + Mp;                   // [16]
-
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int L = tid & 63, w = tid >> 6, nw = nthr >> 6;
-  const int q = blockIdx.x;
-  if (q >= g.nmat) return;
-  double* W = g.work + (g.work_off ? g.work_off[q] : q * g.wstride);
-  const int rb = w * 16 * RT;
-
-  // infinity norm (row sums), one row per thread (nthr >= Mp)
-  double rs = 0.0;
-  if (tid < Mp) {
-    for (int c = 0; c < Mp; ++c) rs += fabs(W[tid + (int64_t)c * Mp]);
-    used[tid] = 0;
-  }
-  for (int off = 32; off > 0; off >>= 1) rs = fmax(rs, __shfl_xor(rs, off));
-  if (L == 0) redv[w] = rs;
-  __syncthreads();
-  double norm = 0.0;
-  for (int v = 0; v < nw; ++v) norm = fmax(norm, redv[v]);
-  const double tol = 1e-14 * norm;
-  __syncthreads();
-  bool singular = false;
-
-  for (int p0 = 0; p0 < Mp; p0 += NB) {
-    for (int e = tid; e < NB * Mp; e += nthr) {
-      const int i = e % Mp, jj = e / Mp;
-      Pn[jj * Mp + i] = W[i + (int64_t)(p0 + jj) * Mp];
-    }
-    __syncthreads();
-    for (int j = 0; j < NB; ++j) {
-      // pivot search over unused rows
-      double bv = -1.0;
-      int bi = INT_MAX;
-      for (int i = tid; i < Mp; i += nthr) {
-        if (!used[i]) {
-          const double v = fabs(Pn[j * Mp + i]);
-          const double vv = (v == v) ? v : DBL_MAX;  // NaN ranks first so that it is reported
-          if (vv > bv || (vv == bv && i < bi)) { bv = vv; bi = i; }
-        }
-      }
-      wave_argmax(bv, bi);
-      if (L == 0) { redv[w] = bv; redi[w] = bi; }
-      __syncthreads();
-      if (tid == 0) {
-        double b2 = redv[0];
-        int i2 = redi[0];
-        for (int v = 1; v < nw; ++v)
-          if (redv[v] > b2 || (redv[v] == b2 && redi[v] < i2)) { b2 = redv[v]; i2 = redi[v]; }
-        pivrow[p0 + j] = i2;
-        used[i2] = 1;
-        const double pv = Pn[j * Mp + i2];
-        redv[16] = (fabs(pv) > tol) ? 0.0 : 1.0;
-        for (int jj = 0; jj < NB; ++jj) prow[jj] = (jj == j) ? 1.0 / pv : Pn[jj * Mp + i2] / pv;
-      }
-      __syncthreads();
-      if (redv[16] != 0.0) singular = true;
-      const int r = pivrow[p0 + j];
-      if (tid < Mp) {
-        const int i = tid;
-        if (i == r) {
-#pragma unroll
-          for (int jj = 0; jj < NB; ++jj) Pn[jj * Mp + i] = prow[jj];
-        } else {
-          const double f = Pn[j * Mp + i];
-#pragma unroll
-          for (int jj = 0; jj < NB; ++jj) Pn[jj * Mp + i] = (jj == j ? 0.0 : Pn[jj * Mp + i]) - f * prow[jj];
-        }
-      }
-      __syncthreads();
-    }
-    // rank-NB update of all other columns: W[:, c] += (Pn - E_R) * W[R, c]
-    for (int c0 = 0; c0 < Mp; c0 += KT) {
-      if (c0 + KT > p0 && c0 < p0 + NB) continue;  // tile lies inside the panel (NB == KT)
-      for (int e = tid; e < NB * KT; e += nthr) {
-        const int jj = e / KT, c = e % KT;
-        Ys[jj * SBY + c] = W[pivrow[p0 + jj] + (int64_t)(c0 + c) * Mp];
-      }
-      __syncthreads();
-      double acc[RT][CT];
-#pragma unroll
-      for (int t = 0; t < RT; ++t) {
-        const int row = rb + 16 * t + out_row(L);
-#pragma unroll
-        for (int c = 0; c < CT; ++c) acc[t][c] = W[row + (int64_t)(c0 + out_col(L) * CT + c) * Mp];
-      }
-#pragma unroll
-      for (int kk = 0; kk < NB / 4; ++kk) {
-        const int k = 4 * kk + (L >> 4);
-        const int pr = pivrow[p0 + k];
-        double av[RT];
-#pragma unroll
-        for (int t = 0; t < RT; ++t) {
-          const int row = rb + 16 * t + (L & 15);
-          av[t] = Pn[k * Mp + row] - (row == pr ? 1.0 : 0.0);
-        }
-        const double* bp = &Ys[k * SBY + (L & 3) * CT];
-        double b[CT];
-#pragma unroll
-        for (int c = 0; c < CT; ++c) b[c] = bp[c];
-#pragma unroll
-        for (int t = 0; t < RT; ++t)
-#pragma unroll
-          for (int c = 0; c < CT; ++c) acc[t][c] = mfma4(av[t], b[c], acc[t][c]);
-      }
-#pragma unroll
-      for (int t = 0; t < RT; ++t) {
-        const int row = rb + 16 * t + out_row(L);
-#pragma unroll
-        for (int c = 0; c < CT; ++c) W[row + (int64_t)(c0 + out_col(L) * CT + c) * Mp] = acc[t][c];
-      }
-      __syncthreads();
-    }
-    for (int e = tid; e < NB * Mp; e += nthr) {
-      const int i = e % Mp, jj = e / Mp;
-      W[i + (int64_t)(p0 + jj) * Mp] = Pn[jj * Mp + i];
-    }
-    __syncthreads();
-  }
-  if (tid == 0 && singular) atomicMin(g.bad, g.tag[q]);
-  // inverse: Dinv[c][pivrow[c']] = S[pivrow[c]][c']
-  int* invpiv = used;  // reuse
-  for (int c = tid; c < Mp; c += nthr) invpiv[pivrow[c]] = c;
-  __syncthreads();
-  double* out = g.out + g.out_off[q];
-  double* al = g.alpha ? g.alpha + g.out_off[q] : nullptr;
-  const double* bd = g.alpha ? g.bdiag + g.bd_off[q] : nullptr;
-  for (int e = tid; e < Mp * Mp; e += nthr) {
-    const int row = e % Mp, oc = e / Mp;
-    const double v = W[pivrow[row] + (int64_t)invpiv[oc] * Mp];
-    out[row + (int64_t)oc * Mp] = v;
-    if (al) al[row + (int64_t)oc * Mp] = v * bd[oc];
-  }
-}
-
 // Gauss-Jordan inversion for block sizes that are multiples of 64 (64 ... 512): one thread per row
 // (Mp threads), the panel's NB columns of the thread's row in registers.  Per column every wave
 // finds its best candidate with a DPP arg-max, and the winning lane of each wave publishes that row
@@ -648,15 +496,6 @@ static hipError_t launch_gj_cand(const GJArgs& g, hipStream_t st) {
   return hipGetLastError();
 }
 
-// TD_GJ_CAND=0 selects the earlier all-thread panel kernels (for comparison)
-static bool gj_cand_disabled() {
-  static const bool off = [] {
-    const char* v = std::getenv("TD_GJ_CAND");
-    return v && v[0] == '0';
-  }();
-  return off;
-}
-
 template <int RT, int NT, int NB>
 static hipError_t launch_gj_cfg(const GJArgs& g, int nthr, hipStream_t st) {
   const size_t lds = (size_t)(2 * NB * g.Mp + 32) * sizeof(double) + (size_t)(32 + 2 * g.Mp) * sizeof(int);
@@ -671,33 +510,24 @@ static hipError_t launch_gj_cfg(const GJArgs& g, int nthr, hipStream_t st) {
 template <int RT>
 static hipError_t launch_gj_rt(const GJArgs& g, hipStream_t st) {
   const int nthr = g.Mp / (16 * RT) * 64;
-  if (g.Mp > 256) {
-    const size_t lds = (size_t)(16 * g.Mp + 16 * 18 + 16 + 32) * sizeof(double) + (size_t)(2 * g.Mp + 16) * sizeof(int);
-    hipError_t e = hipFuncSetAttribute((const void*)k_gj_big<RT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_gj_big<RT>), dim3(g.nmat), dim3(nthr), lds, st, g);
-    return hipGetLastError();
-  }
   // panels of 32 columns halve the passes of the update over the matrix where the block size
-  // divides into them and the two LDS copies fit; 16 otherwise
-  if constexpr (RT == 4) {   // Mp == 256 here: 256 threads
-    return launch_gj_cfg<RT, 256, 32>(g, nthr, st);
-  } else {
-    if (g.Mp % 32 == 0) {
-      if (nthr <= 256) return launch_gj_cfg<RT, 256, 32>(g, nthr, st);
-      return launch_gj_cfg<RT, 512, 32>(g, nthr, st);
-    }
-    if (nthr <= 256) return launch_gj_cfg<RT, 256, 16>(g, nthr, st);
-    return launch_gj_cfg<RT, 512, 16>(g, nthr, st);
+  // divides into them and the two LDS copies fit; 16 otherwise (block sizes up to 256 here)
+  if (g.Mp % 32 == 0) {
+    if (nthr <= 256) return launch_gj_cfg<RT, 256, 32>(g, nthr, st);
+    return launch_gj_cfg<RT, 512, 32>(g, nthr, st);
   }
+  if (nthr <= 256) return launch_gj_cfg<RT, 256, 16>(g, nthr, st);
+  return launch_gj_cfg<RT, 512, 16>(g, nthr, st);
 }
 
 hipError_t launch_gj(const GJArgs& g, hipStream_t st) {
   if (g.nmat == 0) return hipSuccess;
-  // block sizes that are multiples of 64: candidate-row kernel (32-column panels up to 256 rows,
-  // where four waves get the register budget of 256-thread work-groups; 16-column panels above)
-  if (!gj_cand_disabled() && g.Mp % 64 == 0 && g.Mp >= 128 && g.Mp <= 512)
+  // block sizes that are multiples of 64 from 128 (every padded size above 256 is one): the
+  // candidate-row kernel, 32-column panels up to 256 rows (four waves keep the register budget of
+  // 256-thread work-groups), 16-column panels above
+  if (g.Mp % 64 == 0 && g.Mp >= 128)
     return g.Mp <= 256 ? launch_gj_cand<32, 256>(g, st) : launch_gj_cand<16, 512>(g, st);
+  if (g.Mp > 256) return hipErrorInvalidValue;
   switch (choose_rt(g.Mp)) {
     case 4: return launch_gj_rt<4>(g, st);
     case 2: return launch_gj_rt<2>(g, st);

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -94,6 +95,9 @@ struct td_plan_s {
   double* Rbuf = nullptr; double* colpart = nullptr; double* norms = nullptr;
   // low-precision copies of the factor (sweep_prec F32 / BF16), row-major
   void* Dlp = nullptr; void* Alp = nullptr; void* UVlp = nullptr;
+  // scalar plan (block size 1, every row an interface row): Algorithm 1 on the tridiagonal system
+  bool scalar = false;
+  ScalarArgs sc{};            // tree arrays and factor; the per-solve fields are set by each pass
   bool first_pass = false;
   int32_t* d_flag = nullptr;
   td_plan_s* adj = nullptr;
@@ -949,11 +953,157 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
   }
 }
 
+// ------------------------------------------------------------------------------------------
+// Factor of a scalar system (block size 1) with every row an interface row: the dichotomy tree over
+// all rows (Algorithm 1, Sec. 2.1), the stored row of the inverse of every node's submatrix, and the
+// subtree / top-node layout of the solve (kernels_scalar.hip).
+// ------------------------------------------------------------------------------------------
+void factor_scalar(td_plan_s* P, const double* A, const double* B, const double* C, hipStream_t st) {
+  const int N = (int)P->N;
+  const int64_t nC = (P->fmtC == TD_FMT_TRIDIAG) ? 3 * (int64_t)N : N;
+  P->cA = P->alloc(N);
+  P->cB = P->alloc(N);
+  P->cC = P->alloc(nC);
+  HIPCHK(hipMemcpyAsync(P->cA, A, (size_t)N * 8, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(P->cB, B, (size_t)N * 8, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(P->cC, C, (size_t)nC * 8, hipMemcpyDeviceToDevice, st));
+  if (P->fmtA == TD_FMT_DIAG && P->fmtB == TD_FMT_DIAG && P->fmtC == TD_FMT_TRIDIAG)
+    HIPCHK(launch_zero_absent(P->cA, P->cB, P->cC, N, 1, st));   // for the stencil residual
+  P->d_flag = (int32_t*)P->alloc(2);
+  int32_t* bad = P->d_flag;
+  HIPCHK(launch_negate_fill_check(bad, INT_MAX, st));
+
+  // the tree: node of split row m covers [lo[m], hi[m]] at level lvl[m]; levels left to right
+  std::vector<int> lo(N), hi(N), lvl(N);
+  std::vector<std::vector<int>> bylevel;
+  {
+    std::vector<std::pair<int, int>> cur{{0, N - 1}}, nxt;
+    for (int lv = 0; !cur.empty(); ++lv) {
+      bylevel.emplace_back();
+      nxt.clear();
+      for (auto& nd : cur) {
+        const int l = nd.first, r = nd.second, m = (l + r) / 2;
+        lo[m] = l; hi[m] = r; lvl[m] = lv;
+        bylevel.back().push_back(m);
+        if (m > l) nxt.push_back({l, m - 1});
+        if (m < r) nxt.push_back({m + 1, r});
+      }
+      cur.swap(nxt);
+    }
+  }
+  const int depth = (int)bylevel.size();
+  P->depth = depth;
+  int L0 = 0;   // first level whose nodes all have at most SC_SUB rows
+  for (; L0 < depth; ++L0) {
+    int mx = 0;
+    for (int m : bylevel[L0]) mx = std::max(mx, hi[m] - lo[m] + 1);
+    if (mx <= SC_SUB) break;
+  }
+  const std::vector<int>& subs = bylevel[L0];
+  const int nsub = (int)subs.size();
+  std::vector<int> top_m, top_lvl, topidx(N, -1);
+  for (int lv = 0; lv < L0; ++lv)
+    for (int m : bylevel[lv]) {
+      topidx[m] = (int)top_m.size();
+      top_m.push_back(m);
+      top_lvl.push_back(lv);
+    }
+  const int ntop = (int)top_m.size();
+  std::vector<int> toprow_sorted(top_m);
+  std::sort(toprow_sorted.begin(), toprow_sorted.end());
+  std::vector<int> sub_lo(nsub), sub_hi(nsub), sub_left(nsub), sub_right(nsub), sub_off(nsub);
+  const int ndeep = depth - L0;
+  std::vector<int> sub_order, sub_lvoff((size_t)nsub * (ndeep + 1), 0);
+  int maxsub = 1;
+  auto top_of = [&](int row) {   // top-list position of a boundary row (always a top row) or -1
+    if (row < 0 || row >= N) return -1;
+    if (topidx[row] < 0) throw std::string("internal error: subtree boundary row is not a top row");
+    return topidx[row];
+  };
+  for (int q = 0; q < nsub; ++q) {
+    const int m = subs[q];
+    sub_lo[q] = lo[m]; sub_hi[q] = hi[m];
+    maxsub = std::max(maxsub, hi[m] - lo[m] + 1);
+    sub_left[q] = top_of(lo[m] - 1);
+    sub_right[q] = top_of(hi[m] + 1);
+    sub_off[q] = (int)sub_order.size();
+    std::vector<int> cur{m}, nxt;
+    for (int d = 0; d < ndeep; ++d) {
+      sub_lvoff[(size_t)q * (ndeep + 1) + d] = (int)sub_order.size() - sub_off[q];
+      nxt.clear();
+      for (int x : cur) {
+        sub_order.push_back(x);
+        if (x > lo[x]) nxt.push_back((lo[x] + x - 1) / 2);
+        if (x < hi[x]) nxt.push_back((x + 1 + hi[x]) / 2);
+      }
+      cur.swap(nxt);
+    }
+    sub_lvoff[(size_t)q * (ndeep + 1) + ndeep] = (int)sub_order.size() - sub_off[q];
+  }
+  std::vector<int> top_s0(ntop), top_s1(ntop), top_t0(ntop), top_t1(ntop), top_left(ntop), top_right(ntop);
+  for (int t = 0; t < ntop; ++t) {
+    const int m = top_m[t];
+    top_s0[t] = (int)(std::lower_bound(sub_lo.begin(), sub_lo.end(), lo[m]) - sub_lo.begin());
+    top_s1[t] = (int)(std::upper_bound(sub_lo.begin(), sub_lo.end(), hi[m]) - sub_lo.begin());
+    top_t0[t] = (int)(std::lower_bound(toprow_sorted.begin(), toprow_sorted.end(), lo[m]) - toprow_sorted.begin());
+    top_t1[t] = (int)(std::upper_bound(toprow_sorted.begin(), toprow_sorted.end(), hi[m]) - toprow_sorted.begin());
+    top_left[t] = top_of(lo[m] - 1);
+    top_right[t] = top_of(hi[m] + 1);
+  }
+  // every index array in one upload
+  std::vector<int> arena;
+  std::vector<size_t> at;
+  auto add = [&](const std::vector<int>& v) {
+    at.push_back(arena.size());
+    arena.insert(arena.end(), v.begin(), v.end());
+    while (arena.size() % 64) arena.push_back(0);
+  };
+  add(lo); add(hi); add(lvl);
+  add(sub_lo); add(sub_hi); add(sub_left); add(sub_right); add(sub_order); add(sub_off); add(sub_lvoff);
+  add(top_m); add(top_lvl); add(top_s0); add(top_s1); add(top_t0); add(top_t1); add(top_left); add(top_right);
+  add(toprow_sorted);
+  const int* d = P->upload(arena);
+  ScalarArgs& S = P->sc;
+  std::memset(&S, 0, sizeof(S));
+  S.N = N; S.L0 = L0; S.ndeep = ndeep; S.nsub = nsub; S.ntop = ntop; S.maxsub = maxsub;
+  S.lo = d + at[0]; S.hi = d + at[1];
+  const int* d_lvl = d + at[2];
+  S.sub_lo = d + at[3]; S.sub_hi = d + at[4]; S.sub_left = d + at[5]; S.sub_right = d + at[6];
+  S.sub_order = d + at[7]; S.sub_off = d + at[8]; S.sub_lvoff = d + at[9];
+  S.top_m = d + at[10]; S.top_lvl = d + at[11]; S.top_s0 = d + at[12]; S.top_s1 = d + at[13];
+  S.top_t0 = d + at[14]; S.top_t1 = d + at[15]; S.top_left = d + at[16]; S.top_right = d + at[17];
+  S.toprow_sorted = d + at[18];
+  double* G = P->alloc((int64_t)depth * N);
+  HIPCHK(launch_fill(G, (int64_t)depth * N, 0.0, st));
+  double* hl = P->alloc(N);
+  double* hr = P->alloc(N);
+  S.G = G; S.hl = hl; S.hr = hr;
+  const bool tri = P->fmtC == TD_FMT_TRIDIAG;
+  HIPCHK(launch_scalar_factor(P->cA, P->cB, P->cC + (tri ? 1 : 0), tri ? 3 : 1, N, S.lo, S.hi, d_lvl, G, hl, hr, bad,
+                              st));
+  int32_t badv = INT_MAX;
+  HIPCHK(hipMemcpyAsync(&badv, bad, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (badv != INT_MAX) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "singular block at row %d (0-based) of the reduced interface system",
+                  (int)(badv - N));
+    throw std::string(buf);
+  }
+}
+
 // prev: the stream of the plan's previous solve, whose work may still read the old workspace
 void ensure_workspace(td_plan_s* P, int64_t K, hipStream_t st, hipStream_t prev) {
   if (K <= P->kcap) return;
   if (P->kcap > 0 && prev != st) HIPCHK(hipStreamSynchronize(prev));
   ++P->ws_gen;
+  if (P->scalar) {   // top-node partial sums and top-row values only
+    P->release(P->Sp); P->release(P->Xi);
+    P->Sp = P->alloc(std::max<int64_t>(1, (int64_t)P->sc.L0 * P->sc.nsub * K));
+    P->Xi = P->alloc(std::max<int64_t>(1, (int64_t)P->sc.ntop * K));
+    P->kcap = K;
+    return;
+  }
   const int64_t N = P->N, Mp = P->Mp, p = P->p;
   P->release(P->Wbuf); P->release(P->W32); P->release(P->Ft); P->release(P->Xi); P->release(P->Sp);
   P->release(P->Pbuf);
@@ -1026,6 +1176,19 @@ Work plan_work(const td_plan_s* P) { return Work{P->Wbuf, P->W32, P->Ft, P->Xi, 
 // in float64.  With `accumulate` the result is added to X (a refinement correction).
 void solve_pass(td_plan_s* P, const Work& w, const double* F, int64_t ldf, double* X, int64_t ldx, int64_t K,
                 bool accumulate, hipStream_t st) {
+  if (P->scalar) {   // Algorithm 1 on the scalar system: no sweeps, no superposition
+    ScalarArgs A = P->sc;
+    A.K = (int)K; A.F = F; A.ldf = ldf; A.X = X; A.ldx = ldx; A.Pt = w.Sp; A.Xt = w.Xi;
+    A.accumulate = accumulate ? 1 : 0;
+    for (int i = 0; i <= 2; ++i) stage_mark(P, i, st);
+    HIPCHK(launch_scalar_top(A, st));      // stage "dichotomy_partial": the top levels
+    stage_mark(P, 3, st);
+    HIPCHK(launch_scalar_sub(A, st));      // stage "dichotomy_levels": the subtrees
+    stage_mark(P, 4, st);
+    stage_mark(P, 5, st);
+    P->first_pass = false;
+    return;
+  }
   const int64_t N = P->N, M = P->M, Mp = P->Mp, p = P->p;
   const int64_t ldw = N * Mp, ldft = p * Mp, ldxi = (p + 2) * Mp, ldsp = (int64_t)P->nchunks * Mp;
   stage_mark(P, 0, st);
@@ -1281,6 +1444,11 @@ td_status check_desc(const td_desc* d) {
 
 // device bytes the factor needs at its peak (checked against free memory before allocating)
 int64_t factor_bytes(int64_t N, int64_t M, int64_t p, int fA, int fB, int fC, int prec) {
+  if (M == 1 && p == N && prec == TD_PREC_F64) {   // scalar plan: inputs, tree arrays, G by level
+    int64_t depth = 0;
+    for (int64_t q = N; q > 0; q >>= 1) ++depth;
+    return 8 * (6 * N + depth * N) + 4 * 8 * N;
+  }
   const int64_t Mp = pad_block(M, prec), MM = Mp * Mp;
   int64_t depth = 0;
   for (int64_t q = p; q > 0; q >>= 1) ++depth;
@@ -1335,6 +1503,9 @@ td_status factor_top(const td_desc* d, const double* A, const double* B, const d
   P->fmtA = d->fmt_A; P->fmtB = d->fmt_B; P->fmtC = d->fmt_C;
   P->prec = d->sweep_prec; P->adjoint = d->adjoint;
   P->ks = partition(P->N, P->p);
+  // block size 1 with every row an interface row: Algorithm 1 on the scalar system itself
+  P->scalar = d->M == 1 && P->p == d->N && d->sweep_prec == TD_PREC_F64;
+  if (P->scalar) P->Mp = 1;
   try {
     size_t freeb = 0, totb = 0;
     HIPCHK(hipMemGetInfo(&freeb, &totb));
@@ -1344,8 +1515,11 @@ td_status factor_top(const td_desc* d, const double* A, const double* B, const d
       delete P;
       return fail(TD_ENOMEM, "factor needs " + std::to_string(need) + " bytes, " + std::to_string(freeb) + " free");
     }
-    factor_impl(P, A, B, C, st);
-    if (d->adjoint && allow_adjoint && !P->dense) {
+    if (P->scalar)
+      factor_scalar(P, A, B, C, st);
+    else
+      factor_impl(P, A, B, C, st);
+    if (d->adjoint && allow_adjoint && !P->dense && !P->scalar) {
       // the transposed plan from this one's compact inputs and block inverses (before the rounded
       // copies of a low-precision plan release them)
       td_plan_s* Q = new td_plan_s();
@@ -1365,9 +1539,9 @@ td_status factor_top(const td_desc* d, const double* A, const double* B, const d
       P->adj = Q;
     }
     if (P->prec != TD_PREC_F64) make_lowprec(P, st);
-    if (d->adjoint && allow_adjoint && P->dense) {
-      // dense couplings: the transposed plan is factored on its own from P^T's blocks, formed on
-      // the device from this plan's compact copies
+    if (d->adjoint && allow_adjoint && (P->dense || P->scalar)) {
+      // dense couplings or the scalar plan: the transposed plan is factored on its own from P^T's
+      // blocks, formed on the device from this plan's compact copies
       const int64_t N = P->N, M = P->M;
       const int64_t sa = (P->fmtA == TD_FMT_DIAG) ? M : M * M, sb = (P->fmtB == TD_FMT_DIAG) ? M : M * M;
       const int64_t sc = (P->fmtC == TD_FMT_TRIDIAG) ? 3 * M : M * M;
@@ -1711,6 +1885,16 @@ hipError_t scratch_address(void** out) {
 int64_t scratch_layout(const td_plan_s* P, int64_t K, char* base, Work* w, int64_t* clear_doubles) {
   const int64_t N = P->N, Mp = P->Mp, p = P->p;
   auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
+  if (P->scalar) {   // Xt, then Pt (both fully written by every pass)
+    const int64_t bXt = up((int64_t)P->sc.ntop * K * 8), bPt = up((int64_t)P->sc.L0 * P->sc.nsub * K * 8);
+    if (w) {
+      *w = Work{};
+      w->Xi = (double*)base;
+      w->Sp = (double*)(base + bXt);
+    }
+    if (clear_doubles) *clear_doubles = 0;
+    return bXt + bPt;
+  }
   // Xi, Ft, Sp and Pbuf first (cleared on every call), then W
   const int64_t bXi = up((p + 2) * Mp * K * 8), bFt = up(p * Mp * K * 8), bSp = up((int64_t)P->nchunks * Mp * K * 8);
   const int64_t bP = up((int64_t)P->pslots * Mp * K * 8);
@@ -1940,20 +2124,20 @@ td_status tridiag_autotune(int64_t M, int64_t K, int32_t sweep_prec, int64_t pro
       std::memset(&d, 0, sizeof d);
       d.N = probe_N; d.M = M; d.subdomains = std::max<int64_t>(1, probe_N / L);
       d.fmt_A = TD_FMT_DIAG; d.fmt_B = TD_FMT_DIAG; d.fmt_C = TD_FMT_TRIDIAG; d.sweep_prec = sweep_prec;
-      td_plan P = nullptr;
-      td_status s = factor_top(&d, A, B, C, st, &P, false);
+      td_plan Pr = nullptr;
+      td_status s = factor_top(&d, A, B, C, st, &Pr, false);
       if (s != TD_OK) { result = s; break; }
-      s = solve_impl(P, F, probe_N * M, X, probe_N * M, K, nullptr, nullptr, st);
-      if (s == TD_OK) {
-        HIPCHK(hipEventRecord(e0, st));
-        for (int r = 0; r < 3 && s == TD_OK; ++r) s = solve_impl(P, F, probe_N * M, X, probe_N * M, K, nullptr, nullptr, st);
-        HIPCHK(hipEventRecord(e1, st));
-        HIPCHK(hipEventSynchronize(e1));
-      }
+      std::unique_ptr<td_plan_s> P(Pr);   // freed on every exit, also when a HIP call throws
+      s = solve_impl(P.get(), F, probe_N * M, X, probe_N * M, K, nullptr, nullptr, st);
+      if (s != TD_OK) { result = s; break; }
+      HIPCHK(hipEventRecord(e0, st));
+      for (int r = 0; r < 3 && s == TD_OK; ++r)
+        s = solve_impl(P.get(), F, probe_N * M, X, probe_N * M, K, nullptr, nullptr, st);
+      HIPCHK(hipEventRecord(e1, st));
+      HIPCHK(hipEventSynchronize(e1));
+      if (s != TD_OK) { result = s; break; }
       float ms = 0.f;
       HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-      delete P;
-      if (s != TD_OK) { result = s; break; }
       if (ms_per_solve) ms_per_solve[c] = ms / 3.0;
       if (ms / 3.0 < best) { best = ms / 3.0; *best_L = L; }
     }
