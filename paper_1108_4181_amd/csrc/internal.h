@@ -146,9 +146,10 @@ struct ScalarArgs {
   const int* sub_hi;
   const int* sub_left;     // top-list position of row sub_lo - 1, or -1
   const int* sub_right;    // top-list position of row sub_hi + 1, or -1
-  const int* sub_order;    // the subtrees' nodes, each subtree's in level order
-  const int* sub_off;      // [nsub]: start of subtree s in sub_order
-  const int* sub_lvoff;    // [nsub][ndeep + 1]: level starts within the subtree's part of sub_order
+  const int4* sub_rec;     // the subtrees' nodes, each subtree's in level order: {m, l, r, 0}
+  const double2* sub_h;    // their {hl, hr}, same order
+  const int* sub_off;      // [nsub]: start of subtree s in sub_rec
+  const int* sub_lvoff;    // [nsub][ndeep + 1]: level starts within the subtree's records
   // top nodes (levels < L0), in level order
   const int* top_m;
   const int* top_lvl;
@@ -160,6 +161,8 @@ struct ScalarArgs {
   const int* top_right;    // top-list position of row r + 1, or -1
   const int* toprow_sorted;
 };
+hipError_t launch_scalar_gather_h(double* sub_h, const int4* rec, int nrec, const double* hl, const double* hr,
+                                  hipStream_t st);
 hipError_t launch_scalar_factor(const double* a, const double* b, const double* cdiag, int cs, int N, const int* lo,
                                 const int* hi, const int* lvl, double* G, double* hl, double* hr, int32_t* bad,
                                 hipStream_t st);
@@ -303,7 +306,9 @@ hipError_t launch_ftilde_f32(double* Ft, int64_t ldft, const double* F, int64_t 
 // rows x right-hand sides of one work-group (or batched work item) of the stencil residual
 constexpr int RES_ROWS = 1024;
 constexpr int RES_COLS = 16;
-int residual_row_chunks(int64_t n);
+constexpr int RES_ROWS_WIDE = 2048;
+int residual_row_chunks(int64_t n);        // row chunks of the batched kernels' residual items
+int residual_row_chunks_wide(int64_t n);   // row chunks of launch_residual_stencil
 hipError_t launch_zero_absent(double* A, double* B, double* C, int N, int M, hipStream_t st);
 hipError_t launch_residual_stencil(double* R, int64_t ldr, const double* F, int64_t ldf, const double* X, int64_t ldx,
                                    const double* A, const double* B, const double* C, int N, int M, int K,

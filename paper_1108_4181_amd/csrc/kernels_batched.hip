@@ -103,7 +103,7 @@ __device__ __attribute__((noinline)) void run_item(const BatchItem& it, const Ba
       break;
     }
     case BI_RES:
-      residual_cols_tile(S.R, S.ldr, S.F, S.ldf, S.X, S.ldx, S.cA, S.cB, S.cC, S.N, S.M, S.K, S.colpart, S.nchunk,
+      residual_cols_tile<RES_ROWS>(S.R, S.ldr, S.F, S.ldf, S.X, S.ldx, S.cA, S.cB, S.cC, S.N, S.M, S.K, S.colpart, S.nchunk,
                          it.i0, it.i1, reinterpret_cast<double*>(lds), red);
       break;
     case BI_RFIN: {

@@ -254,13 +254,14 @@ __global__ void __launch_bounds__(256) k_residual_stencil(double* R, int64_t ldr
                                                           const double* X, int64_t ldx, const double* A,
                                                           const double* B, const double* C, int N, int M, int K,
                                                           double* colpart, int nchunk) {
-  extern __shared__ double xs[];   // RES_ROWS + 2M
+  extern __shared__ double xs[];   // RES_ROWS_WIDE + 2M
   __shared__ double red[2 * RES_COLS][4];
-  residual_cols_tile(R, ldr, F, ldf, X, ldx, A, B, C, N, M, K, colpart, nchunk, blockIdx.x, blockIdx.y * RES_COLS,
-                     xs, red);
+  residual_cols_tile<RES_ROWS_WIDE>(R, ldr, F, ldf, X, ldx, A, B, C, N, M, K, colpart, nchunk, blockIdx.x,
+                                    blockIdx.y * RES_COLS, xs, red);
 }
 
 int residual_row_chunks(int64_t n) { return (int)((n + RES_ROWS - 1) / RES_ROWS); }
+int residual_row_chunks_wide(int64_t n) { return (int)((n + RES_ROWS_WIDE - 1) / RES_ROWS_WIDE); }
 
 hipError_t launch_residual_stencil(double* R, int64_t ldr, const double* F, int64_t ldf, const double* X, int64_t ldx,
                                    const double* A, const double* B, const double* C, int N, int M, int K,
@@ -268,8 +269,8 @@ hipError_t launch_residual_stencil(double* R, int64_t ldr, const double* F, int6
   if (K == 0) return hipSuccess;
   if (M > 512) return hipErrorInvalidValue;   // the staged span assumes M <= 512
   const int64_t n = (int64_t)N * M;
-  const int nchunk = residual_row_chunks(n);
-  const size_t lds = (size_t)(RES_ROWS + 2 * M) * sizeof(double);
+  const int nchunk = residual_row_chunks_wide(n);
+  const size_t lds = (size_t)(RES_ROWS_WIDE + 2 * M) * sizeof(double);
   hipLaunchKernelGGL(k_residual_stencil, dim3(nchunk, (K + RES_COLS - 1) / RES_COLS), dim3(256), lds, st, R, ldr, F,
                      ldf, X, ldx, A, B, C, N, M, K, colpart, nchunk);
   return hipGetLastError();

@@ -89,29 +89,56 @@ hipError_t launch_scalar_factor(const double* a, const double* b, const double* 
   return hipGetLastError();
 }
 
+// the boundary coefficients of the subtrees' nodes in the order of their records (level order)
+__global__ void k_scalar_gather_h(double* sub_h, const int4* rec, int nrec, const double* hl, const double* hr) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrec) return;
+  const int m = rec[i].x;
+  sub_h[2 * i] = hl[m];
+  sub_h[2 * i + 1] = hr[m];
+}
+
+hipError_t launch_scalar_gather_h(double* sub_h, const int4* rec, int nrec, const double* hl, const double* hr,
+                                  hipStream_t st) {
+  if (nrec == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scalar_gather_h, dim3((nrec + 255) / 256), dim3(256), 0, st, sub_h, rec, nrec, hl, hr);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------------------------
 // Solve
 // ---------------------------------------------------------------------------------------------
 // Kernel 1: Pt[(lv * nsub + s) * K + k] = sum over the rows of subtree s of G[lv][j] F[j, k], lv < L0.
-// Grid (nsub, ceil(K / SC_CPW)), 256 threads.
+// Grid (nsub, ceil(K / SC_CPW)), 256 threads; each thread keeps its SC_SUB / 256 rows of the
+// SC_CPW columns in registers (F read once) and walks the top levels' rows of G.
 __global__ void __launch_bounds__(256) k_scalar_top_partials(const ScalarArgs A) {
+  constexpr int RPT = SC_SUB / 256;
   const int s = blockIdx.x;
   const int k0 = blockIdx.y * SC_CPW;
   const int l = A.sub_lo[s], r = A.sub_hi[s];
   const int tid = threadIdx.x, L = tid & 63, w = tid >> 6;
   __shared__ double red[4][SC_CPW];
+  double fv[RPT][SC_CPW];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int j = min(l + tid + 256 * i, r);   // clamped row: its product is dropped below
+#pragma unroll
+    for (int c = 0; c < SC_CPW; ++c) {
+      const int k = min(k0 + c, A.K - 1);      // clamped column: its sum is not stored
+      fv[i][c] = A.F[j + (int64_t)k * A.ldf];
+    }
+  }
   for (int lv = 0; lv < A.L0; ++lv) {
     const double* g = A.G + (int64_t)lv * A.N;
     double acc[SC_CPW];
 #pragma unroll
     for (int c = 0; c < SC_CPW; ++c) acc[c] = 0.0;
-    for (int j = l + tid; j <= r; j += 256) {
-      const double gj = g[j];
 #pragma unroll
-      for (int c = 0; c < SC_CPW; ++c) {
-        const int k = min(k0 + c, A.K - 1);   // clamped column: its sum is discarded below
-        acc[c] += gj * A.F[j + (int64_t)k * A.ldf];
-      }
+    for (int i = 0; i < RPT; ++i) {
+      const int j = l + tid + 256 * i;
+      const double gj = (j <= r) ? g[min(j, r)] : 0.0;
+#pragma unroll
+      for (int c = 0; c < SC_CPW; ++c) acc[c] += gj * fv[i][c];
     }
 #pragma unroll
     for (int c = 0; c < SC_CPW; ++c) {
@@ -126,29 +153,41 @@ __global__ void __launch_bounds__(256) k_scalar_top_partials(const ScalarArgs A)
   }
 }
 
-// Kernel 2: one thread per column; the top nodes in level order.  x of the top rows -> Xt[t * K + k]
-// (t = position in the top list), and written to (or added to) X.
+// Kernel 2: one wave per column.  First every top node's sum (lanes over the nodes: the subtree
+// parts from kernel 1 and the top rows' own terms), then the top levels in order (the top levels
+// are complete binary levels: level lv is positions [2^lv - 1, 2^(lv+1) - 1) of the top list), x in
+// LDS; x of the top rows -> Xt[t * K + k] and X (written, or added when accumulating).
 __global__ void __launch_bounds__(64) k_scalar_top(const ScalarArgs A) {
-  const int k = blockIdx.x * 64 + threadIdx.x;
-  if (k >= A.K) return;
-  for (int t = 0; t < A.ntop; ++t) {
-    const int m = A.top_m[t];
+  extern __shared__ double sx[];           // [ntop]: the node's sum, then its x
+  const int k = blockIdx.x;
+  const int L = threadIdx.x;
+  for (int t = L; t < A.ntop; t += 64) {
     const int lv = A.top_lvl[t];
     const double* g = A.G + (int64_t)lv * A.N;
     double S = 0.0;
     for (int q = A.top_s0[t]; q < A.top_s1[t]; ++q) S += A.Pt[((int64_t)lv * A.nsub + q) * A.K + k];
-    for (int q = A.top_t0[t]; q < A.top_t1[t]; ++q) {   // top rows inside the node, by row
+    for (int q = A.top_t0[t]; q < A.top_t1[t]; ++q) {
       const int j = A.toprow_sorted[q];
       S += g[j] * A.F[j + (int64_t)k * A.ldf];
     }
-    const int tl = A.top_left[t], tr = A.top_right[t];   // positions of rows l-1, r+1 in the top list, or -1
-    double x = S;
-    if (tl >= 0) x += A.hl[m] * A.Xt[(int64_t)tl * A.K + k];
-    if (tr >= 0) x += A.hr[m] * A.Xt[(int64_t)tr * A.K + k];
-    A.Xt[(int64_t)t * A.K + k] = x;
-    double* xo = A.X + m + (int64_t)k * A.ldx;
-    *xo = A.accumulate ? *xo + x : x;
+    sx[t] = S;
   }
+  __syncthreads();
+  for (int lv = 0; lv < A.L0; ++lv) {
+    const int t1 = min((2 << lv) - 1, A.ntop);
+    for (int t = (1 << lv) - 1 + L; t < t1; t += 64) {
+      const int m = A.top_m[t];
+      const int tl = A.top_left[t], tr = A.top_right[t];   // ancestors: their x is already in sx
+      double x = sx[t];
+      if (tl >= 0) x += A.hl[m] * sx[tl];
+      if (tr >= 0) x += A.hr[m] * sx[tr];
+      sx[t] = x;
+      double* xo = A.X + m + (int64_t)k * A.ldx;
+      *xo = A.accumulate ? *xo + x : x;
+    }
+    __syncthreads();
+  }
+  for (int t = L; t < A.ntop; t += 64) A.Xt[(int64_t)t * A.K + k] = sx[t];
 }
 
 // Kernel 3: grid (nsub, ceil(K / SC_CPW)), 256 threads; LDS: f and x of SC_CPW columns (with one
@@ -164,9 +203,20 @@ __global__ void __launch_bounds__(256) k_scalar_sub(const ScalarArgs A) {
   double* xs = fs + SC_CPW * W;            // [SC_CPW][W]: x at rows l-1 .. r+1
   double* gs = xs + SC_CPW * W;            // [W]: g of the current level at rows l .. r (index j - l + 1)
   const int tid = threadIdx.x, L = tid & 63, w = tid >> 6;
-  for (int c = 0; c < SC_CPW; ++c) {
-    const int k = min(k0 + c, A.K - 1);
-    for (int i = tid; i < n; i += 256) fs[c * W + 1 + i] = A.F[l + i + (int64_t)k * A.ldf];
+  constexpr int RPT = SC_SUB / 256;
+  {   // f of the SC_CPW columns: all loads issued before the LDS stores
+    double t[SC_CPW][RPT];
+#pragma unroll
+    for (int c = 0; c < SC_CPW; ++c) {
+      const int k = min(k0 + c, A.K - 1);
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) t[c][i] = A.F[l + min(tid + 256 * i, n - 1) + (int64_t)k * A.ldf];
+    }
+#pragma unroll
+    for (int c = 0; c < SC_CPW; ++c)
+#pragma unroll
+      for (int i = 0; i < RPT; ++i)
+        if (tid + 256 * i < n) fs[c * W + 1 + tid + 256 * i] = t[c][i];
   }
   if (tid < SC_CPW) {
     const int k = min(k0 + tid, A.K - 1);
@@ -174,37 +224,75 @@ __global__ void __launch_bounds__(256) k_scalar_sub(const ScalarArgs A) {
     xs[tid * W] = tl >= 0 ? A.Xt[(int64_t)tl * A.K + k] : 0.0;
     xs[tid * W + n + 1] = tr >= 0 ? A.Xt[(int64_t)tr * A.K + k] : 0.0;
   }
-  const int* order = A.sub_order + A.sub_off[s];        // this subtree's nodes in level order
-  const int* loff = A.sub_lvoff + s * (A.ndeep + 1);    // level boundaries within `order`
+  // this subtree's nodes in level order: records {m, l, r, -} and coefficients {hl, hr}
+  const int4* rec = A.sub_rec + A.sub_off[s];
+  const double2* hh = A.sub_h + A.sub_off[s];
+  const int* loff = A.sub_lvoff + s * (A.ndeep + 1);    // level boundaries within the records
+  // g of the first deep level in registers; each level stores its g to LDS and loads the next one's
+  double gn[RPT];
+  {
+    const double* g = A.G + (int64_t)A.L0 * A.N;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) gn[i] = g[l + min(tid + 256 * i, n - 1)];
+  }
   for (int d = 0; d < A.ndeep; ++d) {
     const int b0 = loff[d], b1 = loff[d + 1];
     if (b0 == b1) break;
-    const double* g = A.G + (int64_t)(A.L0 + d) * A.N;
-    __syncthreads();                                    // previous level's x (and the loads above)
-    for (int i = tid; i < n; i += 256) gs[1 + i] = g[l + i];
-    __syncthreads();
+    __syncthreads();                                    // previous level's x and g reads are done
+#pragma unroll
+    for (int i = 0; i < RPT; ++i)
+      if (tid + 256 * i < n) gs[1 + tid + 256 * i] = gn[i];
+    if (d + 1 < A.ndeep) {                              // next level's g, in flight during this level
+      const double* g = A.G + (int64_t)(A.L0 + d + 1) * A.N;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) gn[i] = g[l + min(tid + 256 * i, n - 1)];
+    }
     const int nn = b1 - b0;
-    const int m0 = order[b0];
-    const int len0 = A.hi[m0] - A.lo[m0] + 1;          // node sizes within a level differ by at most 1
+    const int4 r0 = rec[b0];
+    const int len0 = r0.z - r0.y + 1;                   // node sizes within a level differ by at most 1
+    __syncthreads();
     if (len0 >= 32) {
       // one wave per (node, column): strided partial sums, then a wave reduction
       for (int p = w; p < nn * SC_CPW; p += 4) {
-        const int m = order[b0 + p / SC_CPW], c = p % SC_CPW;
-        const int nl = A.lo[m], nr = A.hi[m];
+        const int q = __builtin_amdgcn_readfirstlane(b0 + p / SC_CPW), c = p % SC_CPW;
+        const int4 rc = rec[q];
+        const double2 h = hh[q];
         double S = 0.0;
-        for (int j = nl + L; j <= nr; j += 64) S += gs[j - l + 1] * fs[c * W + j - l + 1];
+        for (int j = rc.y + L; j <= rc.z; j += 64) S += gs[j - l + 1] * fs[c * W + j - l + 1];
         for (int off = 32; off > 0; off >>= 1) S += __shfl_xor(S, off);
         if (L == 0)
-          xs[c * W + m - l + 1] = S + A.hl[m] * xs[c * W + nl - l] + A.hr[m] * xs[c * W + nr - l + 2];
+          xs[c * W + rc.x - l + 1] = S + h.x * xs[c * W + rc.y - l] + h.y * xs[c * W + rc.z - l + 2];
       }
     } else {
-      // one thread per (node, column)
-      for (int p = tid; p < nn * SC_CPW; p += 256) {
-        const int m = order[b0 + p / SC_CPW], c = p % SC_CPW;
-        const int nl = A.lo[m], nr = A.hi[m];
-        double S = 0.0;
-        for (int j = nl; j <= nr; ++j) S += gs[j - l + 1] * fs[c * W + j - l + 1];
-        xs[c * W + m - l + 1] = S + A.hl[m] * xs[c * W + nl - l] + A.hr[m] * xs[c * W + nr - l + 2];
+      // one thread per (node, column); a thread's records of the level are loaded together, QM at a
+      // time (a level has at most SC_SUB / 2 nodes, so one round for SC_CPW = 4)
+      constexpr int QM = (SC_SUB / 2 * SC_CPW + 255) / 256;
+      const int np = nn * SC_CPW;
+      for (int p0 = 0; p0 < np; p0 += 256 * QM) {
+        int4 rq[QM];
+        double2 hq[QM];
+#pragma unroll
+        for (int u = 0; u < QM; ++u) {
+          const int p = min(p0 + tid + 256 * u, np - 1);
+          rq[u] = rec[b0 + p / SC_CPW];
+          hq[u] = hh[b0 + p / SC_CPW];
+        }
+#pragma unroll
+        for (int u = 0; u < QM; ++u) {
+          const int p = p0 + tid + 256 * u;
+          if (p >= np) break;
+          const int c = p % SC_CPW;
+          const int4 rc = rq[u];
+          double S0 = 0.0, S1 = 0.0;   // two chains of dependent additions
+          int j = rc.y;
+          for (; j + 1 <= rc.z; j += 2) {
+            S0 += gs[j - l + 1] * fs[c * W + j - l + 1];
+            S1 += gs[j - l + 2] * fs[c * W + j - l + 2];
+          }
+          if (j <= rc.z) S0 += gs[j - l + 1] * fs[c * W + j - l + 1];
+          xs[c * W + rc.x - l + 1] =
+              (S0 + S1) + hq[u].x * xs[c * W + rc.y - l] + hq[u].y * xs[c * W + rc.z - l + 2];
+        }
       }
     }
   }
@@ -224,7 +312,7 @@ hipError_t launch_scalar_top(const ScalarArgs& A, hipStream_t st) {
   if (A.K == 0 || A.L0 == 0) return hipSuccess;
   const int cg = (A.K + SC_CPW - 1) / SC_CPW;
   hipLaunchKernelGGL(k_scalar_top_partials, dim3(A.nsub, cg), dim3(256), 0, st, A);
-  hipLaunchKernelGGL(k_scalar_top, dim3((A.K + 63) / 64), dim3(64), 0, st, A);
+  hipLaunchKernelGGL(k_scalar_top, dim3(A.K), dim3(64), (size_t)A.ntop * sizeof(double), st, A);
   return hipGetLastError();
 }
 

@@ -1009,6 +1009,8 @@ void factor_scalar(td_plan_s* P, const double* A, const double* B, const double*
       top_lvl.push_back(lv);
     }
   const int ntop = (int)top_m.size();
+  for (int lv = 0; lv < L0; ++lv)   // the solve's top kernel walks complete binary levels
+    if ((int)bylevel[lv].size() != (1 << lv)) throw std::string("internal error: incomplete top level");
   std::vector<int> toprow_sorted(top_m);
   std::sort(toprow_sorted.begin(), toprow_sorted.end());
   std::vector<int> sub_lo(nsub), sub_hi(nsub), sub_left(nsub), sub_right(nsub), sub_off(nsub);
@@ -1059,7 +1061,11 @@ void factor_scalar(td_plan_s* P, const double* A, const double* B, const double*
     while (arena.size() % 64) arena.push_back(0);
   };
   add(lo); add(hi); add(lvl);
-  add(sub_lo); add(sub_hi); add(sub_left); add(sub_right); add(sub_order); add(sub_off); add(sub_lvoff);
+  std::vector<int> sub_rec;   // {m, l, r, 0} per node in sub_order
+  for (int m : sub_order) {
+    sub_rec.push_back(m); sub_rec.push_back(lo[m]); sub_rec.push_back(hi[m]); sub_rec.push_back(0);
+  }
+  add(sub_lo); add(sub_hi); add(sub_left); add(sub_right); add(sub_rec); add(sub_off); add(sub_lvoff);
   add(top_m); add(top_lvl); add(top_s0); add(top_s1); add(top_t0); add(top_t1); add(top_left); add(top_right);
   add(toprow_sorted);
   const int* d = P->upload(arena);
@@ -1069,7 +1075,7 @@ void factor_scalar(td_plan_s* P, const double* A, const double* B, const double*
   S.lo = d + at[0]; S.hi = d + at[1];
   const int* d_lvl = d + at[2];
   S.sub_lo = d + at[3]; S.sub_hi = d + at[4]; S.sub_left = d + at[5]; S.sub_right = d + at[6];
-  S.sub_order = d + at[7]; S.sub_off = d + at[8]; S.sub_lvoff = d + at[9];
+  S.sub_rec = (const int4*)(d + at[7]); S.sub_off = d + at[8]; S.sub_lvoff = d + at[9];
   S.top_m = d + at[10]; S.top_lvl = d + at[11]; S.top_s0 = d + at[12]; S.top_s1 = d + at[13];
   S.top_t0 = d + at[14]; S.top_t1 = d + at[15]; S.top_left = d + at[16]; S.top_right = d + at[17];
   S.toprow_sorted = d + at[18];
@@ -1081,6 +1087,9 @@ void factor_scalar(td_plan_s* P, const double* A, const double* B, const double*
   const bool tri = P->fmtC == TD_FMT_TRIDIAG;
   HIPCHK(launch_scalar_factor(P->cA, P->cB, P->cC + (tri ? 1 : 0), tri ? 3 : 1, N, S.lo, S.hi, d_lvl, G, hl, hr, bad,
                               st));
+  double* sub_h = P->alloc(2 * (int64_t)sub_order.size());
+  HIPCHK(launch_scalar_gather_h(sub_h, S.sub_rec, (int)sub_order.size(), hl, hr, st));
+  S.sub_h = (const double2*)sub_h;
   int32_t badv = INT_MAX;
   HIPCHK(hipMemcpyAsync(&badv, bad, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -1126,7 +1135,7 @@ bool stencil_formats(const td_plan_s* P) {
 }
 
 int residual_parts(const td_plan_s* P) {
-  return stencil_formats(P) ? residual_row_chunks(P->N * P->M) : (int)P->N;
+  return stencil_formats(P) ? residual_row_chunks_wide(P->N * P->M) : (int)P->N;
 }
 
 void ensure_refine_ws(td_plan_s* P, int64_t K) {

@@ -519,28 +519,30 @@ __device__ __forceinline__ void superpose_lp_tile(const LpSupArgs& a, int s, int
 }
 
 // Float64 residual R = F - P X for diagonal A, B and tridiagonal C (a five-point stencil over the
-// rows), one work-group of 256 threads: rows [q RES_ROWS, (q+1) RES_ROWS) of the right-hand sides
+// rows), one work-group of 256 threads: rows [q ROWS, (q+1) ROWS) of the right-hand sides
 // c0 .. c0 + RES_COLS - 1 (fewer at the end).  The five coefficients of the work-group's rows stay
 // in registers for all its columns; each column's x, with one block of rows on either side, is
-// staged once in LDS (xs: RES_ROWS + 2M doubles), so every neighbour is an LDS read; the next
+// staged once in LDS (xs: ROWS + 2M doubles), so every neighbour is an LDS read; the next
 // column's x and f are loaded into registers while the current column is computed.  The
 // coefficients of absent neighbours must be zero (the plan's copies are), so the row formula has
 // no branches; halo rows outside the matrix are staged as zeros.  colpart[col][q] receives the sums
 // of squares of R and F over the rows (fixed order, no atomics); red holds 2 RES_COLS x 4 doubles.
-constexpr int RES_RPT = RES_ROWS / 256;   // rows per thread
-constexpr int RES_SPT = RES_RPT + 4;      // staged rows per thread: RES_ROWS + 2M with M <= 512
-
+// ROWS: RES_ROWS in the batched kernels, RES_ROWS_WIDE in the residual kernel of a single solve (the
+// staged halo of 2M rows costs less against more rows).
+template <int ROWS>
 __device__ __forceinline__ void residual_cols_tile(double* __restrict__ R, int64_t ldr, const double* __restrict__ F,
                                                    int64_t ldf, const double* __restrict__ X, int64_t ldx,
                                                    const double* __restrict__ A, const double* __restrict__ B,
                                                    const double* __restrict__ C, int N, int M, int K,
                                                    double* __restrict__ colpart, int nchunk, int q, int c0,
                                                    double* xs, double (*red)[4]) {
+  constexpr int RES_RPT = ROWS / 256;   // rows per thread
+  constexpr int RES_SPT = RES_RPT + 4;  // staged rows per thread: ROWS + 2M with M <= 512
   const int tid = threadIdx.x;
   const int ncol = (K - c0) < RES_COLS ? (K - c0) : RES_COLS;
   const int64_t n = (int64_t)N * M;
-  const int64_t g0 = (int64_t)q * RES_ROWS;
-  const int cnt = (n - g0) < RES_ROWS ? (int)(n - g0) : RES_ROWS;
+  const int64_t g0 = (int64_t)q * ROWS;
+  const int cnt = (n - g0) < ROWS ? (int)(n - g0) : ROWS;
   const int64_t jb = g0 / M;
   const unsigned rb0 = (unsigned)(g0 - jb * M);
   // own rows tid + 256 i (the tail chunk repeats its last row; those copies are not stored)

@@ -74,3 +74,17 @@ def test_noalloc_rejects_workspace_above_the_array(td):
     assert _noalloc(td, plan, F, X) == 1
     assert b"scratch" in td.load_library().tridiag_last_error()
     plan.close()
+
+
+def test_noalloc_scalar_plan(td):
+    """The scalar plan (block size 1, every row an interface row): the no-allocation solve places the
+    top levels' partial sums and top-row values in the fixed array; equal to the plan's own solve."""
+    sys = synth.varcoef_system(3000, 1, seed=93)
+    F = _dev(synth.rhs_columns(93, 3000, 1, range(9)))
+    plan = td.Plan.from_system(sys, subdomains=3000)
+    ref = plan.solve(F).clone()
+    X = torch.full_like(F, float("nan"))
+    assert _noalloc(td, plan, F, X) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(X, ref)
+    plan.close()
