@@ -18,11 +18,21 @@ sys.path.insert(0, ROOT)
 import oracle  # noqa: E402
 import synth   # noqa: E402
 
+def tile_columns(K, tiles, step=32):
+    """One column in each of `tiles` groups of `step` columns, at a different position in each group
+    (so that every column tile of the solve kernels, and lanes across the tile, are sampled), plus the
+    first and the last column."""
+    cols = {0, K - 1}
+    for t in range(tiles):
+        cols.add(min(K - 1, t * (K // tiles) + (7 * t + 3) % step))
+    return sorted(cols)
+
+
 SPECS = {
     # workload: (columns, samples per column)
-    "varcoef_n2048_m256_k512": ([0, 257, 511], 1500),
-    "adjoint_n1024_m256_k256": ([0, 128, 255], 1500),
-    "mixed_n4096_m512_k1024": ([0, 1023], 1500),
+    "varcoef_n2048_m256_k512": (tile_columns(512, 16), 500),
+    "adjoint_n1024_m256_k256": (tile_columns(256, 8), 800),
+    "mixed_n4096_m512_k1024": (tile_columns(1024, 8), 800),
 }
 
 
@@ -83,7 +93,7 @@ def make_batched(samples=500):
 
 
 if __name__ == "__main__":
-    for name in (sys.argv[1:] or ["varcoef_n2048_m256_k512", "adjoint_n1024_m256_k256"]):
+    for name in (sys.argv[1:] or ["varcoef_n2048_m256_k512", "adjoint_n1024_m256_k256", "mixed_n4096_m512_k1024"]):
         if name == "batched_64_largest":
             make_batched()
         else:
