@@ -25,33 +25,37 @@ PEAK_F64_MFMA = 78.6   # TFLOP/s, MI355X dense float64 matrix
 PEAK_F32_MFMA = 157.3
 PEAK_HBM = 8000.0      # GB/s
 
-# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (FETCH_SIZE scaled by 2.0,
-# the factor a 1 GiB device copy shows), valid only for the kernel sources they were taken on
-# (profiles/sweep_superposition_varcoef_n2048_m256_k512.md).
-MEASURED_TRAFFIC = {
-    # kernel: (workload, source hash (kernel_source_hash), read bytes, write bytes)
-    "sweep": ("varcoef_n2048_m256_k512", "acc9770f3ef82867", 6.61451e9, 4.09993e9),
-    "superposition": ("varcoef_n2048_m256_k512", "acc9770f3ef82867", 4.41027e9, 2.08037e9),
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (FETCH_SIZE scaled by 2.0 and
+# WRITE_SIZE by 1.0, the factors a 1 GiB device copy shows), valid only for the kernel sources they
+# were taken on (profiles/solve_f64_n4096_m512_k1024.md, profiles/scalar_dichotomy_n65536_k1024.md).
+KERNEL_SOURCES = {
+    "f64": ["kernels_f64.hip", "tile_bodies.h", "device_common.h", "internal.h"],
+    "scalar": ["kernels_scalar.hip", "device_common.h", "internal.h"],
 }
-KERNEL_SOURCES = ["kernels_f64.hip", "tile_bodies.h", "device_common.h", "internal.h"]
+MEASURED_TRAFFIC = {
+    # (kernel, workload): (source set, source hash (kernel_source_hash), read bytes, write bytes)
+    ("sweep", "mixed_n4096_m512_k1024"): ("f64", "6e00623b90cd4c21", 54.0581e9, 32.7995e9),
+    ("superposition", "mixed_n4096_m512_k1024"): ("f64", "6e00623b90cd4c21", 51.4852e9, 16.6430e9),
+    ("scalar_subtrees", "scalar_n65536_k1024"): ("scalar", "4bef27c9aaf0ad3b", 0.60746e9, 0.53687e9),
+}
 
 
-def kernel_source_hash():
-    """sha256 prefix over the sources that define the float64 sweep and superposition kernels."""
+def kernel_source_hash(which="f64"):
+    """sha256 prefix over the sources that define the kernels of a measured-traffic entry."""
     import hashlib
 
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in KERNEL_SOURCES[which]:
         with open(os.path.join(ROOT, "paper_1108_4181_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel, workload):
-    rec = MEASURED_TRAFFIC.get(kernel)
-    if rec is None or rec[0] != workload or not rec[1]:
+    rec = MEASURED_TRAFFIC.get((kernel, workload))
+    if rec is None:
         return None
-    return rec[2] + rec[3] if kernel_source_hash() == rec[1] else None
+    return rec[2] + rec[3] if kernel_source_hash(rec[0]) == rec[1] else None
 
 
 def partition(N, p):
@@ -372,6 +376,84 @@ def bench_schur(args):
     print(json.dumps(out))
 
 
+# The paper's Tables 1-2 (Sec. 2.3), smallest printed value over the process counts of each column:
+# solve time "Exe" (seconds, presumably one right-hand side) with its process count, and preliminary
+# time "Pre" (the factor) with its process count, on the MBC-100k cluster (Fortran-90 + MPI, node CPU
+# not stated).  Taken as printed, also where a value breaks its column's trend (4096 x 150: 2.6e-3 s
+# at 256 processes between 4.8e-2 and 1.3e-2; 4096 x 60: 1.3e-4 s at 2048).
+PAPER_BEST = {
+    # (N, M): (Exe, processes, Pre, processes)
+    (2048, 60): (4.6e-4, 1024, 1.0, 32), (2048, 150): (4e-3, 1024, 15.0, 64),
+    (4096, 60): (1.3e-4, 2048, 1.9, 32), (4096, 150): (2.6e-3, 256, 22.0, 64),
+    (8192, 60): (1e-3, 512, 3.0, 64), (8192, 150): (1.4e-2, 1024, 30.0, 128),
+    (16384, 60): (8.8e-4, 1024, 4.1, 256), (16384, 150): (2.7e-2, 1024, 44.0, 128),
+    (32768, 60): (2e-3, 2048, 5.0, 256), (32768, 150): (5.5e-2, 1024, 60.0, 256),
+    (65536, 60): (6.6e-3, 2048, 6.9, 256), (65536, 150): (0.1, 1024, 89.0, 256),
+}
+
+
+def bench_paper(args):
+    """The paper's problem sizes (N = 2^11 .. 2^16 block rows, M = 60 and 150; Sec. 2.3) with the
+    variable-coefficient family: factor time, the time of a one-right-hand-side solve (the paper's
+    Exe) and the rate at K right-hand sides, next to the paper's best Exe on its cluster."""
+    import torch
+
+    import synth
+    import paper_1108_4181_amd as td
+
+    dev = torch.device("cuda:0")
+    K = args.paper_k
+    rows = []
+    # one untimed factor first, so that the first size's factor time holds no one-time start-up cost
+    td.Plan.from_system(synth.varcoef_system(64, 60, 1), device=dev, subdomains=4).close()
+    torch.cuda.synchronize()
+    for (N, M), (exe, nproc, pre, nproc_pre) in sorted(PAPER_BEST.items(), key=lambda kv: (kv[0][1], kv[0][0])):
+        sysw = synth.varcoef_system(N, M, 7000 + N + M)
+        p = td.default_subdomains(N, K)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = td.Plan.from_system(sysw, device=dev, subdomains=p)
+        torch.cuda.synchronize()
+        fac_s = time.perf_counter() - t0
+        res = {}
+        for k in (1, K):
+            F = synth.rhs_torch(7100 + N + M, N, M, k, dev)
+            X = torch.empty_like(F)
+            _, info = plan.solve(F, X, info=True)
+            for _ in range(args.warmup):
+                plan.solve(F, X)
+            torch.cuda.synchronize()
+            n = max(3, args.steps)
+            t0 = time.perf_counter()
+            for _ in range(n):
+                plan.solve(F, X)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / n
+            res[k] = (ms, info["max_col_rel_residual"])
+            del F, X
+        plan.close()
+        del plan
+        torch.cuda.empty_cache()
+        rows.append({"N": N, "M": M, "subdomains": p, "factor_s": fac_s, "solve_ms_k1": res[1][0],
+                     f"solve_ms_k{K}": res[K][0], f"rhs_per_s_k{K}": K / (res[K][0] * 1e-3),
+                     "max_col_rel_residual": max(res[1][1], res[K][1]),
+                     "paper_best_exe_s": exe, "paper_nproc": nproc,
+                     "k1_speedup_vs_paper_exe": exe / (res[1][0] * 1e-3),
+                     "paper_best_pre_s": pre, "paper_nproc_pre": nproc_pre,
+                     "factor_speedup_vs_paper_pre": pre / fac_s})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    tot = sum(r[f"solve_ms_k{K}"] for r in rows)
+    out = {
+        "metric": METRIC, "value": len(rows) * K / (tot * 1e-3), "unit": "RHS/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": tot, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "paper_sizes", "sizes": "N 2^11..2^16 x M 60, 150", "K": K,
+                   "coefficients": "varcoef", "paper_hardware": "MBC-100k cluster, Fortran-90 + MPI (Sec. 2.3)"},
+        "sizes": rows,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -387,6 +469,7 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="bytes of a plain device-to-device copy run before the timed region (counter calibration)")
     ap.add_argument("--batch-passes", type=int, default=3)
+    ap.add_argument("--paper-k", type=int, default=256, help="right-hand sides of the paper-size sweep's rate")
     ap.add_argument("--subdomains", type=int, default=0,
                     help="override the workload's subdomain count (= N: Algorithm 1 on the whole system)")
     ap.add_argument("--band", default="65536,60,60,256",
@@ -401,6 +484,9 @@ def main():
 
     if args.workload == "batched_64":
         bench_batched(args)
+        return
+    if args.workload == "paper_sizes":
+        bench_paper(args)
         return
     if args.workload == "band":
         bench_band(args)
@@ -479,7 +565,7 @@ def main():
         t_ms, fl, by = kern[dom]
         achieved = by / (t_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM, "unit": "GB/s",
-                    "frac": achieved / PEAK_HBM, "traffic": None,
+                    "frac": achieved / PEAK_HBM, "traffic": measured_traffic(dom, args.workload),
                     "algorithmic_flops_per_launch": fl, "algorithmic_bytes_per_launch": by,
                     "avg_launch_ms": t_ms}
         other = {k: {"avg_launch_ms": v[0], "gbs": v[2] / (v[0] * 1e-3) / 1e9} for k, v in kern.items()}
