@@ -180,11 +180,40 @@ static hipError_t launch_superpose_cfg(const SupArgs& a0, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Block sizes above 256: 32-column tiles with half of the interface panel in LDS at a time
+// (Mp x 34 doubles: 139 KB at Mp = 512), see superpose_f64_half_tile.
+template <int RT, int CT>
+__global__ void __launch_bounds__(512) k_superpose_f64_half(SupArgs a) {
+  extern __shared__ double Xs[];  // [Mp][4 CT + 2]
+  const int lg = xcd_remap(blockIdx.x, gridDim.x);
+  if (lg >= a.total) return;
+  const int s = lg / a.ncoltiles;
+  superpose_f64_half_tile<RT, CT, 2>(a, s, lg - s * a.ncoltiles, Xs);
+}
+
+template <int RT, int CT>
+static hipError_t launch_superpose_half_cfg(const SupArgs& a0, hipStream_t st) {
+  SupArgs a = a0;
+  constexpr int kt = 4 * CT;
+  a.ncoltiles = (a.K + kt - 1) / kt;
+  a.total = a.p * a.ncoltiles;
+  if (a.total == 0) return hipSuccess;
+  const int nthr = a.Mp / (16 * RT) * 64;
+  const size_t lds = (size_t)a.Mp * (kt + 2) * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void*)k_superpose_f64_half<RT, CT>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_superpose_f64_half<RT, CT>), dim3(grid_pad8(a.total)), dim3(nthr), lds, st, a);
+  return hipGetLastError();
+}
+
 template <int RT>
 static hipError_t launch_superpose_rt(const SupArgs& a, hipStream_t st) {
   // the LDS panel is 2 Mp x (4 CT + 2) doubles and must fit in 160 KB
   const int64_t bytes8 = (int64_t)2 * a.Mp * 34 * 8;
   if (a.K <= 8) return launch_superpose_cfg<RT, 2>(a, st);
+  if (RT == 4 && !a.accumulate && a.K > 16 && a.Mp % 64 == 0 && (int64_t)a.Mp * 34 * 8 <= 160 * 1024)
+    return launch_superpose_half_cfg<4, 8>(a, st);
   if (a.K <= 16 || bytes8 > 160 * 1024 || RT == 4) return launch_superpose_cfg<RT, 4>(a, st);
   return launch_superpose_cfg<RT, (RT == 4 ? 4 : 8)>(a, st);
 }

@@ -895,4 +895,170 @@ __device__ __forceinline__ void superpose_f64_tile(const SupArgs& a, int s, int 
   }
 }
 
+// The same product for block sizes whose 2Mp x 4CT interface panel does not fit in LDS with 32
+// columns: LDS holds one half of the panel at a time (the left interface's Mp rows, which multiply
+// U_i, or the right interface's, which multiply V_i).  A row first multiplies the half already in
+// LDS, then reloads the other half and multiplies that; the next row starts with the half now in
+// LDS, so each row reloads Mp x 4CT values once (from L2: the tile's interface values are re-read
+// by every row of the subdomain).  The [U_i V_i] chunks keep streaming one chunk ahead across the
+// reload and across rows.
+template <int RT, int CT, int KU = 2>
+__device__ __forceinline__ void superpose_f64_half_tile(const SupArgs& a, int s, int ct, double* Xs) {
+  constexpr int KT = 4 * CT;
+  constexpr int SB = KT + 2;
+
+  const int tid = threadIdx.x;
+  const int L = tid & 63, w = tid >> 6;
+  const int col0 = ct * KT;
+  const int64_t first = a.ks[s] + 1, last = a.ks[s + 1] - 1;
+  if (first > last) return;
+  const int Mp = a.Mp, M = a.M, K = a.K;
+  const int rb = w * 16 * RT;
+  const int64_t MM = (int64_t)Mp * Mp;
+  const int nkh = Mp / (4 * KU);   // chunks per half (even: Mp is a multiple of 64 here)
+
+  // Xi rows (s + 1 + h) Mp .. (s + 2 + h) Mp - 1 of the tile's columns -> LDS.  The work-group has
+  // Mp threads (RT = 4: Mp / 64 waves), so thread k loads row k of every column; all loads of a
+  // batch are issued before its stores (columns beyond K read column K - 1 and store zero).
+  static_assert(RT == 4, "one interface row per thread");
+  auto load_half = [&](int h) {
+    constexpr int B = 16;
+    const int nv = min(KT, K - col0);   // columns of the tile below K
+    const double* __restrict__ q = a.Xi + (int64_t)(s + 1 + h) * Mp + tid + (int64_t)col0 * a.ldxi;
+    double* dst = Xs + lds_row(tid) * SB;
+    if (nv == KT) {
+#pragma unroll
+      for (int c0 = 0; c0 < KT; c0 += B) {
+        double v[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+          v[u] = *q;
+          q += a.ldxi;
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u) dst[lds_col<CT>(c0 + u)] = v[u];
+      }
+    } else {   // the last, ragged column tile
+#pragma unroll 1
+      for (int c = 0; c < KT; ++c) dst[lds_col<CT>(c)] = c < nv ? q[(int64_t)c * a.ldxi] : 0.0;
+    }
+  };
+
+  const int64_t lane_off = rb + (L & 15) + (int64_t)(L >> 4) * Mp;
+  double a0[KU][RT], a1[KU][RT];
+  auto loadA = [&](double (&dst)[KU][RT], const double* __restrict__ Ab, int q) {
+    const double* __restrict__ pa = Ab + lane_off + (int64_t)(4 * KU * q) * Mp;
+#pragma unroll
+    for (int u = 0; u < KU; ++u)
+#pragma unroll
+      for (int t = 0; t < RT; ++t) dst[u][t] = pa[16 * t + (int64_t)(4 * u) * Mp];
+  };
+  const double* Bl = &Xs[4 * (L >> 4) * SB + 2 * (L & 3)];   // block L % 4 (see lds_col, lds_row)
+  double b0[CT], b1[CT];
+  auto ldB = [&](double (&b)[CT], int ks) {   // rows 4 ks .. 4 ks + 3 of the half in LDS
+    const double* bp = Bl + (16 * (ks >> 2) + (ks & 3)) * SB;
+#pragma unroll
+    for (int c = 0; c < CT; c += 2) {
+      const double2 v = *reinterpret_cast<const double2*>(bp + (c >> 1) * 8);
+      b[c] = v.x;
+      b[c + 1] = v.y;
+    }
+  };
+  double acc[RT][CT];
+  auto mm = [&](const double (&av)[RT], const double (&b)[CT]) {
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int c = 0; c < CT; ++c) acc[t][c] = mfma4(av[t], b[c], acc[t][c]);
+  };
+  // k-steps KU*q .. KU*q + KU - 1 of the half; on entry b0 holds the operand of the first of them
+  auto compute = [&](const double (&av)[KU][RT], int q, bool last_chunk) {
+#pragma unroll
+    for (int u = 0; u < KU; u += 2) {
+      const int ks = KU * q + u;
+      ldB(b1, ks + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      mm(av[u], b0);
+      __builtin_amdgcn_sched_barrier(0);
+      if (!(last_chunk && u + 2 >= KU)) ldB(b0, ks + 2);
+      __builtin_amdgcn_sched_barrier(0);
+      mm(av[u + 1], b1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+  // all chunks of one half but the last two; a0 holds chunk 0 on entry
+  auto body = [&](const double* __restrict__ Ah) {
+    ldB(b0, 0);
+    for (int kc = 0; kc < nkh - 2; kc += 2) {
+      loadA(a1, Ah, kc + 1);
+      compute(a0, kc, false);
+      loadA(a0, Ah, kc + 2);
+      compute(a1, kc + 1, false);
+    }
+  };
+
+  int cur = 0;   // the half in LDS
+  load_half(0);
+  loadA(a0, a.UV + 2 * first * MM, 0);
+  __syncthreads();
+  for (int64_t i = first; i <= last; ++i) {
+    const double* __restrict__ Ai = a.UV + 2 * i * MM;
+    const double* __restrict__ Anx = (i < last) ? Ai + 2 * MM : Ai;
+    const int nxt = 1 - cur;
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int c = 0; c < CT; ++c) acc[t][c] = 0.0;
+    // the half in LDS; the last chunk prefetches chunk 0 of the other half of this row
+    {
+      const double* __restrict__ Ah = Ai + cur * MM;
+      body(Ah);
+      loadA(a1, Ah, nkh - 1);
+      compute(a0, nkh - 2, false);
+      loadA(a0, Ai + nxt * MM, 0);
+      compute(a1, nkh - 1, true);
+    }
+    __syncthreads();   // every wave is done reading this half
+    load_half(nxt);
+    __syncthreads();
+    // the other half; the last chunk prefetches chunk 0 of the same half of the next row
+    const double* __restrict__ Ah = Ai + nxt * MM;
+    body(Ah);
+    // W_i fetched before the last two chunks by unconditional loads:
+    // one address per column (rows 16 t apart are immediate offsets from it); a lane whose column
+    // is beyond K reads column min(lcol, K - 1) and discards the value
+    double ex[RT][CT];
+    const int lcol = col0 + out_col(L) * CT;              // the lane's first column
+    const int orow = rb + out_row(L);
+    {
+      const double* __restrict__ pw0 = a.W + i * Mp + orow + (int64_t)min(lcol, K - 1) * a.ldw;
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const bool ok = lcol + c < K;
+        const double* __restrict__ pw = pw0 + (ok ? (int64_t)c * a.ldw : 0);
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          const double v = pw[16 * t];
+          ex[t][c] = ok ? v : 0.0;
+        }
+      }
+    }
+    loadA(a1, Ah, nkh - 1);
+    compute(a0, nkh - 2, false);
+    loadA(a0, Anx + nxt * MM, 0);
+    compute(a1, nkh - 1, true);
+    double* __restrict__ px0 = a.X + i * M + orow + (int64_t)lcol * a.ldx;
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      if (lcol + c < K) {
+        double* __restrict__ px = px0 + (int64_t)c * a.ldx;
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+          if (orow + 16 * t < M) px[16 * t] = acc[t][c] + ex[t][c];
+      }
+    }
+    cur = nxt;
+  }
+}
+
 }  // namespace td
