@@ -14,7 +14,7 @@
 // Solve layout: the nodes of level L0 (at most SC_SUB rows each) are the subtrees; the nodes above are
 // the top nodes.  Kernel 1 gives, per subtree and column, the subtree's part of the sums of the top
 // nodes that contain it (one per top level); kernel 2 completes the top nodes' sums and solves the top
-// levels (one thread per column); kernel 3 solves each subtree's levels with f, x and one level of g in
+// levels (one wave per column); kernel 3 solves each subtree's levels with f, x and one level of g in
 // LDS, taking the subtree's two boundary values from kernel 2.
 #include "device_common.h"
 #include "internal.h"
@@ -108,16 +108,37 @@ hipError_t launch_scalar_gather_h(double* sub_h, const int4* rec, int nrec, cons
 // ---------------------------------------------------------------------------------------------
 // Solve
 // ---------------------------------------------------------------------------------------------
+// Sum over aligned groups of G lanes (G a power of two, the same in every lane) with DPP moves:
+// swaps within quads, half-row and row mirrors, then row broadcasts.  The group's total ends in its
+// last lane (in every lane of the group for G <= 16).
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_take(double v) {   // the selected lane's v; 0 in rows outside ROWMASK
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double group_sum(double v, int G) {
+  if (G >= 2) v += dpp_take<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+  if (G >= 4) v += dpp_take<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+  if (G >= 8) v += dpp_take<0x141, 0xF>(v);   // row_half_mirror
+  if (G >= 16) v += dpp_take<0x140, 0xF>(v);  // row_mirror
+  if (G >= 32) v += dpp_take<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  if (G >= 64) v += dpp_take<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
 // Kernel 1: Pt[(lv * nsub + s) * K + k] = sum over the rows of subtree s of G[lv][j] F[j, k], lv < L0.
 // Grid (nsub, ceil(K / SC_CPW)), 256 threads; each thread keeps its SC_SUB / 256 rows of the
-// SC_CPW columns in registers (F read once) and walks the top levels' rows of G.
+// SC_CPW columns in registers (F read once) and walks the top levels' rows of G; each wave's sums
+// (DPP, no barrier) go to LDS and one barrier at the end precedes the sum over the four waves.
+constexpr int SC_MAXTOP = 24;   // top levels (L0 <= log2(N / SC_SUB) + 1 for N below 2^31)
 __global__ void __launch_bounds__(256) k_scalar_top_partials(const ScalarArgs A) {
   constexpr int RPT = SC_SUB / 256;
   const int s = blockIdx.x;
   const int k0 = blockIdx.y * SC_CPW;
   const int l = A.sub_lo[s], r = A.sub_hi[s];
   const int tid = threadIdx.x, L = tid & 63, w = tid >> 6;
-  __shared__ double red[4][SC_CPW];
+  __shared__ double red[SC_MAXTOP][4][SC_CPW];
   double fv[RPT][SC_CPW];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
@@ -128,28 +149,36 @@ __global__ void __launch_bounds__(256) k_scalar_top_partials(const ScalarArgs A)
       fv[i][c] = A.F[j + (int64_t)k * A.ldf];
     }
   }
-  for (int lv = 0; lv < A.L0; ++lv) {
+  double gq[RPT];   // the next level's rows of G, loaded one level ahead
+  auto load_g = [&](int lv) {
     const double* g = A.G + (int64_t)lv * A.N;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) gq[i] = g[min(l + tid + 256 * i, r)];
+  };
+  load_g(0);
+  for (int lv = 0; lv < A.L0; ++lv) {
+    double gv[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) gv[i] = (l + tid + 256 * i <= r) ? gq[i] : 0.0;
+    if (lv + 1 < A.L0) load_g(lv + 1);
     double acc[SC_CPW];
 #pragma unroll
     for (int c = 0; c < SC_CPW; ++c) acc[c] = 0.0;
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-      const int j = l + tid + 256 * i;
-      const double gj = (j <= r) ? g[min(j, r)] : 0.0;
+    for (int i = 0; i < RPT; ++i)
 #pragma unroll
-      for (int c = 0; c < SC_CPW; ++c) acc[c] += gj * fv[i][c];
-    }
+      for (int c = 0; c < SC_CPW; ++c) acc[c] += gv[i] * fv[i][c];
 #pragma unroll
     for (int c = 0; c < SC_CPW; ++c) {
-      double v = acc[c];
-      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-      if (L == 0) red[w][c] = v;
+      const double v = group_sum(acc[c], 64);
+      if (L == 63) red[lv][w][c] = v;
     }
-    __syncthreads();
-    if (tid < SC_CPW && k0 + tid < A.K)
-      A.Pt[((int64_t)lv * A.nsub + s) * A.K + k0 + tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-    __syncthreads();
+  }
+  __syncthreads();
+  for (int e = tid; e < A.L0 * SC_CPW; e += 256) {
+    const int lv = e / SC_CPW, c = e % SC_CPW;
+    if (k0 + c < A.K)
+      A.Pt[((int64_t)lv * A.nsub + s) * A.K + k0 + c] = red[lv][0][c] + red[lv][1][c] + red[lv][2][c] + red[lv][3][c];
   }
 }
 
@@ -190,33 +219,43 @@ __global__ void __launch_bounds__(64) k_scalar_top(const ScalarArgs A) {
   for (int t = L; t < A.ntop; t += 64) A.Xt[(int64_t)t * A.K + k] = sx[t];
 }
 
-// Kernel 3: grid (nsub, ceil(K / SC_CPW)), 256 threads; LDS: f and x of SC_CPW columns (with one
-// boundary entry on each side) and one level of g for the subtree's rows.
-__global__ void __launch_bounds__(256) k_scalar_sub(const ScalarArgs A) {
+// Kernel 3: grid (nsub, ceil(K / SC_CPW)), SC_SUB_THREADS threads; LDS: f of SC_CPW columns (with one
+// boundary entry on each side), overwritten in place by x (row m's f is read only by the sum of the
+// node split at m, which writes x_m; later levels read x only at their nodes' boundaries), and two
+// levels of g for the subtree's rows (the next level's g is stored while the current one is read,
+// so a level needs one barrier).  A level with at
+// most SC_SUB_THREADS (node, column) pairs gives each pair a group of G lanes (the largest power of
+// two with pairs x G <= SC_SUB_THREADS): the lanes sum strided rows of the node, four at a time, and
+// the group's sum is formed with DPP moves, so a level costs about SC_SUB * SC_CPW / SC_SUB_THREADS
+// products per thread whatever its node count; a level with more pairs takes them one per thread, in
+// rounds, with the rounds' node records loaded together.
+constexpr int SC_SUB_THREADS = 512;
+__global__ void __launch_bounds__(SC_SUB_THREADS, 6) k_scalar_sub(const ScalarArgs A) {
+  constexpr int NT = SC_SUB_THREADS;
   extern __shared__ double sm[];
   const int s = blockIdx.x;
   const int k0 = blockIdx.y * SC_CPW;
   const int l = A.sub_lo[s], r = A.sub_hi[s];
   const int n = r - l + 1;                 // <= SC_SUB
   const int W = n + 2;
-  double* fs = sm;                         // [SC_CPW][W]: f at rows l-1 .. r+1 (ends unused)
-  double* xs = fs + SC_CPW * W;            // [SC_CPW][W]: x at rows l-1 .. r+1
-  double* gs = xs + SC_CPW * W;            // [W]: g of the current level at rows l .. r (index j - l + 1)
-  const int tid = threadIdx.x, L = tid & 63, w = tid >> 6;
-  constexpr int RPT = SC_SUB / 256;
+  double* fs = sm;                         // [SC_CPW][W]: f, then x, at rows l-1 .. r+1 (x only at the ends)
+  double* xs = fs;
+  double* gsb = fs + SC_CPW * W;           // [2][W]: g of levels d (buffer d % 2) at rows l .. r (index j - l + 1)
+  const int tid = threadIdx.x;
+  constexpr int RPT = SC_SUB / NT;
   {   // f of the SC_CPW columns: all loads issued before the LDS stores
     double t[SC_CPW][RPT];
 #pragma unroll
     for (int c = 0; c < SC_CPW; ++c) {
       const int k = min(k0 + c, A.K - 1);
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) t[c][i] = A.F[l + min(tid + 256 * i, n - 1) + (int64_t)k * A.ldf];
+      for (int i = 0; i < RPT; ++i) t[c][i] = A.F[l + min(tid + NT * i, n - 1) + (int64_t)k * A.ldf];
     }
 #pragma unroll
     for (int c = 0; c < SC_CPW; ++c)
 #pragma unroll
       for (int i = 0; i < RPT; ++i)
-        if (tid + 256 * i < n) fs[c * W + 1 + tid + 256 * i] = t[c][i];
+        if (tid + NT * i < n) fs[c * W + 1 + tid + NT * i] = t[c][i];
   }
   if (tid < SC_CPW) {
     const int k = min(k0 + tid, A.K - 1);
@@ -228,71 +267,94 @@ __global__ void __launch_bounds__(256) k_scalar_sub(const ScalarArgs A) {
   const int4* rec = A.sub_rec + A.sub_off[s];
   const double2* hh = A.sub_h + A.sub_off[s];
   const int* loff = A.sub_lvoff + s * (A.ndeep + 1);    // level boundaries within the records
-  // g of the first deep level in registers; each level stores its g to LDS and loads the next one's
+  // g of the first deep level to LDS buffer 0, the second one's in registers; level d stores level
+  // d + 1's g (buffer (d + 1) % 2, last read by level d - 1) and loads level d + 2's
   double gn[RPT];
   {
     const double* g = A.G + (int64_t)A.L0 * A.N;
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) gn[i] = g[l + min(tid + 256 * i, n - 1)];
+    for (int i = 0; i < RPT; ++i) gn[i] = g[l + min(tid + NT * i, n - 1)];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i)
+      if (tid + NT * i < n) gsb[1 + tid + NT * i] = gn[i];
+    if (A.ndeep > 1) {
+      const double* g1 = A.G + (int64_t)(A.L0 + 1) * A.N;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) gn[i] = g1[l + min(tid + NT * i, n - 1)];
+    }
   }
+  // a level has at most SC_SUB / 2 nodes: QM rounds of one (node, column) pair per thread
+  constexpr int QM = (SC_SUB / 2 * SC_CPW + NT - 1) / NT;
   for (int d = 0; d < A.ndeep; ++d) {
     const int b0 = loff[d], b1 = loff[d + 1];
     if (b0 == b1) break;
-    __syncthreads();                                    // previous level's x and g reads are done
-#pragma unroll
-    for (int i = 0; i < RPT; ++i)
-      if (tid + 256 * i < n) gs[1 + tid + 256 * i] = gn[i];
-    if (d + 1 < A.ndeep) {                              // next level's g, in flight during this level
-      const double* g = A.G + (int64_t)(A.L0 + d + 1) * A.N;
-#pragma unroll
-      for (int i = 0; i < RPT; ++i) gn[i] = g[l + min(tid + 256 * i, n - 1)];
-    }
-    const int nn = b1 - b0;
-    const int4 r0 = rec[b0];
-    const int len0 = r0.z - r0.y + 1;                   // node sizes within a level differ by at most 1
-    __syncthreads();
-    if (len0 >= 32) {
-      // one wave per (node, column): strided partial sums, then a wave reduction
-      for (int p = w; p < nn * SC_CPW; p += 4) {
-        const int q = __builtin_amdgcn_readfirstlane(b0 + p / SC_CPW), c = p % SC_CPW;
-        const int4 rc = rec[q];
-        const double2 h = hh[q];
-        double S = 0.0;
-        for (int j = rc.y + L; j <= rc.z; j += 64) S += gs[j - l + 1] * fs[c * W + j - l + 1];
-        for (int off = 32; off > 0; off >>= 1) S += __shfl_xor(S, off);
-        if (L == 0)
-          xs[c * W + rc.x - l + 1] = S + h.x * xs[c * W + rc.y - l] + h.y * xs[c * W + rc.z - l + 2];
-      }
+    const int np = (b1 - b0) * SC_CPW;                  // (node, column) pairs of the level
+    int G = 64;
+    while (G > 1 && np * G > NT) G >>= 1;
+    // this thread's node records, loaded before the barrier so that their latency overlaps it
+    int4 rq[QM];
+    double2 hq[QM];
+    const int sub = tid & (G - 1);
+    if (np <= NT) {
+      const int p = min(tid / G, np - 1);
+      rq[0] = rec[b0 + p / SC_CPW];
+      hq[0] = hh[b0 + p / SC_CPW];
     } else {
-      // one thread per (node, column); a thread's records of the level are loaded together, QM at a
-      // time (a level has at most SC_SUB / 2 nodes, so one round for SC_CPW = 4)
-      constexpr int QM = (SC_SUB / 2 * SC_CPW + 255) / 256;
-      const int np = nn * SC_CPW;
-      for (int p0 = 0; p0 < np; p0 += 256 * QM) {
-        int4 rq[QM];
-        double2 hq[QM];
 #pragma unroll
-        for (int u = 0; u < QM; ++u) {
-          const int p = min(p0 + tid + 256 * u, np - 1);
-          rq[u] = rec[b0 + p / SC_CPW];
-          hq[u] = hh[b0 + p / SC_CPW];
-        }
+      for (int u = 0; u < QM; ++u) {
+        const int p = min(tid + NT * u, np - 1);
+        rq[u] = rec[b0 + p / SC_CPW];
+        hq[u] = hh[b0 + p / SC_CPW];
+      }
+    }
+    __syncthreads();   // level d - 1's x writes and its reads of buffer (d + 1) % 2 are done
+    const double* gs = gsb + (d & 1) * W;
+    if (d + 1 < A.ndeep) {
+      double* gw = gsb + ((d + 1) & 1) * W;
 #pragma unroll
-        for (int u = 0; u < QM; ++u) {
-          const int p = p0 + tid + 256 * u;
-          if (p >= np) break;
-          const int c = p % SC_CPW;
-          const int4 rc = rq[u];
-          double S0 = 0.0, S1 = 0.0;   // two chains of dependent additions
-          int j = rc.y;
-          for (; j + 1 <= rc.z; j += 2) {
-            S0 += gs[j - l + 1] * fs[c * W + j - l + 1];
-            S1 += gs[j - l + 2] * fs[c * W + j - l + 2];
-          }
-          if (j <= rc.z) S0 += gs[j - l + 1] * fs[c * W + j - l + 1];
-          xs[c * W + rc.x - l + 1] =
-              (S0 + S1) + hq[u].x * xs[c * W + rc.y - l] + hq[u].y * xs[c * W + rc.z - l + 2];
+      for (int i = 0; i < RPT; ++i)
+        if (tid + NT * i < n) gw[1 + tid + NT * i] = gn[i];
+      if (d + 2 < A.ndeep) {
+        const double* g = A.G + (int64_t)(A.L0 + d + 2) * A.N;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) gn[i] = g[l + min(tid + NT * i, n - 1)];
+      }
+    }
+    if (np <= NT) {
+      // one round: G lanes per pair; lanes beyond the last pair repeat it and write nothing
+      const int p = tid / G;
+      const int c = min(p, np - 1) % SC_CPW;
+      const int4 rc = rq[0];
+      const double* gp = gs - l + 1;
+      const double* fp = fs + c * W - l + 1;
+      double S0 = 0.0, S1 = 0.0, S2 = 0.0, S3 = 0.0;   // four chains, their loads issued together
+      int j = rc.y + sub;
+      for (; j + 3 * G <= rc.z; j += 4 * G) {
+        S0 += gp[j] * fp[j];
+        S1 += gp[j + G] * fp[j + G];
+        S2 += gp[j + 2 * G] * fp[j + 2 * G];
+        S3 += gp[j + 3 * G] * fp[j + 3 * G];
+      }
+      for (; j <= rc.z; j += G) S0 += gp[j] * fp[j];
+      const double S = group_sum((S0 + S1) + (S2 + S3), G);
+      if (p < np && sub == G - 1)
+        xs[c * W + rc.x - l + 1] = S + hq[0].x * xs[c * W + rc.y - l] + hq[0].y * xs[c * W + rc.z - l + 2];
+    } else {
+#pragma unroll
+      for (int u = 0; u < QM; ++u) {
+        const int p = tid + NT * u;
+        if (p >= np) break;
+        const int c = p % SC_CPW;
+        const int4 rc = rq[u];
+        double S0 = 0.0, S1 = 0.0;
+        int j = rc.y;
+        for (; j + 1 <= rc.z; j += 2) {
+          S0 += gs[j - l + 1] * fs[c * W + j - l + 1];
+          S1 += gs[j - l + 2] * fs[c * W + j - l + 2];
         }
+        if (j <= rc.z) S0 += gs[j - l + 1] * fs[c * W + j - l + 1];
+        xs[c * W + rc.x - l + 1] =
+            (S0 + S1) + hq[u].x * xs[c * W + rc.y - l] + hq[u].y * xs[c * W + rc.z - l + 2];
       }
     }
   }
@@ -301,7 +363,7 @@ __global__ void __launch_bounds__(256) k_scalar_sub(const ScalarArgs A) {
     const int k = k0 + c;
     if (k >= A.K) break;
     double* xo = A.X + l + (int64_t)k * A.ldx;
-    for (int i = tid; i < n; i += 256) {
+    for (int i = tid; i < n; i += NT) {
       const double v = xs[c * W + 1 + i];
       xo[i] = A.accumulate ? xo[i] + v : v;
     }
@@ -310,6 +372,7 @@ __global__ void __launch_bounds__(256) k_scalar_sub(const ScalarArgs A) {
 
 hipError_t launch_scalar_top(const ScalarArgs& A, hipStream_t st) {
   if (A.K == 0 || A.L0 == 0) return hipSuccess;
+  if (A.L0 > SC_MAXTOP) return hipErrorInvalidValue;   // not reached for N below 2^31
   const int cg = (A.K + SC_CPW - 1) / SC_CPW;
   hipLaunchKernelGGL(k_scalar_top_partials, dim3(A.nsub, cg), dim3(256), 0, st, A);
   hipLaunchKernelGGL(k_scalar_top, dim3(A.K), dim3(64), (size_t)A.ntop * sizeof(double), st, A);
@@ -319,10 +382,10 @@ hipError_t launch_scalar_top(const ScalarArgs& A, hipStream_t st) {
 hipError_t launch_scalar_sub(const ScalarArgs& A, hipStream_t st) {
   if (A.K == 0) return hipSuccess;
   const int cg = (A.K + SC_CPW - 1) / SC_CPW;
-  const size_t lds = (size_t)(2 * SC_CPW + 1) * (A.maxsub + 2) * sizeof(double);
+  const size_t lds = (size_t)(SC_CPW + 2) * (A.maxsub + 2) * sizeof(double);
   hipError_t e = hipFuncSetAttribute((const void*)k_scalar_sub, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_scalar_sub, dim3(A.nsub, cg), dim3(256), lds, st, A);
+  hipLaunchKernelGGL(k_scalar_sub, dim3(A.nsub, cg), dim3(SC_SUB_THREADS), lds, st, A);
   return hipGetLastError();
 }
 
