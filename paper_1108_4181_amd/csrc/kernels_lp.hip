@@ -157,6 +157,180 @@ hipError_t launch_sweep_lp(int prec, const LpSweepArgs& a, hipStream_t st) {
   return launch_sweep_lp_rt<2, 1>(a, st);
 }
 
+// Float32 superposition above block size 256 with 64-column tiles: the `2Mp x 64` float32 panel
+// (264 KB at Mp = 512) does not fit in LDS, so LDS holds one half of it at a time (the left
+// interface's Mp rows for U_i, or the right interface's for V_i); a row multiplies the half in LDS,
+// reloads the other half and multiplies that, and the next row starts with the half now in LDS.
+// Against 32-column tiles this halves the L2-to-CU traffic of [U_i V_i] per flop.  Writes X (the
+// accumulating form keeps the 32-column kernel).
+template <int PREC, int RT, int CT, int KU>
+__device__ __forceinline__ void superpose_lp_half_tile(const LpSupArgs& a, int s, int ct, uint4* lds_raw) {
+  using Tr = LP<PREC>;
+  using T = typename Tr::T;
+  constexpr int KG = Tr::KG;
+  constexpr int KT = 16 * CT;
+  static_assert(W32_PANEL % KT == 0, "a column tile must lie in one workspace panel");
+  T* Xs = reinterpret_cast<T*>(lds_raw);   // [KT][SK]: one half of the panel
+  const int Mp = a.Mp, M = a.M, K = a.K;
+  const int kd = 2 * Mp;
+  const int SK = Mp + 32 / (int)sizeof(T);
+
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int L = tid & 63, w = tid >> 6;
+  const int col0 = ct * KT;
+  const int64_t first = a.ks[s] + 1, last = a.ks[s + 1] - 1;
+  if (first > last) return;
+  const int rb = w * 16 * RT;
+  const int64_t MM2 = (int64_t)Mp * kd;
+  const int nkh = Mp / (KG * KU);          // chunks per half (even: Mp is a multiple of 64 here)
+  const float* const Wp = a.W + (int64_t)(col0 / W32_PANEL) * a.N * W32_PANEL * Mp;
+  const int cp0 = col0 % W32_PANEL;
+
+  // Xi rows (s + 1 + h) Mp .. (s + 2 + h) Mp - 1 of the tile's columns, rounded, -> LDS; a batch's
+  // loads are issued before its stores (columns beyond K read column K - 1 and store zero)
+  auto load_half = [&](int h) {
+    constexpr int B = 8;
+    const double* __restrict__ src = a.Xi + (int64_t)(s + 1 + h) * Mp;
+    const int n = Mp * KT;
+    for (int e0 = tid; e0 < n; e0 += B * nthr) {
+      double v[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int e = min(e0 + u * nthr, n - 1);
+        const int k = e % Mp, col = min(col0 + e / Mp, K - 1);
+        v[u] = src[k + (int64_t)col * a.ldxi];
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int e = e0 + u * nthr;
+        if (e < n) {
+          const int k = e % Mp, c = e / Mp;
+          Xs[c * SK + k] = Tr::from_f((col0 + c < K) ? (float)v[u] : 0.f);
+        }
+      }
+    }
+  };
+
+  const int64_t lane_off = (int64_t)(rb + (L & 15)) * kd + (KG / 4) * (L >> 4);
+  uint4 a0[KU][RT], a1[KU][RT];
+  auto loadA = [&](uint4 (&dst)[KU][RT], const T* __restrict__ Ab, int q) {   // Ab: the half's first k
+#pragma unroll
+    for (int u = 0; u < KU; ++u)
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+        dst[u][t] = *reinterpret_cast<const uint4*>(Ab + lane_off + (int64_t)16 * t * kd + KG * (KU * q + u));
+  };
+  f32x4 acc[RT][CT];
+  auto compute = [&](const uint4 (&av)[KU][RT], int q) {
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      const int g = KU * q + u;
+      uint4 b[CT];
+#pragma unroll
+      for (int c = 0; c < CT; ++c)
+        b[c] = *reinterpret_cast<const uint4*>(Xs + (16 * c + (L & 15)) * SK + KG * g + (KG / 4) * (L >> 4));
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) Tr::mma(acc[t][c], av[u][t], b[c]);
+    }
+  };
+  auto body = [&](const T* __restrict__ Ah) {   // all chunks of a half but the last two
+    for (int g = 0; g < nkh - 2; g += 2) {
+      loadA(a1, Ah, g + 1);
+      compute(a0, g);
+      loadA(a0, Ah, g + 2);
+      compute(a1, g + 1);
+    }
+  };
+
+  const T* UVb = (const T*)a.UV;
+  int cur = 0;   // the half in LDS
+  load_half(0);
+  loadA(a0, UVb + first * MM2, 0);
+  __syncthreads();
+  for (int64_t i = first; i <= last; ++i) {
+    const T* __restrict__ Ai = UVb + i * MM2;
+    const T* __restrict__ Anx = (i < last) ? Ai + MM2 : Ai;
+    const int nxt = 1 - cur;
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int c = 0; c < CT; ++c) acc[t][c] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    {   // the half in LDS; its last chunk prefetches chunk 0 of the other half of this row
+      const T* __restrict__ Ah = Ai + cur * Mp;
+      body(Ah);
+      loadA(a1, Ah, nkh - 1);
+      compute(a0, nkh - 2);
+      loadA(a0, Ai + nxt * Mp, 0);
+      compute(a1, nkh - 1);
+    }
+    __syncthreads();   // every wave is done reading this half
+    load_half(nxt);
+    __syncthreads();
+    const T* __restrict__ Ah = Ai + nxt * Mp;
+    body(Ah);
+    float wv[RT][CT][4];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int row0 = rb + 16 * t + 4 * (L >> 4);
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const int col = col0 + 16 * c + (L & 15);
+        f32x4 x = (f32x4){0.f, 0.f, 0.f, 0.f};
+        if (col < K) x = *reinterpret_cast<const f32x4*>(Wp + i * (W32_PANEL * Mp) + (int64_t)(cp0 + 16 * c + (L & 15)) * Mp + row0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) wv[t][c][v] = x[v];
+      }
+    }
+    loadA(a1, Ah, nkh - 1);
+    compute(a0, nkh - 2);
+    loadA(a0, Anx + nxt * Mp, 0);   // the next row starts with the half now in LDS
+    compute(a1, nkh - 1);
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int row0 = rb + 16 * t + 4 * (L >> 4);
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const int col = col0 + 16 * c + (L & 15);
+        if (col >= K) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = row0 + v;
+          if (row < M) a.X[i * M + row + (int64_t)col * a.ldx] = (double)acc[t][c][v] + (double)wv[t][c][v];
+        }
+      }
+    }
+    cur = nxt;
+  }
+}
+
+template <int PREC, int RT, int CT, int KU>
+__global__ void __launch_bounds__(512) k_superpose_lp_half(LpSupArgs a) {
+  extern __shared__ uint4 lds_raw[];
+  const int lg = lp_xcd_remap(blockIdx.x, gridDim.x);
+  if (lg >= a.total) return;
+  const int s = lg / a.ncoltiles;
+  superpose_lp_half_tile<PREC, RT, CT, KU>(a, s, lg - s * a.ncoltiles, lds_raw);
+}
+
+template <int PREC, int RT, int CT, int KU>
+static hipError_t launch_sup_lp_half_cfg(const LpSupArgs& a0, hipStream_t st) {
+  LpSupArgs a = a0;
+  constexpr int kt = 16 * CT;
+  a.ncoltiles = (a.K + kt - 1) / kt;
+  a.total = a.p * a.ncoltiles;
+  if (a.total == 0) return hipSuccess;
+  const int nthr = a.Mp / (16 * RT) * 64;
+  const size_t esz = (PREC == 1) ? 4 : 2;
+  const size_t lds = (size_t)kt * ((size_t)a.Mp * esz + 32);
+  hipError_t e = hipFuncSetAttribute((const void*)k_superpose_lp_half<PREC, RT, CT, KU>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_superpose_lp_half<PREC, RT, CT, KU>), dim3(lp_pad8(a.total)), dim3(nthr), lds, st, a);
+  return hipGetLastError();
+}
+
 template <int PREC, int RT, int CT, int KU>
 static hipError_t launch_sup_lp_cfg(const LpSupArgs& a0, hipStream_t st) {
   LpSupArgs a = a0;
@@ -197,6 +371,11 @@ template <int PREC, int RT>
 static hipError_t launch_sup_lp_rt(const LpSupArgs& a, hipStream_t st) {
   const size_t esz = (PREC == 1) ? 4 : 2;
   const size_t lds4 = (size_t)64 * ((size_t)2 * a.Mp * esz + 32);
+  if constexpr (PREC == 1 && RT == 4) {   // float32 above block size 256: half of the panel in LDS
+    if (a.K > 32 && !a.accumulate && a.Mp % 64 == 0 && lds4 > 160 * 1024 &&
+        (size_t)64 * ((size_t)a.Mp * esz + 32) <= 160 * 1024)
+      return launch_sup_lp_half_cfg<PREC, 4, 4, 1>(a, st);
+  }
   if (a.K <= 16) return launch_sup_lp_ku<PREC, RT, 1>(a, st);
   if (a.K <= 32 || lds4 > 160 * 1024) return launch_sup_lp_ku<PREC, RT, 2>(a, st);
   return launch_sup_lp_ku<PREC, RT, 4>(a, st);

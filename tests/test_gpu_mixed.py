@@ -38,8 +38,10 @@ def _colres(sys, X, F):
 
 @pytest.mark.parametrize("prec,maxit", [("f32", 3), ("bf16", 10)])
 @pytest.mark.parametrize("N,M,K,p", [(128, 64, 20, 8), (64, 16, 8, 4), (96, 48, 37, 6), (48, 256, 70, 4),
-                                     (40, 224, 33, 5), (24, 320, 17, 3)])
+                                     (40, 224, 33, 5), (24, 320, 17, 3), (20, 384, 100, 4), (12, 512, 70, 3)])
 def test_refined_to_1e10(td, prec, maxit, N, M, K, p):
+    """(The last two: float32 above block size 256 with more than 32 columns, whose first pass runs the
+    superposition with half of the interface panel in LDS: one full and one ragged 64-column tile.)"""
     sys = synth.varcoef_system(N, M, seed=200 + N + M)
     F = synth.rhs_columns(200 + N, N, M, range(K))
     plan = td.Plan.from_system(sys, subdomains=p, sweep_prec=prec)
@@ -83,13 +85,15 @@ def test_f64_plan_refine_is_noop(td):
     assert info["iterations"] == 0 and info["max_col_rel_residual"] < 1e-14
 
 
-def test_f64_correction_pass_adds_to_x(td):
+@pytest.mark.parametrize("N,M,K,p", [(70, 40, 37, 6), (20, 384, 40, 4)])
+def test_f64_correction_pass_adds_to_x(td, N, M, K, p):
     """An unreachable tolerance forces one correction pass on a float64 plan: the superposition and
-    the dichotomy's last level then add to X (their accumulating forms), and X must stay the
-    float64 solution."""
-    sys = synth.varcoef_system(70, 40, seed=36)
-    F = synth.rhs_columns(36, 70, 40, range(37))
-    plan = td.Plan.from_system(sys, subdomains=6)
+    the dichotomy's last level then add to X (their accumulating forms; above block size 256 the
+    adding superposition is the 16-column kernel, the writing one the half-panel 32-column kernel),
+    and X must stay the float64 solution."""
+    sys = synth.varcoef_system(N, M, seed=36)
+    F = synth.rhs_columns(36, N, M, range(K))
+    plan = td.Plan.from_system(sys, subdomains=p)
     X, info = plan.solve(_dev(F), refine={"tol": 1e-300, "max_iter": 1}, info=True)
     assert info["iterations"] == 1 and not info["converged"]
     assert rel_err(X.cpu().numpy(), oracle.solve(sys, F)) < 1e-12

@@ -177,9 +177,10 @@ def test_solve_graph_replays_match_eager(td):
 @pytest.mark.parametrize("M", [288, 384, 448, 512])
 @pytest.mark.parametrize("K", [17, 40])
 def test_large_blocks_f64(td, M, K):
-    """Block sizes above 256 (padded to 320, 384, 448 and 512): the superposition's four-row-tile
-    form and the sweep with five to eight waves of 64 rows, which the 4096 x 512 workload's float64
-    solve runs; one full and one ragged 32-column tile."""
+    """Block sizes above 256 (padded to 320, 384, 448 and 512): the superposition with half of the
+    interface panel in LDS at a time (32-column tiles, lanes beyond K in the ragged tile) and the
+    sweep with five to eight waves of 64 rows, which the 4096 x 512 workload's float64 solve runs;
+    one full and one ragged 32-column tile."""
     N, p = 20, 4
     sys = synth.varcoef_system(N, M, seed=500 + M + K)
     F = synth.rhs_columns(500 + M + K, N, M, range(K))
