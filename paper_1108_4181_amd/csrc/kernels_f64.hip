@@ -66,7 +66,10 @@ static hipError_t launch_bgemm_rt(const BArgs& a0, hipStream_t st) {
   BArgs a = a0;
   const int nthr = a.Mp / (16 * RT) * 64;
   if (nthr < 64 * RT) return hipErrorInvalidValue;   // the tile stages B with at least 64 RT threads
-  const int kt = bgemm_coltile(a.ncols);
+  // 16-column tiles where 32-column ones would leave fewer than two work-groups per compute unit
+  // (small dichotomy levels and partial sums: the device fills at the cost of half the B reuse)
+  int kt = bgemm_coltile(a.ncols);
+  if (kt == 32 && (int64_t)a.nprob * ((a.ncols + 31) / 32) < 512) kt = 16;
   a.ncoltiles = (a.ncols + kt - 1) / kt;
   a.total = a.nprob * a.ncoltiles;
   if (a.total == 0) return hipSuccess;
