@@ -41,6 +41,7 @@ struct BArgs {
   int32_t x2rows;
   int32_t x2accum;    // nonzero: X2 += result instead of X2 = result
   int32_t brows;      // > 0: rows of each B segment at or beyond brows read as zero
+  int32_t kalign;     // every descriptor's kd and segrows are multiples of kalign (0 = 16)
   double alpha;
   const double* A; int64_t lda;
   const double* B; int64_t ldb;

@@ -17,13 +17,13 @@ namespace td {
 // ---------------------------------------------------------------------------
 // Block GEMM (see BArgs): one work-group = Mp rows x 4*CT columns of one problem.
 // ---------------------------------------------------------------------------
-template <int RT, int CT>
+template <int RT, int CT, int KC>
 __global__ void __launch_bounds__(512) k_bgemm(BArgs args) {
-  __shared__ double Bs[2 * 16 * (4 * CT + 2)];
+  __shared__ double Bs[2 * KC * (4 * CT + 2)];
   const int lg = xcd_remap(blockIdx.x, gridDim.x);
   if (lg >= args.total) return;
   const int prob = lg / args.ncoltiles;
-  bgemm_tile<RT, CT>(args, prob, lg - prob * args.ncoltiles, Bs);
+  bgemm_tile<RT, CT, KC>(args, prob, lg - prob * args.ncoltiles, Bs);
 }
 
 // ---------------------------------------------------------------------------
@@ -74,10 +74,22 @@ static hipError_t launch_bgemm_rt(const BArgs& a0, hipStream_t st) {
   a.total = a.nprob * a.ncoltiles;
   if (a.total == 0) return hipSuccess;
   dim3 grid(grid_pad8(a.total)), block(nthr);
+  // 64-row B chunks (a quarter of the barriers) where every descriptor's inner dimension allows,
+  // for block sizes from 256 (four row tiles per wave: the staging registers stay few)
+  if constexpr (RT == 4) {
+    if (a.kalign > 0 && a.kalign % 64 == 0) {
+      switch (kt) {
+        case 8: hipLaunchKernelGGL((k_bgemm<RT, 2, 64>), grid, block, 0, st, a); break;
+        case 16: hipLaunchKernelGGL((k_bgemm<RT, 4, 64>), grid, block, 0, st, a); break;
+        default: hipLaunchKernelGGL((k_bgemm<RT, 8, 64>), grid, block, 0, st, a); break;
+      }
+      return hipGetLastError();
+    }
+  }
   switch (kt) {
-    case 8: hipLaunchKernelGGL((k_bgemm<RT, 2>), grid, block, 0, st, a); break;
-    case 16: hipLaunchKernelGGL((k_bgemm<RT, 4>), grid, block, 0, st, a); break;
-    default: hipLaunchKernelGGL((k_bgemm<RT, 8>), grid, block, 0, st, a); break;
+    case 8: hipLaunchKernelGGL((k_bgemm<RT, 2, 16>), grid, block, 0, st, a); break;
+    case 16: hipLaunchKernelGGL((k_bgemm<RT, 4, 16>), grid, block, 0, st, a); break;
+    default: hipLaunchKernelGGL((k_bgemm<RT, 8, 16>), grid, block, 0, st, a); break;
   }
   return hipGetLastError();
 }

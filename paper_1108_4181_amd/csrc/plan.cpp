@@ -281,10 +281,19 @@ struct DescPool {
   }
 };
 
+// the largest of 64, 32 and 16 that divides every descriptor's inner dimension and segment rows
+int kalign_of(const std::vector<BDesc>& d) {
+  int a = 64;
+  for (const BDesc& x : d)
+    while (a > 16 && ((x.kd % a) != 0 || (x.segrows % a) != 0)) a >>= 1;
+  return a;
+}
+
 void run_bgemm(BArgs a, const std::vector<BDesc>& d, DescPool& pool, hipStream_t st) {
   if (d.empty()) return;
   a.descs = pool.put(d);
   a.nprob = (int32_t)d.size();
+  a.kalign = kalign_of(d);
   HIPCHK(launch_bgemm(a, st));
 }
 
@@ -1209,6 +1218,7 @@ void solve_pass(td_plan_s* P, const Work& w, const double* F, int64_t ldf, doubl
       g.B = F; g.ldb = ldf; g.brows = (int32_t)M;
       g.C = w.W; g.ldc = ldw;
       g.ncols = (int32_t)K;
+      g.kalign = (int32_t)Mp;   // kd = segrows = Mp
       HIPCHK(launch_bgemm(g, st));
     }
     SweepArgs sa{};
@@ -1229,6 +1239,7 @@ void solve_pass(td_plan_s* P, const Work& w, const double* F, int64_t ldf, doubl
       f.C = w.Ft; f.ldc = ldft;
       f.Cin = w.Ft; f.ldcin = ldft;
       f.ncols = (int32_t)K;
+      f.kalign = (int32_t)Mp;   // kd Mp or 2 Mp, segrows Mp
       HIPCHK(launch_bgemm(f, st));
     }
   } else {
@@ -1250,6 +1261,7 @@ void solve_pass(td_plan_s* P, const Work& w, const double* F, int64_t ldf, doubl
     a.B = w.Ft; a.ldb = ldft;
     a.C = w.Sp; a.ldc = ldsp;
     a.ncols = (int32_t)K;
+    a.kalign = (int32_t)Mp;   // chunks of whole blocks
     HIPCHK(launch_bgemm(a, st));
   }
   stage_mark(P, 3, st);
@@ -1263,6 +1275,7 @@ void solve_pass(td_plan_s* P, const Work& w, const double* F, int64_t ldf, doubl
       a.B = w.Xi; a.ldb = ldxi;
       a.C = w.Pbuf; a.ldc = ldp;
       a.ncols = (int32_t)K;
+      a.kalign = (int32_t)(2 * Mp / P->lev_nslab[lv]);   // slabs of 2 Mp / nslab rows
       HIPCHK(launch_bgemm(a, st));
       CombArgs c;
       std::memset(&c, 0, sizeof(c));
@@ -1286,6 +1299,7 @@ void solve_pass(td_plan_s* P, const Work& w, const double* F, int64_t ldf, doubl
     a.C = w.Xi; a.ldc = ldxi;
     a.X2 = X; a.ldx2 = ldx; a.x2rows = (int32_t)M; a.x2accum = accumulate ? 1 : 0;
     a.ncols = (int32_t)K;
+    a.kalign = (int32_t)Mp;   // kd 2 Mp, segrows Mp
     HIPCHK(launch_bgemm(a, st));
   }
   stage_mark(P, 4, st);

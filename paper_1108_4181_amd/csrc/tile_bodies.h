@@ -23,9 +23,11 @@ __device__ __forceinline__ int lds_col(int c) {
 // the sixteen 16-byte pieces a k-step reads (four rows, four column blocks) in distinct LDS banks.
 __device__ __forceinline__ int lds_row(int k) { return (k & ~15) + 4 * (k & 3) + ((k >> 2) & 3); }
 
-template <int RT, int CT>
+// KC: inner rows of B per LDS chunk (a multiple of 16 that divides every descriptor's kd and
+// segrows); one barrier per chunk.
+template <int RT, int CT, int KC = 16>
 __device__ __forceinline__ void bgemm_tile(const BArgs& args, int prob, int ct, double* lds) {
-  constexpr int KC = 16;
+  static_assert(KC % 16 == 0, "chunks of 16-row groups");
   constexpr int KT = 4 * CT;
   constexpr int SB = KT + 2;
   // staging slots per thread for one B chunk; every caller runs at least 64 RT threads
@@ -101,11 +103,11 @@ __device__ __forceinline__ void bgemm_tile(const BArgs& args, int prob, int ct, 
 #pragma unroll
       for (int t = 0; t < RT; ++t) dst[u][t] = pa[16 * t + (int64_t)(4 * u) * lda];
   };
-  auto compute = [&](const double (&av)[2][RT], int buf, int half) {
+  auto compute = [&](const double (&av)[2][RT], int buf, int r, int half) {   // 16-row group r of the chunk
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      // rows 4m + L/16 of the chunk, m = 2 half + u (see lds_row, lds_col)
-      const double* bp = &Bs0[buf * KC * SB + (4 * (L >> 4) + 2 * half + u) * SB + 2 * (L & 3)];
+      // rows 4m + L/16 of the group, m = 2 half + u (see lds_row, lds_col)
+      const double* bp = &Bs0[buf * KC * SB + (16 * r + 4 * (L >> 4) + 2 * half + u) * SB + 2 * (L & 3)];
       double b[CT];
 #pragma unroll
       for (int c = 0; c < CT; c += 2) {
@@ -128,10 +130,14 @@ __device__ __forceinline__ void bgemm_tile(const BArgs& args, int prob, int ct, 
     const int buf = q & 1;
     const bool more = q + 1 < nch;
     if (more) gload(q + 1);
-    loadA(a1, q * KC + 8);
-    compute(a0, buf, 0);
-    loadA(a0, more ? (q + 1) * KC : 0);
-    compute(a1, buf, 1);
+#pragma unroll
+    for (int r = 0; r < KC / 16; ++r) {
+      const int kb = q * KC + 16 * r;
+      loadA(a1, kb + 8);
+      compute(a0, buf, r, 0);
+      loadA(a0, (kb + 16 < nch * KC) ? kb + 16 : 0);
+      compute(a1, buf, r, 1);
+    }
     if (more) lstore(buf ^ 1);
     __syncthreads();
   }
