@@ -179,7 +179,8 @@ def bench_batched(args):
     prec = "f32"   # float64 plans of all 64 systems with their workspaces exceed one GPU's HBM
     passes = args.batch_passes
     for M, Kb in sorted({(m, td._kbucket(k)) for _, m, k, _ in shapes}):
-        tuned[f"M{M}|K{Kb}"] = td.autotune(M, Kb, prec, probe_N=1024, candidates=(16, 32, 64))["L"]
+        # (the batch's work items have fixed tiles: only the subdomain length is searched)
+        tuned[f"M{M}|K{Kb}"] = td.autotune(M, Kb, prec, probe_N=1024, candidates=(16, 32, 64), tiles=False)["L"]
     tune_s = time.perf_counter() - t0
     plans, Fs, Xs, systems = [], [], [], []
     t0 = time.perf_counter()

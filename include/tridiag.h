@@ -225,6 +225,37 @@ td_status tridiag_autotune(int64_t M, int64_t K, int32_t sweep_prec, int64_t pro
                            int ncand, void* stream, int64_t* best_L, double* ms_per_solve);
 
 /*
+ * Launch shapes of a plan's solve kernels (not in the paper): right-hand-side columns per
+ * work-group (sweep_cols, sup_cols: 8, 16 or 32 for float64 plans; 16, 32 or 64 for float32 and
+ * bfloat16 plans) and waves per work-group (sweep_waves, sup_waves: a divisor of Mp / 16 that
+ * gives 16, 32 or 64 rows per wave, at most 8) of the subdomain sweeps and of the superposition.
+ * 0, or a value that the block size, the precision or the LDS does not allow, keeps the library's
+ * rule for that field.  They change the solution at most at the rounding level (every shape runs
+ * the same products; the half-panel superposition above block size 256 adds the two interface
+ * halves in an order that alternates by row, the other forms in one order).  tridiag_set_tiles
+ * (tiles NULL = all rules) applies to the plan and to its transposed plan; it drops the plan's
+ * captured solve graph.  Not for calls that overlap a solve of the plan.
+ */
+typedef struct td_tiles {
+  int32_t sweep_cols, sweep_waves, sup_cols, sup_waves;
+} td_tiles;
+td_status tridiag_set_tiles(td_plan plan, const td_tiles* tiles);
+td_status tridiag_get_tiles(td_plan plan, td_tiles* tiles);
+
+/*
+ * Autotuner over the subdomain length and the launch shapes together (not in the paper): for
+ * each candidate subdomain length L the probe system of tridiag_autotune is factored once and its
+ * solve of K right-hand sides timed with the library's rules and with each alternative column
+ * count and wave count of the sweeps and of the superposition (one field changed at a time, then
+ * the best of each field together).  Returns the fastest length in *best_L, its launch shapes in
+ * *best_tiles (0 where the rule was fastest) and its milliseconds per solve in *best_ms (may be
+ * NULL).  Allocates and frees its own device memory; synchronises the stream.
+ */
+td_status tridiag_autotune_tiles(int64_t M, int64_t K, int32_t sweep_prec, int64_t probe_N,
+                                 const int64_t* candidates, int ncand, void* stream, int64_t* best_L,
+                                 td_tiles* best_tiles, double* best_ms);
+
+/*
  * Batched solve of many independent systems (not in the paper): a work list of all systems'
  * stages (sweep tiles, interface right-hand sides, dichotomy partial sums and levels,
  * superposition tiles, residual chunks), captured once in a HIP graph and replayed by

@@ -75,6 +75,14 @@ class _Info(ctypes.Structure):
                 ("max_col_rel_residual", ctypes.c_double)]
 
 
+class _Tiles(ctypes.Structure):
+    _fields_ = [("sweep_cols", ctypes.c_int32), ("sweep_waves", ctypes.c_int32), ("sup_cols", ctypes.c_int32),
+                ("sup_waves", ctypes.c_int32)]
+
+
+TILE_FIELDS = ("sweep_cols", "sweep_waves", "sup_cols", "sup_waves")
+
+
 class _PlanInfo(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int64), ("M", ctypes.c_int64), ("subdomains", ctypes.c_int64),
                 ("Mp", ctypes.c_int64), ("tree_depth", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
@@ -85,7 +93,8 @@ class _PlanInfo(ctypes.Structure):
 EXPORTS = ["tridiag_factor", "tridiag_solve", "tridiag_solve_adjoint", "tridiag_diag_grad", "tridiag_destroy",
            "tridiag_plan_info", "tridiag_set_profiling", "tridiag_stage_times", "tridiag_status_string",
            "tridiag_last_error", "tridiag_batch_create", "tridiag_batch_solve", "tridiag_batch_info",
-           "tridiag_batch_destroy", "tridiag_autotune", "tridiag_band_to_blocks", "tridiag_schur_create",
+           "tridiag_batch_destroy", "tridiag_autotune", "tridiag_autotune_tiles", "tridiag_set_tiles",
+           "tridiag_get_tiles", "tridiag_band_to_blocks", "tridiag_schur_create",
            "tridiag_schur_apply", "tridiag_schur_solve", "tridiag_schur_destroy", "tridiag_default_subdomains",
            "tridiag_plan_bytes", "tridiag_solve_batched", "tridiag_solve_noalloc"]
 
@@ -138,6 +147,13 @@ def load_library(path: str = LIB_PATH):
     lib.tridiag_batch_destroy.restype = i32
     lib.tridiag_autotune.argtypes = [i64, i64, i32, i64, pi64, ctypes.c_int, vp, pi64, ctypes.POINTER(dp)]
     lib.tridiag_autotune.restype = i32
+    lib.tridiag_autotune_tiles.argtypes = [i64, i64, i32, i64, pi64, ctypes.c_int, vp, pi64, ctypes.POINTER(_Tiles),
+                                           ctypes.POINTER(dp)]
+    lib.tridiag_autotune_tiles.restype = i32
+    lib.tridiag_set_tiles.argtypes = [vp, ctypes.POINTER(_Tiles)]
+    lib.tridiag_set_tiles.restype = i32
+    lib.tridiag_get_tiles.argtypes = [vp, ctypes.POINTER(_Tiles)]
+    lib.tridiag_get_tiles.restype = i32
     lib.tridiag_band_to_blocks.argtypes = [i64, i32, i32, vp, i64, i64, vp, vp, vp, vp]
     lib.tridiag_band_to_blocks.restype = i32
     lib.tridiag_schur_create.argtypes = [i64, i64, vp, vp, vp, i64, pi64, i32, vp, ctypes.POINTER(vp)]
@@ -193,15 +209,21 @@ class Plan:
     """A factored block-tridiagonal matrix (tridiag_factor) reusable for many right-hand sides."""
 
     def __init__(self, A, B, C, N, M, fmt_A="diag", fmt_B="diag", fmt_C="tridiag", subdomains=0,
-                 sweep_prec="f64", adjoint=False, k_hint=512, torch_allocator=True):
+                 sweep_prec="f64", adjoint=False, k_hint=512, torch_allocator=True, tiles="auto"):
         """subdomains = 0: choose_subdomains(N, M, k_hint, sweep_prec) (the autotuned length for the
         expected number of right-hand sides per solve, else the library's default rule).
         torch_allocator: the plan's device memory comes from torch's caching allocator (td_desc
-        callbacks); False: the library's own hipMalloc."""
+        callbacks); False: the library's own hipMalloc.
+        tiles: launch shapes of the sweeps and the superposition (tridiag_set_tiles): "auto" = the
+        autotuner's cached shapes for (M, k_hint bucket, precision) when the plan also uses the cached
+        subdomain length, else the library's rules; a dict of TILE_FIELDS; None = the rules."""
         self.lib = load_library()
         self.N, self.M = int(N), int(M)
+        tuned = autotuned_entry(self.M, int(k_hint), sweep_prec)
         if not subdomains:
             subdomains = choose_subdomains(self.N, self.M, int(k_hint), sweep_prec)
+            if tiles == "auto" and tuned and "tiles" in tuned and tuned.get("L"):
+                tiles = tuned["tiles"]
         d = _Desc(self.N, self.M, int(subdomains), FMT[fmt_A], FMT[fmt_B], FMT[fmt_C], PREC[sweep_prec],
                   1 if adjoint else 0, 0, int(k_hint), TORCH_ALLOC if torch_allocator else _ALLOC_FN(),
                   TORCH_FREE if torch_allocator else _FREE_FN(), None)
@@ -221,6 +243,18 @@ class Plan:
         _check(code)
         self.h = h
         self.device = A.device
+        if isinstance(tiles, dict):
+            self.set_tiles(**tiles)
+
+    def set_tiles(self, **tiles):
+        """Launch shapes (TILE_FIELDS, 0 = the library's rule) of this plan and its transposed plan."""
+        t = _Tiles(*(int(tiles.get(k, 0)) for k in TILE_FIELDS))
+        _check(self.lib.tridiag_set_tiles(self.h, ctypes.byref(t)))
+
+    def get_tiles(self) -> dict:
+        t = _Tiles()
+        _check(self.lib.tridiag_get_tiles(self.h, ctypes.byref(t)))
+        return {k: int(getattr(t, k)) for k in TILE_FIELDS}
 
     @classmethod
     def from_system(cls, sys, device="cuda", **kw):
@@ -591,27 +625,43 @@ def _kbucket(K):
     return b
 
 
-def autotuned_length(M, K, sweep_prec="f64", default=0):
+def autotuned_entry(M, K, sweep_prec="f64"):
+    """The cached autotuner result for (M, K bucket, precision), or None."""
     import json
     try:
         with open(_cache_path()) as f:
             cache = json.load(f)
     except (OSError, ValueError):
-        return default
-    return int(cache.get(f"gfx950|M{M}|K{_kbucket(K)}|{sweep_prec}", {}).get("L", default))
+        return None
+    return cache.get(f"gfx950|M{M}|K{_kbucket(K)}|{sweep_prec}")
 
 
-def autotune(M, K, sweep_prec="f64", probe_N=1024, candidates=(8, 16, 32, 64, 128), store=True):
+def autotuned_length(M, K, sweep_prec="f64", default=0):
+    e = autotuned_entry(M, K, sweep_prec)
+    return int(e.get("L", default)) if e else default
+
+
+def autotune(M, K, sweep_prec="f64", probe_N=1024, candidates=(8, 16, 32, 64, 128), store=True, tiles=True):
     """Time the candidate subdomain lengths on a probe system (C++ search in the library) and
-    record the fastest in the JSON cache keyed by (arch, M, K bucket, precision)."""
+    record the fastest in the JSON cache keyed by (arch, M, K bucket, precision).  tiles: search the
+    sweeps' and the superposition's launch shapes as well (tridiag_autotune_tiles) and record them."""
     import json
     lib = load_library()
     cand = [c for c in candidates if c <= probe_N]
     best = ctypes.c_int64()
-    ms = (ctypes.c_double * len(cand))()
-    _check(lib.tridiag_autotune(int(M), int(_kbucket(K)), PREC[sweep_prec], int(probe_N),
-                                (ctypes.c_int64 * len(cand))(*cand), len(cand), _stream(), ctypes.byref(best), ms))
-    result = {"L": int(best.value), "ms_per_solve": dict(zip(map(str, cand), list(ms))), "probe_N": probe_N}
+    if tiles:
+        t = _Tiles()
+        bms = ctypes.c_double()
+        _check(lib.tridiag_autotune_tiles(int(M), int(_kbucket(K)), PREC[sweep_prec], int(probe_N),
+                                          (ctypes.c_int64 * len(cand))(*cand), len(cand), _stream(),
+                                          ctypes.byref(best), ctypes.byref(t), ctypes.byref(bms)))
+        result = {"L": int(best.value), "tiles": {k: int(getattr(t, k)) for k in TILE_FIELDS},
+                  "ms_per_solve": float(bms.value), "probe_N": probe_N}
+    else:
+        ms = (ctypes.c_double * len(cand))()
+        _check(lib.tridiag_autotune(int(M), int(_kbucket(K)), PREC[sweep_prec], int(probe_N),
+                                    (ctypes.c_int64 * len(cand))(*cand), len(cand), _stream(), ctypes.byref(best), ms))
+        result = {"L": int(best.value), "ms_per_solve": dict(zip(map(str, cand), list(ms))), "probe_N": probe_N}
     if store:
         path = _cache_path()
         try:

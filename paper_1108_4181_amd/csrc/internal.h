@@ -64,6 +64,7 @@ struct SweepArgs {
   const double* F; int64_t ldf;
   double* W; int64_t ldw;
   int32_t N, M, Mp, p, K, ncoltiles, total;
+  int32_t kt_hint, rt_hint;   // columns per work-group, row tiles per wave (0 = the launcher's rule)
 };
 
 // Superposition, eq. (superposition): X_i = W_i + U_i X_{k_s} + V_i X_{k_{s+1}} for the interior rows.
@@ -75,6 +76,7 @@ struct SupArgs {
   const double* W; int64_t ldw;
   double* X; int64_t ldx;
   int32_t N, M, Mp, p, K, ncoltiles, total, accumulate;  // accumulate: X += result
+  int32_t kt_hint, rt_hint;   // columns per work-group, row tiles per wave (0 = the launcher's rule)
 };
 
 // Float32 workspace of the low-precision solve (beta, then W): panels of W32_PANEL right-hand
@@ -100,6 +102,7 @@ struct LpSweepArgs {
   const double* F; int64_t ldf;
   float* W;              // panel layout (w32_off)
   int32_t N, M, Mp, p, K, ncoltiles, total;
+  int32_t kt_hint, rt_hint;   // columns per work-group, row tiles per wave (0 = the launcher's rule)
 };
 
 struct LpSupArgs {
@@ -109,6 +112,7 @@ struct LpSupArgs {
   const float* W;        // panel layout (w32_off)
   double* X; int64_t ldx;
   int32_t N, M, Mp, p, K, ncoltiles, total, accumulate;
+  int32_t kt_hint, rt_hint;   // columns per work-group, row tiles per wave (0 = the launcher's rule)
 };
 
 // Batched Gauss-Jordan inversion with partial pivoting.

@@ -126,10 +126,16 @@ int sweep_coltile(int Mp, int K) {
   return 32;
 }
 
+// a row-tile count from a hint when the block size divides into it and the waves stay at most 8
+static int hinted_rt(int rule, int hint, int Mp) {
+  if ((hint == 1 || hint == 2 || hint == 4) && Mp % (16 * hint) == 0 && Mp / (16 * hint) <= 8) return hint;
+  return rule;
+}
+
 template <int RT>
 static hipError_t launch_sweep_rt(const SweepArgs& a0, hipStream_t st) {
   SweepArgs a = a0;
-  const int kt = sweep_coltile(a.Mp, a.K);
+  const int kt = (a.kt_hint == 8 || a.kt_hint == 16 || a.kt_hint == 32) ? a.kt_hint : sweep_coltile(a.Mp, a.K);
   a.ncoltiles = (a.K + kt - 1) / kt;
   a.total = a.p * a.ncoltiles;
   if (a.total == 0) return hipSuccess;
@@ -156,7 +162,7 @@ static hipError_t launch_sweep_rt(const SweepArgs& a0, hipStream_t st) {
 }
 
 hipError_t launch_sweep(const SweepArgs& a, hipStream_t st) {
-  switch (choose_rt(a.Mp)) {
+  switch (hinted_rt(choose_rt(a.Mp), a.rt_hint, a.Mp)) {
     case 4: return launch_sweep_rt<4>(a, st);
     case 2: return launch_sweep_rt<2>(a, st);
     default: return launch_sweep_rt<1>(a, st);
@@ -226,8 +232,11 @@ template <int RT>
 static hipError_t launch_superpose_rt(const SupArgs& a, hipStream_t st) {
   // the LDS panel is 2 Mp x (4 CT + 2) doubles and must fit in 160 KB
   const int64_t bytes8 = (int64_t)2 * a.Mp * 34 * 8;
+  if (a.kt_hint == 8) return launch_superpose_cfg<RT, 2>(a, st);
+  if (a.kt_hint == 16 && (int64_t)2 * a.Mp * 18 * 8 <= 160 * 1024) return launch_superpose_cfg<RT, 4>(a, st);
   if (a.K <= 8) return launch_superpose_cfg<RT, 2>(a, st);
-  if (RT == 4 && !a.accumulate && a.K > 16 && a.Mp % 64 == 0 && (int64_t)a.Mp * 34 * 8 <= 160 * 1024)
+  if (RT == 4 && !a.accumulate && a.K > 16 && a.Mp % 64 == 0 && bytes8 > 160 * 1024 &&
+      (int64_t)a.Mp * 34 * 8 <= 160 * 1024)
     return launch_superpose_half_cfg<4, 8>(a, st);
   if (a.K <= 16 || bytes8 > 160 * 1024 || RT == 4) return launch_superpose_cfg<RT, 4>(a, st);
   return launch_superpose_cfg<RT, (RT == 4 ? 4 : 8)>(a, st);
@@ -238,6 +247,7 @@ hipError_t launch_superpose(const SupArgs& a, hipStream_t st) {
   int rt = choose_rt(a.Mp);
   const int nw = a.Mp / (16 * rt);
   if (rt >= 2 && 2 * nw <= 8) rt /= 2;
+  rt = hinted_rt(rt, a.rt_hint, a.Mp);
   switch (rt) {
     case 4: return launch_superpose_rt<4>(a, st);
     case 2: return launch_superpose_rt<2>(a, st);

@@ -100,6 +100,12 @@ static inline int lp_choose_rt(int Mp) {
   return 1;
 }
 
+// the rule's row-tile count, or a hinted one where the block size divides into it within 8 waves
+static inline int lp_hinted_rt(int Mp, int hint) {
+  if ((hint == 1 || hint == 2 || hint == 4) && Mp % (16 * hint) == 0 && Mp / (16 * hint) <= 8) return hint;
+  return lp_choose_rt(Mp);
+}
+
 template <int PREC, int RT, int CT, int KU>
 static hipError_t launch_sweep_lp_cfg(const LpSweepArgs& a0, hipStream_t st) {
   LpSweepArgs a = a0;
@@ -139,13 +145,17 @@ static hipError_t launch_sweep_lp_ku(const LpSweepArgs& a, hipStream_t st) {
 
 template <int PREC, int RT>
 static hipError_t launch_sweep_lp_rt(const LpSweepArgs& a, hipStream_t st) {
+  // hinted columns per work-group (four row tiles of 64 columns spill registers)
+  if (a.kt_hint == 16) return launch_sweep_lp_ku<PREC, RT, 1>(a, st);
+  if (a.kt_hint == 32) return launch_sweep_lp_ku<PREC, RT, 2>(a, st);
+  if (a.kt_hint == 64 && RT < 4) return launch_sweep_lp_ku<PREC, RT, (RT < 4 ? 4 : 2)>(a, st);
   if (a.K <= 16) return launch_sweep_lp_ku<PREC, RT, 1>(a, st);
   if (a.K <= 32 || RT == 4) return launch_sweep_lp_ku<PREC, RT, 2>(a, st);
   return launch_sweep_lp_ku<PREC, RT, (RT == 4 ? 2 : 4)>(a, st);
 }
 
 hipError_t launch_sweep_lp(int prec, const LpSweepArgs& a, hipStream_t st) {
-  const int rt = lp_choose_rt(a.Mp);
+  const int rt = lp_hinted_rt(a.Mp, a.rt_hint);
   if (prec == 1) {
     if (rt == 4) return launch_sweep_lp_rt<1, 4>(a, st);
     if (rt == 2) return launch_sweep_lp_rt<1, 2>(a, st);
@@ -371,9 +381,13 @@ template <int PREC, int RT>
 static hipError_t launch_sup_lp_rt(const LpSupArgs& a, hipStream_t st) {
   const size_t esz = (PREC == 1) ? 4 : 2;
   const size_t lds4 = (size_t)64 * ((size_t)2 * a.Mp * esz + 32);
+  const size_t lds2 = (size_t)32 * ((size_t)2 * a.Mp * esz + 32);
+  if (a.kt_hint == 16) return launch_sup_lp_ku<PREC, RT, 1>(a, st);
+  if (a.kt_hint == 32 && lds2 <= 160 * 1024) return launch_sup_lp_ku<PREC, RT, 2>(a, st);
+  if (a.kt_hint == 64 && lds4 <= 160 * 1024) return launch_sup_lp_ku<PREC, RT, 4>(a, st);
   if constexpr (PREC == 1 && RT == 4) {   // float32 above block size 256: half of the panel in LDS
-    if (a.K > 32 && !a.accumulate && a.Mp % 64 == 0 && lds4 > 160 * 1024 &&
-        (size_t)64 * ((size_t)a.Mp * esz + 32) <= 160 * 1024)
+    if ((a.kt_hint == 0 || a.kt_hint == 64) && a.K > 32 && !a.accumulate && a.Mp % 64 == 0 &&
+        lds4 > 160 * 1024 && (size_t)64 * ((size_t)a.Mp * esz + 32) <= 160 * 1024)
       return launch_sup_lp_half_cfg<PREC, 4, 4, 1>(a, st);
   }
   if (a.K <= 16) return launch_sup_lp_ku<PREC, RT, 1>(a, st);
@@ -382,7 +396,7 @@ static hipError_t launch_sup_lp_rt(const LpSupArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_superpose_lp(int prec, const LpSupArgs& a, hipStream_t st) {
-  const int rt = lp_choose_rt(a.Mp);
+  const int rt = lp_hinted_rt(a.Mp, a.rt_hint);
   if (prec == 1) {
     if (rt == 4) return launch_sup_lp_rt<1, 4>(a, st);
     if (rt == 2) return launch_sup_lp_rt<1, 2>(a, st);

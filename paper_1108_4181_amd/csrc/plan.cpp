@@ -98,6 +98,7 @@ struct td_plan_s {
   // scalar plan (block size 1, every row an interface row): Algorithm 1 on the tridiagonal system
   bool scalar = false;
   ScalarArgs sc{};            // tree arrays and factor; the per-solve fields are set by each pass
+  td_tiles tiles{};           // launch shapes of the sweeps and the superposition (0 = the rules)
   bool first_pass = false;
   int32_t* d_flag = nullptr;
   td_plan_s* adj = nullptr;
@@ -1192,6 +1193,11 @@ Work plan_work(const td_plan_s* P) { return Work{P->Wbuf, P->W32, P->Ft, P->Xi, 
 // the reduced system, eq. (superposition).  The sweeps and the superposition run in the plan's
 // precision (float64, or float32 / bfloat16 with float32 accumulation); the reduced system always
 // in float64.  With `accumulate` the result is added to X (a refinement correction).
+// row tiles per wave (16 rows each) for a requested wave count, 0 when it does not divide Mp
+int32_t rt_for_waves(int64_t Mp, int32_t waves) {
+  return (waves > 0 && Mp % (16 * (int64_t)waves) == 0) ? (int32_t)(Mp / (16 * (int64_t)waves)) : 0;
+}
+
 void solve_pass(td_plan_s* P, const Work& w, const double* F, int64_t ldf, double* X, int64_t ldx, int64_t K,
                 bool accumulate, hipStream_t st) {
   if (P->scalar) {   // Algorithm 1 on the scalar system: no sweeps, no superposition
@@ -1227,6 +1233,7 @@ void solve_pass(td_plan_s* P, const Work& w, const double* F, int64_t ldf, doubl
     sa.F = F; sa.ldf = ldf; sa.W = w.W; sa.ldw = ldw;
     sa.N = (int32_t)N; sa.M = (int32_t)M; sa.Mp = (int32_t)Mp; sa.p = (int32_t)p; sa.K = (int32_t)K;
     sa.ncoltiles = 0; sa.total = 0;
+    sa.kt_hint = P->tiles.sweep_cols; sa.rt_hint = rt_for_waves(Mp, P->tiles.sweep_waves);
     if (N > p) HIPCHK(launch_sweep(sa, st));
     stage_mark(P, 1, st);
     HIPCHK(launch_ftilde(w.Ft, ldft, F, ldf, w.W, ldw, P->d_ks, P->adiag, P->bdiag, (int)p, (int)M, (int)Mp,
@@ -1248,6 +1255,7 @@ void solve_pass(td_plan_s* P, const Work& w, const double* F, int64_t ldf, doubl
     sa.F = F; sa.ldf = ldf; sa.W = w.W32;
     sa.N = (int32_t)N; sa.M = (int32_t)M; sa.Mp = (int32_t)Mp; sa.p = (int32_t)p; sa.K = (int32_t)K;
     sa.ncoltiles = 0; sa.total = 0;
+    sa.kt_hint = P->tiles.sweep_cols; sa.rt_hint = rt_for_waves(Mp, P->tiles.sweep_waves);
     if (N > p) HIPCHK(launch_sweep_lp(P->prec, sa, st));
     stage_mark(P, 1, st);
     HIPCHK(launch_ftilde_f32(w.Ft, ldft, F, ldf, w.W32, N, P->d_ks, P->adiag, P->bdiag, (int)p, (int)M,
@@ -1311,6 +1319,7 @@ void solve_pass(td_plan_s* P, const Work& w, const double* F, int64_t ldf, doubl
     u.X = X; u.ldx = ldx;
     u.N = (int32_t)N; u.M = (int32_t)M; u.Mp = (int32_t)Mp; u.p = (int32_t)p; u.K = (int32_t)K;
     u.ncoltiles = 0; u.total = 0; u.accumulate = accumulate ? 1 : 0;
+    u.kt_hint = P->tiles.sup_cols; u.rt_hint = rt_for_waves(Mp, P->tiles.sup_waves);
     if (N > p) HIPCHK(launch_superpose(u, st));
   } else {
     LpSupArgs u{};
@@ -1320,6 +1329,7 @@ void solve_pass(td_plan_s* P, const Work& w, const double* F, int64_t ldf, doubl
     u.X = X; u.ldx = ldx;
     u.N = (int32_t)N; u.M = (int32_t)M; u.Mp = (int32_t)Mp; u.p = (int32_t)p; u.K = (int32_t)K;
     u.ncoltiles = 0; u.total = 0; u.accumulate = accumulate ? 1 : 0;
+    u.kt_hint = P->tiles.sup_cols; u.rt_hint = rt_for_waves(Mp, P->tiles.sup_waves);
     if (N > p) HIPCHK(launch_superpose_lp(P->prec, u, st));
   }
   stage_mark(P, 5, st);
@@ -2091,6 +2101,24 @@ td_status tridiag_stage_times(td_plan plan, double* ms, int n) {
   return TD_OK;
 }
 
+td_status tridiag_set_tiles(td_plan plan, const td_tiles* tiles) {
+  if (!plan) return fail(TD_EINVAL, "null plan");
+  td_tiles t{};
+  if (tiles) t = *tiles;
+  for (td_plan_s* P : {plan, plan->adj}) {
+    if (!P) continue;
+    P->tiles = t;
+    P->drop_graph();
+  }
+  return TD_OK;
+}
+
+td_status tridiag_get_tiles(td_plan plan, td_tiles* tiles) {
+  if (!plan || !tiles) return fail(TD_EINVAL, "bad argument");
+  *tiles = plan->tiles;
+  return TD_OK;
+}
+
 const char* tridiag_status_string(td_status s) {
   switch (s) {
     case TD_OK: return "TD_OK";
@@ -2164,6 +2192,104 @@ td_status tridiag_autotune(int64_t M, int64_t K, int32_t sweep_prec, int64_t pro
       if (ms_per_solve) ms_per_solve[c] = ms / 3.0;
       if (ms / 3.0 < best) { best = ms / 3.0; *best_L = L; }
     }
+  } catch (const HipFail& e) {
+    result = fail(e.e == hipErrorOutOfMemory ? TD_ENOMEM : TD_EHIP,
+                  std::string("HIP error ") + hipGetErrorString(e.e) + " in " + e.where);
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(A); (void)hipFree(B); (void)hipFree(C); (void)hipFree(F); (void)hipFree(X);
+  return result;
+}
+
+td_status tridiag_autotune_tiles(int64_t M, int64_t K, int32_t sweep_prec, int64_t probe_N,
+                                 const int64_t* candidates, int ncand, void* stream, int64_t* best_L,
+                                 td_tiles* best_tiles, double* best_ms) {
+  g_err.clear();
+  if (M < 1 || M > 512 || K < 1 || probe_N < 2 || !candidates || ncand < 1 || !best_L || !best_tiles)
+    return fail(TD_EINVAL, "bad autotune arguments");
+  hipStream_t st = (hipStream_t)stream;
+  double *A = nullptr, *B = nullptr, *C = nullptr, *F = nullptr, *X = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  td_status result = TD_OK;
+  try {
+    HIPCHK(hipMalloc((void**)&A, probe_N * M * 8));
+    HIPCHK(hipMalloc((void**)&B, probe_N * M * 8));
+    HIPCHK(hipMalloc((void**)&C, probe_N * 3 * M * 8));
+    HIPCHK(hipMalloc((void**)&F, probe_N * M * K * 8));
+    HIPCHK(hipMalloc((void**)&X, probe_N * M * K * 8));
+    HIPCHK(launch_probe_inputs(A, B, C, F, (int)probe_N, (int)M, K, st));
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    double best = INFINITY;
+    *best_L = candidates[0];
+    *best_tiles = td_tiles{};
+    const int64_t Mp = pad_block(M, sweep_prec);
+    // alternatives of each field: column counts of the precision, and the wave counts (16, 32 or
+    // 64 rows per wave, at most 8 waves) that the padded block size allows
+    std::vector<int32_t> cols = (sweep_prec == TD_PREC_F64) ? std::vector<int32_t>{16, 32}
+                                                            : std::vector<int32_t>{16, 32, 64};
+    std::vector<int32_t> waves;
+    for (int rt : {1, 2, 4})
+      if (Mp % (16 * rt) == 0 && Mp / (16 * rt) <= 8) waves.push_back((int32_t)(Mp / (16 * rt)));
+    for (int c = 0; c < ncand && result == TD_OK; ++c) {
+      const int64_t L = std::max<int64_t>(1, candidates[c]);
+      td_desc d;
+      std::memset(&d, 0, sizeof d);
+      d.N = probe_N; d.M = M; d.subdomains = std::max<int64_t>(1, probe_N / L);
+      d.fmt_A = TD_FMT_DIAG; d.fmt_B = TD_FMT_DIAG; d.fmt_C = TD_FMT_TRIDIAG; d.sweep_prec = sweep_prec;
+      td_plan Pr = nullptr;
+      td_status s = factor_top(&d, A, B, C, st, &Pr, false);
+      if (s != TD_OK) { result = s; break; }
+      std::unique_ptr<td_plan_s> P(Pr);   // freed on every exit, also when a HIP call throws
+      auto time_tiles = [&](const td_tiles& t, double& ms_out) -> td_status {
+        P->tiles = t;
+        P->drop_graph();
+        td_status r = solve_impl(P.get(), F, probe_N * M, X, probe_N * M, K, nullptr, nullptr, st);
+        if (r != TD_OK) return r;
+        HIPCHK(hipEventRecord(e0, st));
+        for (int k = 0; k < 3 && r == TD_OK; ++k)
+          r = solve_impl(P.get(), F, probe_N * M, X, probe_N * M, K, nullptr, nullptr, st);
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        if (r != TD_OK) return r;
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        ms_out = ms / 3.0;
+        return TD_OK;
+      };
+      td_tiles cur{};
+      double cur_ms = 0.0;
+      if ((s = time_tiles(cur, cur_ms)) != TD_OK) { result = s; break; }
+      // one field at a time against the rules; then the best of every field together
+      td_tiles comb{};
+      int32_t td_tiles::*fields[4] = {&td_tiles::sweep_cols, &td_tiles::sweep_waves, &td_tiles::sup_cols,
+                                      &td_tiles::sup_waves};
+      for (int f = 0; f < 4 && s == TD_OK; ++f) {
+        const std::vector<int32_t>& opts = (f % 2 == 0) ? cols : waves;
+        double fbest = cur_ms;
+        for (int32_t v : opts) {
+          td_tiles t{};
+          t.*fields[f] = v;
+          double ms = 0.0;
+          if ((s = time_tiles(t, ms)) != TD_OK) break;
+          if (ms < fbest) { fbest = ms; comb.*fields[f] = v; }
+        }
+      }
+      if (s != TD_OK) { result = s; break; }
+      double comb_ms = cur_ms;
+      const bool any = comb.sweep_cols || comb.sweep_waves || comb.sup_cols || comb.sup_waves;
+      if (any && (s = time_tiles(comb, comb_ms)) != TD_OK) { result = s; break; }
+      const td_tiles win = (any && comb_ms < cur_ms) ? comb : td_tiles{};
+      const double win_ms = (any && comb_ms < cur_ms) ? comb_ms : cur_ms;
+      if (win_ms < best) {
+        best = win_ms;
+        *best_L = L;
+        *best_tiles = win;
+      }
+    }
+    if (best_ms) *best_ms = best;
   } catch (const HipFail& e) {
     result = fail(e.e == hipErrorOutOfMemory ? TD_ENOMEM : TD_EHIP,
                   std::string("HIP error ") + hipGetErrorString(e.e) + " in " + e.where);
