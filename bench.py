@@ -34,9 +34,9 @@ KERNEL_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     # (kernel, workload): (source set, source hash (kernel_source_hash), read bytes, write bytes)
-    ("sweep", "mixed_n4096_m512_k1024"): ("f64", "430016bbf614ddec", 54.7452e9, 32.7995e9),
-    ("superposition", "mixed_n4096_m512_k1024"): ("f64", "430016bbf614ddec", 50.5348e9, 16.6430e9),
-    ("scalar_subtrees", "scalar_n65536_k1024"): ("scalar", "d2169700acd62c1c", 0.55340e9, 0.53687e9),
+    ("sweep", "mixed_n4096_m512_k1024"): ("f64", "7ad1eb38ee72c5e7", 53.7926e9, 32.7995e9),
+    ("superposition", "mixed_n4096_m512_k1024"): ("f64", "7ad1eb38ee72c5e7", 50.5180e9, 16.6430e9),
+    ("scalar_subtrees", "scalar_n65536_k1024"): ("scalar", "9223c77be2e66006", 0.55352e9, 0.53687e9),
 }
 
 
