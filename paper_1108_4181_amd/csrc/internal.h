@@ -127,6 +127,8 @@ struct GJArgs {
   const int64_t* bd_off;
   const int32_t* tag;    // block label reported on a singular pivot
   int32_t* bad;          // atomic min of the labels of singular matrices
+  int32_t* piv;          // optional scratch, nmat x Mp: pivot rows (block sizes multiples of 64 from 128
+  double* nrm;           // take the one-launch-per-panel path when given); nrm: nmat infinity norms
   int32_t nmat, Mp;
 };
 

@@ -57,6 +57,19 @@ __device__ __forceinline__ void wave_argmax(double& v, int& i) {
   i = __builtin_amdgcn_readlane(i, 63);
 }
 
+// Arg-max of the waves' pivot candidates: lane u < 8 holds wave u's (magnitude, row), absent waves
+// (-2, INT_MAX).  Three DPP steps within groups of eight lanes (rows are below 2^16, so row and wave
+// pack into one key whose order is the row's); the pivot row r and its wave wr come back uniform.
+__device__ __forceinline__ void slot_argmax(double v, int row, int& r, int& wr) {
+  int key = (row == INT_MAX) ? INT_MAX : (row << 3) | (threadIdx.x & 7);
+  argmax_dpp_step<0xB1, 0xF>(v, key);    // quad_perm [1,0,3,2]
+  argmax_dpp_step<0x4E, 0xF>(v, key);    // quad_perm [2,3,0,1]
+  argmax_dpp_step<0x141, 0xF>(v, key);   // row_half_mirror: lane i of eight meets lane 7 - i
+  key = __builtin_amdgcn_readfirstlane(key);
+  r = key >> 3;
+  wr = key & 7;
+}
+
 template <int RT, int NT, int NB>
 __global__ void __launch_bounds__(NT) k_gj(GJArgs g) {
   constexpr int CT = 4;           // 16 columns per update tile
@@ -277,199 +290,230 @@ __global__ void __launch_bounds__(NT) k_gj(GJArgs g) {
   }
 }
 
-// Gauss-Jordan inversion for block sizes that are multiples of 64 (64 ... 512): one thread per row
-// (Mp threads), the panel's NB columns of the thread's row in registers.  Per column every wave
-// finds its best candidate with a DPP arg-max, and the winning lane of each wave publishes that row
-// (NB values) next to its magnitude; after one work-group barrier every thread picks the overall
-// pivot among the waves' candidates (larger magnitude, then smaller row) and reads the pivot row from
-// the winning wave's slot.  Slots alternate between two copies, so one barrier per column suffices and
-// the LDS traffic per column is one row per wave (the all-thread kernel above publishes every row).
-// After the panel, all waves apply the rank-NB update to the other columns on MFMA with four row tiles
-// of 16 rows per wave and tile operands loaded three tiles ahead.
+// Gauss-Jordan elimination of one panel of NB columns, one row per thread: v[j] is the thread's entry
+// of panel column j, rows with `used` set were pivots of earlier panels.  Per column every wave finds
+// its best candidate with a DPP arg-max, and the winning lane of each wave publishes that row and its
+// reciprocal pivot next to its magnitude; after one work-group barrier every thread picks the overall
+// pivot among the waves' candidates (larger magnitude, then smaller row: a DPP arg-max over eight
+// lanes) and reads the pivot row from the winning wave's slot.  Slots alternate between two copies, so one
+// barrier per column suffices.
+//   The loop stays rolled without indexing registers at run time: the row is kept rotated so that v[0]
+// is always the current column, and the update writes each entry one place down (column j's new entry
+// goes to the end), so after NB columns the order is the original one again.  The pivot row is not
+// scaled when it is chosen: later eliminations are linear in each row, so its entries are multiplied
+// by the reciprocal pivot once after the panel (its column-j entry is kept as 1 until then), and every
+// row takes the same single fused multiply-add per entry and column.  Every lane divides by its own
+// entry while the arg-max runs, so the reciprocal is ready when its lane wins.  The pivot row of
+// column j goes to prow[j] (written by thread 0).  cand holds [2][8][NB] rows, cv [2][8] magnitudes
+// and, from cv[32], [2][8] reciprocals, ci [2][8] rows.
+template <int NB>
+__device__ __forceinline__ void gj_panel(double (&v)[NB], bool& used, bool& singular, double tol, double* cand,
+                                         double* cv, int* ci, int* prow, int nw) {
+  const int tid = threadIdx.x, L = tid & 63, w = tid >> 6;
+  double sr = 1.0;   // deferred scale of this thread's row (the reciprocal pivot if it was chosen)
+#pragma unroll 1
+  for (int j = 0; j < NB; ++j) {
+    const int slot = j & 1;
+    const double vj = v[0];
+    const double rcp = 1.0 / vj;            // used only if this lane's row wins
+    double bv = -1.0;
+    int bi = INT_MAX;
+    if (!used) {
+      const double a = fabs(vj);
+      bv = (a == a) ? a : DBL_MAX;   // NaN ranks first so that it is reported
+      bi = tid;
+    }
+    wave_argmax(bv, bi);
+    if (tid == bi) {
+      double* cp = cand + (slot * 8 + w) * NB;
+#pragma unroll
+      for (int jj = 0; jj < NB; ++jj) cp[jj] = v[jj];
+      cv[32 + slot * 8 + w] = rcp;
+    }
+    if (L == 0) { cv[slot * 8 + w] = bv; ci[slot * 8 + w] = bi; }
+    __syncthreads();
+    int r, wr;
+    slot_argmax(L < nw ? cv[slot * 8 + (L & 7)] : -2.0, L < nw ? ci[slot * 8 + (L & 7)] : INT_MAX, r, wr);
+    const double* pr = cand + (slot * 8 + wr) * NB;
+    double prv[NB];
+#pragma unroll
+    for (int jj = 0; jj < NB; ++jj) prv[jj] = pr[jj];
+    const double ipv = cv[32 + slot * 8 + wr];
+    if (!(fabs(prv[0]) > tol)) singular = true;
+    const bool piv = (tid == r);
+    const double f = piv ? 0.0 : vj * ipv;   // v <- v - v_j * (pivot row / pivot), column j <- -v_j / pivot
+#pragma unroll
+    for (int jj = 0; jj + 1 < NB; ++jj) v[jj] = v[jj + 1] - f * prv[jj + 1];
+    v[NB - 1] = piv ? 1.0 : -f;
+    sr = piv ? ipv : sr;
+    used = used | piv;
+    if (tid == 0) prow[j] = r;
+  }
+#pragma unroll
+  for (int jj = 0; jj < NB; ++jj) v[jj] *= sr;
+}
+
+// Gauss-Jordan inversion with one launch per panel, for block sizes that are multiples of 64 from 128:
+// the matrix's columns form Mp / NB tiles of one panel's width, and launch k has one work-group per
+// (matrix, tile).  Eliminating a set S of columns with pivot rows R is one block pivot: every other
+// column c becomes c + (Z - E_R) c_R, where Z holds the columns of S after their elimination (in place,
+// so Z is what the previous launch stored in panel k's columns) and c_R the entries of c in rows R
+// before it.  So in launch k every tile other than panel k applies panel k's transform to its own
+// columns (a rank-NB product on MFMA), and the work-group of tile k + 1 then eliminates that panel
+// (gj_panel, one row per thread).  Launch -1 only eliminates panel 0 and stores the infinity norm.
+// (An earlier form inverted each matrix in one work-group and one launch; at block size 512 a matrix
+// then took 6.4 ms, most of it the passes of one work-group's update over the 2 MB matrix.)
+// The pivot rows of every panel go to g.piv; k_gj_readout applies the permutation.  A matrix thus has
+// Mp / NB work-groups in flight instead of one, and the update of a panel no longer waits behind the
+// elimination of the next.
 template <int NB, int NT>
-__global__ void __launch_bounds__(NT) k_gj_cand(GJArgs g) {
-  constexpr int RT = 4;           // 64 rows per wave
-  constexpr int CT = 4;           // 16 columns per update tile
-  constexpr int KT = 4 * CT;
+__global__ void __launch_bounds__(NT) k_gj_step(GJArgs g, int k) {
+  constexpr int RT = 4;                    // 64 rows per wave
+  constexpr int CTN = NB / 4;              // 4-column output tiles per tile
   extern __shared__ double sm[];
   const int Mp = g.Mp;                     // a multiple of 64, blockDim.x == Mp
-  double* Pn = sm;                         // [NB][Mp]: the eliminated panel
-  double* Ys = Pn + NB * Mp;               // [NB][Mp]: pivot rows of W, all columns
-  double* cand = Ys + NB * Mp;             // [2][8][NB]: candidate pivot rows of the waves
-  double* cv = cand + 2 * 8 * NB;          // [2][8]: their magnitudes; [16 .. 23]: row-sum maxima
-  int* ci = (int*)(cv + 24);               // [2][8]: their rows
-  int* pivrow = ci + 16;                   // [Mp]
-  int* invpiv = pivrow + Mp;               // [Mp]
-
-  const int tid = threadIdx.x, nthr = blockDim.x;
-  const int L = tid & 63, w = tid >> 6, nw = nthr >> 6;
-  const int q = blockIdx.x;
-  if (q >= g.nmat) return;
-  double* W = g.work + (g.work_off ? g.work_off[q] : q * g.wstride);
-  const int rb = w * 16 * RT;
-
-  // infinity norm (row sums), one row per thread; eight loads in flight per thread (a loop that
-  // waits for each load before the next spends a memory latency per column)
-  double rs = 0.0;
-#pragma unroll 1
-  for (int c0 = 0; c0 < Mp; c0 += 8) {
-    double t[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) t[u] = W[tid + (int64_t)(c0 + u) * Mp];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) rs += fabs(t[u]);
+  double* Ts = sm;                         // [NB][Mp]: the updated panel (panel work-group)
+  double* Bs = Ts + NB * Mp;               // [NB][NB]: rows R_k of the tile's columns
+  double* cand = Bs + NB * NB;             // [2][8][NB]: candidate pivot rows of the waves
+  double* cv = cand + 2 * 8 * NB;          // [2][8]: their magnitudes; [16 .. 23]: row-sum maxima;
+                                           // [32 .. 47]: their reciprocal pivots
+  int* ci = (int*)(cv + 48);               // [2][8]: their rows
+  int* pl = ci + 16;                       // [NB]: pivot rows of the panel eliminated here
+  int* rk = pl + NB;                       // [NB]: pivot rows of panel k
+  int* usedf = rk + NB;                    // [Mp]: rows that were pivots of earlier panels
+  const int tid = threadIdx.x, L = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
+  const int ntile = Mp / NB;
+  // Work-groups [0, nmat8) eliminate the next panel of matrix blockIdx.x, so they are dispatched
+  // before any update; update work-group t = blockIdx.x - nmat8 takes tile t/8 % ntile of matrix
+  // t % 8 + 8 (t/8 / ntile): work-groups go to the eight XCDs in turn, so every work-group of a matrix
+  // runs on the XCD of its panel work-group and reads panel k from that XCD's L2.
+  const int nmat8 = (g.nmat + 7) & ~7;
+  int q, c;
+  if ((int)blockIdx.x < nmat8) {
+    q = blockIdx.x;
+    c = k + 1;
+    if (q >= g.nmat || c >= ntile) return;
+  } else {
+    const int t = blockIdx.x - nmat8, i = t >> 3;
+    q = (t & 7) + 8 * (i / ntile);
+    c = i % ntile;
+    if (q >= g.nmat || c == k || c == k + 1) return;
   }
-  for (int off = 32; off > 0; off >>= 1) rs = fmax(rs, __shfl_xor(rs, off));
-  if (L == 0) cv[16 + w] = rs;
-  __syncthreads();
-  double norm = 0.0;
-  for (int u = 0; u < nw; ++u) norm = fmax(norm, cv[16 + u]);
-  const double tol = 1e-14 * norm;
-  bool singular = false;
-  bool used = false;
+  double* W = g.work + (g.work_off ? g.work_off[q] : q * g.wstride);
+  int* piv = g.piv + (int64_t)q * Mp;
+  const int c0 = c * NB;
+  const int rb = w * 16 * RT;
+  const bool panel = (c == k + 1);
 
-  for (int p0 = 0; p0 < Mp; p0 += NB) {
-    double v[NB];
-#pragma unroll
-    for (int jj = 0; jj < NB; ++jj) v[jj] = W[tid + (int64_t)(p0 + jj) * Mp];
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int slot = j & 1;
-      // v[j] by selection, so that a loop the compiler leaves rolled keeps v in registers
-      double vj = 0.0;
-#pragma unroll
-      for (int jj = 0; jj < NB; ++jj) vj = (jj == j) ? v[jj] : vj;
-      double bv = -1.0;
-      int bi = INT_MAX;
-      if (!used) {
-        const double a = fabs(vj);
-        bv = (a == a) ? a : DBL_MAX;   // NaN ranks first so that it is reported
-        bi = tid;
-      }
-      wave_argmax(bv, bi);
-      if (tid == bi) {
-        double* cp = cand + (slot * 8 + w) * NB;
-#pragma unroll
-        for (int jj = 0; jj < NB; ++jj) cp[jj] = v[jj];
-      }
-      if (L == 0) { cv[slot * 8 + w] = bv; ci[slot * 8 + w] = bi; }
-      __syncthreads();
-      double b2 = cv[slot * 8];
-      int r = ci[slot * 8], wr = 0;
-      for (int u = 1; u < nw; ++u) {
-        const double ov = cv[slot * 8 + u];
-        const int oi = ci[slot * 8 + u];
-        if (ov > b2 || (ov == b2 && oi < r)) { b2 = ov; r = oi; wr = u; }
-      }
-      const double* pr = cand + (slot * 8 + wr) * NB;
-      const double pv = pr[j];
-      if (!(fabs(pv) > tol)) singular = true;
-      const double ipv = 1.0 / pv;
-      if (tid == r) {
-#pragma unroll
-        for (int jj = 0; jj < NB; ++jj) v[jj] = (jj == j) ? ipv : v[jj] * ipv;
-        used = true;
-      } else {
-        const double fi = vj * ipv;   // v <- v - v_j * (pivot row / pivot), column j <- -v_j / pivot
-#pragma unroll
-        for (int jj = 0; jj < NB; ++jj) v[jj] = (jj == j) ? -fi : v[jj] - fi * pr[jj];
-      }
-      if (tid == 0) pivrow[p0 + j] = r;
-    }
-#pragma unroll
-    for (int jj = 0; jj < NB; ++jj) Pn[jj * Mp + tid] = v[jj];
+  if (k >= 0) {
+    if (tid < NB) rk[tid] = piv[k * NB + tid];
     __syncthreads();
-    // pivot rows of W, column tid of each: eight loads issued before their LDS stores
-#pragma unroll 1
-    for (int j0 = 0; j0 < NB; j0 += 8) {
-      double t[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) t[u] = W[pivrow[p0 + j0 + u] + (int64_t)tid * Mp];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) Ys[(j0 + u) * Mp + tid] = t[u];
+    for (int e = tid; e < NB * NB; e += blockDim.x) {   // a row of R_k per column: one column's rows per pass
+      const int j = e / NB, kk = e - j * NB;
+      Bs[kk * NB + j] = W[rk[kk] + (int64_t)(c0 + j) * Mp];
     }
-    __syncthreads();
-    // rank-NB update of all other columns: W[:, c] += (Pn - E_R) * W[R, c]
-    double av[NB / 4][RT];
+    double a[NB / 4][RT];                  // (Z - E_R) rows of this wave, Z = panel k's columns
 #pragma unroll
-    for (int kk = 0; kk < NB / 4; ++kk) {
-      const int k = 4 * kk + (L >> 4);
-      const int prw = pivrow[p0 + k];
+    for (int k4 = 0; k4 < NB / 4; ++k4) {
+      const int kc = 4 * k4 + (L >> 4);
+      const int prw = rk[kc];
 #pragma unroll
       for (int t = 0; t < RT; ++t) {
         const int row = rb + 16 * t + (L & 15);
-        av[kk][t] = Pn[k * Mp + row] - (row == prw ? 1.0 : 0.0);
+        a[k4][t] = W[row + (int64_t)(k * NB + kc) * Mp] - (row == prw ? 1.0 : 0.0);
       }
     }
-    const int ntile = Mp / KT;
-    auto load_tile = [&](double (&acc)[RT][CT], int tile) {
-      const int c0 = tile * KT;
+    double acc[RT][CTN];
 #pragma unroll
-      for (int t = 0; t < RT; ++t) {
-        const int row = rb + 16 * t + out_row(L);
+    for (int t = 0; t < RT; ++t)
 #pragma unroll
-        for (int c = 0; c < CT; ++c) acc[t][c] = W[row + (int64_t)(c0 + out_col(L) * CT + c) * Mp];
-      }
-    };
-    auto update_tile = [&](double (&acc)[RT][CT], int tile) {
-      const int c0 = tile * KT;
+      for (int ct = 0; ct < CTN; ++ct)
+        acc[t][ct] = W[rb + 16 * t + out_row(L) + (int64_t)(c0 + 4 * ct + out_col(L)) * Mp];
+    __syncthreads();   // Bs complete; every read of rows R_k of the tile precedes the stores below
 #pragma unroll
-      for (int kk = 0; kk < NB / 4; ++kk) {
-        const int k = 4 * kk + (L >> 4);
-        const double* bp = &Ys[k * Mp + c0 + (L & 3) * CT];
-        double bb[CT];
+    for (int k4 = 0; k4 < NB / 4; ++k4) {
+      const double* bp = Bs + (4 * k4 + (L >> 4)) * NB + (L & 3);
+      double b[CTN];
 #pragma unroll
-        for (int c = 0; c < CT; ++c) bb[c] = bp[c];
+      for (int ct = 0; ct < CTN; ++ct) b[ct] = bp[4 * ct];
 #pragma unroll
-        for (int t = 0; t < RT; ++t)
+      for (int t = 0; t < RT; ++t)
 #pragma unroll
-          for (int c = 0; c < CT; ++c) acc[t][c] = mfma4(av[kk][t], bb[c], acc[t][c]);
-      }
-#pragma unroll
-      for (int t = 0; t < RT; ++t) {
-        const int row = rb + 16 * t + out_row(L);
-#pragma unroll
-        for (int c = 0; c < CT; ++c) W[row + (int64_t)(c0 + out_col(L) * CT + c) * Mp] = acc[t][c];
-      }
-    };
-    constexpr int PT = NB / KT;               // tiles covered by the panel
-    const int ptile = p0 / KT;
-    const int cnt = ntile - PT;               // >= 2 for Mp >= 64 (NB = 16) or Mp >= 128 (NB = 32)
-    auto tile_of = [&](int n) { return n < ptile ? n : n + PT; };
-    double tb0[RT][CT], tb1[RT][CT], tb2[RT][CT], tb3[RT][CT];
-    if (cnt > 0) load_tile(tb0, tile_of(0));
-    if (cnt > 1) load_tile(tb1, tile_of(1));
-    if (cnt > 2) load_tile(tb2, tile_of(2));
-    for (int n = 0; n < cnt; n += 4) {
-      if (n + 3 < cnt) load_tile(tb3, tile_of(n + 3));
-      update_tile(tb0, tile_of(n));
-      if (n + 1 >= cnt) break;
-      if (n + 4 < cnt) load_tile(tb0, tile_of(n + 4));
-      update_tile(tb1, tile_of(n + 1));
-      if (n + 2 >= cnt) break;
-      if (n + 5 < cnt) load_tile(tb1, tile_of(n + 5));
-      update_tile(tb2, tile_of(n + 2));
-      if (n + 3 >= cnt) break;
-      if (n + 6 < cnt) load_tile(tb2, tile_of(n + 6));
-      update_tile(tb3, tile_of(n + 3));
+        for (int ct = 0; ct < CTN; ++ct) acc[t][ct] = mfma4(a[k4][t], b[ct], acc[t][ct]);
     }
-    for (int e = tid; e < NB * Mp; e += nthr) {   // stores only: no load latency to hide
-      const int i = e % Mp, jj = e / Mp;
-      W[i + (int64_t)(p0 + jj) * Mp] = Pn[jj * Mp + i];
+    if (!panel) {
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int ct = 0; ct < CTN; ++ct)
+          W[rb + 16 * t + out_row(L) + (int64_t)(c0 + 4 * ct + out_col(L)) * Mp] = acc[t][ct];
+      return;
     }
-    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int ct = 0; ct < CTN; ++ct) Ts[(4 * ct + out_col(L)) * Mp + rb + 16 * t + out_row(L)] = acc[t][ct];
   }
-  if (tid == 0 && singular) atomicMin(g.bad, g.tag[q]);
-  // inverse: Dinv[c][pivrow[c']] = S[pivrow[c]][c']
-  invpiv[pivrow[tid]] = tid;
+  if (!panel) return;
+
+  // the panel work-group: tolerance, rows already used as pivots, then the elimination
+  double norm;
+  if (k < 0) {
+    double rs = 0.0;
+#pragma unroll 1
+    for (int c8 = 0; c8 < Mp; c8 += 8) {
+      double t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = W[tid + (int64_t)(c8 + u) * Mp];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) rs += fabs(t[u]);
+    }
+    for (int off = 32; off > 0; off >>= 1) rs = fmax(rs, __shfl_xor(rs, off));
+    if (L == 0) cv[16 + w] = rs;
+    __syncthreads();
+    norm = 0.0;
+    for (int u = 0; u < nw; ++u) norm = fmax(norm, cv[16 + u]);
+    if (tid == 0) g.nrm[q] = norm;
+  } else {
+    norm = g.nrm[q];
+  }
+  usedf[tid] = 0;
+  __syncthreads();   // also orders the Ts stores above before the reads below
+  for (int i = tid; i < c0; i += blockDim.x) usedf[piv[i]] = 1;
   __syncthreads();
+  bool used = usedf[tid] != 0;
+  bool singular = false;
+  double v[NB];
+#pragma unroll
+  for (int jj = 0; jj < NB; ++jj) v[jj] = (k < 0) ? W[tid + (int64_t)jj * Mp] : Ts[jj * Mp + tid];
+  gj_panel<NB>(v, used, singular, 1e-14 * norm, cand, cv, ci, pl, nw);
+#pragma unroll
+  for (int jj = 0; jj < NB; ++jj) W[tid + (int64_t)(c0 + jj) * Mp] = v[jj];
+  __syncthreads();
+  if (tid < NB) piv[c0 + tid] = pl[tid];
+  if (tid == 0 && singular) atomicMin(g.bad, g.tag[q]);
+}
+
+// Read-out after k_gj_step: inverse[c][piv[c']] = S[piv[c]][c'] for the eliminated matrix S, and
+// alpha = inverse * diag(bdiag) when requested.  One work-group per (matrix, chunk of Mp / nchunk
+// columns), thread i writes row i.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_gj_readout(GJArgs g, int nchunk) {
+  __shared__ int invpiv[NT];
+  const int q = blockIdx.x / nchunk, ch = blockIdx.x - q * nchunk;
+  if (q >= g.nmat) return;
+  const int Mp = g.Mp, tid = threadIdx.x;
+  const int* piv = g.piv + (int64_t)q * Mp;
+  const int prow_t = piv[tid];
+  invpiv[prow_t] = tid;
+  __syncthreads();
+  const double* W = g.work + (g.work_off ? g.work_off[q] : q * g.wstride);
   double* out = g.out + g.out_off[q];
   double* al = g.alpha ? g.alpha + g.out_off[q] : nullptr;
   const double* bd = g.alpha ? g.bdiag + g.bd_off[q] : nullptr;
-  // thread tid writes row tid of every column; eight columns' loads in flight at a time
-  const int prow_t = pivrow[tid];
+  const int cw = Mp / nchunk;
 #pragma unroll 1
-  for (int oc0 = 0; oc0 < Mp; oc0 += 8) {
+  for (int oc0 = ch * cw; oc0 < (ch + 1) * cw; oc0 += 8) {
     double t[8], b[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) t[u] = W[prow_t + (int64_t)invpiv[oc0 + u] * Mp];
@@ -487,12 +531,19 @@ __global__ void __launch_bounds__(NT) k_gj_cand(GJArgs g) {
 }
 
 template <int NB, int NT>
-static hipError_t launch_gj_cand(const GJArgs& g, hipStream_t st) {
-  const size_t lds = (size_t)(2 * NB * g.Mp + 2 * 8 * NB + 24) * sizeof(double) + (size_t)(16 + 2 * g.Mp) * sizeof(int);
-  hipError_t e = hipFuncSetAttribute((const void*)k_gj_cand<NB, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+static hipError_t launch_gj_split(const GJArgs& g, hipStream_t st) {
+  const int Mp = g.Mp, ntile = Mp / NB;
+  const size_t lds = (size_t)(NB * Mp + NB * NB + 2 * 8 * NB + 48) * sizeof(double) +
+                     (size_t)(16 + 2 * NB + Mp) * sizeof(int);
+  hipError_t e = hipFuncSetAttribute((const void*)k_gj_step<NB, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_gj_cand<NB, NT>), dim3(g.nmat), dim3(g.Mp), lds, st, g);
+  const int nmat8 = grid_pad8(g.nmat);
+  hipLaunchKernelGGL((k_gj_step<NB, NT>), dim3(nmat8), dim3(Mp), lds, st, g, -1);
+  for (int k = 0; k < ntile; ++k)
+    hipLaunchKernelGGL((k_gj_step<NB, NT>), dim3(nmat8 * (1 + ntile)), dim3(Mp), lds, st, g, k);
+  const int nchunk = Mp / 64;
+  hipLaunchKernelGGL((k_gj_readout<NT>), dim3(g.nmat * nchunk), dim3(Mp), 0, st, g, nchunk);
   return hipGetLastError();
 }
 
@@ -522,11 +573,12 @@ static hipError_t launch_gj_rt(const GJArgs& g, hipStream_t st) {
 
 hipError_t launch_gj(const GJArgs& g, hipStream_t st) {
   if (g.nmat == 0) return hipSuccess;
-  // block sizes that are multiples of 64 from 128 (every padded size above 256 is one): the
-  // candidate-row kernel, 32-column panels up to 256 rows (four waves keep the register budget of
-  // 256-thread work-groups), 16-column panels above
-  if (g.Mp % 64 == 0 && g.Mp >= 128)
-    return g.Mp <= 256 ? launch_gj_cand<32, 256>(g, st) : launch_gj_cand<16, 512>(g, st);
+  // block sizes that are multiples of 64 from 128 (every padded size above 256 is one): one launch
+  // per 32-column panel, with the caller's scratch for pivot rows and norms
+  if (g.Mp % 64 == 0 && g.Mp >= 128) {
+    if (!g.piv || !g.nrm) return hipErrorInvalidValue;
+    return g.Mp <= 256 ? launch_gj_split<32, 256>(g, st) : launch_gj_split<32, 512>(g, st);
+  }
   if (g.Mp > 256) return hipErrorInvalidValue;
   switch (choose_rt(g.Mp)) {
     case 4: return launch_gj_rt<4>(g, st);

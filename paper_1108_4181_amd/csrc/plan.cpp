@@ -370,6 +370,14 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
   double* Ga = P->alloc((1 + N) * MM);
   HIPCHK(launch_identity(Ga, (int)Mp, st));
   double* Dwork = P->alloc(p * MM);
+  // Gauss-Jordan scratch: pivot rows and norms of up to 2p matrices per launch (the tree's chain
+  // steps invert a left and a right chain matrix of each of its p nodes)
+  double* gjs = P->alloc(p * Mp + 2 * p);
+  auto gj_scratch = [&](GJArgs& g) {
+    if (g.nmat > 2 * p) throw std::string("internal error: Gauss-Jordan scratch too small");
+    g.piv = reinterpret_cast<int32_t*>(gjs);
+    g.nrm = gjs + p * Mp;
+  };
 
   int32_t* bad = P->d_flag;
   HIPCHK(launch_negate_fill_check(bad, INT_MAX, st));
@@ -443,6 +451,7 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
       g.alpha = P->dense ? nullptr : P->alpha; g.bdiag = P->bdiag; g.bd_off = pool.put_vec(bdoff);
       g.tag = pool.put_vec(tag); g.bad = bad;
       g.nmat = nm; g.Mp = (int32_t)Mp;
+      gj_scratch(g);
       HIPCHK(launch_gj(g, st));
     }
     if (P->dense) {   // alpha_i = D_i^{-1} B_i, E_i = D_i^{-1} A_i, Gamma_i = E_i Gamma_{i-1}
@@ -676,6 +685,7 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
       g.alpha = nullptr; g.bdiag = nullptr; g.bd_off = nullptr;
       g.tag = pool.put_vec(tag); g.bad = bad;
       g.nmat = nm; g.Mp = (int32_t)Mp;
+      gj_scratch(g);
       HIPCHK(launch_gj(g, st));
     }
     BArgs b = bargs_base((int)Mp);
@@ -728,6 +738,7 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
     g.alpha = nullptr; g.bdiag = nullptr; g.bd_off = nullptr;
     g.tag = pool.put_vec(tag); g.bad = bad;
     g.nmat = nn; g.Mp = (int32_t)Mp;
+    gj_scratch(g);
     HIPCHK(launch_gj(g, st));
   }
   // G_j = G_{j+1} At_{j+1} (D^L_j)^{-1} for j < m;  G_j = G_{j-1} Bt_{j-1} (D^R_j)^{-1} for j > m
@@ -810,6 +821,7 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
   }
   HIPCHK(hipStreamSynchronize(st));
   P->release(Da);
+  P->release(gjs);
 
   // ---- descriptors of the solve
   {
@@ -1489,7 +1501,7 @@ int64_t factor_bytes(int64_t N, int64_t M, int64_t p, int fA, int fB, int fC, in
   b += (fA == TD_FMT_DIAG ? N * M : N * M * M) + (fB == TD_FMT_DIAG ? N * M : N * M * M);
   b += (fC == TD_FMT_TRIDIAG ? 3 * N * M : N * M * M) + 2 * N * Mp;
   b += N * MM * 2 + (2 + 2 * N) * MM;     // Dinv, alpha, UV
-  b += (1 + N) * MM + p * MM;              // Gamma arena, Dwork (temporary)
+  b += (1 + N) * MM + p * MM + p * Mp + 2 * p;   // Gamma arena, Dwork, Gauss-Jordan scratch (temporary)
   b += 3 * p * MM + p * (depth + 1) * MM + 2 * p * MM + (1 + 6 * p) * MM + p * MM;  // reduced, G, H, arenas
   if (prec != TD_PREC_F64) b += (4 * N * MM * (prec == TD_PREC_F32 ? 4 : 2) + 7) / 8;  // rounded copies
   if (fA == TD_FMT_DENSE || fB == TD_FMT_DENSE) b += 3 * N * MM;                     // [A|B] blocks, E

@@ -4,6 +4,7 @@ plan's own solve (tridiag_solve) bitwise, on two calls in a row whose second inp
 array keeps the first call's contents), on float64 and float32 plans; sizes above the array are
 rejected on the host; and the solve allocates nothing through torch either."""
 import ctypes
+import gc
 
 import numpy as np
 import pytest
@@ -48,11 +49,19 @@ def test_noalloc_matches_plan_solve_twice(td, prec):
     torch.cuda.synchronize()
     Xb = torch.full_like(Fb, float("nan"))
     Xs = torch.full_like(Fs, float("nan"))
-    before = torch.cuda.memory_allocated()
-    assert _noalloc(td, pb, Fb, Xb) == 0               # first call: the larger system
-    assert _noalloc(td, ps, Fs, Xs) == 0               # second call: smaller, other plan, same array
-    torch.cuda.synchronize()
-    assert torch.cuda.memory_allocated() == before
+    # unreachable objects of earlier tests (a plan in a reference cycle frees its memory when the
+    # collector runs) must not be collected inside the measured window
+    gc.collect()
+    gc.disable()
+    try:
+        before = torch.cuda.memory_allocated()
+        assert _noalloc(td, pb, Fb, Xb) == 0           # first call: the larger system
+        assert _noalloc(td, ps, Fs, Xs) == 0           # second call: smaller, other plan, same array
+        torch.cuda.synchronize()
+        after = torch.cuda.memory_allocated()
+    finally:
+        gc.enable()
+    assert after == before
     assert torch.equal(Xb, refb)
     assert torch.equal(Xs, refs)
     # and a smaller call on the same plan after the larger one
