@@ -689,4 +689,35 @@ hipError_t launch_transpose_scale(double* Dinv_t, double* alpha_t, const double*
   return hipGetLastError();
 }
 
+// dst[b] = src[b]^T for nblk consecutive Mp x Mp column-major blocks; the same 32 x 32 LDS tiles as
+// k_transpose_scale.  Grid: (tiles of the block, blocks).
+__global__ void __launch_bounds__(256) k_transpose_blocks(double* dst, const double* src, int Mp) {
+  __shared__ double tile[32][33];
+  const int64_t MM = (int64_t)Mp * Mp;
+  const double* s = src + (int64_t)blockIdx.y * MM;
+  double* d = dst + (int64_t)blockIdx.y * MM;
+  const int nt = (Mp + 31) / 32;
+  const int ti = blockIdx.x % nt, tj = blockIdx.x / nt;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int c = tj * 32 + ty + 8 * k, r = ti * 32 + tx;
+    if (r < Mp && c < Mp) tile[ty + 8 * k][tx] = s[r + (int64_t)c * Mp];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int cp = ti * 32 + ty + 8 * k, rp = tj * 32 + tx;
+    if (rp < Mp && cp < Mp) d[rp + (int64_t)cp * Mp] = tile[tx][ty + 8 * k];
+  }
+}
+
+hipError_t launch_transpose_blocks(double* dst, const double* src, int64_t nblk, int Mp, hipStream_t st) {
+  if (nblk == 0) return hipSuccess;
+  if (nblk > 65535) return hipErrorInvalidValue;
+  const int nt = (Mp + 31) / 32;
+  hipLaunchKernelGGL(k_transpose_blocks, dim3(nt * nt, (unsigned)nblk), dim3(256), 0, st, dst, src, Mp);
+  return hipGetLastError();
+}
+
 }  // namespace td

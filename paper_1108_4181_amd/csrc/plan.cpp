@@ -76,6 +76,7 @@ struct td_plan_s {
   double* red = nullptr;      // [At | Ct | Bt], each [p][Mp][Mp]
   double* G = nullptr;        // dichotomy rows of the inverse
   double* H = nullptr;        // [nodes][H^L | H^R]
+  double* chain_inv = nullptr;  // the tree's chain inverses and G_m, kept for the transposed plan's factor
   std::vector<Node> nodes;
   int depth = 0;
   int nchunks = 0;
@@ -320,7 +321,7 @@ int64_t default_subdomains(int64_t N, int64_t K) {
 // couplings): its compact inputs are transposed on the device from fwd's, and its subdomain block
 // inverses are the transposes of fwd's (no elimination of its own); the rest is factored as usual.
 void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C, hipStream_t st,
-                 const td_plan_s* fwd = nullptr) {
+                 const td_plan_s* fwd = nullptr, bool keep_chain = false) {
   const int64_t N = P->N, M = P->M, Mp = P->Mp, p = P->p;
   const int64_t MM = Mp * Mp;
   const auto& ks = P->ks;
@@ -620,126 +621,140 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
   int maxchain = 0;
   for (auto& n : nodes) maxchain = std::max(maxchain, std::max(n.m - n.l, n.r - n.m));
 
-  // left chains D^L_j = Ct_j - At_j alphaL_{j-1}, alphaL_j = (D^L_j)^{-1} Bt_j  (j = l..m-1)
-  // right chains D^R_j = Ct_j - Bt_j alphaR_{j+1}, alphaR_j = (D^R_j)^{-1} At_j (j = r..m+1)
-  for (int t = 0; t < maxchain; ++t) {
-    std::vector<BDesc> dd, da;
-    std::vector<int64_t> outoff;
-    std::vector<int32_t> tag;
-    std::vector<int64_t> woff;
-    for (int n = 0; n < nn; ++n) {
-      const Node& nd = nodes[n];
-      if (nd.m - nd.l > t) {
-        const int j = nd.l + t;
-        BDesc d = desc0();
-        d.kd = (int32_t)Mp; d.segrows = (int32_t)Mp;
-        d.a_off = oA + j * MM;
-        d.b_off = (t == 0) ? 0 : AL(n);
-        d.cin_off = oC + j * MM;
-        d.c_off = DWL(n);
-        dd.push_back(d);
-        BDesc e = desc0();
-        e.kd = (int32_t)Mp; e.segrows = (int32_t)Mp;
-        e.a_off = gslot(n, j);
-        e.b_off = oB + j * MM;
-        e.c_off = AL(n);
-        da.push_back(e);
-        woff.push_back(DWL(n));
-        outoff.push_back(gslot(n, j));
-        tag.push_back((int32_t)(N + j));
+  // The transposed system's tree has the same nodes, and its chain matrices and middle Schur
+  // complements are the transposes of this system's (D'^L_j = (D^L_j)^T by induction on
+  // Ct'_j - At'_j (D'^L_{j-1})^{-1} Bt'_{j-1} with At'_j = Bt_{j-1}^T, Bt'_j = At_{j+1}^T, Ct'_j = Ct_j^T;
+  // likewise D'^R_j and S'_m): a transposed plan whose forward plan kept them takes their inverses
+  // transposed, in one launch, instead of the chain eliminations.
+  const bool reuse_tree = fwd != nullptr && fwd->chain_inv != nullptr;
+  if (reuse_tree) {
+    HIPCHK(launch_transpose_blocks(P->G, fwd->chain_inv, goff / MM, (int)Mp, st));
+  } else {
+    // left chains D^L_j = Ct_j - At_j alphaL_{j-1}, alphaL_j = (D^L_j)^{-1} Bt_j  (j = l..m-1)
+    // right chains D^R_j = Ct_j - Bt_j alphaR_{j+1}, alphaR_j = (D^R_j)^{-1} At_j (j = r..m+1)
+    for (int t = 0; t < maxchain; ++t) {
+      std::vector<BDesc> dd, da;
+      std::vector<int64_t> outoff;
+      std::vector<int32_t> tag;
+      std::vector<int64_t> woff;
+      for (int n = 0; n < nn; ++n) {
+        const Node& nd = nodes[n];
+        if (nd.m - nd.l > t) {
+          const int j = nd.l + t;
+          BDesc d = desc0();
+          d.kd = (int32_t)Mp; d.segrows = (int32_t)Mp;
+          d.a_off = oA + j * MM;
+          d.b_off = (t == 0) ? 0 : AL(n);
+          d.cin_off = oC + j * MM;
+          d.c_off = DWL(n);
+          dd.push_back(d);
+          BDesc e = desc0();
+          e.kd = (int32_t)Mp; e.segrows = (int32_t)Mp;
+          e.a_off = gslot(n, j);
+          e.b_off = oB + j * MM;
+          e.c_off = AL(n);
+          da.push_back(e);
+          woff.push_back(DWL(n));
+          outoff.push_back(gslot(n, j));
+          tag.push_back((int32_t)(N + j));
+        }
+        if (nd.r - nd.m > t) {
+          const int j = nd.r - t;
+          BDesc d = desc0();
+          d.kd = (int32_t)Mp; d.segrows = (int32_t)Mp;
+          d.a_off = oB + j * MM;
+          d.b_off = (t == 0) ? 0 : AR(n);
+          d.cin_off = oC + j * MM;
+          d.c_off = DWR(n);
+          dd.push_back(d);
+          BDesc e = desc0();
+          e.kd = (int32_t)Mp; e.segrows = (int32_t)Mp;
+          e.a_off = gslot(n, j);
+          e.b_off = oA + j * MM;
+          e.c_off = AR(n);
+          da.push_back(e);
+          woff.push_back(DWR(n));
+          outoff.push_back(gslot(n, j));
+          tag.push_back((int32_t)(N + j));
+        }
       }
-      if (nd.r - nd.m > t) {
-        const int j = nd.r - t;
-        BDesc d = desc0();
-        d.kd = (int32_t)Mp; d.segrows = (int32_t)Mp;
-        d.a_off = oB + j * MM;
-        d.b_off = (t == 0) ? 0 : AR(n);
-        d.cin_off = oC + j * MM;
-        d.c_off = DWR(n);
-        dd.push_back(d);
-        BDesc e = desc0();
-        e.kd = (int32_t)Mp; e.segrows = (int32_t)Mp;
-        e.a_off = gslot(n, j);
-        e.b_off = oA + j * MM;
-        e.c_off = AR(n);
-        da.push_back(e);
-        woff.push_back(DWR(n));
-        outoff.push_back(gslot(n, j));
-        tag.push_back((int32_t)(N + j));
+      BArgs a = bargs_base((int)Mp);
+      a.A = P->red; a.lda = Mp;
+      a.B = Da; a.ldb = Mp;
+      a.Cin = P->red; a.ldcin = Mp;
+      a.C = Da; a.ldc = Mp;
+      a.alpha = -1.0;
+      a.ncols = (int32_t)Mp;
+      run_bgemm(a, dd, pool, st);
+      // invert the chain matrices in place in the arena (one launch for all nodes)
+      const int nm = (int)woff.size();
+      if (nm > 0) {
+        GJArgs g{};
+        g.work = Da; g.work_off = pool.put_vec(woff); g.wstride = 0;
+        g.out = P->G; g.out_off = pool.put_vec(outoff);
+        g.alpha = nullptr; g.bdiag = nullptr; g.bd_off = nullptr;
+        g.tag = pool.put_vec(tag); g.bad = bad;
+        g.nmat = nm; g.Mp = (int32_t)Mp;
+        gj_scratch(g);
+        HIPCHK(launch_gj(g, st));
       }
+      BArgs b = bargs_base((int)Mp);
+      b.A = P->G; b.lda = Mp;
+      b.B = P->red; b.ldb = Mp;
+      b.C = Da; b.ldc = Mp;
+      b.ncols = (int32_t)Mp;
+      run_bgemm(b, da, pool, st);
     }
-    BArgs a = bargs_base((int)Mp);
-    a.A = P->red; a.lda = Mp;
-    a.B = Da; a.ldb = Mp;
-    a.Cin = P->red; a.ldcin = Mp;
-    a.C = Da; a.ldc = Mp;
-    a.alpha = -1.0;
-    a.ncols = (int32_t)Mp;
-    run_bgemm(a, dd, pool, st);
-    // invert the chain matrices in place in the arena (one launch for all nodes)
-    const int nm = (int)woff.size();
-    if (nm > 0) {
+    // S_m = Ct_m - At_m alphaL_{m-1} - Bt_m alphaR_{m+1};  G_m = S_m^{-1}
+    {
+      std::vector<BDesc> d1, d2;
+      std::vector<int64_t> outoff;
+      std::vector<int32_t> tag;
+      for (int n = 0; n < nn; ++n) {
+        const Node& nd = nodes[n];
+        BDesc d = desc0();
+        d.kd = (int32_t)Mp; d.segrows = (int32_t)Mp;
+        d.a_off = oA + nd.m * MM;
+        d.b_off = (nd.m > nd.l) ? AL(n) : 0;
+        d.cin_off = oC + nd.m * MM;
+        d.c_off = DWL(n);
+        d1.push_back(d);
+        BDesc e = desc0();
+        e.kd = (int32_t)Mp; e.segrows = (int32_t)Mp;
+        e.a_off = oB + nd.m * MM;
+        e.b_off = (nd.r > nd.m) ? AR(n) : 0;
+        e.cin_off = DWL(n);
+        e.c_off = DWL(n);
+        d2.push_back(e);
+        outoff.push_back(gslot(n, nd.m));
+        tag.push_back((int32_t)(N + nd.m));
+      }
+      BArgs a = bargs_base((int)Mp);
+      a.A = P->red; a.lda = Mp;
+      a.B = Da; a.ldb = Mp;
+      a.Cin = P->red; a.ldcin = Mp;
+      a.C = Da; a.ldc = Mp;
+      a.alpha = -1.0;
+      a.ncols = (int32_t)Mp;
+      run_bgemm(a, d1, pool, st);
+      BArgs a2 = a;
+      a2.Cin = Da;
+      run_bgemm(a2, d2, pool, st);
+      std::vector<int64_t> woff;
+      for (int n = 0; n < nn; ++n) woff.push_back(DWL(n));
       GJArgs g{};
       g.work = Da; g.work_off = pool.put_vec(woff); g.wstride = 0;
       g.out = P->G; g.out_off = pool.put_vec(outoff);
       g.alpha = nullptr; g.bdiag = nullptr; g.bd_off = nullptr;
       g.tag = pool.put_vec(tag); g.bad = bad;
-      g.nmat = nm; g.Mp = (int32_t)Mp;
+      g.nmat = nn; g.Mp = (int32_t)Mp;
       gj_scratch(g);
       HIPCHK(launch_gj(g, st));
     }
-    BArgs b = bargs_base((int)Mp);
-    b.A = P->G; b.lda = Mp;
-    b.B = P->red; b.ldb = Mp;
-    b.C = Da; b.ldc = Mp;
-    b.ncols = (int32_t)Mp;
-    run_bgemm(b, da, pool, st);
-  }
-  // S_m = Ct_m - At_m alphaL_{m-1} - Bt_m alphaR_{m+1};  G_m = S_m^{-1}
-  {
-    std::vector<BDesc> d1, d2;
-    std::vector<int64_t> outoff;
-    std::vector<int32_t> tag;
-    for (int n = 0; n < nn; ++n) {
-      const Node& nd = nodes[n];
-      BDesc d = desc0();
-      d.kd = (int32_t)Mp; d.segrows = (int32_t)Mp;
-      d.a_off = oA + nd.m * MM;
-      d.b_off = (nd.m > nd.l) ? AL(n) : 0;
-      d.cin_off = oC + nd.m * MM;
-      d.c_off = DWL(n);
-      d1.push_back(d);
-      BDesc e = desc0();
-      e.kd = (int32_t)Mp; e.segrows = (int32_t)Mp;
-      e.a_off = oB + nd.m * MM;
-      e.b_off = (nd.r > nd.m) ? AR(n) : 0;
-      e.cin_off = DWL(n);
-      e.c_off = DWL(n);
-      d2.push_back(e);
-      outoff.push_back(gslot(n, nd.m));
-      tag.push_back((int32_t)(N + nd.m));
+    if (keep_chain && !P->dense) {   // the inverses in G are overwritten by the rows G_j below
+      P->chain_inv = P->alloc(goff);
+      HIPCHK(hipMemcpyAsync(P->chain_inv, P->G, (size_t)goff * sizeof(double), hipMemcpyDeviceToDevice, st));
     }
-    BArgs a = bargs_base((int)Mp);
-    a.A = P->red; a.lda = Mp;
-    a.B = Da; a.ldb = Mp;
-    a.Cin = P->red; a.ldcin = Mp;
-    a.C = Da; a.ldc = Mp;
-    a.alpha = -1.0;
-    a.ncols = (int32_t)Mp;
-    run_bgemm(a, d1, pool, st);
-    BArgs a2 = a;
-    a2.Cin = Da;
-    run_bgemm(a2, d2, pool, st);
-    std::vector<int64_t> woff;
-    for (int n = 0; n < nn; ++n) woff.push_back(DWL(n));
-    GJArgs g{};
-    g.work = Da; g.work_off = pool.put_vec(woff); g.wstride = 0;
-    g.out = P->G; g.out_off = pool.put_vec(outoff);
-    g.alpha = nullptr; g.bdiag = nullptr; g.bd_off = nullptr;
-    g.tag = pool.put_vec(tag); g.bad = bad;
-    g.nmat = nn; g.Mp = (int32_t)Mp;
-    gj_scratch(g);
-    HIPCHK(launch_gj(g, st));
   }
   // G_j = G_{j+1} At_{j+1} (D^L_j)^{-1} for j < m;  G_j = G_{j-1} Bt_{j-1} (D^R_j)^{-1} for j > m
   for (int t = 0; t < maxchain; ++t) {
@@ -1563,7 +1578,7 @@ td_status factor_top(const td_desc* d, const double* A, const double* B, const d
     if (P->scalar)
       factor_scalar(P, A, B, C, st);
     else
-      factor_impl(P, A, B, C, st);
+      factor_impl(P, A, B, C, st, nullptr, d->adjoint && allow_adjoint);
     if (d->adjoint && allow_adjoint && !P->dense && !P->scalar) {
       // the transposed plan from this one's compact inputs and block inverses (before the rounded
       // copies of a low-precision plan release them)
@@ -1580,6 +1595,9 @@ td_status factor_top(const td_desc* d, const double* A, const double* B, const d
         delete Q;
         throw;
       }
+      HIPCHK(hipStreamSynchronize(st));
+      P->release(P->chain_inv);
+      P->chain_inv = nullptr;
       Q->last_stream = st;
       P->adj = Q;
     }
