@@ -34,9 +34,9 @@ KERNEL_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     # (kernel, workload): (source set, source hash (kernel_source_hash), read bytes, write bytes)
-    ("sweep", "mixed_n4096_m512_k1024"): ("f64", "7ad1eb38ee72c5e7", 53.7926e9, 32.7995e9),
-    ("superposition", "mixed_n4096_m512_k1024"): ("f64", "7ad1eb38ee72c5e7", 50.5180e9, 16.6430e9),
-    ("scalar_subtrees", "scalar_n65536_k1024"): ("scalar", "9223c77be2e66006", 0.55352e9, 0.53687e9),
+    ("sweep", "mixed_n4096_m512_k1024"): ("f64", "f1595a750c058cf2", 53.5337e9, 32.7995e9),
+    ("superposition", "mixed_n4096_m512_k1024"): ("f64", "f1595a750c058cf2", 50.5535e9, 16.6430e9),
+    ("scalar_subtrees", "scalar_n65536_k1024"): ("scalar", "e3ad9b92c4b952a1", 0.55325e9, 0.53687e9),
 }
 
 
@@ -130,6 +130,7 @@ def cpu_baseline(w, rows, cols, cols_1t, threads):
     t0 = time.perf_counter()
     fac.solve(F)
     ts = time.perf_counter() - t0
+    print(f"bench: oracle sample on {threads} threads {ts:.1f} s", file=sys.stderr, flush=True)
     fac.threads = 1
     F1 = np.ascontiguousarray(F[:cols_1t])
     t0 = time.perf_counter()
@@ -455,6 +456,11 @@ def bench_paper(args):
     print(json.dumps(out))
 
 
+def progress(msg):
+    """One line per finished stage on stderr, so that a long run shows that it is alive."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -530,6 +536,7 @@ def main():
     torch.cuda.synchronize()
     factor_ms = (time.perf_counter() - t0) * 1e3
     pinfo = plan.plan_info()
+    progress(f"factor {factor_ms:.1f} ms")
 
     _, info = plan.solve(F, X, info=True)
     # timed: plain solves, as a caller runs them (the library replays a captured HIP graph)
@@ -554,6 +561,7 @@ def main():
     eager_ms = (time.perf_counter() - t0) * 1e3 / n_prof
     stages = plan.stage_times()
     plan.set_profiling(False)
+    progress(f"float64 solves timed: {ms_per_step:.2f} ms per step")
 
     work = algorithmic_work(N, M, K, p)
     scalar = M == 1 and p == N
@@ -680,12 +688,14 @@ def main():
         mplan.close()
         del mplan
         plan = None
+        progress(f"{prec} + refinement timed: {mms:.2f} ms per step")
     out["mixed_refined"] = mixed
     if not args.no_cpu_baseline:
         import oracle
 
         # the scalar system's oracle (the Thomas algorithm) solves every row of the sample quickly
         rows = 0 if M == 1 else args.cpu_rows
+        progress("oracle sample on the host")
         out["cpu_baseline"] = cpu_baseline(w, rows, args.cpu_cols, args.cpu_cols_1t, oracle.default_threads())
     print(json.dumps(out))
 
