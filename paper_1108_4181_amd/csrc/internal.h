@@ -127,8 +127,10 @@ struct GJArgs {
   const int64_t* bd_off;
   const int32_t* tag;    // block label reported on a singular pivot
   int32_t* bad;          // atomic min of the labels of singular matrices
-  int32_t* piv;          // optional scratch, nmat x Mp: pivot rows (block sizes multiples of 64 from 128
-  double* nrm;           // take the one-launch-per-panel path when given); nrm: nmat infinity norms
+  // scratch of the one-launch-per-panel path (block sizes that are multiples of 64 from 128):
+  int32_t* piv;          // nmat x Mp pivot rows
+  double* pmin;          // nmat smallest pivot magnitudes so far (NaN once a pivot is NaN)
+  double* part;          // nmat x (Mp / 32) x Mp partial row sums of the matrices' magnitudes
   int32_t nmat, Mp;
 };
 

@@ -304,13 +304,15 @@ __global__ void __launch_bounds__(NT) k_gj(GJArgs g) {
 // by the reciprocal pivot once after the panel (its column-j entry is kept as 1 until then), and every
 // row takes the same single fused multiply-add per entry and column.  Every lane divides by its own
 // entry while the arg-max runs, so the reciprocal is ready when its lane wins.  The pivot row of
-// column j goes to prow[j] (written by thread 0).  cand holds [2][8][NB] rows, cv [2][8] magnitudes
-// and, from cv[32], [2][8] reciprocals, ci [2][8] rows.
+// column j goes to prow[j] (written by thread 0).  Returns the smallest pivot magnitude of the panel
+// (NaN if a pivot was NaN; the caller tests it against the tolerance).  cand holds [2][8][NB] rows,
+// cv [2][8] magnitudes and, from cv[32], [2][8] reciprocals, ci [2][8] rows.
 template <int NB>
-__device__ __forceinline__ void gj_panel(double (&v)[NB], bool& used, bool& singular, double tol, double* cand,
-                                         double* cv, int* ci, int* prow, int nw) {
+__device__ __forceinline__ double gj_panel(double (&v)[NB], bool& used, double* cand, double* cv, int* ci, int* prow,
+                                           int nw) {
   const int tid = threadIdx.x, L = tid & 63, w = tid >> 6;
   double sr = 1.0;   // deferred scale of this thread's row (the reciprocal pivot if it was chosen)
+  double pm = INFINITY;   // smallest pivot magnitude of the panel; NaN once a pivot is NaN
 #pragma unroll 1
   for (int j = 0; j < NB; ++j) {
     const int slot = j & 1;
@@ -339,7 +341,8 @@ __device__ __forceinline__ void gj_panel(double (&v)[NB], bool& used, bool& sing
 #pragma unroll
     for (int jj = 0; jj < NB; ++jj) prv[jj] = pr[jj];
     const double ipv = cv[32 + slot * 8 + wr];
-    if (!(fabs(prv[0]) > tol)) singular = true;
+    const double apv = fabs(prv[0]);
+    pm = (pm != pm) ? pm : ((apv != apv) ? apv : fmin(pm, apv));
     const bool piv = (tid == r);
     const double f = piv ? 0.0 : vj * ipv;   // v <- v - v_j * (pivot row / pivot), column j <- -v_j / pivot
 #pragma unroll
@@ -351,6 +354,7 @@ __device__ __forceinline__ void gj_panel(double (&v)[NB], bool& used, bool& sing
   }
 #pragma unroll
   for (int jj = 0; jj < NB; ++jj) v[jj] *= sr;
+  return pm;
 }
 
 // Gauss-Jordan inversion with one launch per panel, for block sizes that are multiples of 64 from 128:
@@ -359,20 +363,24 @@ __device__ __forceinline__ void gj_panel(double (&v)[NB], bool& used, bool& sing
 // column c becomes c + (Z - E_R) c_R, where Z holds the columns of S after their elimination (in place,
 // so Z is what the previous launch stored in panel k's columns) and c_R the entries of c in rows R
 // before it.  So in launch k every tile other than panel k applies panel k's transform to its own
-// columns (a rank-NB product on MFMA), and the work-group of tile k + 1 then eliminates that panel
-// (gj_panel, one row per thread).  Launch -1 only eliminates panel 0 and stores the infinity norm.
-// (An earlier form inverted each matrix in one work-group and one launch; at block size 512 a matrix
-// then took 6.4 ms, most of it the passes of one work-group's update over the 2 MB matrix.)
-// The pivot rows of every panel go to g.piv; k_gj_readout applies the permutation.  A matrix thus has
-// Mp / NB work-groups in flight instead of one, and the update of a panel no longer waits behind the
-// elimination of the next.
+// columns (a rank-NB product on MFMA), and the matrix's lead work-group updates tile k + 1 the same
+// way and then eliminates that panel (gj_panel, one row per thread).  Launch -1 eliminates panel 0
+// while the other tiles store their partial row sums of the matrix (for the infinity norm); every
+// panel keeps the smallest pivot magnitude so far in g.pmin.  In the last launch every tile writes its
+// final columns through the pivot permutation into the inverse (inverse[r][piv[j]] = S[piv[r]][j] for
+// the eliminated matrix S; alpha = inverse * diag(bdiag) when requested), and the lead work-group
+// writes the last panel and marks the matrix singular when a pivot was not above 1e-14 times the
+// infinity norm (or NaN).  A matrix thus has Mp / NB work-groups in flight instead of one, and the
+// update of a panel no longer waits behind the elimination of the next.  (An earlier form inverted
+// each matrix in one work-group and one launch; at block size 512 a matrix then took 6.4 ms, most of
+// it the passes of one work-group's update over the 2 MB matrix.)
 template <int NB, int NT>
 __global__ void __launch_bounds__(NT) k_gj_step(GJArgs g, int k) {
   constexpr int RT = 4;                    // 64 rows per wave
   constexpr int CTN = NB / 4;              // 4-column output tiles per tile
   extern __shared__ double sm[];
   const int Mp = g.Mp;                     // a multiple of 64, blockDim.x == Mp
-  double* Ts = sm;                         // [NB][Mp]: the updated panel (panel work-group)
+  double* Ts = sm;                         // [NB][Mp]: a tile's columns (panel or read-out)
   double* Bs = Ts + NB * Mp;               // [NB][NB]: rows R_k of the tile's columns
   double* cand = Bs + NB * NB;             // [2][8][NB]: candidate pivot rows of the waves
   double* cv = cand + 2 * 8 * NB;          // [2][8]: their magnitudes; [16 .. 23]: row-sum maxima;
@@ -380,19 +388,21 @@ __global__ void __launch_bounds__(NT) k_gj_step(GJArgs g, int k) {
   int* ci = (int*)(cv + 48);               // [2][8]: their rows
   int* pl = ci + 16;                       // [NB]: pivot rows of the panel eliminated here
   int* rk = pl + NB;                       // [NB]: pivot rows of panel k
-  int* usedf = rk + NB;                    // [Mp]: rows that were pivots of earlier panels
+  int* ri = rk + NB;                       // [Mp]: rows used as pivots (panel), pivot rows (read-out)
   const int tid = threadIdx.x, L = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
   const int ntile = Mp / NB;
-  // Work-groups [0, nmat8) eliminate the next panel of matrix blockIdx.x, so they are dispatched
-  // before any update; update work-group t = blockIdx.x - nmat8 takes tile t/8 % ntile of matrix
+  const bool last = (k == ntile - 1);
+  // Work-groups [0, nmat8) are the lead work-groups of matrix blockIdx.x, dispatched before any
+  // update; update work-group t = blockIdx.x - nmat8 takes tile t/8 % ntile of matrix
   // t % 8 + 8 (t/8 / ntile): work-groups go to the eight XCDs in turn, so every work-group of a matrix
-  // runs on the XCD of its panel work-group and reads panel k from that XCD's L2.
+  // runs on the XCD of its lead work-group and reads panel k from that XCD's L2.
   const int nmat8 = (g.nmat + 7) & ~7;
   int q, c;
-  if ((int)blockIdx.x < nmat8) {
+  const bool lead = (int)blockIdx.x < nmat8;
+  if (lead) {
     q = blockIdx.x;
-    c = k + 1;
-    if (q >= g.nmat || c >= ntile) return;
+    c = last ? k : k + 1;
+    if (q >= g.nmat) return;
   } else {
     const int t = blockIdx.x - nmat8, i = t >> 3;
     q = (t & 7) + 8 * (i / ntile);
@@ -401,11 +411,25 @@ __global__ void __launch_bounds__(NT) k_gj_step(GJArgs g, int k) {
   }
   double* W = g.work + (g.work_off ? g.work_off[q] : q * g.wstride);
   int* piv = g.piv + (int64_t)q * Mp;
+  double* part = g.part + (int64_t)q * ntile * Mp;   // [ntile][Mp]: partial row sums of |matrix|
   const int c0 = c * NB;
   const int rb = w * 16 * RT;
-  const bool panel = (c == k + 1);
 
-  if (k >= 0) {
+  if (k < 0 && !lead) {   // the tile's share of the row sums of the original matrix
+    double rs = 0.0;
+#pragma unroll
+    for (int j0 = 0; j0 < NB; j0 += 8) {
+      double t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = W[tid + (int64_t)(c0 + j0 + u) * Mp];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) rs += fabs(t[u]);
+    }
+    part[(int64_t)c * Mp + tid] = rs;
+    return;
+  }
+
+  if (k >= 0 && !(last && lead)) {
     if (tid < NB) rk[tid] = piv[k * NB + tid];
     __syncthreads();
     for (int e = tid; e < NB * NB; e += blockDim.x) {   // a row of R_k per column: one column's rows per pass
@@ -441,7 +465,7 @@ __global__ void __launch_bounds__(NT) k_gj_step(GJArgs g, int k) {
 #pragma unroll
         for (int ct = 0; ct < CTN; ++ct) acc[t][ct] = mfma4(a[k4][t], b[ct], acc[t][ct]);
     }
-    if (!panel) {
+    if (!lead && !last) {
 #pragma unroll
       for (int t = 0; t < RT; ++t)
 #pragma unroll
@@ -454,79 +478,60 @@ __global__ void __launch_bounds__(NT) k_gj_step(GJArgs g, int k) {
 #pragma unroll
       for (int ct = 0; ct < CTN; ++ct) Ts[(4 * ct + out_col(L)) * Mp + rb + 16 * t + out_row(L)] = acc[t][ct];
   }
-  if (!panel) return;
 
-  // the panel work-group: tolerance, rows already used as pivots, then the elimination
-  double norm;
-  if (k < 0) {
-    double rs = 0.0;
-#pragma unroll 1
-    for (int c8 = 0; c8 < Mp; c8 += 8) {
-      double t[8];
+  if (last) {
+    if (lead) {   // the last panel (final since the previous launch), and the singularity test
 #pragma unroll
-      for (int u = 0; u < 8; ++u) t[u] = W[tid + (int64_t)(c8 + u) * Mp];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) rs += fabs(t[u]);
+      for (int jj = 0; jj < NB; ++jj) Ts[jj * Mp + tid] = W[tid + (int64_t)(c0 + jj) * Mp];
+      double rs = 0.0;
+      for (int cc = 0; cc < ntile; ++cc) rs += part[(int64_t)cc * Mp + tid];
+      for (int off = 32; off > 0; off >>= 1) rs = fmax(rs, __shfl_xor(rs, off));
+      if (L == 0) cv[16 + w] = rs;
     }
-    for (int off = 32; off > 0; off >>= 1) rs = fmax(rs, __shfl_xor(rs, off));
-    if (L == 0) cv[16 + w] = rs;
-    __syncthreads();
-    norm = 0.0;
-    for (int u = 0; u < nw; ++u) norm = fmax(norm, cv[16 + u]);
-    if (tid == 0) g.nrm[q] = norm;
-  } else {
-    norm = g.nrm[q];
+    ri[tid] = piv[tid];
+    __syncthreads();   // Ts, the pivot rows and the row-sum maxima complete
+    if (lead && tid == 0) {
+      double norm = 0.0;
+      for (int u = 0; u < nw; ++u) norm = fmax(norm, cv[16 + u]);
+      if (!(g.pmin[q] > 1e-14 * norm)) atomicMin(g.bad, g.tag[q]);
+    }
+    double* out = g.out + g.out_off[q];
+    double* al = g.alpha ? g.alpha + g.out_off[q] : nullptr;
+    const double* bd = g.alpha ? g.bdiag + g.bd_off[q] : nullptr;
+    const int prow_t = ri[tid];
+#pragma unroll 8
+    for (int jj = 0; jj < NB; ++jj) {
+      const int oc = ri[c0 + jj];
+      const double v = Ts[jj * Mp + prow_t];
+      out[tid + (int64_t)oc * Mp] = v;
+      if (al) al[tid + (int64_t)oc * Mp] = v * bd[oc];
+    }
+    return;
   }
-  usedf[tid] = 0;
+
+  // the lead work-group of launch k < ntile - 1: rows already used as pivots, then the elimination
+  ri[tid] = 0;
   __syncthreads();   // also orders the Ts stores above before the reads below
-  for (int i = tid; i < c0; i += blockDim.x) usedf[piv[i]] = 1;
+  for (int i = tid; i < c0; i += blockDim.x) ri[piv[i]] = 1;
   __syncthreads();
-  bool used = usedf[tid] != 0;
-  bool singular = false;
+  bool used = ri[tid] != 0;
   double v[NB];
 #pragma unroll
   for (int jj = 0; jj < NB; ++jj) v[jj] = (k < 0) ? W[tid + (int64_t)jj * Mp] : Ts[jj * Mp + tid];
-  gj_panel<NB>(v, used, singular, 1e-14 * norm, cand, cv, ci, pl, nw);
+  if (k < 0) {   // tile 0's share of the row sums, from the original values
+    double rs = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < NB; ++jj) rs += fabs(v[jj]);
+    part[tid] = rs;
+  }
+  const double pm = gj_panel<NB>(v, used, cand, cv, ci, pl, nw);
 #pragma unroll
   for (int jj = 0; jj < NB; ++jj) W[tid + (int64_t)(c0 + jj) * Mp] = v[jj];
   __syncthreads();
   if (tid < NB) piv[c0 + tid] = pl[tid];
-  if (tid == 0 && singular) atomicMin(g.bad, g.tag[q]);
-}
-
-// Read-out after k_gj_step: inverse[c][piv[c']] = S[piv[c]][c'] for the eliminated matrix S, and
-// alpha = inverse * diag(bdiag) when requested.  One work-group per (matrix, chunk of Mp / nchunk
-// columns), thread i writes row i.
-template <int NT>
-__global__ void __launch_bounds__(NT) k_gj_readout(GJArgs g, int nchunk) {
-  __shared__ int invpiv[NT];
-  const int q = blockIdx.x / nchunk, ch = blockIdx.x - q * nchunk;
-  if (q >= g.nmat) return;
-  const int Mp = g.Mp, tid = threadIdx.x;
-  const int* piv = g.piv + (int64_t)q * Mp;
-  const int prow_t = piv[tid];
-  invpiv[prow_t] = tid;
-  __syncthreads();
-  const double* W = g.work + (g.work_off ? g.work_off[q] : q * g.wstride);
-  double* out = g.out + g.out_off[q];
-  double* al = g.alpha ? g.alpha + g.out_off[q] : nullptr;
-  const double* bd = g.alpha ? g.bdiag + g.bd_off[q] : nullptr;
-  const int cw = Mp / nchunk;
-#pragma unroll 1
-  for (int oc0 = ch * cw; oc0 < (ch + 1) * cw; oc0 += 8) {
-    double t[8], b[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) t[u] = W[prow_t + (int64_t)invpiv[oc0 + u] * Mp];
-    if (al) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) b[u] = bd[oc0 + u];
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) out[tid + (int64_t)(oc0 + u) * Mp] = t[u];
-    if (al) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) al[tid + (int64_t)(oc0 + u) * Mp] = t[u] * b[u];
-    }
+  if (tid == 0) {
+    const double o = (k < 0) ? INFINITY : g.pmin[q];
+    g.pmin[q] = (o != o) ? o : ((pm != pm) ? pm : fmin(o, pm));
   }
 }
 
@@ -539,11 +544,8 @@ static hipError_t launch_gj_split(const GJArgs& g, hipStream_t st) {
                                      (int)lds);
   if (e != hipSuccess) return e;
   const int nmat8 = grid_pad8(g.nmat);
-  hipLaunchKernelGGL((k_gj_step<NB, NT>), dim3(nmat8), dim3(Mp), lds, st, g, -1);
-  for (int k = 0; k < ntile; ++k)
+  for (int k = -1; k < ntile; ++k)
     hipLaunchKernelGGL((k_gj_step<NB, NT>), dim3(nmat8 * (1 + ntile)), dim3(Mp), lds, st, g, k);
-  const int nchunk = Mp / 64;
-  hipLaunchKernelGGL((k_gj_readout<NT>), dim3(g.nmat * nchunk), dim3(Mp), 0, st, g, nchunk);
   return hipGetLastError();
 }
 
@@ -576,7 +578,7 @@ hipError_t launch_gj(const GJArgs& g, hipStream_t st) {
   // block sizes that are multiples of 64 from 128 (every padded size above 256 is one): one launch
   // per 32-column panel, with the caller's scratch for pivot rows and norms
   if (g.Mp % 64 == 0 && g.Mp >= 128) {
-    if (!g.piv || !g.nrm) return hipErrorInvalidValue;
+    if (!g.piv || !g.pmin || !g.part) return hipErrorInvalidValue;
     return g.Mp <= 256 ? launch_gj_split<32, 256>(g, st) : launch_gj_split<32, 512>(g, st);
   }
   if (g.Mp > 256) return hipErrorInvalidValue;

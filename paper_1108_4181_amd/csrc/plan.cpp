@@ -371,13 +371,15 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
   double* Ga = P->alloc((1 + N) * MM);
   HIPCHK(launch_identity(Ga, (int)Mp, st));
   double* Dwork = P->alloc(p * MM);
-  // Gauss-Jordan scratch: pivot rows and norms of up to 2p matrices per launch (the tree's chain
-  // steps invert a left and a right chain matrix of each of its p nodes)
-  double* gjs = P->alloc(p * Mp + 2 * p);
+  // Gauss-Jordan scratch for up to 2p matrices per launch (the tree's chain steps invert a left and
+  // a right chain matrix of each of its p nodes): pivot rows, smallest pivots, partial row sums
+  const int64_t gj_part = (Mp + 31) / 32 * Mp;
+  double* gjs = P->alloc(p * Mp + 2 * p + 2 * p * gj_part);
   auto gj_scratch = [&](GJArgs& g) {
     if (g.nmat > 2 * p) throw std::string("internal error: Gauss-Jordan scratch too small");
     g.piv = reinterpret_cast<int32_t*>(gjs);
-    g.nrm = gjs + p * Mp;
+    g.pmin = gjs + p * Mp;
+    g.part = gjs + p * Mp + 2 * p;
   };
 
   int32_t* bad = P->d_flag;
@@ -1516,7 +1518,8 @@ int64_t factor_bytes(int64_t N, int64_t M, int64_t p, int fA, int fB, int fC, in
   b += (fA == TD_FMT_DIAG ? N * M : N * M * M) + (fB == TD_FMT_DIAG ? N * M : N * M * M);
   b += (fC == TD_FMT_TRIDIAG ? 3 * N * M : N * M * M) + 2 * N * Mp;
   b += N * MM * 2 + (2 + 2 * N) * MM;     // Dinv, alpha, UV
-  b += (1 + N) * MM + p * MM + p * Mp + 2 * p;   // Gamma arena, Dwork, Gauss-Jordan scratch (temporary)
+  b += (1 + N) * MM + p * MM + p * Mp + 2 * p + 2 * p * ((Mp + 31) / 32) * Mp;   // Gamma arena, Dwork,
+                                                                                // Gauss-Jordan scratch (temporary)
   b += 3 * p * MM + p * (depth + 1) * MM + 2 * p * MM + (1 + 6 * p) * MM + p * MM;  // reduced, G, H, arenas
   if (prec != TD_PREC_F64) b += (4 * N * MM * (prec == TD_PREC_F32 ? 4 : 2) + 7) / 8;  // rounded copies
   if (fA == TD_FMT_DENSE || fB == TD_FMT_DENSE) b += 3 * N * MM;                     // [A|B] blocks, E

@@ -212,7 +212,8 @@ def _pivoting_system(N, M, seed):
 @pytest.mark.parametrize("M", [64, 128, 256, 320, 512])
 def test_row_interchanges_in_block_inverses(td, M):
     """Every diagonal block of the elimination needs row interchanges (Gauss-Jordan with partial
-    pivoting inside each block), at block sizes handled by the candidate-row Gauss-Jordan kernel."""
+    pivoting inside each block), at the block sizes of the one-launch-per-panel Gauss-Jordan kernel
+    (multiples of 64 from 128) and below it."""
     N, K, p = 9, 6, 3
     sys = _pivoting_system(N, M, 700 + M)
     F = synth.rhs_columns(700 + M, N, M, range(K))
@@ -220,10 +221,22 @@ def test_row_interchanges_in_block_inverses(td, M):
     assert rel_err(X, oracle.solve(sys, F)) < 1e-11
 
 
+@pytest.mark.parametrize("M", [128, 256, 512])
+def test_nan_input_reported_large(td, M):
+    """A NaN on the diagonal of a subdomain's C block, in the last panel of the per-panel
+    Gauss-Jordan kernel: the factor reports TD_ESINGULAR (a NaN pivot candidate ranks first)."""
+    sys = synth.varcoef_system(12, M, seed=40 + M)
+    C = sys.C.copy()
+    C[8, 1, M - 3] = np.nan        # row M - 3 of block row 8 (tridiagonal format: sub, diag, super)
+    with pytest.raises(td.TridiagError) as e:
+        td.Plan.from_system(synth.System(12, M, sys.A, sys.B, C), subdomains=2)
+    assert e.value.code == 3
+
+
 @pytest.mark.parametrize("M", [64, 256, 512])
 def test_singular_block_large(td, M):
-    """A zero C block that opens a subdomain: TD_ESINGULAR with its block row, at block sizes of the
-    candidate-row Gauss-Jordan kernel."""
+    """A zero C block that opens a subdomain: TD_ESINGULAR with its block row, at block sizes of both
+    Gauss-Jordan kernels."""
     sys = synth.varcoef_system(12, M, seed=20 + M)
     C = sys.C.copy()
     C[7] = 0.0                     # p = 2: interface rows 0 and 6, row 7 opens subdomain 1
