@@ -34,9 +34,9 @@ KERNEL_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     # (kernel, workload): (source set, source hash (kernel_source_hash), read bytes, write bytes)
-    ("sweep", "mixed_n4096_m512_k1024"): ("f64", "f1595a750c058cf2", 53.5337e9, 32.7995e9),
-    ("superposition", "mixed_n4096_m512_k1024"): ("f64", "f1595a750c058cf2", 50.5535e9, 16.6430e9),
-    ("scalar_subtrees", "scalar_n65536_k1024"): ("scalar", "e3ad9b92c4b952a1", 0.55325e9, 0.53687e9),
+    ("sweep", "mixed_n4096_m512_k1024"): ("f64", "6a15218ec1bdd946", 53.6718e9, 32.7995e9),
+    ("superposition", "mixed_n4096_m512_k1024"): ("f64", "6a15218ec1bdd946", 50.5253e9, 16.6430e9),
+    ("scalar_subtrees", "scalar_n65536_k1024"): ("scalar", "861f5edd6f153670", 0.55352e9, 0.53687e9),
 }
 
 
