@@ -211,7 +211,7 @@ hipError_t launch_transpose_inputs(double* At, double* Bt, double* Ct, const dou
 // Dinv_t[row] = Dinv[row]^T, alpha_t[row] = Dinv_t[row] diag(bdiag_t[row])
 hipError_t launch_transpose_scale(double* Dinv_t, double* alpha_t, const double* Dinv, const double* bdiag_t,
                                   const int64_t* rows, int nrows, int Mp, hipStream_t st);
-// dst[b] = src[b]^T for nblk consecutive Mp x Mp blocks (nblk <= 65535)
+// dst[b] = src[b]^T for nblk consecutive Mp x Mp blocks
 hipError_t launch_transpose_blocks(double* dst, const double* src, int64_t nblk, int Mp, hipStream_t st);
 int bgemm_coltile(int ncols);    // columns per work-group chosen for ncols
 int sweep_coltile(int Mp, int K);

@@ -684,11 +684,15 @@ __global__ void __launch_bounds__(256) k_transpose_scale(double* Dinv_t, double*
 
 hipError_t launch_transpose_scale(double* Dinv_t, double* alpha_t, const double* Dinv, const double* bdiag_t,
                                   const int64_t* rows, int nrows, int Mp, hipStream_t st) {
-  if (nrows == 0) return hipSuccess;
   const int nt = (Mp + 31) / 32;
-  hipLaunchKernelGGL(k_transpose_scale, dim3(nt * nt, nrows), dim3(256), 0, st, Dinv_t, alpha_t, Dinv, bdiag_t, rows,
-                     Mp);
-  return hipGetLastError();
+  for (int r0 = 0; r0 < nrows; r0 += 65535) {   // grid.y is at most 65535
+    const int nr = nrows - r0 < 65535 ? nrows - r0 : 65535;
+    hipLaunchKernelGGL(k_transpose_scale, dim3(nt * nt, nr), dim3(256), 0, st, Dinv_t, alpha_t, Dinv, bdiag_t,
+                       rows + r0, Mp);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // dst[b] = src[b]^T for nblk consecutive Mp x Mp column-major blocks; the same 32 x 32 LDS tiles as
@@ -715,11 +719,15 @@ __global__ void __launch_bounds__(256) k_transpose_blocks(double* dst, const dou
 }
 
 hipError_t launch_transpose_blocks(double* dst, const double* src, int64_t nblk, int Mp, hipStream_t st) {
-  if (nblk == 0) return hipSuccess;
-  if (nblk > 65535) return hipErrorInvalidValue;
   const int nt = (Mp + 31) / 32;
-  hipLaunchKernelGGL(k_transpose_blocks, dim3(nt * nt, (unsigned)nblk), dim3(256), 0, st, dst, src, Mp);
-  return hipGetLastError();
+  const int64_t MM = (int64_t)Mp * Mp;
+  for (int64_t b0 = 0; b0 < nblk; b0 += 65535) {   // grid.y is at most 65535
+    const int64_t nb = nblk - b0 < 65535 ? nblk - b0 : 65535;
+    hipLaunchKernelGGL(k_transpose_blocks, dim3(nt * nt, (unsigned)nb), dim3(256), 0, st, dst + b0 * MM, src + b0 * MM, Mp);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace td

@@ -1231,12 +1231,20 @@ void solve_pass(td_plan_s* P, const Work& w, const double* F, int64_t ldf, doubl
                 bool accumulate, hipStream_t st) {
   if (P->scalar) {   // Algorithm 1 on the scalar system: no sweeps, no superposition
     ScalarArgs A = P->sc;
-    A.K = (int)K; A.F = F; A.ldf = ldf; A.X = X; A.ldx = ldx; A.Pt = w.Sp; A.Xt = w.Xi;
+    A.ldf = ldf; A.ldx = ldx; A.Pt = w.Sp; A.Xt = w.Xi;
     A.accumulate = accumulate ? 1 : 0;
     for (int i = 0; i <= 2; ++i) stage_mark(P, i, st);
-    HIPCHK(launch_scalar_top(A, st));      // stage "dichotomy_partial": the top levels
-    stage_mark(P, 3, st);
-    HIPCHK(launch_scalar_sub(A, st));      // stage "dichotomy_levels": the subtrees
+    // columns in chunks whose column groups fit a launch's grid.y (at most 65535); the workspace
+    // layout follows each chunk's own K
+    const int64_t kmax = 65535 * (int64_t)SC_CPW;
+    for (int64_t c0 = 0; c0 < K; c0 += kmax) {
+      A.K = (int)std::min(kmax, K - c0);
+      A.F = F + c0 * ldf;
+      A.X = X + c0 * ldx;
+      HIPCHK(launch_scalar_top(A, st));    // stage "dichotomy_partial": the top levels
+      if (c0 + kmax >= K) stage_mark(P, 3, st);
+      HIPCHK(launch_scalar_sub(A, st));    // stage "dichotomy_levels": the subtrees
+    }
     stage_mark(P, 4, st);
     stage_mark(P, 5, st);
     P->first_pass = false;

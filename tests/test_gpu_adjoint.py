@@ -165,3 +165,15 @@ def test_shifted_solver_reuses_its_plan(td):
     Xo = oracle.solve(sys2, F)
     Lam = oracle.solve_adjoint(sys2, Xo - Xt)
     assert rel_err(grads[2], oracle.diag_shift_grad(Lam, Xo, N, M)) <= 1e-12
+
+
+def test_adjoint_more_interior_rows_than_one_launch(td):
+    """The transposed plan takes the forward block inverses transposed, in launches of at most 65535
+    blocks: N = 66000 block rows of 16 in 64 subdomains (65936 interior rows), against the oracle."""
+    N, M, K = 66000, 16, 2
+    sys = synth.varcoef_system(N, M, seed=66)
+    G = synth.rhs_columns(66, N, M, range(K))
+    plan = td.Plan.from_system(sys, subdomains=64, adjoint=True)
+    Lam = plan.solve_adjoint(_dev(G)).cpu().numpy()
+    assert rel_err(Lam, oracle.solve_adjoint(sys, G)) < 1e-12
+    plan.close()

@@ -59,6 +59,21 @@ def test_scalar_column_groups(td, K):
     assert rel_err(X, oracle.solve(sys, F)) < TOL
 
 
+def test_scalar_columns_beyond_one_launch(td):
+    """More right-hand sides than one launch's column groups hold (65535 groups of four): the solve
+    runs in column chunks; columns on both sides of the chunk boundary against the oracle."""
+    N, K = 64, 65535 * 4 + 41
+    sys = _system(N, 77, "varcoef")
+    F = synth.rhs_torch(977, N, 1, K, "cuda")
+    plan = td.Plan.from_system(sys, subdomains=N)
+    X = plan.solve(F)
+    cols = [0, 1, 65535 * 4 - 1, 65535 * 4, 65535 * 4 + 1, K - 1]
+    got = X[cols].cpu().numpy()
+    assert rel_err(got, oracle.solve(sys, synth.rhs_columns(977, N, 1, cols))) < TOL
+    del X, F
+    torch.cuda.empty_cache()
+
+
 def test_scalar_dense_c_and_adjoint(td):
     N, K = 1500, 5
     base = synth.varcoef_system(N, 1, 960)
