@@ -242,12 +242,28 @@ struct DescPool {
   td_plan_s* P;
   hipStream_t st;
   std::vector<Chunk> chunks;
+  size_t sent = 0;        // bytes of the last chunk already sent to the device
+  bool batch = false;     // between begin_batch and end_batch: stage lists, send them in one copy
   DescPool(td_plan_s* plan, hipStream_t s) : P(plan), st(s) {}
   DescPool(const DescPool&) = delete;
   DescPool& operator=(const DescPool&) = delete;
+  // One copy of the lists staged since the last one (the caller's launches that read them come after).
+  void flush() {
+    if (chunks.empty()) return;
+    Chunk& c = chunks.back();
+    if (c.used > sent) HIPCHK(hipMemcpyAsync(c.dev + sent, c.host + sent, c.used - sent, hipMemcpyHostToDevice, st));
+    sent = c.used;
+  }
+  void begin_batch() { batch = true; }
+  void end_batch() {
+    flush();
+    batch = false;
+  }
   void* put_bytes(const void* src, size_t nb) {
     const size_t need = (std::max<size_t>(nb, 1) + 255) & ~(size_t)255;
     if (chunks.empty() || chunks.back().used + need > chunks.back().cap) {
+      flush();
+      sent = 0;
       Chunk c{};
       c.cap = std::max<size_t>(need, (size_t)4 << 20);
       HIPCHK(hipHostMalloc((void**)&c.host, c.cap, hipHostMallocDefault));
@@ -261,11 +277,9 @@ struct DescPool {
     }
     Chunk& c = chunks.back();
     void* d = c.dev + c.used;
-    if (nb) {
-      std::memcpy(c.host + c.used, src, nb);
-      HIPCHK(hipMemcpyAsync(d, c.host + c.used, nb, hipMemcpyHostToDevice, st));
-    }
+    if (nb) std::memcpy(c.host + c.used, src, nb);
     c.used += need;
+    if (!batch) flush();
     return d;
   }
   template <class T>
@@ -291,12 +305,18 @@ int kalign_of(const std::vector<BDesc>& d) {
   return a;
 }
 
-void run_bgemm(BArgs a, const std::vector<BDesc>& d, DescPool& pool, hipStream_t st) {
+// d already on the device at staged (DescPool batch)
+void run_bgemm(BArgs a, const std::vector<BDesc>& d, const BDesc* staged, hipStream_t st) {
   if (d.empty()) return;
-  a.descs = pool.put(d);
+  a.descs = staged;
   a.nprob = (int32_t)d.size();
   a.kalign = kalign_of(d);
   HIPCHK(launch_bgemm(a, st));
+}
+
+void run_bgemm(BArgs a, const std::vector<BDesc>& d, DescPool& pool, hipStream_t st) {
+  if (d.empty()) return;
+  run_bgemm(a, d, pool.put(d), st);
 }
 
 // Default subdomain count (tridiag_default_subdomains): the longest of 32, 16 and 8 rows per subdomain
@@ -424,41 +444,19 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
       gam.push_back(d);
     }
     const int nm = (int)rows.size();
-    if (!reuse) {
-      int64_t* d_rows = pool.put_vec(rows);
-      int32_t* d_first = pool.put_vec(first);
-      HIPCHK(launch_build_D(Dwork, MM, nm, d_rows, d_first, P->cC, P->fmtC, P->adiag, P->alpha, (int)M, (int)Mp, st));
-      if (P->dense && t > 0) {   // D_i -= A_i alpha_{i-1}
-        std::vector<BDesc> da;
-        for (int q = 0; q < nm; ++q) {
-          const int64_t i = rows[q];
-          BDesc d = desc0();
-          d.a_off = i * 2 * MM;
-          d.b_off = (i - 1) * MM;
-          d.c_off = d.cin_off = q * MM;
-          d.kd = d.segrows = (int32_t)Mp;
-          da.push_back(d);
-        }
-        BArgs a = bargs_base((int)Mp);
-        a.alpha = -1.0;
-        a.A = P->ABd; a.lda = Mp;
-        a.B = P->alpha; a.ldb = Mp;
-        a.C = Dwork; a.ldc = Mp;
-        a.Cin = Dwork; a.ldcin = Mp;
-        a.ncols = (int32_t)Mp;
-        run_bgemm(a, da, pool, st);
+    std::vector<BDesc> da, dal, de;
+    if (!reuse && P->dense && t > 0) {   // D_i -= A_i alpha_{i-1}
+      for (int q = 0; q < nm; ++q) {
+        const int64_t i = rows[q];
+        BDesc d = desc0();
+        d.a_off = i * 2 * MM;
+        d.b_off = (i - 1) * MM;
+        d.c_off = d.cin_off = q * MM;
+        d.kd = d.segrows = (int32_t)Mp;
+        da.push_back(d);
       }
-      GJArgs g{};
-      g.work = Dwork; g.work_off = nullptr; g.wstride = MM;
-      g.out = P->Dinv; g.out_off = pool.put_vec(outoff);
-      g.alpha = P->dense ? nullptr : P->alpha; g.bdiag = P->bdiag; g.bd_off = pool.put_vec(bdoff);
-      g.tag = pool.put_vec(tag); g.bad = bad;
-      g.nmat = nm; g.Mp = (int32_t)Mp;
-      gj_scratch(g);
-      HIPCHK(launch_gj(g, st));
     }
-    if (P->dense) {   // alpha_i = D_i^{-1} B_i, E_i = D_i^{-1} A_i, Gamma_i = E_i Gamma_{i-1}
-      std::vector<BDesc> dal, de;
+    if (P->dense) {   // alpha_i = D_i^{-1} B_i, E_i = D_i^{-1} A_i
       for (int q = 0; q < nm; ++q) {
         const int64_t i = rows[q];
         BDesc d = desc0();
@@ -471,6 +469,41 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
         dal.push_back(d);
         de.push_back(x);
       }
+    }
+    // every list of the step goes to the device in one copy
+    pool.begin_batch();
+    int64_t* d_rows = reuse ? nullptr : pool.put_vec(rows);
+    int32_t* d_first = reuse ? nullptr : pool.put_vec(first);
+    int64_t* d_out = reuse ? nullptr : pool.put_vec(outoff);
+    int64_t* d_bd = reuse ? nullptr : pool.put_vec(bdoff);
+    int32_t* d_tag = reuse ? nullptr : pool.put_vec(tag);
+    const BDesc* s_da = da.empty() ? nullptr : pool.put(da);
+    const BDesc* s_dal = dal.empty() ? nullptr : pool.put(dal);
+    const BDesc* s_de = de.empty() ? nullptr : pool.put(de);
+    const BDesc* s_gam = pool.put(gam);
+    pool.end_batch();
+    if (!reuse) {
+      HIPCHK(launch_build_D(Dwork, MM, nm, d_rows, d_first, P->cC, P->fmtC, P->adiag, P->alpha, (int)M, (int)Mp, st));
+      if (!da.empty()) {
+        BArgs a = bargs_base((int)Mp);
+        a.alpha = -1.0;
+        a.A = P->ABd; a.lda = Mp;
+        a.B = P->alpha; a.ldb = Mp;
+        a.C = Dwork; a.ldc = Mp;
+        a.Cin = Dwork; a.ldcin = Mp;
+        a.ncols = (int32_t)Mp;
+        run_bgemm(a, da, s_da, st);
+      }
+      GJArgs g{};
+      g.work = Dwork; g.work_off = nullptr; g.wstride = MM;
+      g.out = P->Dinv; g.out_off = d_out;
+      g.alpha = P->dense ? nullptr : P->alpha; g.bdiag = P->bdiag; g.bd_off = d_bd;
+      g.tag = d_tag; g.bad = bad;
+      g.nmat = nm; g.Mp = (int32_t)Mp;
+      gj_scratch(g);
+      HIPCHK(launch_gj(g, st));
+    }
+    if (P->dense) {   // ... and Gamma_i = E_i Gamma_{i-1}
       BArgs a = bargs_base((int)Mp);
       a.A = P->Dinv; a.lda = Mp;
       a.B = P->ABd; a.ldb = Mp;
@@ -479,14 +512,14 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
       BArgs aa = a, ae = a;
       aa.C = P->alpha;
       ae.C = P->E;
-      run_bgemm(aa, dal, pool, st);
-      run_bgemm(ae, de, pool, st);
+      run_bgemm(aa, dal, s_dal, st);
+      run_bgemm(ae, de, s_de, st);
       BArgs ag = bargs_base((int)Mp);
       ag.A = P->E; ag.lda = Mp;
       ag.B = Ga; ag.ldb = Mp;
       ag.C = Ga; ag.ldc = Mp;
       ag.ncols = (int32_t)Mp;
-      run_bgemm(ag, gam, pool, st);
+      run_bgemm(ag, gam, s_gam, st);
     } else {
       BArgs a = bargs_base((int)Mp);
       a.A = P->Dinv; a.lda = Mp;
@@ -494,7 +527,7 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
       a.bscale = P->adiag;
       a.C = Ga; a.ldc = Mp;
       a.ncols = (int32_t)Mp;
-      run_bgemm(a, gam, pool, st);
+      run_bgemm(a, gam, s_gam, st);
     }
   }
 
@@ -525,8 +558,12 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
     a.ncols = (int32_t)Mp;
     BArgs au = a;
     au.Cin = Ga; au.ldcin = Mp;
-    run_bgemm(au, du, pool, st);
-    run_bgemm(a, dv, pool, st);
+    pool.begin_batch();
+    const BDesc* s_du = pool.put(du);
+    const BDesc* s_dv = pool.put(dv);
+    pool.end_batch();
+    run_bgemm(au, du, s_du, st);
+    run_bgemm(a, dv, s_dv, st);
   }
   HIPCHK(hipStreamSynchronize(st));
   P->release(Ga);
@@ -680,6 +717,15 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
           tag.push_back((int32_t)(N + j));
         }
       }
+      // the step's lists in one copy
+      const int nm = (int)woff.size();
+      pool.begin_batch();
+      const BDesc* s_dd = pool.put(dd);
+      const BDesc* s_da = pool.put(da);
+      int64_t* d_woff = pool.put_vec(woff);
+      int64_t* d_out = pool.put_vec(outoff);
+      int32_t* d_tag = pool.put_vec(tag);
+      pool.end_batch();
       BArgs a = bargs_base((int)Mp);
       a.A = P->red; a.lda = Mp;
       a.B = Da; a.ldb = Mp;
@@ -687,15 +733,14 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
       a.C = Da; a.ldc = Mp;
       a.alpha = -1.0;
       a.ncols = (int32_t)Mp;
-      run_bgemm(a, dd, pool, st);
+      run_bgemm(a, dd, s_dd, st);
       // invert the chain matrices in place in the arena (one launch for all nodes)
-      const int nm = (int)woff.size();
       if (nm > 0) {
         GJArgs g{};
-        g.work = Da; g.work_off = pool.put_vec(woff); g.wstride = 0;
-        g.out = P->G; g.out_off = pool.put_vec(outoff);
+        g.work = Da; g.work_off = d_woff; g.wstride = 0;
+        g.out = P->G; g.out_off = d_out;
         g.alpha = nullptr; g.bdiag = nullptr; g.bd_off = nullptr;
-        g.tag = pool.put_vec(tag); g.bad = bad;
+        g.tag = d_tag; g.bad = bad;
         g.nmat = nm; g.Mp = (int32_t)Mp;
         gj_scratch(g);
         HIPCHK(launch_gj(g, st));
@@ -705,7 +750,7 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
       b.B = P->red; b.ldb = Mp;
       b.C = Da; b.ldc = Mp;
       b.ncols = (int32_t)Mp;
-      run_bgemm(b, da, pool, st);
+      run_bgemm(b, da, s_da, st);
     }
     // S_m = Ct_m - At_m alphaL_{m-1} - Bt_m alphaR_{m+1};  G_m = S_m^{-1}
     {
@@ -794,18 +839,22 @@ void factor_impl(td_plan_s* P, const double* A, const double* B, const double* C
         d2.push_back(e);
       }
     }
+    pool.begin_batch();
+    const BDesc* s_d1 = pool.put(d1);
+    const BDesc* s_d2 = pool.put(d2);
+    pool.end_batch();
     BArgs a = bargs_base((int)Mp);
     a.A = P->G; a.lda = Mp;
     a.B = P->red; a.ldb = Mp;
     a.C = Da; a.ldc = Mp;
     a.ncols = (int32_t)Mp;
-    run_bgemm(a, d1, pool, st);
+    run_bgemm(a, d1, s_d1, st);
     BArgs b = bargs_base((int)Mp);
     b.A = Da; b.lda = Mp;
     b.B = P->G; b.ldb = Mp;
     b.C = P->G; b.ldc = Mp;
     b.ncols = (int32_t)Mp;
-    run_bgemm(b, d2, pool, st);
+    run_bgemm(b, d2, s_d2, st);
   }
   // H^L = G_l At_l (l > 0), H^R = G_r Bt_r (r < p-1)
   {
