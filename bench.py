@@ -34,9 +34,9 @@ KERNEL_SOURCES = {
 }
 MEASURED_TRAFFIC = {
     # (kernel, workload): (source set, source hash (kernel_source_hash), read bytes, write bytes)
-    ("sweep", "mixed_n4096_m512_k1024"): ("f64", "6a15218ec1bdd946", 53.6718e9, 32.7995e9),
-    ("superposition", "mixed_n4096_m512_k1024"): ("f64", "6a15218ec1bdd946", 50.5253e9, 16.6430e9),
-    ("scalar_subtrees", "scalar_n65536_k1024"): ("scalar", "861f5edd6f153670", 0.55352e9, 0.53687e9),
+    ("sweep", "mixed_n4096_m512_k1024"): ("f64", "0a99f9263b833a11", 54.0047e9, 32.7995e9),
+    ("superposition", "mixed_n4096_m512_k1024"): ("f64", "0a99f9263b833a11", 50.5494e9, 16.6430e9),
+    ("scalar_subtrees", "scalar_n65536_k1024"): ("scalar", "ad931b9574f73499", 0.55359e9, 0.53687e9),
 }
 
 
