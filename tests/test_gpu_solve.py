@@ -209,7 +209,7 @@ def _pivoting_system(N, M, seed):
     return synth.System(N, M, base.A / 8.0, base.B / 8.0, np.ascontiguousarray(C), "dense", "dense", "dense")
 
 
-@pytest.mark.parametrize("M", [64, 128, 256, 320, 512])
+@pytest.mark.parametrize("M", [64, 128, 192, 256, 320, 448, 512])
 def test_row_interchanges_in_block_inverses(td, M):
     """Every diagonal block of the elimination needs row interchanges (Gauss-Jordan with partial
     pivoting inside each block), at the block sizes of the one-launch-per-panel Gauss-Jordan kernel
@@ -233,7 +233,7 @@ def test_nan_input_reported_large(td, M):
     assert e.value.code == 3
 
 
-@pytest.mark.parametrize("M", [64, 256, 512])
+@pytest.mark.parametrize("M", [64, 192, 256, 512])
 def test_singular_block_large(td, M):
     """A zero C block that opens a subdomain: TD_ESINGULAR with its block row, at block sizes of both
     Gauss-Jordan kernels."""
