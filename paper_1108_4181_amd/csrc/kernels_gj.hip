@@ -14,7 +14,9 @@ namespace td {
 
 // ---------------------------------------------------------------------------
 // Batched Gauss-Jordan inversion with partial pivoting (row interchanges chosen
-// by the largest remaining entry of each column; ties go to the lowest row).
+// by the largest remaining entry of each column; ties go to the lowest row), for
+// the block sizes below 128 or not a multiple of 64 (k_gj; the others use the
+// per-panel kernel k_gj_step further down, with the same pivoting rule).
 // One work-group per matrix; thread i < Mp owns row i.  Columns are processed in
 // panels of NB: during a panel every thread keeps its row of the panel in
 // registers and publishes it to one of two LDS copies (alternating by column),
@@ -576,7 +578,7 @@ static hipError_t launch_gj_rt(const GJArgs& g, hipStream_t st) {
 hipError_t launch_gj(const GJArgs& g, hipStream_t st) {
   if (g.nmat == 0) return hipSuccess;
   // block sizes that are multiples of 64 from 128 (every padded size above 256 is one): one launch
-  // per 32-column panel, with the caller's scratch for pivot rows and norms
+  // per 32-column panel, with the caller's scratch for pivot rows, smallest pivots and row sums
   if (g.Mp % 64 == 0 && g.Mp >= 128) {
     if (!g.piv || !g.pmin || !g.part) return hipErrorInvalidValue;
     return g.Mp <= 256 ? launch_gj_split<32, 256>(g, st) : launch_gj_split<32, 512>(g, st);

@@ -231,8 +231,10 @@ BDesc desc0() {
 
 // Descriptor lists of the factor's launches: copied into chunks of pinned host memory and sent with
 // asynchronous copies into device chunks (from the plan's allocator), so that building a list never
-// waits for the device.  Each piece of a chunk is written once; the chunks are released when the pool
-// goes out of scope, after the stream has finished with them.
+// waits for the device; between begin_batch and end_batch the lists are only staged, and end_batch
+// sends all of them in one copy (before the launches that read them).  Each piece of a chunk is
+// written once; the chunks are released when the pool goes out of scope, after the stream has
+// finished with them.
 struct DescPool {
   struct Chunk {
     char* host;
