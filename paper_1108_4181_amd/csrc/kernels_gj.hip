@@ -339,14 +339,14 @@ __device__ __forceinline__ double gj_panel(double (&v)[NB], bool& used, double* 
     int r, wr;
     slot_argmax(L < nw ? cv[slot * 8 + (L & 7)] : -2.0, L < nw ? ci[slot * 8 + (L & 7)] : INT_MAX, r, wr);
     const double* pr = cand + (slot * 8 + wr) * NB;
+    const double ipv = cv[32 + slot * 8 + wr];
+    const bool piv = (tid == r);
+    const double f = piv ? 0.0 : vj * ipv;   // v <- v - v_j * (pivot row / pivot), column j <- -v_j / pivot
     double prv[NB];
 #pragma unroll
     for (int jj = 0; jj < NB; ++jj) prv[jj] = pr[jj];
-    const double ipv = cv[32 + slot * 8 + wr];
     const double apv = fabs(prv[0]);
     pm = (pm != pm) ? pm : ((apv != apv) ? apv : fmin(pm, apv));
-    const bool piv = (tid == r);
-    const double f = piv ? 0.0 : vj * ipv;   // v <- v - v_j * (pivot row / pivot), column j <- -v_j / pivot
 #pragma unroll
     for (int jj = 0; jj + 1 < NB; ++jj) v[jj] = v[jj + 1] - f * prv[jj + 1];
     v[NB - 1] = piv ? 1.0 : -f;
@@ -551,6 +551,237 @@ static hipError_t launch_gj_split(const GJArgs& g, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Block pivot of 32 columns onto 32 others, by a work-group of Mp threads (64 rows per wave): the
+// columns from tc become c + (Z - E_R) c_R, with Z the 32 columns from zc after their elimination with
+// pivot rows R (R[0 .. 32), in LDS) and c_R the rows R of c before it; a rank-32 product on MFMA with
+// c_R staged in Hs ([32][32]).  Every thread's stores of Z and R must be complete before the call; at
+// its return the new columns are visible to the work-group and Hs is free.
+__device__ __forceinline__ void gj_half_apply(double* W, int Mp, int zc, const int* R, int tc, double* Hs) {
+  constexpr int RT = 4, KW = 32, CT = 8;
+  const int tid = threadIdx.x, L = tid & 63, w = tid >> 6;
+  const int rb = w * 16 * RT;
+  for (int e = tid; e < KW * 32; e += blockDim.x) {
+    const int j = e / KW, kk = e - j * KW;
+    Hs[kk * 32 + j] = W[R[kk] + (int64_t)(tc + j) * Mp];
+  }
+  double a[KW / 4][RT];
+#pragma unroll
+  for (int k4 = 0; k4 < KW / 4; ++k4) {
+    const int kc = 4 * k4 + (L >> 4);
+    const int prw = R[kc];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int row = rb + 16 * t + (L & 15);
+      a[k4][t] = W[row + (int64_t)(zc + kc) * Mp] - (row == prw ? 1.0 : 0.0);
+    }
+  }
+  double acc[RT][CT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) acc[t][ct] = W[rb + 16 * t + out_row(L) + (int64_t)(tc + 4 * ct + out_col(L)) * Mp];
+  __syncthreads();   // Hs complete; every read of rows R of the target columns precedes the stores below
+#pragma unroll
+  for (int k4 = 0; k4 < KW / 4; ++k4) {
+    const double* bp = Hs + (4 * k4 + (L >> 4)) * 32 + (L & 3);
+    double b[CT];
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) b[ct] = bp[4 * ct];
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) acc[t][ct] = mfma4(a[k4][t], b[ct], acc[t][ct]);
+  }
+#pragma unroll
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) W[rb + 16 * t + out_row(L) + (int64_t)(tc + 4 * ct + out_col(L)) * Mp] = acc[t][ct];
+  __syncthreads();
+}
+
+// The per-panel inversion with 64-column panels and tiles, for block sizes from 384 (multiples of 64)
+// when a launch holds many matrices: there the update passes over the matrices bound the time, and
+// rank-64 products halve them (Mp / 64 + 1 launches per inversion).  Same roles and orders as
+// k_gj_step; a tile is updated in four quarters of 16 columns with the rank-64 operand kept in
+// registers, the lead work-group's updated panel and the last launch's read-out go through the matrix
+// in global memory (a 64-column tile of 512 rows would take 256 KB of LDS), and the lead eliminates
+// its panel as two 32-column halves joined by gj_half_apply.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_gj_step64(GJArgs g, int k) {
+  constexpr int NB = 64, RT = 4, CTN = 4;  // CTN: 4-column output tiles of a 16-column quarter
+  extern __shared__ double sm[];
+  const int Mp = g.Mp;                     // a multiple of 64, blockDim.x == Mp
+  double* Bs = sm;                         // [NB][NB]: rows R_k of the tile's columns
+  double* cand = Bs + NB * NB;             // [2][8][NB]: candidate pivot rows of the waves
+  double* cv = cand + 2 * 8 * NB;          // [2][8]: their magnitudes; [16 .. 23]: row-sum maxima;
+                                           // [32 .. 47]: their reciprocal pivots
+  int* ci = (int*)(cv + 48);               // [2][8]: their rows
+  int* pl = ci + 16;                       // [NB]: pivot rows of the panel eliminated here
+  int* rk = pl + NB;                       // [NB]: pivot rows of panel k
+  int* ri = rk + NB;                       // [Mp]: rows used as pivots (panel), pivot rows (read-out)
+  const int tid = threadIdx.x, L = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
+  const int ntile = Mp / NB;
+  const bool last = (k == ntile - 1);
+  const int nmat8 = (g.nmat + 7) & ~7;     // work-group roles and order as in k_gj_step
+  int q, c;
+  const bool lead = (int)blockIdx.x < nmat8;
+  if (lead) {
+    q = blockIdx.x;
+    c = last ? k : k + 1;
+    if (q >= g.nmat) return;
+  } else {
+    const int t = blockIdx.x - nmat8, i = t >> 3;
+    q = (t & 7) + 8 * (i / ntile);
+    c = i % ntile;
+    if (q >= g.nmat || c == k || c == k + 1) return;
+  }
+  double* W = g.work + (g.work_off ? g.work_off[q] : q * g.wstride);
+  int* piv = g.piv + (int64_t)q * Mp;
+  double* part = g.part + (int64_t)q * ntile * Mp;   // [ntile][Mp]: partial row sums of |matrix|
+  const int c0 = c * NB;
+  const int rb = w * 16 * RT;
+
+  if (k < 0 && !lead) {   // the tile's share of the row sums of the original matrix
+    double rs = 0.0;
+#pragma unroll
+    for (int j0 = 0; j0 < NB; j0 += 8) {
+      double t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = W[tid + (int64_t)(c0 + j0 + u) * Mp];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) rs += fabs(t[u]);
+    }
+    part[(int64_t)c * Mp + tid] = rs;
+    return;
+  }
+
+  if (k >= 0 && !(last && lead)) {
+    if (tid < NB) rk[tid] = piv[k * NB + tid];
+    __syncthreads();
+    for (int e = tid; e < NB * NB; e += blockDim.x) {
+      const int j = e / NB, kk = e - j * NB;
+      Bs[kk * NB + j] = W[rk[kk] + (int64_t)(c0 + j) * Mp];
+    }
+    double a[NB / 4][RT];                  // (Z - E_R) rows of this wave, Z = panel k's columns
+#pragma unroll
+    for (int k4 = 0; k4 < NB / 4; ++k4) {
+      const int kc = 4 * k4 + (L >> 4);
+      const int prw = rk[kc];
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int row = rb + 16 * t + (L & 15);
+        a[k4][t] = W[row + (int64_t)(k * NB + kc) * Mp] - (row == prw ? 1.0 : 0.0);
+      }
+    }
+    __syncthreads();   // Bs complete; every read of rows R_k of the tile precedes the stores below
+#pragma unroll 1
+    for (int h = 0; h < 4; ++h) {
+      const int ch = c0 + 16 * h;
+      double acc[RT][CTN];
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int ct = 0; ct < CTN; ++ct)
+          acc[t][ct] = W[rb + 16 * t + out_row(L) + (int64_t)(ch + 4 * ct + out_col(L)) * Mp];
+#pragma unroll
+      for (int k4 = 0; k4 < NB / 4; ++k4) {
+        const double* bp = Bs + (4 * k4 + (L >> 4)) * NB + 16 * h + (L & 3);
+        double b[CTN];
+#pragma unroll
+        for (int ct = 0; ct < CTN; ++ct) b[ct] = bp[4 * ct];
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+          for (int ct = 0; ct < CTN; ++ct) acc[t][ct] = mfma4(a[k4][t], b[ct], acc[t][ct]);
+      }
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int ct = 0; ct < CTN; ++ct)
+          W[rb + 16 * t + out_row(L) + (int64_t)(ch + 4 * ct + out_col(L)) * Mp] = acc[t][ct];
+    }
+    if (!lead && !last) return;
+  }
+
+  if (last) {
+    if (lead) {   // the singularity test (the last panel is final since the previous launch)
+      double rs = 0.0;
+      for (int cc = 0; cc < ntile; ++cc) rs += part[(int64_t)cc * Mp + tid];
+      for (int off = 32; off > 0; off >>= 1) rs = fmax(rs, __shfl_xor(rs, off));
+      if (L == 0) cv[16 + w] = rs;
+    }
+    ri[tid] = piv[tid];
+    __syncthreads();   // the tile's final values, the pivot rows and the row-sum maxima complete
+    if (lead && tid == 0) {
+      double norm = 0.0;
+      for (int u = 0; u < nw; ++u) norm = fmax(norm, cv[16 + u]);
+      if (!(g.pmin[q] > 1e-14 * norm)) atomicMin(g.bad, g.tag[q]);
+    }
+    double* out = g.out + g.out_off[q];
+    double* al = g.alpha ? g.alpha + g.out_off[q] : nullptr;
+    const double* bd = g.alpha ? g.bdiag + g.bd_off[q] : nullptr;
+    const int prow_t = ri[tid];
+#pragma unroll 8
+    for (int jj = 0; jj < NB; ++jj) {
+      const int oc = ri[c0 + jj];
+      const double v = W[prow_t + (int64_t)(c0 + jj) * Mp];
+      out[tid + (int64_t)oc * Mp] = v;
+      if (al) al[tid + (int64_t)oc * Mp] = v * bd[oc];
+    }
+    return;
+  }
+
+  // the lead work-group of launch k < ntile - 1 eliminates the 64-column panel as two halves A and B
+  // of 32 columns (one row per thread, gj_panel): A; B after A's transform; then A's columns take B's
+  // transform, which leaves the block pivot of all 64 columns (pivot rows R_A, R_B in pl)
+  ri[tid] = 0;
+  __syncthreads();   // also orders the updated panel's stores above before the reads below
+  for (int i = tid; i < c0; i += blockDim.x) ri[piv[i]] = 1;
+  __syncthreads();
+  bool used = ri[tid] != 0;
+  double v[32];
+  if (k < 0) {   // tile 0's share of the row sums, from the original values
+    double rs = 0.0;
+#pragma unroll 8
+    for (int jj = 0; jj < NB; ++jj) rs += fabs(W[tid + (int64_t)(c0 + jj) * Mp]);
+    part[tid] = rs;
+  }
+#pragma unroll
+  for (int jj = 0; jj < 32; ++jj) v[jj] = W[tid + (int64_t)(c0 + jj) * Mp];
+  const double pma = gj_panel<32>(v, used, cand, cv, ci, pl, nw);
+#pragma unroll
+  for (int jj = 0; jj < 32; ++jj) W[tid + (int64_t)(c0 + jj) * Mp] = v[jj];
+  __syncthreads();   // Z_A and R_A complete
+  gj_half_apply(W, Mp, c0, pl, c0 + 32, Bs);
+#pragma unroll
+  for (int jj = 0; jj < 32; ++jj) v[jj] = W[tid + (int64_t)(c0 + 32 + jj) * Mp];
+  const double pmb = gj_panel<32>(v, used, cand, cv, ci, pl + 32, nw);
+#pragma unroll
+  for (int jj = 0; jj < 32; ++jj) W[tid + (int64_t)(c0 + 32 + jj) * Mp] = v[jj];
+  __syncthreads();   // Z_B and R_B complete
+  gj_half_apply(W, Mp, c0 + 32, pl + 32, c0, Bs);
+  if (tid < NB) piv[c0 + tid] = pl[tid];
+  if (tid == 0) {
+    const double o = (k < 0) ? INFINITY : g.pmin[q];
+    const double pm = (pma != pma) ? pma : ((pmb != pmb) ? pmb : fmin(pma, pmb));
+    g.pmin[q] = (o != o) ? o : ((pm != pm) ? pm : fmin(o, pm));
+  }
+}
+
+template <int NT>
+static hipError_t launch_gj_split64(const GJArgs& g, hipStream_t st) {
+  constexpr int NB = 64;
+  const int Mp = g.Mp, ntile = Mp / NB;
+  const size_t lds = (size_t)(NB * NB + 2 * 8 * NB + 48) * sizeof(double) + (size_t)(16 + 2 * NB + Mp) * sizeof(int);
+  hipError_t e = hipFuncSetAttribute((const void*)k_gj_step64<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  const int nmat8 = grid_pad8(g.nmat);
+  for (int k = -1; k < ntile; ++k)
+    hipLaunchKernelGGL((k_gj_step64<NT>), dim3(nmat8 * (1 + ntile)), dim3(Mp), lds, st, g, k);
+  return hipGetLastError();
+}
+
 template <int RT, int NT, int NB>
 static hipError_t launch_gj_cfg(const GJArgs& g, int nthr, hipStream_t st) {
   const size_t lds = (size_t)(2 * NB * g.Mp + 32) * sizeof(double) + (size_t)(32 + 2 * g.Mp) * sizeof(int);
@@ -581,6 +812,8 @@ hipError_t launch_gj(const GJArgs& g, hipStream_t st) {
   // per 32-column panel, with the caller's scratch for pivot rows, smallest pivots and row sums
   if (g.Mp % 64 == 0 && g.Mp >= 128) {
     if (!g.piv || !g.pmin || !g.part) return hipErrorInvalidValue;
+    // many matrices at block sizes from 384: the update passes bound a launch, 64-column panels
+    if (g.Mp >= 384 && g.nmat >= 32) return launch_gj_split64<512>(g, st);
     return g.Mp <= 256 ? launch_gj_split<32, 256>(g, st) : launch_gj_split<32, 512>(g, st);
   }
   if (g.Mp > 256) return hipErrorInvalidValue;
