@@ -292,68 +292,106 @@ __global__ void __launch_bounds__(NT) k_gj(GJArgs g) {
   }
 }
 
+// Pivot candidates of the one-row-per-thread panel as one 64-bit key: the magnitude's bit pattern
+// (monotone in the magnitude for non-negative doubles) with its low 9 bits replaced by 511 - row, so a
+// single unsigned maximum picks the largest magnitude and, among magnitudes that agree in all but
+// their last 9 bits (a relative difference below 2^-43), the smallest row.  Rows already used as
+// pivots get key 0; NaN ranks as the largest finite value so that it is chosen and reported.  Rows
+// are below 512.  Key 0 decodes to row 511, which it is only when every other row is used.
+__device__ __forceinline__ uint64_t pivot_key(double v, bool used, int row) {
+  const double a = fabs(v);
+  const uint64_t bits = (uint64_t)__double_as_longlong((a == a) ? a : DBL_MAX);
+  return used ? 0ull : ((bits & ~511ull) | (uint64_t)(511 - row));
+}
+__device__ __forceinline__ int pivot_key_row(uint64_t k) { return 511 - (int)(k & 511); }
+
+// One step of a wave-wide key maximum against the key of the lane that the DPP control CTRL
+// selects (rows outside ROWMASK keep their own).
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ void keymax_dpp_step(uint64_t& k) {
+  const int lo = (int)(uint32_t)k, hi = (int)(uint32_t)(k >> 32);
+  const int olo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xF, false);
+  const int ohi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xF, false);
+  const uint64_t o = ((uint64_t)(uint32_t)ohi << 32) | (uint32_t)olo;
+  k = (o > k) ? o : k;
+}
+
 // Gauss-Jordan elimination of one panel of NB columns, one row per thread: v[j] is the thread's entry
 // of panel column j, rows with `used` set were pivots of earlier panels.  Per column every wave finds
-// its best candidate with a DPP arg-max, and the winning lane of each wave publishes that row and its
-// reciprocal pivot next to its magnitude; after one work-group barrier every thread picks the overall
-// pivot among the waves' candidates (larger magnitude, then smaller row: a DPP arg-max over eight
-// lanes) and reads the pivot row from the winning wave's slot.  Slots alternate between two copies, so one
-// barrier per column suffices.
+// its best candidate with a DPP maximum of pivot keys (pivot_key), and the winning lane of each wave
+// publishes that row and its reciprocal pivot, the wave's key next to them; after one work-group
+// barrier every thread takes the largest of the waves' keys (a DPP maximum over eight lanes) and
+// reads the pivot row from the slot of the wave that holds that row.  Slots alternate between two
+// copies, so one barrier per column suffices.
 //   The loop stays rolled without indexing registers at run time: the row is kept rotated so that v[0]
 // is always the current column, and the update writes each entry one place down (column j's new entry
 // goes to the end), so after NB columns the order is the original one again.  The pivot row is not
 // scaled when it is chosen: later eliminations are linear in each row, so its entries are multiplied
 // by the reciprocal pivot once after the panel (its column-j entry is kept as 1 until then), and every
-// row takes the same single fused multiply-add per entry and column.  Every lane divides by its own
-// entry while the arg-max runs, so the reciprocal is ready when its lane wins.  The pivot row of
-// column j goes to prow[j] (written by thread 0).  Returns the smallest pivot magnitude of the panel
-// (NaN if a pivot was NaN; the caller tests it against the tolerance).  cand holds [2][8][NB] rows,
-// cv [2][8] magnitudes and, from cv[32], [2][8] reciprocals, ci [2][8] rows.
+// row takes the same single fused multiply-add per entry and column.  Every lane divides by its own entry
+// before the key maximum, so that the winning lane's reciprocal is ready when it publishes its row.
+// The pivot row of column j goes to prow[j] (written by thread 0).  Returns the smallest pivot magnitude of the panel (NaN if a pivot was NaN; the caller tests it
+// against the tolerance).  cand holds [2][8][NB] rows, cv [2][8] keys and, from cv[32], [2][8]
+// reciprocals.
+// One column of gj_panel: src holds the row rotated so that src[0] is column j; the updated row goes to
+// dst one place down (column j's new entry at the end; dst may be src: each entry is read before it is
+// written).
 template <int NB>
-__device__ __forceinline__ double gj_panel(double (&v)[NB], bool& used, double* cand, double* cv, int* ci, int* prow,
-                                           int nw) {
+__device__ __forceinline__ void gj_column(const double (&src)[NB], double (&dst)[NB], int j, bool& used, double& sr,
+                                          double& pm, double* cand, double* cv, int* prow, int nw) {
   const int tid = threadIdx.x, L = tid & 63, w = tid >> 6;
+  const int slot = j & 1;
+  const double vj = src[0];
+  double rcp = 1.0 / vj;                  // used only if this lane's row wins
+  asm volatile("" : "+v"(rcp));
+  uint64_t key = pivot_key(vj, used, tid);
+  keymax_dpp_step<0xB1, 0xF>(key);    // quad_perm [1,0,3,2]
+  keymax_dpp_step<0x4E, 0xF>(key);    // quad_perm [2,3,0,1]
+  keymax_dpp_step<0x141, 0xF>(key);   // row_half_mirror
+  keymax_dpp_step<0x140, 0xF>(key);   // row_mirror
+  keymax_dpp_step<0x142, 0xA>(key);   // row_bcast:15 into rows 1 and 3
+  keymax_dpp_step<0x143, 0xC>(key);   // row_bcast:31 into rows 2 and 3
+  const uint32_t klo = __builtin_amdgcn_readlane((int)(uint32_t)key, 63);
+  const uint32_t khi = __builtin_amdgcn_readlane((int)(uint32_t)(key >> 32), 63);
+  const uint64_t wkey = ((uint64_t)khi << 32) | klo;
+  if (tid == pivot_key_row(wkey)) {
+    double* cp = cand + (slot * 8 + w) * NB;
+#pragma unroll
+    for (int jj = 0; jj < NB; ++jj) cp[jj] = src[jj];
+    cv[32 + slot * 8 + w] = rcp;
+  }
+  if (L == 0) cv[slot * 8 + w] = __longlong_as_double((long long)wkey);
+  __syncthreads();
+  uint64_t bk = (L < nw) ? (uint64_t)__double_as_longlong(cv[slot * 8 + (L & 7)]) : 0ull;
+  keymax_dpp_step<0xB1, 0xF>(bk);    // quad_perm [1,0,3,2]
+  keymax_dpp_step<0x4E, 0xF>(bk);    // quad_perm [2,3,0,1]
+  keymax_dpp_step<0x141, 0xF>(bk);   // row_half_mirror: lane i of eight meets lane 7 - i
+  const int r = __builtin_amdgcn_readfirstlane(pivot_key_row(bk));
+  const int wr = r >> 6;
+  const double* pr = cand + (slot * 8 + wr) * NB;
+  const double ipv = cv[32 + slot * 8 + wr];
+  const bool piv = (tid == r);
+  const double f = piv ? 0.0 : vj * ipv;   // v <- v - v_j * (pivot row / pivot), column j <- -v_j / pivot
+  double prv[NB];
+#pragma unroll
+  for (int jj = 0; jj < NB; ++jj) prv[jj] = pr[jj];
+  const double apv = fabs(prv[0]);
+  pm = (pm != pm) ? pm : ((apv != apv) ? apv : fmin(pm, apv));
+#pragma unroll
+  for (int jj = 0; jj + 1 < NB; ++jj) dst[jj] = src[jj + 1] - f * prv[jj + 1];
+  dst[NB - 1] = piv ? 1.0 : -f;
+  sr = piv ? ipv : sr;
+  used = used | piv;
+  if (tid == 0) prow[j] = r;
+}
+
+template <int NB>
+__device__ __forceinline__ double gj_panel(double (&v)[NB], bool& used, double* cand, double* cv, int* prow,
+                                           int nw) {
   double sr = 1.0;   // deferred scale of this thread's row (the reciprocal pivot if it was chosen)
   double pm = INFINITY;   // smallest pivot magnitude of the panel; NaN once a pivot is NaN
 #pragma unroll 1
-  for (int j = 0; j < NB; ++j) {
-    const int slot = j & 1;
-    const double vj = v[0];
-    const double rcp = 1.0 / vj;            // used only if this lane's row wins
-    double bv = -1.0;
-    int bi = INT_MAX;
-    if (!used) {
-      const double a = fabs(vj);
-      bv = (a == a) ? a : DBL_MAX;   // NaN ranks first so that it is reported
-      bi = tid;
-    }
-    wave_argmax(bv, bi);
-    if (tid == bi) {
-      double* cp = cand + (slot * 8 + w) * NB;
-#pragma unroll
-      for (int jj = 0; jj < NB; ++jj) cp[jj] = v[jj];
-      cv[32 + slot * 8 + w] = rcp;
-    }
-    if (L == 0) { cv[slot * 8 + w] = bv; ci[slot * 8 + w] = bi; }
-    __syncthreads();
-    int r, wr;
-    slot_argmax(L < nw ? cv[slot * 8 + (L & 7)] : -2.0, L < nw ? ci[slot * 8 + (L & 7)] : INT_MAX, r, wr);
-    const double* pr = cand + (slot * 8 + wr) * NB;
-    const double ipv = cv[32 + slot * 8 + wr];
-    const bool piv = (tid == r);
-    const double f = piv ? 0.0 : vj * ipv;   // v <- v - v_j * (pivot row / pivot), column j <- -v_j / pivot
-    double prv[NB];
-#pragma unroll
-    for (int jj = 0; jj < NB; ++jj) prv[jj] = pr[jj];
-    const double apv = fabs(prv[0]);
-    pm = (pm != pm) ? pm : ((apv != apv) ? apv : fmin(pm, apv));
-#pragma unroll
-    for (int jj = 0; jj + 1 < NB; ++jj) v[jj] = v[jj + 1] - f * prv[jj + 1];
-    v[NB - 1] = piv ? 1.0 : -f;
-    sr = piv ? ipv : sr;
-    used = used | piv;
-    if (tid == 0) prow[j] = r;
-  }
+  for (int j = 0; j < NB; ++j) gj_column<NB>(v, v, j, used, sr, pm, cand, cv, prow, nw);
 #pragma unroll
   for (int jj = 0; jj < NB; ++jj) v[jj] *= sr;
   return pm;
@@ -385,10 +423,9 @@ __global__ void __launch_bounds__(NT) k_gj_step(GJArgs g, int k) {
   double* Ts = sm;                         // [NB][Mp]: a tile's columns (panel or read-out)
   double* Bs = Ts + NB * Mp;               // [NB][NB]: rows R_k of the tile's columns
   double* cand = Bs + NB * NB;             // [2][8][NB]: candidate pivot rows of the waves
-  double* cv = cand + 2 * 8 * NB;          // [2][8]: their magnitudes; [16 .. 23]: row-sum maxima;
+  double* cv = cand + 2 * 8 * NB;          // [2][8]: their pivot keys; [16 .. 23]: row-sum maxima;
                                            // [32 .. 47]: their reciprocal pivots
-  int* ci = (int*)(cv + 48);               // [2][8]: their rows
-  int* pl = ci + 16;                       // [NB]: pivot rows of the panel eliminated here
+  int* pl = (int*)(cv + 48);               // [NB]: pivot rows of the panel eliminated here
   int* rk = pl + NB;                       // [NB]: pivot rows of panel k
   int* ri = rk + NB;                       // [Mp]: rows used as pivots (panel), pivot rows (read-out)
   const int tid = threadIdx.x, L = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
@@ -526,7 +563,7 @@ __global__ void __launch_bounds__(NT) k_gj_step(GJArgs g, int k) {
     for (int jj = 0; jj < NB; ++jj) rs += fabs(v[jj]);
     part[tid] = rs;
   }
-  const double pm = gj_panel<NB>(v, used, cand, cv, ci, pl, nw);
+  const double pm = gj_panel<NB>(v, used, cand, cv, pl, nw);
 #pragma unroll
   for (int jj = 0; jj < NB; ++jj) W[tid + (int64_t)(c0 + jj) * Mp] = v[jj];
   __syncthreads();
@@ -541,7 +578,7 @@ template <int NB, int NT>
 static hipError_t launch_gj_split(const GJArgs& g, hipStream_t st) {
   const int Mp = g.Mp, ntile = Mp / NB;
   const size_t lds = (size_t)(NB * Mp + NB * NB + 2 * 8 * NB + 48) * sizeof(double) +
-                     (size_t)(16 + 2 * NB + Mp) * sizeof(int);
+                     (size_t)(2 * NB + Mp) * sizeof(int);
   hipError_t e = hipFuncSetAttribute((const void*)k_gj_step<NB, NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
@@ -613,10 +650,9 @@ __global__ void __launch_bounds__(NT) k_gj_step64(GJArgs g, int k) {
   const int Mp = g.Mp;                     // a multiple of 64, blockDim.x == Mp
   double* Bs = sm;                         // [NB][NB]: rows R_k of the tile's columns
   double* cand = Bs + NB * NB;             // [2][8][NB]: candidate pivot rows of the waves
-  double* cv = cand + 2 * 8 * NB;          // [2][8]: their magnitudes; [16 .. 23]: row-sum maxima;
+  double* cv = cand + 2 * 8 * NB;          // [2][8]: their pivot keys; [16 .. 23]: row-sum maxima;
                                            // [32 .. 47]: their reciprocal pivots
-  int* ci = (int*)(cv + 48);               // [2][8]: their rows
-  int* pl = ci + 16;                       // [NB]: pivot rows of the panel eliminated here
+  int* pl = (int*)(cv + 48);               // [NB]: pivot rows of the panel eliminated here
   int* rk = pl + NB;                       // [NB]: pivot rows of panel k
   int* ri = rk + NB;                       // [Mp]: rows used as pivots (panel), pivot rows (read-out)
   const int tid = threadIdx.x, L = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
@@ -748,14 +784,14 @@ __global__ void __launch_bounds__(NT) k_gj_step64(GJArgs g, int k) {
   }
 #pragma unroll
   for (int jj = 0; jj < 32; ++jj) v[jj] = W[tid + (int64_t)(c0 + jj) * Mp];
-  const double pma = gj_panel<32>(v, used, cand, cv, ci, pl, nw);
+  const double pma = gj_panel<32>(v, used, cand, cv, pl, nw);
 #pragma unroll
   for (int jj = 0; jj < 32; ++jj) W[tid + (int64_t)(c0 + jj) * Mp] = v[jj];
   __syncthreads();   // Z_A and R_A complete
   gj_half_apply(W, Mp, c0, pl, c0 + 32, Bs);
 #pragma unroll
   for (int jj = 0; jj < 32; ++jj) v[jj] = W[tid + (int64_t)(c0 + 32 + jj) * Mp];
-  const double pmb = gj_panel<32>(v, used, cand, cv, ci, pl + 32, nw);
+  const double pmb = gj_panel<32>(v, used, cand, cv, pl + 32, nw);
 #pragma unroll
   for (int jj = 0; jj < 32; ++jj) W[tid + (int64_t)(c0 + 32 + jj) * Mp] = v[jj];
   __syncthreads();   // Z_B and R_B complete
@@ -772,7 +808,7 @@ template <int NT>
 static hipError_t launch_gj_split64(const GJArgs& g, hipStream_t st) {
   constexpr int NB = 64;
   const int Mp = g.Mp, ntile = Mp / NB;
-  const size_t lds = (size_t)(NB * NB + 2 * 8 * NB + 48) * sizeof(double) + (size_t)(16 + 2 * NB + Mp) * sizeof(int);
+  const size_t lds = (size_t)(NB * NB + 2 * 8 * NB + 48) * sizeof(double) + (size_t)(2 * NB + Mp) * sizeof(int);
   hipError_t e = hipFuncSetAttribute((const void*)k_gj_step64<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
