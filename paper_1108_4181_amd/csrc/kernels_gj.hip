@@ -310,8 +310,14 @@ __device__ __forceinline__ int pivot_key_row(uint64_t k) { return 511 - (int)(k 
 template <int CTRL, int ROWMASK>
 __device__ __forceinline__ void keymax_dpp_step(uint64_t& k) {
   const int lo = (int)(uint32_t)k, hi = (int)(uint32_t)(k >> 32);
-  const int olo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xF, false);
-  const int ohi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xF, false);
+  int olo, ohi;
+  if constexpr (ROWMASK == 0xF && CTRL < 0x142) {   // quad permutes and row mirrors: every lane has a source
+    olo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false);
+    ohi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false);
+  } else {                                          // row broadcasts: lanes outside ROWMASK keep their own
+    olo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xF, false);
+    ohi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xF, false);
+  }
   const uint64_t o = ((uint64_t)(uint32_t)ohi << 32) | (uint32_t)olo;
   k = (o > k) ? o : k;
 }
@@ -355,7 +361,9 @@ __device__ __forceinline__ void gj_column(const double (&src)[NB], double (&dst)
   const uint32_t khi = __builtin_amdgcn_readlane((int)(uint32_t)(key >> 32), 63);
   const uint64_t wkey = ((uint64_t)khi << 32) | klo;
   if (tid == pivot_key_row(wkey)) {
-    double* cp = cand + (slot * 8 + w) * NB;
+    int co = (slot * 8 + w) * NB;
+    asm volatile("" : "+v"(co));   // one base register, the entries at immediate offsets
+    double* cp = cand + co;
 #pragma unroll
     for (int jj = 0; jj < NB; ++jj) cp[jj] = src[jj];
     cv[32 + slot * 8 + w] = rcp;
@@ -368,7 +376,9 @@ __device__ __forceinline__ void gj_column(const double (&src)[NB], double (&dst)
   keymax_dpp_step<0x141, 0xF>(bk);   // row_half_mirror: lane i of eight meets lane 7 - i
   const int r = __builtin_amdgcn_readfirstlane(pivot_key_row(bk));
   const int wr = r >> 6;
-  const double* pr = cand + (slot * 8 + wr) * NB;
+  int po = (slot * 8 + wr) * NB;
+  asm volatile("" : "+v"(po));     // as above
+  const double* pr = cand + po;
   const double ipv = cv[32 + slot * 8 + wr];
   const bool piv = (tid == r);
   const double f = piv ? 0.0 : vj * ipv;   // v <- v - v_j * (pivot row / pivot), column j <- -v_j / pivot
