@@ -245,11 +245,12 @@ def test_singular_block_large(td, M):
     assert e.value.code == 3 and "block row 7" in str(e.value)
 
 
-@pytest.mark.parametrize("M", [384, 448, 512])
+@pytest.mark.parametrize("M", [256, 384, 448, 512])
 def test_row_interchanges_many_blocks_per_launch(td, M):
-    """Row interchanges at block sizes from 384 with 32 subdomains of three rows: each step of the
-    subdomain elimination inverts 32 blocks in one launch, which takes the Gauss-Jordan path with
-    64-column panels (two 32-column halves per panel in the lead work-group)."""
+    """Row interchanges with 32 subdomains of three rows: each step of the subdomain elimination
+    inverts 32 blocks in one launch, which takes the Gauss-Jordan path with 64-column panels at
+    block sizes from 384 (two 32-column halves per panel in the lead work-group) and the one with
+    32-column panels at 256."""
     N, K, p = 96, 5, 32
     sys = _pivoting_system(N, M, 900 + M)
     F = synth.rhs_columns(900 + M, N, M, range(K))
@@ -257,11 +258,11 @@ def test_row_interchanges_many_blocks_per_launch(td, M):
     assert rel_err(X, oracle.solve(sys, F)) < 1e-11
 
 
-@pytest.mark.parametrize("M", [384, 512])
+@pytest.mark.parametrize("M", [256, 384, 512])
 def test_singular_and_nan_many_blocks_per_launch(td, M):
-    """TD_ESINGULAR from the 64-column-panel path (32 blocks per launch): a zero C block that opens
-    subdomain 5 (block row 16) and, separately, a NaN on the diagonal of block row 50 in the last
-    panel."""
+    """TD_ESINGULAR with 32 blocks per launch (the 64-column-panel path from block size 384): a zero
+    C block that opens subdomain 5 (block row 16) and, separately, a NaN on the diagonal of block row
+    50 in the last panel."""
     N, p = 96, 32
     sys = synth.varcoef_system(N, M, seed=60 + M)
     C = sys.C.copy()
