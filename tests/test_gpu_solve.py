@@ -245,15 +245,16 @@ def test_singular_block_large(td, M):
     assert e.value.code == 3 and "block row 7" in str(e.value)
 
 
-@pytest.mark.parametrize("M", [256, 384, 448, 512])
-def test_row_interchanges_many_blocks_per_launch(td, M):
-    """Row interchanges with 32 subdomains of three rows: each step of the subdomain elimination
-    inverts 32 blocks in one launch, which takes the Gauss-Jordan path with 64-column panels at
-    block sizes from 384 (two 32-column halves per panel in the lead work-group) and the one with
-    32-column panels at 256."""
-    N, K, p = 96, 5, 32
-    sys = _pivoting_system(N, M, 900 + M)
-    F = synth.rhs_columns(900 + M, N, M, range(K))
+@pytest.mark.parametrize("M,p", [(256, 32), (384, 32), (448, 32), (512, 32), (384, 35), (512, 37)])
+def test_row_interchanges_many_blocks_per_launch(td, M, p):
+    """Row interchanges with 32 or more subdomains of three rows: each step of the subdomain
+    elimination inverts that many blocks in one launch, which takes the Gauss-Jordan path with
+    64-column panels at block sizes from 384 (two 32-column halves per panel in the lead
+    work-group) and the one with 32-column panels at 256.  35 and 37 subdomains leave the
+    work-group grid's last group of eight matrices partly empty."""
+    N, K = 3 * p, 5
+    sys = _pivoting_system(N, M, 900 + M + p)
+    F = synth.rhs_columns(900 + M + p, N, M, range(K))
     _, X = _solve(td, sys, F, p)
     assert rel_err(X, oracle.solve(sys, F)) < 1e-11
 
