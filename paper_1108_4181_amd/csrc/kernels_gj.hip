@@ -650,9 +650,10 @@ __device__ __forceinline__ void gj_half_apply(double* W, int Mp, int zc, const i
 // when a launch holds many matrices: there the update passes over the matrices bound the time, and
 // rank-64 products halve them (Mp / 64 + 1 launches per inversion).  Same roles and orders as
 // k_gj_step; a tile is updated in four quarters of 16 columns with the rank-64 operand kept in
-// registers, the lead work-group's updated panel and the last launch's read-out go through the matrix
-// in global memory (a 64-column tile of 512 rows would take 256 KB of LDS), and the lead eliminates
-// its panel as two 32-column halves joined by gj_half_apply.
+// registers, the lead work-group's updated panel goes through the matrix in global memory (a 64-column
+// tile of 512 rows would take 256 KB of LDS), the last launch's other tiles write the inverse straight
+// from the products' registers, and the lead eliminates its panel as two 32-column halves joined by
+// gj_half_apply.
 template <int NT>
 __global__ void __launch_bounds__(NT) k_gj_step64(GJArgs g, int k) {
   constexpr int NB = 64, RT = 4, CTN = 4;  // CTN: 4-column output tiles of a 16-column quarter
@@ -702,7 +703,15 @@ __global__ void __launch_bounds__(NT) k_gj_step64(GJArgs g, int k) {
   }
 
   if (k >= 0 && !(last && lead)) {
+    // the last launch writes the tile's final columns into the inverse from the products' registers:
+    // S[i][j] goes to inverse[invp[i]][piv[j]], invp the inverse of the pivot-row permutation
+    int* invp = (int*)cand;                // [Mp] (the candidate rows are not used by these work-groups)
     if (tid < NB) rk[tid] = piv[k * NB + tid];
+    if (last) {
+      const int pr = piv[tid];
+      ri[tid] = pr;
+      invp[pr] = tid;
+    }
     __syncthreads();
     for (int e = tid; e < NB * NB; e += blockDim.x) {
       const int j = e / NB, kk = e - j * NB;
@@ -740,25 +749,42 @@ __global__ void __launch_bounds__(NT) k_gj_step64(GJArgs g, int k) {
 #pragma unroll
           for (int ct = 0; ct < CTN; ++ct) acc[t][ct] = mfma4(a[k4][t], b[ct], acc[t][ct]);
       }
+      if (last) {
+        double* out = g.out + g.out_off[q];
+        double* al = g.alpha ? g.alpha + g.out_off[q] : nullptr;
+        const double* bd = g.alpha ? g.bdiag + g.bd_off[q] : nullptr;
 #pragma unroll
-      for (int t = 0; t < RT; ++t)
+        for (int ct = 0; ct < CTN; ++ct) {
+          const int oc = ri[ch + 4 * ct + out_col(L)];
+          const double bo = al ? bd[oc] : 0.0;
 #pragma unroll
-        for (int ct = 0; ct < CTN; ++ct)
-          W[rb + 16 * t + out_row(L) + (int64_t)(ch + 4 * ct + out_col(L)) * Mp] = acc[t][ct];
+          for (int t = 0; t < RT; ++t) {
+            const int64_t o = invp[rb + 16 * t + out_row(L)] + (int64_t)oc * Mp;
+            out[o] = acc[t][ct];
+            if (al) al[o] = acc[t][ct] * bo;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+          for (int ct = 0; ct < CTN; ++ct)
+            W[rb + 16 * t + out_row(L) + (int64_t)(ch + 4 * ct + out_col(L)) * Mp] = acc[t][ct];
+      }
     }
-    if (!lead && !last) return;
+    if (!lead) return;
   }
 
-  if (last) {
-    if (lead) {   // the singularity test (the last panel is final since the previous launch)
+  if (last) {   // the lead work-group: the last panel (final since the previous launch), the singularity test
+    {
       double rs = 0.0;
       for (int cc = 0; cc < ntile; ++cc) rs += part[(int64_t)cc * Mp + tid];
       for (int off = 32; off > 0; off >>= 1) rs = fmax(rs, __shfl_xor(rs, off));
       if (L == 0) cv[16 + w] = rs;
     }
     ri[tid] = piv[tid];
-    __syncthreads();   // the tile's final values, the pivot rows and the row-sum maxima complete
-    if (lead && tid == 0) {
+    __syncthreads();   // the pivot rows and the row-sum maxima complete
+    if (tid == 0) {
       double norm = 0.0;
       for (int u = 0; u < nw; ++u) norm = fmax(norm, cv[16 + u]);
       if (!(g.pmin[q] > 1e-14 * norm)) atomicMin(g.bad, g.tag[q]);
