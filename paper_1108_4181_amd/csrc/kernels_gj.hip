@@ -322,32 +322,14 @@ __device__ __forceinline__ void keymax_dpp_step(uint64_t& k) {
   k = (o > k) ? o : k;
 }
 
-// Gauss-Jordan elimination of one panel of NB columns, one row per thread: v[j] is the thread's entry
-// of panel column j, rows with `used` set were pivots of earlier panels.  Per column every wave finds
-// its best candidate with a DPP maximum of pivot keys (pivot_key), and the winning lane of each wave
-// publishes that row and its reciprocal pivot, the wave's key next to them; after one work-group
-// barrier every thread takes the largest of the waves' keys (a DPP maximum over eight lanes) and
-// reads the pivot row from the slot of the wave that holds that row.  Slots alternate between two
-// copies, so one barrier per column suffices.
-//   The loop stays rolled without indexing registers at run time: the row is kept rotated so that v[0]
-// is always the current column, and the update writes each entry one place down (column j's new entry
-// goes to the end), so after NB columns the order is the original one again.  The pivot row is not
-// scaled when it is chosen: later eliminations are linear in each row, so its entries are multiplied
-// by the reciprocal pivot once after the panel (its column-j entry is kept as 1 until then), and every
-// row takes the same single fused multiply-add per entry and column.  Every lane divides by its own entry
-// before the key maximum, so that the winning lane's reciprocal is ready when it publishes its row.
-// The pivot row of column j goes to prow[j] (written by thread 0).  Returns the smallest pivot magnitude of the panel (NaN if a pivot was NaN; the caller tests it
-// against the tolerance).  cand holds [2][8][NB] rows, cv [2][8] keys and, from cv[32], [2][8]
-// reciprocals.
-// One column of gj_panel: src holds the row rotated so that src[0] is column j; the updated row goes to
-// dst one place down (column j's new entry at the end; dst may be src: each entry is read before it is
-// written).
+// One column of gj_panel: v holds the row rotated so that v[0] is column j; the updated row is written
+// one place down (column j's new entry at the end).
 template <int NB>
-__device__ __forceinline__ void gj_column(const double (&src)[NB], double (&dst)[NB], int j, bool& used, double& sr,
-                                          double& pm, double* cand, double* cv, int* prow, int nw) {
+__device__ __forceinline__ void gj_column(double (&v)[NB], int j, bool& used, double& sr, double& pm, double* cand,
+                                          double* cv, int* prow, int nw) {
   const int tid = threadIdx.x, L = tid & 63, w = tid >> 6;
   const int slot = j & 1;
-  const double vj = src[0];
+  const double vj = v[0];
   double rcp = 1.0 / vj;                  // used only if this lane's row wins
   asm volatile("" : "+v"(rcp));
   uint64_t key = pivot_key(vj, used, tid);
@@ -365,7 +347,7 @@ __device__ __forceinline__ void gj_column(const double (&src)[NB], double (&dst)
     asm volatile("" : "+v"(co));   // one base register, the entries at immediate offsets
     double* cp = cand + co;
 #pragma unroll
-    for (int jj = 0; jj < NB; ++jj) cp[jj] = src[jj];
+    for (int jj = 0; jj < NB; ++jj) cp[jj] = v[jj];
     cv[32 + slot * 8 + w] = rcp;
   }
   if (L == 0) cv[slot * 8 + w] = __longlong_as_double((long long)wkey);
@@ -388,20 +370,37 @@ __device__ __forceinline__ void gj_column(const double (&src)[NB], double (&dst)
   const double apv = fabs(prv[0]);
   pm = (pm != pm) ? pm : ((apv != apv) ? apv : fmin(pm, apv));
 #pragma unroll
-  for (int jj = 0; jj + 1 < NB; ++jj) dst[jj] = src[jj + 1] - f * prv[jj + 1];
-  dst[NB - 1] = piv ? 1.0 : -f;
+  for (int jj = 0; jj + 1 < NB; ++jj) v[jj] = v[jj + 1] - f * prv[jj + 1];
+  v[NB - 1] = piv ? 1.0 : -f;
   sr = piv ? ipv : sr;
   used = used | piv;
   if (tid == 0) prow[j] = r;
 }
 
+// Gauss-Jordan elimination of one panel of NB columns, one row per thread: v[j] is the thread's entry
+// of panel column j, rows with `used` set were pivots of earlier panels.  Per column every wave finds
+// its best candidate with a DPP maximum of pivot keys (pivot_key), and the winning lane of each wave
+// publishes that row and its reciprocal pivot, the wave's key next to them; after one work-group
+// barrier every thread takes the largest of the waves' keys (a DPP maximum over eight lanes) and
+// reads the pivot row from the slot of the wave that holds that row.  Slots alternate between two
+// copies, so one barrier per column suffices.
+//   The loop stays rolled without indexing registers at run time: the row is kept rotated so that v[0]
+// is always the current column, and the update writes each entry one place down (column j's new entry
+// goes to the end), so after NB columns the order is the original one again.  The pivot row is not
+// scaled when it is chosen: later eliminations are linear in each row, so its entries are multiplied
+// by the reciprocal pivot once after the panel (its column-j entry is kept as 1 until then), and every
+// row takes the same single fused multiply-add per entry and column.  Every lane divides by its own
+// entry before the key maximum, so that the winning lane's reciprocal is ready when it publishes its
+// row.  The pivot row of column j goes to prow[j] (written by thread 0).  Returns the smallest pivot
+// magnitude of the panel (NaN if a pivot was NaN; the caller tests it against the tolerance).  cand
+// holds [2][8][NB] rows, cv [2][8] keys and, from cv[32], [2][8] reciprocals.
 template <int NB>
 __device__ __forceinline__ double gj_panel(double (&v)[NB], bool& used, double* cand, double* cv, int* prow,
                                            int nw) {
   double sr = 1.0;   // deferred scale of this thread's row (the reciprocal pivot if it was chosen)
   double pm = INFINITY;   // smallest pivot magnitude of the panel; NaN once a pivot is NaN
 #pragma unroll 1
-  for (int j = 0; j < NB; ++j) gj_column<NB>(v, v, j, used, sr, pm, cand, cv, prow, nw);
+  for (int j = 0; j < NB; ++j) gj_column<NB>(v, j, used, sr, pm, cand, cv, prow, nw);
 #pragma unroll
   for (int jj = 0; jj < NB; ++jj) v[jj] *= sr;
   return pm;
