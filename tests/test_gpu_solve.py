@@ -259,6 +259,24 @@ def test_row_interchanges_many_blocks_per_launch(td, M, p):
     assert rel_err(X, oracle.solve(sys, F)) < 1e-11
 
 
+@pytest.mark.parametrize("M,p", [(128, 3), (256, 32), (512, 32)])
+def test_exact_pivot_ties(td, M, p):
+    """Diagonal blocks C_j = H / sqrt(M), H a Sylvester Hadamard matrix (orthogonal once scaled),
+    with the dense couplings of dense_system (norm about 1.15 / sqrt(M)): in the first block of every
+    subdomain all candidates of each pivot column tie exactly in magnitude, so the pivot search's
+    tie-break (the smaller row) decides every pivot; the per-panel Gauss-Jordan paths with 32-column
+    panels (128, 256) and 64-column panels (512, 32 blocks per launch)."""
+    from scipy.linalg import hadamard
+    N, K = 3 * p, 4
+    base = synth.dense_system(N, M, 1300 + M)
+    H = hadamard(M).astype(np.float64) / np.sqrt(M)    # symmetric: the storage order does not matter
+    C = np.ascontiguousarray(np.broadcast_to(H, (N, M, M)))
+    sys = synth.System(N, M, base.A, base.B, C, "dense", "dense", "dense")
+    F = synth.rhs_columns(1300 + M, N, M, range(K))
+    _, X = _solve(td, sys, F, p)
+    assert rel_err(X, oracle.solve(sys, F)) < 1e-11
+
+
 @pytest.mark.parametrize("M", [256, 384, 512])
 def test_singular_and_nan_many_blocks_per_launch(td, M):
     """TD_ESINGULAR with 32 blocks per launch (the 64-column-panel path from block size 384): a zero
