@@ -819,6 +819,7 @@ __global__ void __launch_bounds__(NT) k_gj_step64(GJArgs g, int k) {
   }
 #pragma unroll
   for (int jj = 0; jj < 32; ++jj) v[jj] = W[tid + (int64_t)(c0 + jj) * Mp];
+  __builtin_amdgcn_s_waitcnt(0);   // the row is in registers before the column loop (no waits inside it)
   const double pma = gj_panel<32>(v, used, cand, cv, pl, nw);
 #pragma unroll
   for (int jj = 0; jj < 32; ++jj) W[tid + (int64_t)(c0 + jj) * Mp] = v[jj];
@@ -826,6 +827,7 @@ __global__ void __launch_bounds__(NT) k_gj_step64(GJArgs g, int k) {
   gj_half_apply(W, Mp, c0, pl, c0 + 32, Bs);
 #pragma unroll
   for (int jj = 0; jj < 32; ++jj) v[jj] = W[tid + (int64_t)(c0 + 32 + jj) * Mp];
+  __builtin_amdgcn_s_waitcnt(0);
   const double pmb = gj_panel<32>(v, used, cand, cv, pl + 32, nw);
 #pragma unroll
   for (int jj = 0; jj < 32; ++jj) W[tid + (int64_t)(c0 + 32 + jj) * Mp] = v[jj];
