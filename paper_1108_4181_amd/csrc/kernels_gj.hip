@@ -647,9 +647,12 @@ __device__ __forceinline__ void gj_half_apply(double* W, int Mp, int zc, const i
 
 // The per-panel inversion with 64-column panels and tiles, for block sizes from 384 (multiples of 64)
 // when a launch holds many matrices: there the update passes over the matrices bound the time, and
-// rank-64 products halve them (Mp / 64 + 1 launches per inversion).  Same roles and orders as
-// k_gj_step; a tile is updated in four quarters of 16 columns with the rank-64 operand kept in
-// registers, the lead work-group's updated panel goes through the matrix in global memory (a 64-column
+// rank-64 products halve them (Mp / 64 + 1 launches per inversion).  The lead work-group has the role
+// it has in k_gj_step; in the panel launches the other tiles of a matrix are updated in turn by one
+// work-group (the leads hold half of the compute units for their panels, so more work-groups would
+// only queue), in the prologue and the last launch by one work-group per tile, each tile
+// in four quarters of 16 columns with the rank-64 operand loaded once into registers; the lead
+// work-group's updated panel goes through the matrix in global memory (a 64-column
 // tile of 512 rows would take 256 KB of LDS), the last launch's other tiles write the inverse straight
 // from the products' registers, and the lead eliminates its panel as two 32-column halves joined by
 // gj_half_apply.
@@ -668,41 +671,54 @@ __global__ void __launch_bounds__(NT) k_gj_step64(GJArgs g, int k) {
   const int tid = threadIdx.x, L = tid & 63, w = tid >> 6, nw = blockDim.x >> 6;
   const int ntile = Mp / NB;
   const bool last = (k == ntile - 1);
-  const int nmat8 = (g.nmat + 7) & ~7;     // work-group roles and order as in k_gj_step
-  int q, c;
+  // Work-groups [0, nmat8) are the lead work-groups of matrix blockIdx.x (dispatched first).  In the
+  // panel launches work-group nmat8 + q updates every other tile of matrix q in turn, so the rank-64
+  // operand is loaded once per matrix, and a launch over 128 matrices holds one work-group per compute
+  // unit; in the prologue and the last launch, where the leads finish early, work-group nmat8 + t
+  // takes tile t/8 % ntile of matrix t % 8 + 8 (t/8 / ntile) alone.  All work-groups of a matrix run
+  // on the XCD of its lead (nmat8 is a multiple of 8).
+  const int nmat8 = (g.nmat + 7) & ~7;
   const bool lead = (int)blockIdx.x < nmat8;
+  const bool per_tile = (k < 0) || (k == ntile - 1);
+  int q, tbeg = 0, tend = ntile;           // the update work-group's tiles [tbeg, tend)
   if (lead) {
     q = blockIdx.x;
-    c = last ? k : k + 1;
-    if (q >= g.nmat) return;
-  } else {
+  } else if (per_tile) {
     const int t = blockIdx.x - nmat8, i = t >> 3;
     q = (t & 7) + 8 * (i / ntile);
-    c = i % ntile;
-    if (q >= g.nmat || c == k || c == k + 1) return;
+    tbeg = i % ntile;
+    tend = tbeg + 1;
+    if (tbeg == k || (k < 0 && tbeg == 0)) return;   // the lead's tile
+  } else {
+    q = blockIdx.x - nmat8;
   }
+  if (q >= g.nmat) return;
+  const int c = last ? k : k + 1;          // the lead's tile
   double* W = g.work + (g.work_off ? g.work_off[q] : q * g.wstride);
   int* piv = g.piv + (int64_t)q * Mp;
   double* part = g.part + (int64_t)q * ntile * Mp;   // [ntile][Mp]: partial row sums of |matrix|
   const int c0 = c * NB;
   const int rb = w * 16 * RT;
 
-  if (k < 0 && !lead) {   // the tile's share of the row sums of the original matrix
-    double rs = 0.0;
+  if (k < 0 && !lead) {   // the other tiles' shares of the row sums of the original matrix
+#pragma unroll 1
+    for (int ct = max(tbeg, 1); ct < tend; ++ct) {
+      double rs = 0.0;
 #pragma unroll
-    for (int j0 = 0; j0 < NB; j0 += 8) {
-      double t[8];
+      for (int j0 = 0; j0 < NB; j0 += 8) {
+        double t[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) t[u] = W[tid + (int64_t)(c0 + j0 + u) * Mp];
+        for (int u = 0; u < 8; ++u) t[u] = W[tid + (int64_t)(ct * NB + j0 + u) * Mp];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) rs += fabs(t[u]);
+        for (int u = 0; u < 8; ++u) rs += fabs(t[u]);
+      }
+      part[(int64_t)ct * Mp + tid] = rs;
     }
-    part[(int64_t)c * Mp + tid] = rs;
     return;
   }
 
   if (k >= 0 && !(last && lead)) {
-    // the last launch writes the tile's final columns into the inverse from the products' registers:
+    // the last launch writes the tiles' final columns into the inverse from the products' registers:
     // S[i][j] goes to inverse[invp[i]][piv[j]], invp the inverse of the pivot-row permutation
     int* invp = (int*)cand;                // [Mp] (the candidate rows are not used by these work-groups)
     if (tid < NB) rk[tid] = piv[k * NB + tid];
@@ -712,10 +728,6 @@ __global__ void __launch_bounds__(NT) k_gj_step64(GJArgs g, int k) {
       invp[pr] = tid;
     }
     __syncthreads();
-    for (int e = tid; e < NB * NB; e += blockDim.x) {
-      const int j = e / NB, kk = e - j * NB;
-      Bs[kk * NB + j] = W[rk[kk] + (int64_t)(c0 + j) * Mp];
-    }
     double a[NB / 4][RT];                  // (Z - E_R) rows of this wave, Z = panel k's columns
 #pragma unroll
     for (int k4 = 0; k4 < NB / 4; ++k4) {
@@ -727,48 +739,59 @@ __global__ void __launch_bounds__(NT) k_gj_step64(GJArgs g, int k) {
         a[k4][t] = W[row + (int64_t)(k * NB + kc) * Mp] - (row == prw ? 1.0 : 0.0);
       }
     }
-    __syncthreads();   // Bs complete; every read of rows R_k of the tile precedes the stores below
+    // the lead work-group updates its tile k + 1; the others their tiles but k and k + 1
 #pragma unroll 1
-    for (int h = 0; h < 4; ++h) {
-      const int ch = c0 + 16 * h;
-      double acc[RT][CTN];
-#pragma unroll
-      for (int t = 0; t < RT; ++t)
-#pragma unroll
-        for (int ct = 0; ct < CTN; ++ct)
-          acc[t][ct] = W[rb + 16 * t + out_row(L) + (int64_t)(ch + 4 * ct + out_col(L)) * Mp];
-#pragma unroll
-      for (int k4 = 0; k4 < NB / 4; ++k4) {
-        const double* bp = Bs + (4 * k4 + (L >> 4)) * NB + 16 * h + (L & 3);
-        double b[CTN];
-#pragma unroll
-        for (int ct = 0; ct < CTN; ++ct) b[ct] = bp[4 * ct];
-#pragma unroll
-        for (int t = 0; t < RT; ++t)
-#pragma unroll
-          for (int ct = 0; ct < CTN; ++ct) acc[t][ct] = mfma4(a[k4][t], b[ct], acc[t][ct]);
+    for (int tc = lead ? k + 1 : tbeg; tc < (lead ? k + 2 : tend); ++tc) {
+      if (!lead && (tc == k || tc == k + 1)) continue;
+      const int t0 = tc * NB;
+      __syncthreads();   // the previous tile's reads of Bs are done
+      for (int e = tid; e < NB * NB; e += blockDim.x) {
+        const int j = e / NB, kk = e - j * NB;
+        Bs[kk * NB + j] = W[rk[kk] + (int64_t)(t0 + j) * Mp];
       }
-      if (last) {
-        double* out = g.out + g.out_off[q];
-        double* al = g.alpha ? g.alpha + g.out_off[q] : nullptr;
-        const double* bd = g.alpha ? g.bdiag + g.bd_off[q] : nullptr;
-#pragma unroll
-        for (int ct = 0; ct < CTN; ++ct) {
-          const int oc = ri[ch + 4 * ct + out_col(L)];
-          const double bo = al ? bd[oc] : 0.0;
-#pragma unroll
-          for (int t = 0; t < RT; ++t) {
-            const int64_t o = invp[rb + 16 * t + out_row(L)] + (int64_t)oc * Mp;
-            out[o] = acc[t][ct];
-            if (al) al[o] = acc[t][ct] * bo;
-          }
-        }
-      } else {
+      __syncthreads();   // Bs complete; every read of rows R_k of the tile precedes the stores below
+#pragma unroll 1
+      for (int h = 0; h < 4; ++h) {
+        const int ch = t0 + 16 * h;
+        double acc[RT][CTN];
 #pragma unroll
         for (int t = 0; t < RT; ++t)
 #pragma unroll
           for (int ct = 0; ct < CTN; ++ct)
-            W[rb + 16 * t + out_row(L) + (int64_t)(ch + 4 * ct + out_col(L)) * Mp] = acc[t][ct];
+            acc[t][ct] = W[rb + 16 * t + out_row(L) + (int64_t)(ch + 4 * ct + out_col(L)) * Mp];
+#pragma unroll
+        for (int k4 = 0; k4 < NB / 4; ++k4) {
+          const double* bp = Bs + (4 * k4 + (L >> 4)) * NB + 16 * h + (L & 3);
+          double b[CTN];
+#pragma unroll
+          for (int ct = 0; ct < CTN; ++ct) b[ct] = bp[4 * ct];
+#pragma unroll
+          for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int ct = 0; ct < CTN; ++ct) acc[t][ct] = mfma4(a[k4][t], b[ct], acc[t][ct]);
+        }
+        if (last) {
+          double* out = g.out + g.out_off[q];
+          double* al = g.alpha ? g.alpha + g.out_off[q] : nullptr;
+          const double* bd = g.alpha ? g.bdiag + g.bd_off[q] : nullptr;
+#pragma unroll
+          for (int ct = 0; ct < CTN; ++ct) {
+            const int oc = ri[ch + 4 * ct + out_col(L)];
+            const double bo = al ? bd[oc] : 0.0;
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+              const int64_t o = invp[rb + 16 * t + out_row(L)] + (int64_t)oc * Mp;
+              out[o] = acc[t][ct];
+              if (al) al[o] = acc[t][ct] * bo;
+            }
+          }
+        } else {
+#pragma unroll
+          for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int ct = 0; ct < CTN; ++ct)
+              W[rb + 16 * t + out_row(L) + (int64_t)(ch + 4 * ct + out_col(L)) * Mp] = acc[t][ct];
+        }
       }
     }
     if (!lead) return;
@@ -850,8 +873,10 @@ static hipError_t launch_gj_split64(const GJArgs& g, hipStream_t st) {
                                      (int)lds);
   if (e != hipSuccess) return e;
   const int nmat8 = grid_pad8(g.nmat);
-  for (int k = -1; k < ntile; ++k)
-    hipLaunchKernelGGL((k_gj_step64<NT>), dim3(nmat8 * (1 + ntile)), dim3(Mp), lds, st, g, k);
+  for (int k = -1; k < ntile; ++k) {   // per-tile work-groups in the prologue and the last launch
+    const int nwg = (k < 0 || k == ntile - 1) ? nmat8 * (1 + ntile) : 2 * nmat8;
+    hipLaunchKernelGGL((k_gj_step64<NT>), dim3(nwg), dim3(Mp), lds, st, g, k);
+  }
   return hipGetLastError();
 }
 
